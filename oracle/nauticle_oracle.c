@@ -1,0 +1,925 @@
+/*
+ * nauticle_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT PATH.
+ *
+ * A plain, slow, obviously-correct CPU implementation of the weakly
+ * compressible SPH step that the HIP library computes.  It exists only to
+ * check that library: tests/, the package's smoke() and bench.py's
+ * cpu_baseline leg may load it; nothing in paper_1710_08259_amd/ may.
+ * It shares no code, header, constant or table with the HIP sources.
+ *
+ * Arithmetic: FP64 for every physical quantity.  The only FP32 code is the
+ * part whose result is defined bit-exactly in FP32 (the binning of FP32
+ * positions into cells and the FP32 neighbour predicate); it uses plain C
+ * float operations and fmaf, with contraction disabled at build time
+ * (-ffp-contract=off) so that every operation is rounded as written.
+ *
+ * Parallelism follows the paper's own scheme (Sec. "Multithreading"): the
+ * particle set is split into N_t contiguous ranges of N_p/N_t particles,
+ * one per thread, and a phase finishes for all particles (thread join)
+ * before the next phase starts.  No particle is handled by two threads.
+ *
+ * Method (paper Sec. 2, "Definition of the general formulation", and
+ * Sec. 5.1, Example 1):
+ *   - interaction sums over all neighbours j within the influence radius
+ *     (eq. interaction_formula), found through the cell grid of the domain
+ *     (Sec. 3.2.1, "The computational domain": cells no smaller than the
+ *     influence radius, pairs farther than one cell ignored);
+ *   - Wendland kernel W = alpha_D (1 - q/2)^4 (2q + 1), q = r/h, support 2h,
+ *     alpha_1 = 3/(4h), alpha_2 = 7/(4 pi h^2), alpha_3 = 21/(16 pi h^3)
+ *     (Example 1a, kernel equation);
+ *   - density by SPH sampling of rho itself, rho_i = sum_j m W_ij (the SPH
+ *     sampling expression with A = rho, self term included);
+ *   - Tait equation of state p = B((rho/rho0)^gamma - 1), B = c0^2 rho0/gamma,
+ *     whose linearisation at rho0 is the paper's p = c^2 (rho - rho0);
+ *   - symmetric pressure gradient (eq. diffop1 with A = p, as used in the
+ *     momentum equation of Example 1a), grad_i W_ij = F(r_ij) r_ij,
+ *     F(r) = (1/r) dW/dr = -5 alpha_D (1 - q/2)^3 / h^2;
+ *   - Laplacian viscosity (eq. diffop3 applied to v with V_j = m/rho_j, in
+ *     the Morris form nu m (1/rho_i + 1/rho_j) F_ij (v_i - v_j));
+ *   - first-order semi-implicit Euler: v <- v + dt a, then r <- r + dt v
+ *     with the new v (Example 1a, equations eq6 and eq7);
+ *   - particles leaving the box are shifted periodically on every axis
+ *     (Sec. 3.2.1).
+ * Wall particles are ordinary particles held fixed (paper Sec. 5.3 builds
+ * walls from fixed particles): they contribute density and pressure, keep
+ * v = 0 and are not integrated.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+#define OR_EMPTY 0xFFFFFFFFu
+#define OR_MAX_THREADS 256
+
+/* ------------------------------------------------------------------------- */
+/* Problem description                                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Axis-aligned box split into n[k] cells of edge cs[k]; L_k = n[k]*cs[k]. */
+typedef struct {
+    int32_t dim;         /* 1, 2 or 3 */
+    int32_t n[3];        /* cells per axis (unused axes: 1) */
+    int32_t periodic[3]; /* 1 = periodic, 0 = cut-off */
+    double origin[3];
+    double cs[3];
+} or_domain;
+
+typedef struct {
+    double h, mass, rho0, c0, gamma, nu, dt;
+    double g[3];
+} or_params;
+
+/* ------------------------------------------------------------------------- */
+/* Smoothing kernel (Example 1a, Wendland kernel equation)                    */
+/* ------------------------------------------------------------------------- */
+
+double or_alpha(int32_t dim, double h)
+{
+    if (dim == 1) return 3.0 / (4.0 * h);
+    if (dim == 2) return 7.0 / (4.0 * M_PI * h * h);
+    return 21.0 / (16.0 * M_PI * h * h * h);
+}
+
+/* W(r) = alpha (1 - q/2)^4 (2q + 1) for q < 2, zero otherwise. */
+double or_W(int32_t dim, double h, double r)
+{
+    double q = r / h;
+    if (q >= 2.0) return 0.0;
+    double t = 1.0 - 0.5 * q;
+    return or_alpha(dim, h) * t * t * t * t * (2.0 * q + 1.0);
+}
+
+/* F(r) = (1/r) dW/dr = -5 alpha (1 - q/2)^3 / h^2; finite at r = 0. */
+double or_F(int32_t dim, double h, double r)
+{
+    double q = r / h;
+    if (q >= 2.0) return 0.0;
+    double t = 1.0 - 0.5 * q;
+    return -5.0 * or_alpha(dim, h) * t * t * t / (h * h);
+}
+
+/* dF/dr = (15 alpha / (2 h^3)) (1 - q/2)^2. */
+double or_dF(int32_t dim, double h, double r)
+{
+    double q = r / h;
+    if (q >= 2.0) return 0.0;
+    double t = 1.0 - 0.5 * q;
+    return 7.5 * or_alpha(dim, h) * t * t / (h * h * h);
+}
+
+/* Tait equation of state. */
+double or_tait(const or_params* P, double rho)
+{
+    double B = P->c0 * P->c0 * P->rho0 / P->gamma;
+    return B * (pow(rho / P->rho0, P->gamma) - 1.0);
+}
+
+/* ------------------------------------------------------------------------- */
+/* FP32 binning of positions into (cell, offset) and the FP32 neighbour       */
+/* predicate.  These define the bit-exact results.                            */
+/* ------------------------------------------------------------------------- */
+
+static int64_t or_floor_mod(int64_t a, int64_t n)
+{
+    int64_t r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Offset t (FP32, measured from the lower face of cell c along one axis) is
+ * split into a whole number of cells k and a remainder in [0, cs):
+ *   k = floor(t * inv_cs), off = t - k*cs (one rounding, via fmaf);
+ * if rounding of t*inv_cs put k one cell off, k is corrected and off
+ * recomputed; a remainder that rounds up to cs itself is pulled to the
+ * largest float below cs.  The cell index then wraps modulo n (periodic
+ * shifting of leaving particles, on every axis). */
+static void or_split_f32(float t, float cs, float inv_cs, int64_t n, int64_t c,
+                         int64_t* c_out, float* off_out)
+{
+    float q = t * inv_cs;
+    int64_t k = (int64_t)floorf(q);
+    float off = fmaf(-(float)k, cs, t);
+    if (off < 0.0f) {
+        k -= 1;
+        off = fmaf(-(float)k, cs, t);
+    } else if (off >= cs) {
+        k += 1;
+        off = fmaf(-(float)k, cs, t);
+    }
+    if (off < 0.0f) off = 0.0f;
+    if (off >= cs) off = nextafterf(cs, 0.0f);
+    *c_out = or_floor_mod(c + k, n);
+    *off_out = off;
+}
+
+/* Absolute FP32 positions -> linear cell index (x fastest) and FP32 offsets
+ * from the cell's lower corner.  pos[k] may be NULL for k >= dim. */
+void or_bin_f32(const or_domain* D, int64_t n, const float* px, const float* py,
+                const float* pz, uint32_t* cell, float* ox, float* oy, float* oz)
+{
+    const float* pos[3] = {px, py, pz};
+    float* off[3] = {ox, oy, oz};
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3] = {0, 0, 0};
+        for (int k = 0; k < D->dim; ++k) {
+            float o = (float)D->origin[k];
+            float cs = (float)D->cs[k];
+            float inv = (float)(1.0 / D->cs[k]);
+            float t = pos[k][i] - o;
+            float r;
+            or_split_f32(t, cs, inv, D->n[k], 0, &c[k], &r);
+            off[k][i] = r;
+        }
+        cell[i] = (uint32_t)(c[0] + (int64_t)D->n[0] * (c[1] + (int64_t)D->n[1] * c[2]));
+    }
+}
+
+static void or_cell_coords(const or_domain* D, uint32_t cell, int64_t c[3])
+{
+    int64_t v = cell;
+    c[0] = v % D->n[0];
+    v /= D->n[0];
+    c[1] = v % D->n[1];
+    c[2] = v / D->n[1];
+}
+
+/* Signed cell distance from ci to cj along axis k, folded onto the nearest
+ * periodic image on periodic axes; 2 means "not adjacent". */
+static int or_cell_delta(const or_domain* D, int k, int64_t ci, int64_t cj)
+{
+    int64_t d = cj - ci;
+    int64_t n = D->n[k];
+    if (D->periodic[k]) {
+        if (d > n / 2) d -= n;
+        if (d < -(n / 2)) d += n;
+        /* n >= 3 is required, so +-1 images are distinct */
+    }
+    if (d < -1 || d > 1) return 2;
+    return (int)d;
+}
+
+/* FP32 neighbour predicate between particle i and j whose cells differ by
+ * delta (each component in {-1,0,1}):
+ *   s_k  = fl32(off_j,k + delta_k * cs_k)      (delta*cs is exact)
+ *   d_k  = fl32(s_k - off_i,k)
+ *   r2   = fmaf(d_z, d_z, fmaf(d_y, d_y, d_x * d_x))
+ *   neighbour iff r2 < fl32(4 h^2) and j != i. */
+static int or_pred_f32(const or_domain* D, float R2, const int delta[3],
+                       const float* offi, const float* offj)
+{
+    float d[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < D->dim; ++k) {
+        float cs = (float)D->cs[k];
+        float s = offj[k] + (float)delta[k] * cs;
+        d[k] = s - offi[k];
+    }
+    float r2 = d[0] * d[0];
+    if (D->dim >= 2) r2 = fmaf(d[1], d[1], r2);
+    if (D->dim >= 3) r2 = fmaf(d[2], d[2], r2);
+    return r2 < R2;
+}
+
+static float or_R2_f32(double h) { return (float)(4.0 * h * h); }
+
+/* ------------------------------------------------------------------------- */
+/* Stable counting sort by key; cell start/end table                          */
+/* ------------------------------------------------------------------------- */
+
+/* perm[p] = input position of the p-th element in key order (ties keep the
+ * input order); key_sorted[p] = key[perm[p]]; start/end per key value, with
+ * OR_EMPTY for both when no element has that key. */
+int or_sort_keys(int64_t n, const uint32_t* key, uint32_t n_keys, uint32_t* key_sorted,
+                 uint32_t* perm, uint32_t* start, uint32_t* end)
+{
+    int64_t* count = (int64_t*)calloc((size_t)n_keys + 1, sizeof(int64_t));
+    if (!count) return -1;
+    for (int64_t i = 0; i < n; ++i) count[key[i] + 1] += 1;
+    for (uint32_t c = 0; c < n_keys; ++c) count[c + 1] += count[c];
+    for (uint32_t c = 0; c < n_keys; ++c) {
+        if (count[c + 1] > count[c]) {
+            start[c] = (uint32_t)count[c];
+            end[c] = (uint32_t)count[c + 1];
+        } else {
+            start[c] = OR_EMPTY;
+            end[c] = OR_EMPTY;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t pos = count[key[i]]++;
+        perm[pos] = (uint32_t)i;
+        key_sorted[pos] = key[i];
+    }
+    free(count);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* FP32 neighbour counts / lists on the (cell, offset) layout                 */
+/* ------------------------------------------------------------------------- */
+
+/* Particle list per cell, built by the stable counting sort above. */
+typedef struct {
+    uint32_t* start;
+    uint32_t* end;
+    uint32_t* perm;
+    uint32_t* key_sorted;
+    int64_t n_cells;
+} or_cell_list;
+
+static int or_cell_list_build(const or_domain* D, int64_t n, const uint32_t* cell, or_cell_list* L)
+{
+    int64_t nc = (int64_t)D->n[0] * D->n[1] * D->n[2];
+    L->n_cells = nc;
+    L->start = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)nc);
+    L->end = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)nc);
+    L->perm = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    L->key_sorted = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    if (!L->start || !L->end || !L->perm || !L->key_sorted) return -1;
+    return or_sort_keys(n, cell, (uint32_t)nc, L->key_sorted, L->perm, L->start, L->end);
+}
+
+static void or_cell_list_free(or_cell_list* L)
+{
+    free(L->start);
+    free(L->end);
+    free(L->perm);
+    free(L->key_sorted);
+}
+
+/* For every particle i: count[i] = number of j satisfying the FP32
+ * predicate.  If list != NULL, list[i*max_nbr + k] receives the neighbours'
+ * input indices (stencil order, then index order), up to max_nbr of them.
+ * Found through the cell grid: only the 3^dim cells around i's cell. */
+int or_neighbours_f32(const or_domain* D, double h, int64_t n, const uint32_t* cell,
+                      const float* ox, const float* oy, const float* oz, int32_t* count,
+                      uint32_t* list, int32_t max_nbr)
+{
+    or_cell_list L;
+    if (or_cell_list_build(D, n, cell, &L) != 0) return -1;
+    const float* off[3] = {ox, oy, oz};
+    float R2 = or_R2_f32(h);
+    int span[3] = {1, 1, 1};
+    for (int k = 0; k < D->dim; ++k) span[k] = 3;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t ci[3];
+        or_cell_coords(D, cell[i], ci);
+        float offi[3] = {0, 0, 0};
+        for (int k = 0; k < D->dim; ++k) offi[k] = off[k][i];
+        int32_t cnt = 0;
+        for (int dz = 0; dz < span[2]; ++dz)
+            for (int dy = 0; dy < span[1]; ++dy)
+                for (int dx = 0; dx < span[0]; ++dx) {
+                    int delta[3] = {span[0] == 3 ? dx - 1 : 0, span[1] == 3 ? dy - 1 : 0,
+                                    span[2] == 3 ? dz - 1 : 0};
+                    int64_t cj[3];
+                    int ok = 1;
+                    for (int k = 0; k < 3; ++k) {
+                        int64_t c = ci[k] + delta[k];
+                        if (k < D->dim) {
+                            if (D->periodic[k])
+                                c = or_floor_mod(c, D->n[k]);
+                            else if (c < 0 || c >= D->n[k])
+                                ok = 0;
+                        }
+                        cj[k] = c;
+                    }
+                    if (!ok) continue;
+                    uint32_t nc = (uint32_t)(cj[0] + (int64_t)D->n[0] * (cj[1] + (int64_t)D->n[1] * cj[2]));
+                    if (L.start[nc] == OR_EMPTY) continue;
+                    for (uint32_t p = L.start[nc]; p < L.end[nc]; ++p) {
+                        uint32_t j = L.perm[p];
+                        if ((int64_t)j == i) continue;
+                        float offj[3] = {0, 0, 0};
+                        for (int k = 0; k < D->dim; ++k) offj[k] = off[k][j];
+                        if (or_pred_f32(D, R2, delta, offi, offj)) {
+                            if (list && cnt < max_nbr) list[i * (int64_t)max_nbr + cnt] = j;
+                            ++cnt;
+                        }
+                    }
+                }
+        count[i] = cnt;
+    }
+    or_cell_list_free(&L);
+    return 0;
+}
+
+/* The same counts by brute force over all pairs: used to pin the cell-grid
+ * enumeration above. */
+void or_neighbours_f32_brute(const or_domain* D, double h, int64_t n, const uint32_t* cell,
+                             const float* ox, const float* oy, const float* oz, int32_t* count)
+{
+    const float* off[3] = {ox, oy, oz};
+    float R2 = or_R2_f32(h);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t ci[3];
+        or_cell_coords(D, cell[i], ci);
+        float offi[3] = {0, 0, 0};
+        for (int k = 0; k < D->dim; ++k) offi[k] = off[k][i];
+        int32_t cnt = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            int64_t cj[3];
+            or_cell_coords(D, cell[j], cj);
+            int delta[3] = {0, 0, 0};
+            int adjacent = 1;
+            for (int k = 0; k < D->dim; ++k) {
+                delta[k] = or_cell_delta(D, k, ci[k], cj[k]);
+                if (delta[k] == 2) adjacent = 0;
+            }
+            if (!adjacent) continue;
+            float offj[3] = {0, 0, 0};
+            for (int k = 0; k < D->dim; ++k) offj[k] = off[k][j];
+            cnt += or_pred_f32(D, R2, delta, offi, offj);
+        }
+        count[i] = cnt;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* FP64 neighbour search on absolute positions                                */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    const or_domain* D;
+    double R2;
+    or_cell_list L;
+    int32_t* cell_of; /* per particle cell (linear) */
+} or_grid64;
+
+static int64_t or_cell_axis64(const or_domain* D, int k, double x)
+{
+    int64_t c = (int64_t)floor((x - D->origin[k]) / D->cs[k]);
+    if (c < 0) c = 0;
+    if (c >= D->n[k]) c = D->n[k] - 1;
+    return c;
+}
+
+static int or_grid64_build(or_grid64* G, const or_domain* D, double h, int64_t n, const double* x)
+{
+    G->D = D;
+    G->R2 = 4.0 * h * h;
+    uint32_t* cell = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    G->cell_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!cell || !G->cell_of) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3] = {0, 0, 0};
+        for (int k = 0; k < D->dim; ++k) c[k] = or_cell_axis64(D, k, x[3 * i + k]);
+        cell[i] = (uint32_t)(c[0] + (int64_t)D->n[0] * (c[1] + (int64_t)D->n[1] * c[2]));
+        G->cell_of[i] = (int32_t)cell[i];
+    }
+    int rc = or_cell_list_build(D, n, cell, &G->L);
+    free(cell);
+    return rc;
+}
+
+static void or_grid64_free(or_grid64* G)
+{
+    or_cell_list_free(&G->L);
+    free(G->cell_of);
+}
+
+/* r_ij = x_i - x_j, minimum image on periodic axes. */
+static void or_rel(const or_domain* D, const double* xi, const double* xj, double r[3])
+{
+    for (int k = 0; k < 3; ++k) r[k] = 0.0;
+    for (int k = 0; k < D->dim; ++k) {
+        double d = xi[k] - xj[k];
+        if (D->periodic[k]) {
+            double L = D->n[k] * D->cs[k];
+            d -= L * nearbyint(d / L);
+        }
+        r[k] = d;
+    }
+}
+
+/* Calls visit(ctx, i, j, r_ij, |r_ij|) for every j != i with |r_ij| < 2h.
+ * Neighbours are enumerated from the 3^dim cells around i's cell. */
+typedef void (*or_visit_fn)(void* ctx, int64_t i, int64_t j, const double r[3], double rn);
+
+static void or_for_neighbours(const or_grid64* G, const double* x, int64_t i, or_visit_fn visit, void* ctx)
+{
+    const or_domain* D = G->D;
+    int64_t ci[3];
+    or_cell_coords(D, (uint32_t)G->cell_of[i], ci);
+    int span[3] = {1, 1, 1};
+    for (int k = 0; k < D->dim; ++k) span[k] = 3;
+    for (int dz = 0; dz < span[2]; ++dz)
+        for (int dy = 0; dy < span[1]; ++dy)
+            for (int dx = 0; dx < span[0]; ++dx) {
+                int delta[3] = {span[0] == 3 ? dx - 1 : 0, span[1] == 3 ? dy - 1 : 0,
+                                span[2] == 3 ? dz - 1 : 0};
+                int64_t cj[3];
+                int ok = 1;
+                for (int k = 0; k < 3; ++k) {
+                    int64_t c = ci[k] + delta[k];
+                    if (k < D->dim) {
+                        if (D->periodic[k])
+                            c = or_floor_mod(c, D->n[k]);
+                        else if (c < 0 || c >= D->n[k])
+                            ok = 0;
+                    }
+                    cj[k] = c;
+                }
+                if (!ok) continue;
+                uint32_t nc = (uint32_t)(cj[0] + (int64_t)D->n[0] * (cj[1] + (int64_t)D->n[1] * cj[2]));
+                if (G->L.start[nc] == OR_EMPTY) continue;
+                for (uint32_t p = G->L.start[nc]; p < G->L.end[nc]; ++p) {
+                    int64_t j = G->L.perm[p];
+                    if (j == i) continue;
+                    double r[3];
+                    or_rel(D, &x[3 * i], &x[3 * j], r);
+                    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                    if (r2 < G->R2) visit(ctx, i, j, r, sqrt(r2));
+                }
+            }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Thread pool in the paper's particle-decomposition style                    */
+/* ------------------------------------------------------------------------- */
+
+typedef void (*or_range_fn)(void* ctx, int64_t begin, int64_t end);
+
+typedef struct {
+    or_range_fn fn;
+    void* ctx;
+    int64_t begin, end;
+} or_task;
+
+static void* or_task_run(void* arg)
+{
+    or_task* t = (or_task*)arg;
+    t->fn(t->ctx, t->begin, t->end);
+    return NULL;
+}
+
+/* Runs fn over [0, n) split into nthreads contiguous ranges of about
+ * n/nthreads particles; returns when every range is done. */
+static void or_parallel(int64_t n, int nthreads, or_range_fn fn, void* ctx)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > OR_MAX_THREADS) nthreads = OR_MAX_THREADS;
+    if (nthreads == 1 || n < 2 * nthreads) {
+        fn(ctx, 0, n);
+        return;
+    }
+    pthread_t th[OR_MAX_THREADS];
+    or_task task[OR_MAX_THREADS];
+    int64_t nppt = n / nthreads;
+    for (int t = 0; t < nthreads; ++t) {
+        task[t].fn = fn;
+        task[t].ctx = ctx;
+        task[t].begin = t * nppt;
+        task[t].end = (t == nthreads - 1) ? n : (t + 1) * nppt;
+    }
+    int started = 0;
+    for (int t = 1; t < nthreads; ++t) {
+        if (pthread_create(&th[t], NULL, or_task_run, &task[t]) != 0) break;
+        ++started;
+    }
+    or_task_run(&task[0]);
+    for (int t = 1; t <= started; ++t) pthread_join(th[t], NULL);
+    for (int t = started + 1; t < nthreads; ++t) or_task_run(&task[t]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Density and equation of state                                              */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    const or_domain* D;
+    const or_params* P;
+    const or_grid64* G;
+    const double* x;
+    const int64_t* which; /* optional subset of particles to evaluate */
+    double* rho;
+    double* p;
+    int32_t* count;
+    double acc;      /* per-visit accumulator (thread private copy) */
+    int32_t cnt;
+} or_density_ctx;
+
+static void or_density_visit(void* c, int64_t i, int64_t j, const double r[3], double rn)
+{
+    (void)i; (void)j; (void)r;
+    or_density_ctx* ctx = (or_density_ctx*)c;
+    ctx->acc += ctx->P->mass * or_W(ctx->D->dim, ctx->P->h, rn);
+    ctx->cnt += 1;
+}
+
+static void or_density_range(void* c, int64_t begin, int64_t end)
+{
+    or_density_ctx local = *(or_density_ctx*)c;
+    for (int64_t s = begin; s < end; ++s) {
+        int64_t i = local.which ? local.which[s] : s;
+        /* self term: W(0) = alpha */
+        local.acc = local.P->mass * or_alpha(local.D->dim, local.P->h);
+        local.cnt = 0;
+        or_for_neighbours(local.G, local.x, i, or_density_visit, &local);
+        local.rho[s] = local.acc;
+        if (local.p) local.p[s] = or_tait(local.P, local.acc);
+        if (local.count) local.count[s] = local.cnt;
+    }
+}
+
+/* rho_i = m alpha + sum_{j != i, |r_ij| < 2h} m W(|r_ij|); p_i = Tait(rho_i).
+ * x is (n,3) row-major absolute positions inside the box.  If which != NULL,
+ * only particles which[0..n_eval) are evaluated, results at rho[s], p[s]. */
+int or_density(const or_domain* D, const or_params* P, int64_t n, const double* x,
+               int64_t n_eval, const int64_t* which, double* rho, double* p, int32_t* count,
+               int nthreads)
+{
+    or_grid64 G;
+    if (or_grid64_build(&G, D, P->h, n, x) != 0) return -1;
+    or_density_ctx ctx = {D, P, &G, x, which, rho, p, count, 0.0, 0};
+    or_parallel(which ? n_eval : n, nthreads, or_density_range, &ctx);
+    or_grid64_free(&G);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Accelerations                                                              */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    const or_domain* D;
+    const or_params* P;
+    const or_grid64* G;
+    const double* x;
+    const double* v;
+    const double* rho;
+    const double* p;
+    const uint8_t* fixed;
+    const int64_t* which;
+    double* a;
+    double acc[3];
+} or_force_ctx;
+
+static void or_force_visit(void* c, int64_t i, int64_t j, const double r[3], double rn)
+{
+    or_force_ctx* ctx = (or_force_ctx*)c;
+    const or_params* P = ctx->P;
+    double F = or_F(ctx->D->dim, P->h, rn);
+    double si = ctx->p[i] / (ctx->rho[i] * ctx->rho[i]);
+    double sj = ctx->p[j] / (ctx->rho[j] * ctx->rho[j]);
+    double visc = P->nu * (1.0 / ctx->rho[i] + 1.0 / ctx->rho[j]);
+    for (int k = 0; k < 3; ++k) {
+        /* symmetric pressure gradient: -m (s_i + s_j) grad_i W_ij */
+        ctx->acc[k] -= P->mass * (si + sj) * F * r[k];
+        /* Laplacian viscosity: m nu (1/rho_i + 1/rho_j) F_ij (v_i - v_j) */
+        ctx->acc[k] += P->mass * visc * F * (ctx->v[3 * i + k] - ctx->v[3 * j + k]);
+    }
+}
+
+static void or_force_range(void* c, int64_t begin, int64_t end)
+{
+    or_force_ctx local = *(or_force_ctx*)c;
+    for (int64_t s = begin; s < end; ++s) {
+        int64_t i = local.which ? local.which[s] : s;
+        for (int k = 0; k < 3; ++k) local.acc[k] = 0.0;
+        or_for_neighbours(local.G, local.x, i, or_force_visit, &local);
+        int is_fixed = local.fixed ? local.fixed[i] : 0;
+        for (int k = 0; k < 3; ++k)
+            local.a[3 * s + k] = is_fixed ? 0.0 : local.acc[k] + (k < local.D->dim ? local.P->g[k] : 0.0);
+    }
+}
+
+/* a_i = -sum_j m (p_i/rho_i^2 + p_j/rho_j^2) F_ij r_ij
+ *       + sum_j m nu (1/rho_i + 1/rho_j) F_ij (v_i - v_j) + g
+ * for every non-fixed i (fixed particles get a = 0).  rho and p are inputs
+ * (for all n particles); x, v, a are (n,3) row-major. */
+int or_forces(const or_domain* D, const or_params* P, int64_t n, const double* x, const double* v,
+              const double* rho, const double* p, const uint8_t* fixed, int64_t n_eval,
+              const int64_t* which, double* a, int nthreads)
+{
+    or_grid64 G;
+    if (or_grid64_build(&G, D, P->h, n, x) != 0) return -1;
+    or_force_ctx ctx = {D, P, &G, x, v, rho, p, fixed, which, a, {0, 0, 0}};
+    or_parallel(which ? n_eval : n, nthreads, or_force_range, &ctx);
+    or_grid64_free(&G);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Time step                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* Periodic shifting of a coordinate into [o, o + L). */
+static double or_wrap(double x, double o, double L)
+{
+    double y = x - L * floor((x - o) / L);
+    if (y >= o + L) y = o;
+    if (y < o) y = o;
+    return y;
+}
+
+typedef struct {
+    const or_domain* D;
+    const or_params* P;
+    double* x;
+    double* v;
+    const double* a;
+    const uint8_t* fixed;
+} or_integrate_ctx;
+
+static void or_integrate_range(void* c, int64_t begin, int64_t end)
+{
+    or_integrate_ctx* ctx = (or_integrate_ctx*)c;
+    const or_domain* D = ctx->D;
+    double dt = ctx->P->dt;
+    for (int64_t i = begin; i < end; ++i) {
+        if (ctx->fixed && ctx->fixed[i]) continue;
+        for (int k = 0; k < D->dim; ++k) {
+            /* semi-implicit Euler: velocity first, then position with the new velocity */
+            ctx->v[3 * i + k] += dt * ctx->a[3 * i + k];
+            double L = D->n[k] * D->cs[k];
+            ctx->x[3 * i + k] = or_wrap(ctx->x[3 * i + k] + dt * ctx->v[3 * i + k], D->origin[k], L);
+        }
+    }
+}
+
+/* Advances (x, v) by n_steps steps.  Each step recomputes neighbours,
+ * density and pressure from the current positions, then accelerations, then
+ * integrates.  rho, p, a (optional) receive the values of the last step. */
+int or_step(const or_domain* D, const or_params* P, int64_t n, double* x, double* v,
+            const uint8_t* fixed, int32_t n_steps, double* rho_out, double* p_out, double* a_out,
+            int nthreads)
+{
+    double* rho = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* p = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* a = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!rho || !p || !a) return -1;
+    int rc = 0;
+    for (int32_t s = 0; s < n_steps && rc == 0; ++s) {
+        rc = or_density(D, P, n, x, 0, NULL, rho, p, NULL, nthreads);
+        if (rc == 0) rc = or_forces(D, P, n, x, v, rho, p, fixed, 0, NULL, a, nthreads);
+        if (rc == 0) {
+            or_integrate_ctx ic = {D, P, x, v, a, fixed};
+            or_parallel(n, nthreads, or_integrate_range, &ic);
+        }
+    }
+    if (rc == 0 && n_steps > 0) {
+        if (rho_out) memcpy(rho_out, rho, sizeof(double) * (size_t)n);
+        if (p_out) memcpy(p_out, p, sizeof(double) * (size_t)n);
+        if (a_out) memcpy(a_out, a, sizeof(double) * 3 * (size_t)n);
+    }
+    free(rho);
+    free(p);
+    free(a);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Domain validation                                                          */
+/* ------------------------------------------------------------------------- */
+
+/* 0 if the domain can be searched with a 3^dim cell stencil: every cell edge
+ * at least the influence radius 2h (Sec. 3.2.1) and at least 3 cells on a
+ * periodic axis (so the stencil never meets the same image twice). */
+int or_validate_domain(const or_domain* D, double h)
+{
+    if (D->dim < 1 || D->dim > 3) return -1;
+    for (int k = 0; k < D->dim; ++k) {
+        if (D->n[k] < 1) return -1;
+        if (D->cs[k] < 2.0 * h) return -2;
+        if (D->periodic[k] && D->n[k] < 3) return -3;
+    }
+    for (int k = D->dim; k < 3; ++k)
+        if (D->n[k] != 1) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* One-step vector-Jacobian product (reverse mode of or_step with one step)   */
+/* ------------------------------------------------------------------------- */
+/*
+ * Forward step, fluid particle i (fixed particles keep x and v = 0):
+ *   rho_i = m alpha + m sum_j W_ij,  p_i = B((rho_i/rho0)^gamma - 1)
+ *   s_i = p_i / rho_i^2,  k_i = 1 / rho_i
+ *   a_i = -m sum_j (s_i + s_j) F_ij r_ij + m nu sum_j (k_i + k_j) F_ij (v_i - v_j) + g
+ *   v'_i = v_i + dt a_i,  x'_i = x_i + dt v'_i
+ * Given cotangents (X', V') of (x', v'), the cotangents of (x, v, nu, c0):
+ *   Vh_i = V'_i + dt X'_i ;  A_i = dt Vh_i (fluid), A_i = 0 (fixed)
+ *   sbar_i = -m sum_j F_ij r_ij . (A_i - A_j)
+ *   kbar_i =  m nu sum_j F_ij (v_i - v_j) . (A_i - A_j)
+ *   rhobar_i = sbar_i (p'(rho_i)/rho_i^2 - 2 p_i/rho_i^3) - kbar_i / rho_i^2,
+ *              p'(rho) = gamma (p + B) / rho
+ *   X_i = X'_i + m sum_j F_ij r_ij (rhobar_i + rhobar_j)
+ *              - m sum_j (s_i + s_j) H_ij (A_i - A_j)
+ *              + m nu sum_j (k_i + k_j) (F'_ij / r_ij) r_ij [(v_i - v_j) . (A_i - A_j)]
+ *         with H_ij = F_ij I + (F'_ij / r_ij) r_ij r_ij^T
+ *   V_i = Vh_i + m nu sum_j (k_i + k_j) F_ij (A_i - A_j)
+ *   dL/dnu += sum_i A_i . m sum_j (k_i + k_j) F_ij (v_i - v_j)
+ *   dL/dc0 += sum_i sbar_i (2 p_i / c0) / rho_i^2      (dp/dc0 = 2p/c0)
+ * Fixed particles get X = V = 0 (their state does not depend on the
+ * parameters).  The neighbour set is held fixed within the step; coincident
+ * pairs (r = 0) contribute no F' term.
+ */
+
+typedef struct {
+    const or_domain* D;
+    const or_params* P;
+    const or_grid64* G;
+    const double* x;
+    const double* v;
+    const double* rho;
+    const double* p;
+    const double* A;      /* (n,3) */
+    const double* rhobar; /* pass B input */
+    const uint8_t* fixed;
+    double* sbar;
+    double* kbar;
+    double* vvisc;        /* (n,3) */
+    double* nubar;        /* per particle */
+    double* X;            /* (n,3) pass B output (accumulated) */
+    double acc_s, acc_k, acc_nu;
+    double acc_v[3], acc_x[3];
+} or_vjp_ctx;
+
+static void or_vjp_a_visit(void* c, int64_t i, int64_t j, const double r[3], double rn)
+{
+    or_vjp_ctx* ctx = (or_vjp_ctx*)c;
+    const or_params* P = ctx->P;
+    double F = or_F(ctx->D->dim, P->h, rn);
+    double ki = 1.0 / ctx->rho[i], kj = 1.0 / ctx->rho[j];
+    double dA[3], dv[3];
+    double rdA = 0.0, vdA = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        dA[k] = ctx->A[3 * i + k] - ctx->A[3 * j + k];
+        dv[k] = ctx->v[3 * i + k] - ctx->v[3 * j + k];
+        rdA += r[k] * dA[k];
+        vdA += dv[k] * dA[k];
+    }
+    ctx->acc_s += -P->mass * F * rdA;
+    ctx->acc_k += P->mass * P->nu * F * vdA;
+    double w = P->mass * (ki + kj) * F;
+    for (int k = 0; k < 3; ++k) ctx->acc_v[k] += P->nu * w * dA[k];
+    double Ai_dv = 0.0;
+    for (int k = 0; k < 3; ++k) Ai_dv += ctx->A[3 * i + k] * dv[k];
+    ctx->acc_nu += w * Ai_dv;
+}
+
+static void or_vjp_a_range(void* c, int64_t begin, int64_t end)
+{
+    or_vjp_ctx local = *(or_vjp_ctx*)c;
+    for (int64_t i = begin; i < end; ++i) {
+        local.acc_s = local.acc_k = local.acc_nu = 0.0;
+        for (int k = 0; k < 3; ++k) local.acc_v[k] = 0.0;
+        or_for_neighbours(local.G, local.x, i, or_vjp_a_visit, &local);
+        local.sbar[i] = local.acc_s;
+        local.kbar[i] = local.acc_k;
+        local.nubar[i] = local.acc_nu;
+        for (int k = 0; k < 3; ++k) local.vvisc[3 * i + k] = local.acc_v[k];
+    }
+}
+
+static void or_vjp_b_visit(void* c, int64_t i, int64_t j, const double r[3], double rn)
+{
+    or_vjp_ctx* ctx = (or_vjp_ctx*)c;
+    const or_params* P = ctx->P;
+    int dim = ctx->D->dim;
+    double F = or_F(dim, P->h, rn);
+    double Fp_over_r = rn > 0.0 ? or_dF(dim, P->h, rn) / rn : 0.0;
+    double si = ctx->p[i] / (ctx->rho[i] * ctx->rho[i]);
+    double sj = ctx->p[j] / (ctx->rho[j] * ctx->rho[j]);
+    double ki = 1.0 / ctx->rho[i], kj = 1.0 / ctx->rho[j];
+    double dA[3], dv[3];
+    double rdA = 0.0, vdA = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        dA[k] = ctx->A[3 * i + k] - ctx->A[3 * j + k];
+        dv[k] = ctx->v[3 * i + k] - ctx->v[3 * j + k];
+        rdA += r[k] * dA[k];
+        vdA += dv[k] * dA[k];
+    }
+    double rb = ctx->rhobar[i] + ctx->rhobar[j];
+    for (int k = 0; k < 3; ++k) {
+        /* density geometry */
+        ctx->acc_x[k] += P->mass * F * r[k] * rb;
+        /* pressure Hessian: H (A_i - A_j) = F dA + (F'/r) r (r . dA) */
+        ctx->acc_x[k] -= P->mass * (si + sj) * (F * dA[k] + Fp_over_r * r[k] * rdA);
+        /* viscous geometry */
+        ctx->acc_x[k] += P->mass * P->nu * (ki + kj) * Fp_over_r * r[k] * vdA;
+    }
+}
+
+static void or_vjp_b_range(void* c, int64_t begin, int64_t end)
+{
+    or_vjp_ctx local = *(or_vjp_ctx*)c;
+    for (int64_t i = begin; i < end; ++i) {
+        for (int k = 0; k < 3; ++k) local.acc_x[k] = 0.0;
+        or_for_neighbours(local.G, local.x, i, or_vjp_b_visit, &local);
+        for (int k = 0; k < 3; ++k) local.X[3 * i + k] += local.acc_x[k];
+    }
+}
+
+/* x, v, lam_x_next, lam_v_next, lam_x, lam_v are (n,3) row-major.  dnu and
+ * dc0 receive this step's contributions (overwritten, not accumulated). */
+int or_step_vjp(const or_domain* D, const or_params* P, int64_t n, const double* x,
+                const double* v, const uint8_t* fixed, const double* lam_x_next,
+                const double* lam_v_next, double* lam_x, double* lam_v, double* dnu,
+                double* dc0, int nthreads)
+{
+    size_t N = (size_t)(n > 0 ? n : 1);
+    double* rho = (double*)malloc(sizeof(double) * N);
+    double* p = (double*)malloc(sizeof(double) * N);
+    double* A = (double*)malloc(sizeof(double) * 3 * N);
+    double* sbar = (double*)malloc(sizeof(double) * N);
+    double* kbar = (double*)malloc(sizeof(double) * N);
+    double* rhobar = (double*)malloc(sizeof(double) * N);
+    double* vvisc = (double*)malloc(sizeof(double) * 3 * N);
+    double* nubar = (double*)malloc(sizeof(double) * N);
+    if (!rho || !p || !A || !sbar || !kbar || !rhobar || !vvisc || !nubar) return -1;
+    int rc = or_density(D, P, n, x, 0, NULL, rho, p, NULL, nthreads);
+    or_grid64 G;
+    if (rc == 0) rc = or_grid64_build(&G, D, P->h, n, x);
+    if (rc != 0) return rc;
+
+    double dt = P->dt;
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            double vh = lam_v_next[3 * i + k] + dt * lam_x_next[3 * i + k];
+            int fluid = !(fixed && fixed[i]) && k < D->dim;
+            A[3 * i + k] = fluid ? dt * vh : 0.0;
+            lam_v[3 * i + k] = fluid ? vh : 0.0;
+            lam_x[3 * i + k] = fluid ? lam_x_next[3 * i + k] : 0.0;
+        }
+
+    or_vjp_ctx ctx;
+    memset(&ctx, 0, sizeof(ctx));
+    ctx.D = D; ctx.P = P; ctx.G = &G; ctx.x = x; ctx.v = v; ctx.rho = rho; ctx.p = p;
+    ctx.A = A; ctx.rhobar = rhobar; ctx.fixed = fixed; ctx.sbar = sbar; ctx.kbar = kbar;
+    ctx.vvisc = vvisc; ctx.nubar = nubar; ctx.X = lam_x;
+    or_parallel(n, nthreads, or_vjp_a_range, &ctx);
+
+    double B = P->c0 * P->c0 * P->rho0 / P->gamma;
+    double sum_nu = 0.0, sum_c0 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double r = rho[i];
+        double dp = P->gamma * (p[i] + B) / r;
+        rhobar[i] = sbar[i] * (dp / (r * r) - 2.0 * p[i] / (r * r * r)) - kbar[i] / (r * r);
+        sum_c0 += sbar[i] * (2.0 * p[i] / P->c0) / (r * r);
+        sum_nu += nubar[i];
+    }
+    or_parallel(n, nthreads, or_vjp_b_range, &ctx);
+    for (int64_t i = 0; i < n; ++i) {
+        int fluid = !(fixed && fixed[i]);
+        for (int k = 0; k < 3; ++k) {
+            if (!fluid || k >= D->dim) {
+                lam_x[3 * i + k] = 0.0;
+                lam_v[3 * i + k] = 0.0;
+            } else {
+                lam_v[3 * i + k] += vvisc[3 * i + k];
+            }
+        }
+    }
+    *dnu = sum_nu;
+    *dc0 = sum_c0;
+    or_grid64_free(&G);
+    free(rho); free(p); free(A); free(sbar); free(kbar); free(rhobar); free(vvisc); free(nubar);
+    return 0;
+}

@@ -1,0 +1,432 @@
+"""FP64 CPU oracle for the WCSPH hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s cpu_baseline
+leg may import this module.  It loads ``oracle/liboracle.so`` (built from
+``nauticle_oracle.c`` by ``oracle/build.py``) and shares no code with the HIP
+library.
+
+Every function follows the paper (arXiv:1710.08259):
+
+* kernel, normalisation and derivative: Example 1a, Wendland kernel equation;
+* density: SPH sampling expression with A = rho (Sec. 5.1);
+* pressure gradient: eq. diffop1; viscosity: eq. diffop3 in Morris form;
+* time step: semi-implicit Euler of Example 1a (velocity, then position);
+* neighbour search: cell grid of Sec. 3.2.1 ("The computational domain");
+* periodic shifting of leaving particles: Sec. 3.2.1.
+
+The one-step adjoint (:func:`step_vjp`) is not in the paper; it is the exact
+reverse-mode derivative of :func:`step` with one step, pinned against central
+finite differences of :func:`step` in the tests.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+EMPTY = 0xFFFFFFFF
+
+
+class _Domain(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("periodic", ctypes.c_int32 * 3),
+        ("origin", ctypes.c_double * 3),
+        ("cs", ctypes.c_double * 3),
+    ]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("h", ctypes.c_double),
+        ("mass", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("c0", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("nu", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("g", ctypes.c_double * 3),
+    ]
+
+
+@dataclass
+class Domain:
+    """Axis-aligned box of ``n[k]`` cells of edge ``cs[k]`` per axis."""
+
+    dim: int
+    n: tuple
+    cs: tuple
+    origin: tuple = (0.0, 0.0, 0.0)
+    periodic: tuple = (True, True, True)
+
+    def length(self) -> np.ndarray:
+        return np.array([self.n[k] * self.cs[k] for k in range(3)], dtype=np.float64)
+
+    def n_cells(self) -> int:
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+    def _c(self) -> _Domain:
+        d = _Domain()
+        d.dim = self.dim
+        for k in range(3):
+            d.n[k] = int(self.n[k])
+            d.periodic[k] = 1 if self.periodic[k] else 0
+            d.origin[k] = float(self.origin[k])
+            d.cs[k] = float(self.cs[k])
+        return d
+
+
+@dataclass
+class Params:
+    h: float
+    mass: float
+    rho0: float = 1000.0
+    c0: float = 10.0
+    gamma: float = 7.0
+    nu: float = 1e-3
+    dt: float = 1e-4
+    g: tuple = (0.0, 0.0, 0.0)
+
+    def _c(self) -> _Params:
+        p = _Params()
+        p.h, p.mass, p.rho0, p.c0 = self.h, self.mass, self.rho0, self.c0
+        p.gamma, p.nu, p.dt = self.gamma, self.nu, self.dt
+        for k in range(3):
+            p.g[k] = float(self.g[k])
+        return p
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from oracle import build as _build  # noqa: WPS433 (build on first use)
+
+        _build.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.or_alpha.restype = dbl
+    lib.or_alpha.argtypes = [i32, dbl]
+    for name in ("or_W", "or_F", "or_dF"):
+        getattr(lib, name).restype = dbl
+        getattr(lib, name).argtypes = [i32, dbl, dbl]
+    lib.or_tait.restype = dbl
+    lib.or_tait.argtypes = [P(_Params), dbl]
+    lib.or_validate_domain.restype = ctypes.c_int
+    lib.or_validate_domain.argtypes = [P(_Domain), dbl]
+    lib.or_bin_f32.restype = None
+    lib.or_bin_f32.argtypes = [P(_Domain), i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.or_sort_keys.restype = ctypes.c_int
+    lib.or_sort_keys.argtypes = [i64, vp, ctypes.c_uint32, vp, vp, vp, vp]
+    lib.or_neighbours_f32.restype = ctypes.c_int
+    lib.or_neighbours_f32.argtypes = [P(_Domain), dbl, i64, vp, vp, vp, vp, vp, vp, i32]
+    lib.or_neighbours_f32_brute.restype = None
+    lib.or_neighbours_f32_brute.argtypes = [P(_Domain), dbl, i64, vp, vp, vp, vp, vp]
+    lib.or_density.restype = ctypes.c_int
+    lib.or_density.argtypes = [P(_Domain), P(_Params), i64, vp, i64, vp, vp, vp, vp, ctypes.c_int]
+    lib.or_forces.restype = ctypes.c_int
+    lib.or_forces.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, i64, vp, vp, ctypes.c_int]
+    lib.or_step.restype = ctypes.c_int
+    lib.or_step.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, i32, vp, vp, vp, ctypes.c_int]
+    lib.or_step_vjp.restype = ctypes.c_int
+    lib.or_step_vjp.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, vp,
+                                P(dbl), P(dbl), ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_threads() -> int:
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+# --------------------------------------------------------------------------
+# kernel and equation of state
+# --------------------------------------------------------------------------
+
+def alpha(dim: int, h: float) -> float:
+    return _load().or_alpha(dim, h)
+
+
+def W(dim: int, h: float, r: float) -> float:
+    return _load().or_W(dim, h, r)
+
+
+def F(dim: int, h: float, r: float) -> float:
+    """(1/r) dW/dr, so that grad_i W_ij = F(r_ij) r_ij."""
+    return _load().or_F(dim, h, r)
+
+
+def dF(dim: int, h: float, r: float) -> float:
+    return _load().or_dF(dim, h, r)
+
+
+def tait(prm: Params, rho: float) -> float:
+    return _load().or_tait(ctypes.byref(prm._c()), rho)
+
+
+def validate_domain(dom: Domain, h: float) -> int:
+    return _load().or_validate_domain(ctypes.byref(dom._c()), h)
+
+
+# --------------------------------------------------------------------------
+# FP32 binning, sort and neighbour counts (the bit-exact part)
+# --------------------------------------------------------------------------
+
+def bin_f32(dom: Domain, pos32: np.ndarray):
+    """Absolute FP32 positions (n, dim) -> (cell u32[n], offsets f32[n, dim])."""
+    pos32 = np.ascontiguousarray(pos32, dtype=np.float32)
+    n = pos32.shape[0]
+    cols = [np.ascontiguousarray(pos32[:, k]) for k in range(dom.dim)]
+    offs = [np.zeros(n, np.float32) for _ in range(dom.dim)]
+    cell = np.zeros(n, np.uint32)
+    args = [_ptr(cols[k]) if k < dom.dim else None for k in range(3)]
+    outs = [_ptr(offs[k]) if k < dom.dim else None for k in range(3)]
+    _load().or_bin_f32(ctypes.byref(dom._c()), n, *args, _ptr(cell), *outs)
+    return cell, np.stack(offs, axis=1)
+
+
+def sort_keys(keys: np.ndarray, n_keys: int):
+    """Stable counting sort: returns (key_sorted, perm, start, end)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint32)
+    n = keys.shape[0]
+    ks = np.zeros(n, np.uint32)
+    perm = np.zeros(n, np.uint32)
+    start = np.zeros(n_keys, np.uint32)
+    end = np.zeros(n_keys, np.uint32)
+    rc = _load().or_sort_keys(n, _ptr(keys), n_keys, _ptr(ks), _ptr(perm), _ptr(start), _ptr(end))
+    if rc != 0:
+        raise MemoryError("or_sort_keys failed")
+    return ks, perm, start, end
+
+
+def neighbours_f32(dom: Domain, h: float, cell: np.ndarray, off: np.ndarray,
+                   max_nbr: int = 0, brute: bool = False):
+    """FP32-predicate neighbour counts (and lists if max_nbr > 0)."""
+    cell = np.ascontiguousarray(cell, dtype=np.uint32)
+    n = cell.shape[0]
+    cols = [np.ascontiguousarray(off[:, k], dtype=np.float32) for k in range(dom.dim)]
+    args = [_ptr(cols[k]) if k < dom.dim else None for k in range(3)]
+    count = np.zeros(n, np.int32)
+    if brute:
+        _load().or_neighbours_f32_brute(ctypes.byref(dom._c()), h, n, _ptr(cell), *args, _ptr(count))
+        return count
+    lst = np.zeros((n, max_nbr), np.uint32) if max_nbr > 0 else None
+    rc = _load().or_neighbours_f32(ctypes.byref(dom._c()), h, n, _ptr(cell), *args, _ptr(count),
+                                   _ptr(lst), max_nbr)
+    if rc != 0:
+        raise MemoryError("or_neighbours_f32 failed")
+    return (count, lst) if max_nbr > 0 else count
+
+
+# --------------------------------------------------------------------------
+# FP64 physics
+# --------------------------------------------------------------------------
+
+def _x3(x: np.ndarray) -> np.ndarray:
+    """(n, dim) -> contiguous (n, 3) FP64 with zero padding."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros((x.shape[0], 3), np.float64)
+    out[:, : x.shape[1]] = x
+    return out
+
+
+def density(dom: Domain, prm: Params, x, which=None, nthreads=None, counts=False):
+    """rho, p for all particles (or for the subset ``which``)."""
+    x3 = _x3(x)
+    n = x3.shape[0]
+    w = None if which is None else np.ascontiguousarray(which, dtype=np.int64)
+    m = n if w is None else w.shape[0]
+    rho = np.zeros(m)
+    p = np.zeros(m)
+    cnt = np.zeros(m, np.int32)
+    rc = _load().or_density(ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3),
+                            m, _ptr(w), _ptr(rho), _ptr(p), _ptr(cnt),
+                            nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_density failed")
+    return (rho, p, cnt) if counts else (rho, p)
+
+
+def forces(dom: Domain, prm: Params, x, v, rho, p, fixed=None, which=None, nthreads=None):
+    """Accelerations (n, dim); rho and p are given for all particles."""
+    x3, v3 = _x3(x), _x3(v)
+    n = x3.shape[0]
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+    w = None if which is None else np.ascontiguousarray(which, dtype=np.int64)
+    m = n if w is None else w.shape[0]
+    a = np.zeros((m, 3))
+    rc = _load().or_forces(ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3), _ptr(v3),
+                           _ptr(rho), _ptr(p), _ptr(fx), m, _ptr(w), _ptr(a),
+                           nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_forces failed")
+    return a[:, : dom.dim]
+
+
+def forces_at(dom: Domain, prm: Params, x, v, which, fixed=None, nthreads=None):
+    """Accelerations of the particles ``which`` only, with the densities
+    they need (theirs and their neighbours') computed by the oracle."""
+    x3 = _x3(x)
+    which = np.asarray(which, dtype=np.int64)
+    # densities are needed at the sample and at every neighbour of it
+    need = _neighbourhood(dom, prm, x3, which)
+    rho_s, p_s = density(dom, prm, x3, which=need, nthreads=nthreads)
+    rho = np.full(x3.shape[0], np.nan)
+    p = np.full(x3.shape[0], np.nan)
+    rho[need] = rho_s
+    p[need] = p_s
+    return forces(dom, prm, x3, v, rho, p, fixed=fixed, which=which, nthreads=nthreads)
+
+
+def _neighbourhood(dom: Domain, prm: Params, x3, which):
+    """which plus every particle within 2h of one of them (min image)."""
+    L = dom.length()
+    sel = set(int(i) for i in which)
+    xs = x3[which]
+    # cell grid lookup in numpy: bucket all particles by cell once
+    cells = np.zeros((x3.shape[0], 3), np.int64)
+    for k in range(dom.dim):
+        cells[:, k] = np.clip(np.floor((x3[:, k] - dom.origin[k]) / dom.cs[k]), 0, dom.n[k] - 1)
+    lin = cells[:, 0] + dom.n[0] * (cells[:, 1] + dom.n[1] * cells[:, 2])
+    order = np.argsort(lin, kind="stable")
+    lin_sorted = lin[order]
+    r2max = 4.0 * prm.h * prm.h
+    import itertools
+
+    for s, i in enumerate(which):
+        ci = cells[i]
+        for d in itertools.product(*[(-1, 0, 1) if k < dom.dim else (0,) for k in range(3)]):
+            c = ci + np.array(d)
+            ok = True
+            for k in range(dom.dim):
+                if dom.periodic[k]:
+                    c[k] %= dom.n[k]
+                elif c[k] < 0 or c[k] >= dom.n[k]:
+                    ok = False
+            if not ok:
+                continue
+            key = c[0] + dom.n[0] * (c[1] + dom.n[1] * c[2])
+            lo = np.searchsorted(lin_sorted, key, "left")
+            hi = np.searchsorted(lin_sorted, key, "right")
+            js = order[lo:hi]
+            r = x3[js] - xs[s]
+            for k in range(dom.dim):
+                if dom.periodic[k]:
+                    r[:, k] -= L[k] * np.rint(r[:, k] / L[k])
+            hit = js[(r * r).sum(axis=1) < r2max]
+            sel.update(int(j) for j in hit)
+    return np.array(sorted(sel), dtype=np.int64)
+
+
+def step(dom: Domain, prm: Params, x, v, fixed=None, n_steps=1, nthreads=None):
+    """Advance (x, v) by n_steps; returns (x, v, rho, p, a) of the last step."""
+    x3, v3 = _x3(x), _x3(v)
+    n = x3.shape[0]
+    fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+    rho = np.zeros(n)
+    p = np.zeros(n)
+    a = np.zeros((n, 3))
+    rc = _load().or_step(ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3), _ptr(v3),
+                         _ptr(fx), int(n_steps), _ptr(rho), _ptr(p), _ptr(a),
+                         nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_step failed")
+    d = dom.dim
+    return x3[:, :d], v3[:, :d], rho, p, a[:, :d]
+
+
+def step_vjp(dom: Domain, prm: Params, x, v, lam_x_next, lam_v_next, fixed=None, nthreads=None):
+    """Reverse mode of one :func:`step`: returns (lam_x, lam_v, dL/dnu, dL/dc0)."""
+    x3, v3 = _x3(x), _x3(v)
+    lx, lv = _x3(lam_x_next), _x3(lam_v_next)
+    n = x3.shape[0]
+    fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+    ox = np.zeros((n, 3))
+    ov = np.zeros((n, 3))
+    dnu = ctypes.c_double(0.0)
+    dc0 = ctypes.c_double(0.0)
+    rc = _load().or_step_vjp(ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3), _ptr(v3),
+                             _ptr(fx), _ptr(lx), _ptr(lv), _ptr(ox), _ptr(ov),
+                             ctypes.byref(dnu), ctypes.byref(dc0), nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_step_vjp failed")
+    d = dom.dim
+    return ox[:, :d], ov[:, :d], dnu.value, dc0.value
+
+
+# --------------------------------------------------------------------------
+# rollout loss and its gradient (checkpointed reverse sweep)
+# --------------------------------------------------------------------------
+
+def min_image(dom: Domain, d):
+    """Displacements folded onto the nearest periodic image on periodic axes."""
+    d = np.array(d, dtype=np.float64, copy=True)
+    L = dom.length()
+    for k in range(dom.dim):
+        if dom.periodic[k]:
+            d[:, k] -= L[k] * np.rint(d[:, k] / L[k])
+    return d
+
+
+def rollout_loss(dom: Domain, prm: Params, x0, v0, target, n_steps, fixed=None, nthreads=None):
+    """L = (1/(N d)) sum_i |x_i^T - target_i|^2 (minimum image), over fluid."""
+    x, _, _, _, _ = step(dom, prm, x0, v0, fixed=fixed, n_steps=n_steps, nthreads=nthreads)
+    d = min_image(dom, x - np.asarray(target)[:, : dom.dim])
+    mask = np.ones(d.shape[0], bool) if fixed is None else ~np.asarray(fixed, bool)
+    return float((d[mask] ** 2).sum() / (mask.sum() * dom.dim))
+
+
+def rollout_grad(dom: Domain, prm: Params, x0, v0, target, n_steps, checkpoint_every=20,
+                 fixed=None, nthreads=None):
+    """(L, dL/dv0, dL/dnu, dL/dc0) by a reverse sweep over one-step VJPs.
+
+    Forward: store (x, v) every ``checkpoint_every`` steps.  Backward: for
+    each segment, recompute its states from the checkpoint, then apply the
+    one-step VJPs in reverse order."""
+    d = dom.dim
+    x = np.asarray(x0, np.float64)[:, :d].copy()
+    v = np.asarray(v0, np.float64)[:, :d].copy()
+    ckpt = []
+    for s in range(n_steps):
+        if s % checkpoint_every == 0:
+            ckpt.append((s, x.copy(), v.copy()))
+        x, v, _, _, _ = step(dom, prm, x, v, fixed=fixed, n_steps=1, nthreads=nthreads)
+    delta = min_image(dom, x - np.asarray(target)[:, :d])
+    mask = np.ones(delta.shape[0], bool) if fixed is None else ~np.asarray(fixed, bool)
+    nf = int(mask.sum())
+    loss = float((delta[mask] ** 2).sum() / (nf * d))
+    lam_x = np.where(mask[:, None], 2.0 * delta / (nf * d), 0.0)
+    lam_v = np.zeros_like(lam_x)
+    dnu = 0.0
+    dc0 = 0.0
+    for (s0, xc, vc) in reversed(ckpt):
+        s1 = min(s0 + checkpoint_every, n_steps)
+        states = [(xc.copy(), vc.copy())]
+        for _ in range(s0, s1 - 1):
+            xn, vn, _, _, _ = step(dom, prm, states[-1][0], states[-1][1], fixed=fixed,
+                                   n_steps=1, nthreads=nthreads)
+            states.append((xn, vn))
+        for (xs, vs) in reversed(states):
+            lam_x, lam_v, a, b = step_vjp(dom, prm, xs, vs, lam_x, lam_v, fixed=fixed,
+                                          nthreads=nthreads)
+            dnu += a
+            dc0 += b
+    return loss, lam_v, dnu, dc0

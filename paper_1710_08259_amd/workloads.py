@@ -1,0 +1,196 @@
+"""Seeded synthetic inputs for the WCSPH hot path.
+
+This module only *generates* inputs: particle lattices with jitter, random
+velocities, wall layers and the case constants.  It contains none of the
+method's arithmetic (no kernel, no sums, no equation of state) and imports
+neither the HIP binding nor the oracle, so both sides of every parity test
+can take their inputs from here.
+
+Conventions
+-----------
+* Everything is generated in FP64 with ``numpy.random.default_rng(seed)``
+  and rounded once to FP32; the GPU receives the FP32 values and the oracle
+  the same values widened to FP64.
+* Lattice sites sit at ``(i + 1/2) dx``; jitter is uniform per component.
+* The cell edge of every axis is rounded to FP32 first and the box length is
+  then ``n_cells * cell_edge`` exactly, so a periodic box means the same
+  thing in FP32 and FP64.  The lattice spacing is derived from that length.
+* Cell edges are ``L / floor(L / 2h)`` (never below the support 2h).
+* Fixed (wall) particles come last within a case.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+PERIODIC = 0
+CUTOFF = 1
+
+
+def _f32(x: float) -> float:
+    return float(np.float32(x))
+
+
+@dataclass
+class Case:
+    """One independent WCSPH problem."""
+
+    dim: int
+    ncell: tuple          # cells per axis, (nx, ny, nz); unused axes 1
+    cell_size: tuple      # FP32-representable edge per axis
+    origin: tuple         # FP32-representable lower corner
+    boundary: tuple       # PERIODIC / CUTOFF per axis
+    h: float
+    mass: float
+    rho0: float
+    c0: float
+    gamma: float
+    nu: float
+    dt: float
+    g: tuple
+    pos: np.ndarray       # (n, dim) float32 absolute positions
+    vel: np.ndarray       # (n, dim) float32
+    n_fixed: int = 0
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.ncell[0]) * int(self.ncell[1]) * int(self.ncell[2])
+
+    def length(self) -> np.ndarray:
+        return np.array([self.ncell[k] * self.cell_size[k] for k in range(3)])
+
+    def fixed_mask(self) -> np.ndarray:
+        m = np.zeros(self.n, bool)
+        if self.n_fixed:
+            m[self.n - self.n_fixed:] = True
+        return m
+
+
+def _cells_for(length: float, h: float) -> tuple[int, float]:
+    n = int(math.floor(length / (2.0 * h)))
+    n = max(n, 1)
+    cs = _f32(length / n)
+    if cs < 2.0 * h:  # FP32 rounding went below the support: one cell fewer
+        n -= 1
+        cs = _f32(length / n)
+    return n, cs
+
+
+def lattice_case(dim, n_side, dx, h_over_dx, jitter, v_sigma, seed, *, c0=10.0, nu=1e-3,
+                 dt=1e-4, rho0=1000.0, gamma=7.0, g=(0.0, 0.0, 0.0), name="") -> Case:
+    """Periodic box filled with a jittered square/cubic lattice.
+
+    ``n_side`` lattice sites per axis at nominal spacing ``dx``; ``jitter``
+    is the half-width of the uniform per-component perturbation in units of
+    dx; velocities are N(0, v_sigma) per component."""
+    rng = np.random.default_rng(seed)
+    n_side = tuple(int(s) for s in n_side) + (1,) * (3 - dim)
+    h = h_over_dx * dx
+    ncell, cs, spacing = [1, 1, 1], [1.0, 1.0, 1.0], [dx, dx, dx]
+    for k in range(dim):
+        n, c = _cells_for(n_side[k] * dx, h)
+        ncell[k], cs[k] = n, c
+        spacing[k] = n * c / n_side[k]
+    grids = np.meshgrid(*[(np.arange(n_side[k]) + 0.5) * spacing[k] for k in range(dim)],
+                        indexing="ij")
+    pos = np.stack([g_.ravel(order="F") for g_ in grids], axis=1)  # x fastest
+    pos += (rng.uniform(-1.0, 1.0, pos.shape) * jitter) * np.array(spacing[:dim])
+    for k in range(dim):
+        L = ncell[k] * cs[k]
+        pos[:, k] = np.mod(pos[:, k], L)
+    vel = rng.normal(0.0, v_sigma, pos.shape)
+    mass = rho0 * float(np.prod(spacing[:dim]))
+    return Case(dim=dim, ncell=tuple(ncell), cell_size=tuple(cs), origin=(0.0, 0.0, 0.0),
+                boundary=(PERIODIC,) * 3, h=h, mass=mass, rho0=rho0, c0=c0, gamma=gamma,
+                nu=nu, dt=dt, g=tuple(g), pos=pos.astype(np.float32),
+                vel=vel.astype(np.float32), n_fixed=0, name=name)
+
+
+def dam_break_case(dx=0.005, h_over_dx=1.2, c0=30.0, nu=1e-6, rho0=1000.0, gamma=7.0,
+                   fluid=(0.4, 0.4, 0.8), tank=(1.6, 0.4, 1.0), layers=3, g=-9.81,
+                   cfl=0.25, name="dam_break") -> Case:
+    """3-D dam-break shape: a fluid column against the x = 0 wall of an
+    open-top tank whose floor and four sides are ``layers`` layers of fixed
+    particles on the same lattice.  Cut-off box, gravity along -z,
+    dt = cfl * h / c0, fluid at rest."""
+    h = h_over_dx * dx
+    nf = [int(round(fluid[k] / dx)) for k in range(3)]
+    nt = [int(round(tank[k] / dx)) for k in range(3)]
+    fl = np.stack(np.meshgrid(*[np.arange(nf[k]) for k in range(3)], indexing="ij"), -1)
+    fl = fl.reshape(-1, 3, order="F")
+    ix = np.arange(-layers, nt[0] + layers)
+    iy = np.arange(-layers, nt[1] + layers)
+    iz = np.arange(-layers, nt[2])
+    W = np.stack(np.meshgrid(ix, iy, iz, indexing="ij"), -1).reshape(-1, 3, order="F")
+    inside = ((W[:, 0] >= 0) & (W[:, 0] < nt[0]) & (W[:, 1] >= 0) & (W[:, 1] < nt[1])
+              & (W[:, 2] >= 0))
+    W = W[~inside]
+    idx = np.concatenate([fl, W], axis=0).astype(np.float64)
+    pos = (idx + 0.5) * dx
+    # cut-off box: one extra lattice spacing around the walls, 10 % headroom
+    lo = np.array([-(layers + 1) * dx] * 3)
+    hi = np.array([tank[0] + (layers + 1) * dx, tank[1] + (layers + 1) * dx, tank[2] * 1.1])
+    origin = tuple(_f32(v) for v in lo)
+    ncell, cs = [1, 1, 1], [1.0, 1.0, 1.0]
+    for k in range(3):
+        ncell[k], cs[k] = _cells_for(hi[k] - origin[k], h)
+    vel = np.zeros_like(pos)
+    return Case(dim=3, ncell=tuple(ncell), cell_size=tuple(cs), origin=origin,
+                boundary=(CUTOFF,) * 3, h=h, mass=rho0 * dx ** 3, rho0=rho0, c0=c0,
+                gamma=gamma, nu=nu, dt=cfl * h / c0, g=(0.0, 0.0, g),
+                pos=pos.astype(np.float32), vel=vel.astype(np.float32),
+                n_fixed=int(W.shape[0]), name=name)
+
+
+# ---------------------------------------------------------------------------
+# the named workloads
+# ---------------------------------------------------------------------------
+
+def periodic_2d_4096() -> Case:
+    """2-D periodic, 64x64 lattice, dx 0.01 m, jitter U(+-0.01 dx), h 1.3 dx,
+    c0 10 m/s, nu 1e-3, v ~ N(0, 0.1), dt 1e-4 (100-step parity case)."""
+    return lattice_case(2, (64, 64), 0.01, 1.3, 0.01, 0.1, seed=1, c0=10.0, nu=1e-3,
+                        dt=1e-4, name="periodic_2d_4096")
+
+
+def dam_break_3d(dx=0.005) -> Case:
+    """3-D dam-break shape: 0.4 x 0.4 x 0.8 m column, dx 0.005 m (1,024,000
+    fluid + 571,308 wall particles), tank 1.6 x 0.4 x 1.0 m, c0 30 m/s."""
+    return dam_break_case(dx=dx, name=f"dam_break_3d_dx{dx:g}")
+
+
+def periodic_3d_8m() -> Case:
+    """3-D periodic 256 x 256 x 128 jittered lattice = 8,388,608 particles,
+    h 1.2 dx (56 lattice neighbours), jitter U(+-0.05 dx), v ~ N(0, 0.05)."""
+    return lattice_case(3, (256, 256, 128), 0.01, 1.2, 0.05, 0.05, seed=3, c0=10.0,
+                        nu=1e-3, dt=1e-4, name="periodic_3d_8388608")
+
+
+def periodic_3d_262k() -> Case:
+    """3-D periodic 64^3 = 262,144 (differentiation case)."""
+    return lattice_case(3, (64, 64, 64), 0.01, 1.2, 0.05, 0.05, seed=5, c0=10.0, nu=1e-3,
+                        dt=1e-4, name="periodic_3d_262144")
+
+
+def batched_2d(n_cases=256, seed=4, max_side_exp=8.0) -> list[Case]:
+    """Independent 2-D periodic cases: side round(2^U(5, max)), so particle
+    counts are log-uniform in [1024, 65536]; nu ~ U(1e-6, 1e-3),
+    c0 ~ U(5, 20) m/s; case b uses seed 1000 + b."""
+    rng = np.random.default_rng(seed)
+    sides = np.rint(2.0 ** rng.uniform(5.0, max_side_exp, n_cases)).astype(int)
+    nus = rng.uniform(1e-6, 1e-3, n_cases)
+    c0s = rng.uniform(5.0, 20.0, n_cases)
+    return [lattice_case(2, (s, s), 0.01, 1.3, 0.01, 0.1, seed=1000 + b, c0=float(c0s[b]),
+                         nu=float(nus[b]), dt=1e-4, name=f"batched_{b}")
+            for b, s in enumerate(sides)]
+
+
+def scaled(case: Case, **changes) -> Case:
+    return replace(case, **changes)

@@ -1,0 +1,479 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics
+(no GPU).  Each test names what it pins and why a plausible mistake in the
+oracle (a dropped term, a wrong sign, a wrong normalisation, a missed
+neighbour) would make it fail."""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import oracle as O
+from paper_1710_08259_amd import workloads as WL
+from tests.oracle_helpers import domain_of, params_of, v64, x64
+
+
+# ---------------------------------------------------------------------------
+# kernel: normalisation (Wendland alpha_D), derivative, Hessian factor
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("h", [0.013, 1.0, 2.5])
+def test_kernel_normalisation_integral_is_one(dim, h):
+    """int W dV = 1 with the paper's alpha_1, alpha_2, alpha_3 (quadrature)."""
+    surf = {1: lambda r: 2.0, 2: lambda r: 2.0 * math.pi * r, 3: lambda r: 4.0 * math.pi * r * r}[dim]
+    val, _ = integrate.quad(lambda r: surf(r) * O.W(dim, h, r), 0.0, 2.0 * h, epsabs=0, epsrel=1e-13)
+    assert val == pytest.approx(1.0, rel=1e-10)
+    assert O.W(dim, h, 2.0 * h) == 0.0 and O.W(dim, h, 2.0 * h * 1.0001) == 0.0
+    assert O.W(dim, h, 0.0) == pytest.approx(O.alpha(dim, h), rel=1e-15)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_kernel_derivative_matches_finite_difference(dim):
+    """F(r) r = dW/dr and dF/dr by central differences; F(0) h^2/alpha = -5."""
+    h = 0.7
+    for r in np.linspace(0.05 * h, 1.95 * h, 37):
+        e = 1e-6 * h
+        dW = (O.W(dim, h, r + e) - O.W(dim, h, r - e)) / (2 * e)
+        assert O.F(dim, h, r) * r == pytest.approx(dW, rel=1e-7, abs=1e-12 * O.alpha(dim, h) / h)
+        dFn = (O.F(dim, h, r + e) - O.F(dim, h, r - e)) / (2 * e)
+        assert O.dF(dim, h, r) == pytest.approx(dFn, rel=1e-7, abs=1e-12 * O.alpha(dim, h) / h ** 3)
+    assert O.F(dim, h, 0.0) * h * h / O.alpha(dim, h) == pytest.approx(-5.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_kernel_gradient_second_moment_is_minus_identity(dim):
+    """(1/d) int F(r) r^2 dV = -1 (integration by parts of int W dV = 1):
+    this fixes F's normalisation relative to W independently of the FD test."""
+    h = 1.3
+    surf = {1: lambda r: 2.0, 2: lambda r: 2.0 * math.pi * r, 3: lambda r: 4.0 * math.pi * r * r}[dim]
+    val, _ = integrate.quad(lambda r: surf(r) * O.F(dim, h, r) * r * r, 0.0, 2 * h, epsrel=1e-13)
+    assert val / dim == pytest.approx(-1.0, rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Tait equation of state
+# ---------------------------------------------------------------------------
+
+def test_tait_reduces_to_the_papers_linear_eos():
+    """p(rho0) = 0 and dp/drho at rho0 = c0^2: the linearisation is the
+    paper's p = c^2 (rho - rho0) (Example 1a)."""
+    prm = O.Params(h=0.01, mass=0.1, rho0=1000.0, c0=10.0, gamma=7.0)
+    assert O.tait(prm, 1000.0) == 0.0
+    e = 1e-4
+    slope = (O.tait(prm, 1000.0 + e) - O.tait(prm, 1000.0 - e)) / (2 * e)
+    assert slope == pytest.approx(prm.c0 ** 2, rel=1e-8)
+    for d in (1e-4, 1e-3):
+        lin = prm.c0 ** 2 * (1000.0 * d)
+        assert O.tait(prm, 1000.0 * (1 + d)) == pytest.approx(lin, rel=4 * d * prm.gamma)
+    # gamma = 1 makes Tait exactly linear
+    prm1 = O.Params(h=0.01, mass=0.1, rho0=1000.0, c0=10.0, gamma=1.0)
+    assert O.tait(prm1, 1234.5) == pytest.approx(100.0 * 234.5, rel=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# binning and sorting (the bit-exact part)
+# ---------------------------------------------------------------------------
+
+def _exact_bin(case, pos32):
+    """Exact-rational binning of FP32 positions: c = floor(t / cs),
+    off = t - c cs rounded once to FP32 (t = fl32(x - o))."""
+    cells = []
+    offs = []
+    for i in range(pos32.shape[0]):
+        c_lin, mult = 0, 1
+        o_row = []
+        for k in range(case.dim):
+            t = np.float32(pos32[i, k]) - np.float32(case.origin[k])
+            cs = Fraction(float(np.float32(case.cell_size[k])))
+            T = Fraction(float(t))
+            c = math.floor(T / cs)
+            off = np.float32(float(T - c * cs))
+            if off >= np.float32(case.cell_size[k]):
+                off = np.nextafter(np.float32(case.cell_size[k]), np.float32(0))
+            c %= case.ncell[k]
+            c_lin += c * mult
+            mult *= case.ncell[k]
+            o_row.append(off)
+        cells.append(c_lin)
+        offs.append(o_row)
+    return np.array(cells, np.uint32), np.array(offs, np.float32)
+
+
+@pytest.mark.parametrize("maker", ["p2", "p3", "dam"])
+def test_bin_matches_exact_rational_floor(maker):
+    case = {"p2": lambda: WL.lattice_case(2, (20, 17), 0.01, 1.3, 0.4, 0.1, seed=11),
+            "p3": lambda: WL.lattice_case(3, (9, 11, 8), 0.01, 1.2, 0.45, 0.05, seed=12),
+            "dam": lambda: WL.dam_break_case(dx=0.05)}[maker]()
+    pos = case.pos.copy()
+    # add points on cell faces, at the box faces and just outside the box
+    L = case.length()
+    extra = []
+    for k in range(case.dim):
+        for v in (case.origin[k], case.origin[k] + L[k], case.origin[k] + case.cell_size[k] * 2,
+                  case.origin[k] - 1e-7, case.origin[k] + L[k] + 3 * case.cell_size[k]):
+            row = np.array(pos[0], np.float64)
+            row[k] = v
+            extra.append(row)
+    pos = np.concatenate([pos, np.array(extra, np.float32)]).astype(np.float32)
+    cell, off = O.bin_f32(domain_of(case), pos)
+    c_ref, o_ref = _exact_bin(case, pos)
+    np.testing.assert_array_equal(cell, c_ref)
+    np.testing.assert_array_equal(off.view(np.uint32), o_ref.view(np.uint32))
+    cs = np.array(case.cell_size[: case.dim], np.float32)
+    assert np.all(off >= 0) and np.all(off < cs)
+
+
+def test_sort_keys_is_numpy_stable_argsort():
+    rng = np.random.default_rng(7)
+    for n, nk in [(0, 5), (1, 1), (1000, 7), (5000, 3000), (20000, 50)]:
+        keys = rng.integers(0, nk, n).astype(np.uint32)
+        ks, perm, start, end = O.sort_keys(keys, nk)
+        ref = np.argsort(keys, kind="stable").astype(np.uint32)
+        np.testing.assert_array_equal(perm, ref)
+        np.testing.assert_array_equal(ks, keys[ref])
+        for c in range(nk):
+            hit = np.nonzero(ks == c)[0]
+            if hit.size:
+                assert start[c] == hit[0] and end[c] == hit[-1] + 1
+            else:
+                assert start[c] == O.EMPTY and end[c] == O.EMPTY
+
+
+# ---------------------------------------------------------------------------
+# neighbour search: cell grid == brute force
+# ---------------------------------------------------------------------------
+
+def _layouts():
+    out = []
+    for dim in (2, 3):
+        side = (40, 37) if dim == 2 else (12, 11, 10)
+        lat = WL.lattice_case(dim, side, 0.01, 1.3 if dim == 2 else 1.2, 0.3, 0.0, seed=20 + dim)
+        out.append((f"lattice{dim}", lat))
+        rnd = WL.scaled(lat, pos=(np.random.default_rng(30 + dim).uniform(0, 1, lat.pos.shape)
+                                  * lat.length()[:dim]).astype(np.float32))
+        out.append((f"random{dim}", rnd))
+        rng = np.random.default_rng(40 + dim)
+        centres = rng.uniform(0, 1, (5, dim)) * lat.length()[:dim]
+        blob = centres[rng.integers(0, 5, lat.n)] + rng.normal(0, 0.6 * lat.h, (lat.n, dim))
+        blob = np.mod(blob, lat.length()[:dim])
+        out.append((f"clustered{dim}", WL.scaled(lat, pos=blob.astype(np.float32))))
+        cut = WL.scaled(rnd, boundary=(WL.CUTOFF,) * 3)
+        out.append((f"cutoff{dim}", cut))
+    return out
+
+
+@pytest.mark.parametrize("name,case", _layouts(), ids=[n for n, _ in _layouts()])
+def test_fp32_neighbour_counts_cell_grid_equals_brute_force(name, case):
+    dom = domain_of(case)
+    cell, off = O.bin_f32(dom, case.pos)
+    cnt_grid = O.neighbours_f32(dom, case.h, cell, off)
+    cnt_brute = O.neighbours_f32(dom, case.h, cell, off, brute=True)
+    np.testing.assert_array_equal(cnt_grid, cnt_brute)
+    assert cnt_grid.sum() > 0
+
+
+@pytest.mark.parametrize("name,case", _layouts(), ids=[n for n, _ in _layouts()])
+def test_neighbour_sets_match_exact_distances(name, case):
+    """The FP32 predicate and the FP64 cell search both give exactly the
+    pairs with minimum-image distance < 2h, except pairs within 1e-5 (relative)
+    of the cut-off, which may go either way in FP32."""
+    dom = domain_of(case)
+    cell, off = O.bin_f32(dom, case.pos)
+    cnt32, lst = O.neighbours_f32(dom, case.h, cell, off, max_nbr=512)
+    x = x64(case)
+    L = case.length()[: case.dim]
+    d = x[:, None, :] - x[None, :, :]
+    for k in range(case.dim):
+        if case.boundary[k] == WL.PERIODIC:
+            d[..., k] -= L[k] * np.rint(d[..., k] / L[k])
+    r = np.sqrt((d ** 2).sum(-1))
+    np.fill_diagonal(r, np.inf)
+    R = 2 * case.h
+    inside = r < R
+    near = np.abs(r - R) < 1e-5 * R
+    for i in range(case.n):
+        got = np.zeros(case.n, bool)
+        got[lst[i, : cnt32[i]]] = True
+        bad = (got != inside[i]) & ~near[i]
+        assert not bad.any(), (i, np.nonzero(bad))
+    _, _, cnt64 = O.density(dom, params_of(case), x, counts=True)
+    np.testing.assert_array_equal(cnt64, inside.sum(1))
+
+
+# ---------------------------------------------------------------------------
+# density, pressure and accelerations on lattices
+# ---------------------------------------------------------------------------
+
+def _exact_lattice(case, side):
+    """FP64 lattice sites (i + 1/2) dx of a jitter-free lattice case, x fastest."""
+    dim = case.dim
+    sp = [case.length()[k] / side[k] for k in range(dim)]
+    grids = np.meshgrid(*[(np.arange(side[k]) + 0.5) * sp[k] for k in range(dim)], indexing="ij")
+    return np.stack([g.ravel(order="F") for g in grids], axis=1)
+
+
+def _lattice_moments(dim, h_over_dx):
+    """Sum over lattice vectors k (|k| dx < 2h) of W and of -F k_x^2 dx^2,
+    with the oracle's W and F (pinned above)."""
+    dx = 1.0
+    h = h_over_dx * dx
+    rng = range(-3 * int(h_over_dx) - 2, 3 * int(h_over_dx) + 3)
+    sw, sf = 0.0, 0.0
+    for k in itertools.product(rng, repeat=dim):
+        r = math.sqrt(sum(c * c for c in k)) * dx
+        if r == 0.0 or r >= 2 * h:
+            continue
+        sw += O.W(dim, h, r)
+        sf += -O.F(dim, h, r) * (k[0] * dx) ** 2
+    return (O.alpha(dim, h) + sw) * dx ** dim, sf * dx ** dim
+
+
+@pytest.mark.parametrize("dim,hr,side", [(2, 1.3, (24, 24)), (3, 1.2, (12, 12, 12)), (2, 2.0, (30, 30)),
+                                         (3, 1.05, (10, 10, 10))])
+def test_lattice_density_equals_lattice_sum_and_converges(dim, hr, side):
+    case = WL.lattice_case(dim, side, 0.01, hr, 0.0, 0.0, seed=0)
+    dom, prm = domain_of(case), params_of(case)
+    rho, p = O.density(dom, prm, _exact_lattice(case, side))
+    ratio = rho / prm.rho0
+    assert np.ptp(ratio) < 1e-12
+    dx = case.length()[0] / side[0]
+    ws, _ = _lattice_moments(dim, case.h / dx)
+    assert ratio.mean() == pytest.approx(ws, rel=1e-9)
+    assert abs(ratio.mean() - 1.0) < 0.03
+    # uniform background pressure from the Tait law
+    np.testing.assert_allclose(p, O.tait(prm, rho.mean()), rtol=1e-10)
+
+
+def test_lattice_density_converges_to_rho0():
+    errs = []
+    for hr in (1.3, 2.0, 3.0, 4.0):
+        ws, _ = _lattice_moments(2, hr)
+        errs.append(abs(ws - 1.0))
+    assert errs[-1] < 1e-3 and errs[-1] < errs[0]
+
+
+def test_survey_lattice_values():
+    """Regression values of the exact lattice sums (2-D h = 1.3 dx, 3-D
+    h = 1.2 dx and 1.05 dx) and of the gradient moments."""
+    assert _lattice_moments(2, 1.3)[0] == pytest.approx(1.01047315, abs=1e-8)
+    assert _lattice_moments(3, 1.2)[0] == pytest.approx(1.01745693, abs=1e-8)
+    assert _lattice_moments(3, 1.05)[0] == pytest.approx(1.02809732, abs=1e-8)
+    assert _lattice_moments(2, 1.3)[1] == pytest.approx(0.97392148, abs=1e-8)
+    assert _lattice_moments(3, 1.2)[1] == pytest.approx(0.98522927, abs=1e-8)
+
+
+def test_lattice_at_rest_is_an_equilibrium():
+    case = WL.lattice_case(2, (20, 20), 0.01, 1.3, 0.0, 0.0, seed=0)
+    dom, prm = domain_of(case), params_of(case)
+    x0 = _exact_lattice(case, (20, 20))
+    x, v, rho, p, a = O.step(dom, prm, x0, np.zeros_like(x0), n_steps=20)
+    scale = prm.c0 ** 2 / prm.h
+    assert np.abs(a).max() < 1e-11 * scale
+    assert np.abs(O.min_image(dom, x - x0)).max() < 1e-12
+
+
+def _interior_cutoff_lattice(dim, hr, side):
+    case = WL.lattice_case(dim, side, 0.01, hr, 0.0, 0.0, seed=0)
+    case = WL.scaled(case, boundary=(WL.CUTOFF,) * 3)
+    x = _exact_lattice(case, side)
+    L = case.length()[:dim]
+    margin = 2.01 * case.h
+    interior = np.all((x > margin) & (x < L - margin), axis=1)
+    return case, x, interior
+
+
+@pytest.mark.parametrize("dim,hr,side", [(2, 1.3, (24, 24)), (3, 1.2, (12, 12, 12))])
+def test_linear_pressure_field_gives_scaled_gradient(dim, hr, side):
+    """Imposed p = P0 + G.x and uniform rho: a_i = -kappa G/rho on interior
+    particles, kappa the lattice gradient moment (P7 of the pins)."""
+    case, x, interior = _interior_cutoff_lattice(dim, hr, side)
+    dom, prm = domain_of(case), params_of(case)
+    prm.g = (0.0, 0.0, 0.0)
+    G = np.array([3.0e4, -1.5e4, 0.7e4])[:dim]
+    rho = np.full(case.n, 1010.0)
+    p = 2000.0 + x @ G
+    a = O.forces(dom, prm, x, np.zeros_like(x), rho, p)
+    dx = case.length()[0] / side[0]
+    _, kappa = _lattice_moments(dim, case.h / dx)
+    # m/rho = dx^d rho0/rho
+    expect = -(prm.rho0 / rho[0]) * kappa * G / rho[0]
+    np.testing.assert_allclose(a[interior], np.broadcast_to(expect, a[interior].shape), rtol=1e-9,
+                               atol=1e-9 * np.abs(expect).max())
+
+
+@pytest.mark.parametrize("dim,hr,side", [(2, 1.3, (24, 24)), (3, 1.2, (12, 12, 12))])
+def test_viscous_laplacian_of_linear_and_quadratic_fields(dim, hr, side):
+    """With p = 0: linear v gives a = 0 on the interior; v_x = x^2 gives
+    a_x = 2 nu kappa (Laplacian of x^2 is 2, times the lattice moment)."""
+    case, x, interior = _interior_cutoff_lattice(dim, hr, side)
+    dom, prm = domain_of(case), params_of(case)
+    prm.g = (0.0, 0.0, 0.0)
+    prm.nu = 1e-3
+    rho = np.full(case.n, prm.rho0)
+    p = np.zeros(case.n)
+    v_lin = x @ np.array([[0.3, -0.2, 0.5][:dim]] * dim).T * 0 + x * 0.7 + 0.1
+    a = O.forces(dom, prm, x, v_lin, rho, p)
+    assert np.abs(a[interior]).max() < 1e-12
+    v_q = np.zeros_like(x)
+    v_q[:, 0] = x[:, 0] ** 2
+    a = O.forces(dom, prm, x, v_q, rho, p)
+    dx = case.length()[0] / side[0]
+    _, kappa = _lattice_moments(dim, case.h / dx)
+    np.testing.assert_allclose(a[interior, 0], 2.0 * prm.nu * kappa, rtol=1e-8)
+    assert np.abs(a[interior, 1:]).max() < 1e-12
+
+
+def test_momentum_is_conserved_by_pair_forces():
+    """Antisymmetric pair terms: sum_i m a_i = N m g to round-off."""
+    case = WL.lattice_case(3, (10, 9, 8), 0.01, 1.2, 0.2, 0.3, seed=9, g=(0.0, 0.0, -9.81))
+    dom, prm = domain_of(case), params_of(case)
+    x, v = x64(case), v64(case)
+    rho, p = O.density(dom, prm, x)
+    a = O.forces(dom, prm, x, v, rho, p)
+    total = case.mass * a.sum(0) - case.n * case.mass * np.array(case.g)
+    scale = case.mass * np.abs(a - np.array(case.g)).sum()
+    assert np.abs(total).max() < 1e-12 * scale
+
+
+def test_viscosity_dissipates_kinetic_energy():
+    case = WL.lattice_case(2, (16, 16), 0.01, 1.3, 0.2, 0.5, seed=13)
+    dom, prm = domain_of(case), params_of(case)
+    x, v = x64(case), v64(case)
+    rho = np.full(case.n, prm.rho0)
+    a = O.forces(dom, prm, x, v, rho, np.zeros(case.n))
+    assert (case.mass * (v * a).sum()) < 0.0
+
+
+def test_isolated_particle_follows_the_semi_implicit_euler_closed_form():
+    """One particle: rho = m alpha, a = g and, after n steps,
+    v_n = v_0 + n dt g, x_n = x_0 + n dt v_0 + dt^2 g n(n+1)/2 (Example 1a's
+    velocity-then-position Euler update)."""
+    dom = O.Domain(dim=3, n=(5, 5, 5), cs=(0.1, 0.1, 0.1), periodic=(True, True, True))
+    prm = O.Params(h=0.02, mass=0.3, rho0=1000.0, c0=10.0, nu=1e-3, dt=1e-3, g=(0.5, -1.0, -9.81))
+    x0 = np.array([[0.21, 0.22, 0.23]])
+    v0 = np.array([[0.3, 0.1, -0.2]])
+    rho, p = O.density(dom, prm, x0)
+    assert rho[0] == pytest.approx(prm.mass * O.alpha(3, prm.h), rel=1e-15)
+    n = 17
+    x, v, _, _, a = O.step(dom, prm, x0, v0, n_steps=n)
+    g = np.array(prm.g)
+    np.testing.assert_allclose(a[0], g, rtol=1e-15)
+    np.testing.assert_allclose(v[0], v0[0] + n * prm.dt * g, rtol=1e-13)
+    np.testing.assert_allclose(x[0], x0[0] + n * prm.dt * v0[0] + prm.dt ** 2 * g * n * (n + 1) / 2,
+                               rtol=1e-12)
+
+
+def test_two_particles_repel_under_positive_pressure_and_conserve_momentum():
+    dom = O.Domain(dim=2, n=(6, 6, 1), cs=(0.05, 0.05, 1.0), periodic=(True, True, True))
+    h = 0.02
+    x = np.array([[0.10, 0.10], [0.125, 0.11]])
+    r12 = x[0] - x[1]
+    for rho_val, sign in ((1100.0, 1.0), (900.0, -1.0)):
+        prm = O.Params(h=h, mass=1.0, rho0=1000.0, c0=10.0, nu=0.0)
+        rho = np.full(2, rho_val)
+        p = np.array([O.tait(prm, rho_val)] * 2)
+        a = O.forces(dom, prm, x, np.zeros_like(x), rho, p)
+        np.testing.assert_allclose(a[0], -a[1], rtol=1e-14)
+        cos = a[0] @ r12 / (np.linalg.norm(a[0]) * np.linalg.norm(r12))
+        assert cos == pytest.approx(sign, abs=1e-12)
+
+
+def test_periodic_shifting_keeps_particles_in_the_box():
+    case = WL.lattice_case(2, (10, 10), 0.01, 1.3, 0.0, 0.0, seed=0)
+    dom, prm = domain_of(case), params_of(case)
+    prm.dt = 1e-2
+    x0 = _exact_lattice(case, (10, 10))
+    v0 = np.tile([[2.0, -3.0]], (case.n, 1))  # moves several cells per step
+    x, v, _, _, _ = O.step(dom, prm, x0, v0, n_steps=3)
+    L = case.length()[:2]
+    assert np.all(x >= 0) and np.all(x < L)
+    # a uniformly translated lattice feels no force: pure periodic shifting
+    np.testing.assert_allclose(O.min_image(dom, x - (x0 + 3 * prm.dt * v0)), 0.0, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# adjoint: one-step VJP and rollout gradient vs central finite differences
+# ---------------------------------------------------------------------------
+
+def _small_case(walls=False):
+    if not walls:
+        return WL.lattice_case(2, (9, 8), 0.01, 1.3, 0.2, 0.3, seed=17, c0=10.0, nu=2e-3, dt=2e-4)
+    c = WL.dam_break_case(dx=0.08, h_over_dx=1.3, c0=10.0, nu=1e-3, fluid=(0.32, 0.24, 0.4),
+                          tank=(0.64, 0.24, 0.56), layers=2)
+    return WL.scaled(c, vel=(np.random.default_rng(3).normal(0, 0.2, c.vel.shape)).astype(np.float32))
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_step_vjp_matches_central_differences(walls):
+    case = _small_case(walls)
+    dom, prm = domain_of(case), params_of(case)
+    fixed = case.fixed_mask()
+    x, v = x64(case), v64(case)
+    rng = np.random.default_rng(5)
+    lx, lv = rng.normal(size=x.shape), rng.normal(size=v.shape)
+    gx, gv, dnu, dc0 = O.step_vjp(dom, prm, x, v, lx, lv, fixed=fixed, nthreads=2)
+
+    def J(xx, vv, p):
+        xn, vn, _, _, _ = O.step(dom, p, xx, vv, fixed=fixed, n_steps=1, nthreads=2)
+        dxn = O.min_image(dom, xn - x)
+        return (dxn * lx).sum() + (vn * lv).sum()
+
+    ux, uv = rng.normal(size=x.shape), rng.normal(size=v.shape)
+    ux[fixed] = 0.0
+    uv[fixed] = 0.0
+    e = 1e-7
+    fd_x = (J(x + e * ux, v, prm) - J(x - e * ux, v, prm)) / (2 * e)
+    assert (gx * ux).sum() == pytest.approx(fd_x, rel=1e-6)
+    e = 1e-5
+    fd_v = (J(x, v + e * uv, prm) - J(x, v - e * uv, prm)) / (2 * e)
+    assert (gv * uv).sum() == pytest.approx(fd_v, rel=1e-6)
+    import copy
+
+    def with_(attr, val):
+        p = copy.copy(prm)
+        setattr(p, attr, val)
+        return p
+    e = 1e-4 * prm.nu
+    fd_nu = (J(x, v, with_("nu", prm.nu + e)) - J(x, v, with_("nu", prm.nu - e))) / (2 * e)
+    assert dnu == pytest.approx(fd_nu, rel=1e-6)
+    e = 1e-5 * prm.c0
+    fd_c0 = (J(x, v, with_("c0", prm.c0 + e)) - J(x, v, with_("c0", prm.c0 - e))) / (2 * e)
+    assert dc0 == pytest.approx(fd_c0, rel=1e-6)
+    assert np.all(gx[fixed] == 0) and np.all(gv[fixed] == 0)
+
+
+def test_rollout_gradient_matches_central_differences_and_vanishes_at_target():
+    case = WL.lattice_case(2, (8, 8), 0.01, 1.3, 0.1, 0.2, seed=19, c0=8.0, nu=1e-3, dt=2e-4)
+    dom, prm = domain_of(case), params_of(case)
+    x0, v0 = x64(case), v64(case)
+    steps = 12
+    import copy
+    tgt = copy.copy(prm)
+    tgt.nu, tgt.c0 = prm.nu * 1.5, prm.c0 * 0.8
+    target, _, _, _, _ = O.step(dom, tgt, x0, v0, n_steps=steps, nthreads=2)
+    L, gv0, gnu, gc0 = O.rollout_grad(dom, prm, x0, v0, target, steps, checkpoint_every=5, nthreads=2)
+    assert L > 0
+
+    def loss(p, v):
+        return O.rollout_loss(dom, p, x0, v, target, steps, nthreads=2)
+
+    def with_(attr, val):
+        p = copy.copy(prm)
+        setattr(p, attr, val)
+        return p
+    e = 1e-4 * prm.nu
+    fd = (loss(with_("nu", prm.nu + e), v0) - loss(with_("nu", prm.nu - e), v0)) / (2 * e)
+    assert gnu == pytest.approx(fd, rel=1e-5)
+    e = 1e-5 * prm.c0
+    fd = (loss(with_("c0", prm.c0 + e), v0) - loss(with_("c0", prm.c0 - e), v0)) / (2 * e)
+    assert gc0 == pytest.approx(fd, rel=1e-5)
+    u = np.random.default_rng(2).normal(size=v0.shape)
+    e = 1e-6
+    fd = (loss(prm, v0 + e * u) - loss(prm, v0 - e * u)) / (2 * e)
+    assert (gv0 * u).sum() == pytest.approx(fd, rel=1e-5)
+    # at the target parameters the loss and every gradient vanish
+    L0, g0, n0, c0_ = O.rollout_grad(dom, tgt, x0, v0, target, steps, checkpoint_every=5, nthreads=2)
+    assert L0 == 0.0 and np.all(g0 == 0) and n0 == 0.0 and c0_ == 0.0
