@@ -1,0 +1,156 @@
+"""Benchmark of the WCSPH hot path on one MI355X.
+
+A step is one pass of the whole hot path over the 3-D periodic jittered
+lattice of 8,388,608 particles (256 x 256 x 128, h = 1.2 dx, ~56
+neighbours): neighbour search (keys, radix sort, cell table, reorder,
+neighbour lists), density + Tait pressure, accelerations with the fused
+semi-implicit Euler update.  Inputs are resident in HBM before timing.
+
+Prints ONE JSON line.  `value` is pair interactions per second over the
+whole step (each ordered neighbour pair counted once per step); the force
+pass alone is reported under `phases`.  `roofline` is for the force kernel
+(its launch is timed alone with HIP events on the library's stream).
+`cpu_baseline` times the FP64 oracle on a bounded sample of the same
+workload (a smaller box of the same lattice recipe).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# per-interaction algorithmic work of the force kernel (3-D), see the design notes
+FORCE_FLOP_PER_PAIR_3D = 39
+FORCE_BYTES_PER_PARTICLE_3D = 4 * (3 + 3 + 1 + 1 + 1 + 1) + 4 * (3 + 3 + 3 + 1 + 1)  # in: off,v,s,k,cell,id,count; out: a,off',v',cell',id'
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="periodic_3d_8388608",
+                    choices=["periodic_3d_8388608", "periodic_3d_262144", "periodic_2d_4096", "dam_break_3d"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", default="128x128x64", help="oracle sample box (lattice sites per axis)")
+    return ap.parse_args()
+
+
+def make_case(name):
+    from paper_1710_08259_amd import workloads as WL
+
+    return {"periodic_3d_8388608": WL.periodic_3d_8m, "periodic_3d_262144": WL.periodic_3d_262k,
+            "periodic_2d_4096": WL.periodic_2d_4096, "dam_break_3d": WL.dam_break_3d}[name]()
+
+
+def cpu_baseline(args, case):
+    """The oracle, as it stands, on a smaller box of the same lattice recipe:
+    one full step (density, pressure, accelerations, integration)."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1710_08259_amd import workloads as WL
+
+    side = tuple(int(s) for s in args.cpu_sample.split("x"))
+    sample = WL.lattice_case(3, side, 0.01, 1.2, 0.05, 0.05, seed=3, c0=case.c0, nu=case.nu, dt=case.dt)
+    dom = O.Domain(dim=3, n=sample.ncell, cs=sample.cell_size, origin=sample.origin)
+    prm = O.Params(h=sample.h, mass=sample.mass, rho0=sample.rho0, c0=sample.c0, gamma=sample.gamma,
+                   nu=sample.nu, dt=sample.dt, g=sample.g)
+    threads = O.default_threads()
+    x = sample.pos.astype(np.float64)
+    v = sample.vel.astype(np.float64)
+    _, _, counts = O.density(dom, prm, x, counts=True, nthreads=threads)
+    pairs = int(counts.sum())
+    t0 = time.perf_counter()
+    O.step(dom, prm, x, v, n_steps=1, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"one FP64 step of a {side[0]}x{side[1]}x{side[2]} box ({sample.n} particles, "
+                      f"{pairs} interactions) of the same lattice recipe, {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is "
+              f"described in the design notes but not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1710_08259_amd import nauticle as N
+
+    case = make_case(args.workload)
+    prob = N.Problem([case])
+    st = prob.state_from_cases()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def one_step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        prob.build_cells(st)
+        if ev:
+            ev[1].record(stream)
+        prob.density()
+        if ev:
+            ev[2].record(stream)
+        prob.forces(next_=st)
+        if ev:
+            ev[3].record(stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    prob.check()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    pairs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        one_step(evs[k])
+        pairs.append(prob.cells.nbr_count[: case.n].sum(dtype=torch.int64))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prob.check()
+    phase = np.zeros(3)
+    for e in evs:
+        phase += [e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
+    phase_ms = phase / args.steps
+    total_pairs = int(sum(int(p.item()) for p in pairs))
+    pairs_per_step = total_pairs / args.steps
+    ms_step = wall * 1e3 / args.steps
+    value = total_pairs / wall
+    force_s = phase_ms[2] * 1e-3
+    flops = FORCE_FLOP_PER_PAIR_3D * pairs_per_step
+    achieved_tflops = flops / force_s / 1e12
+    roofline = {"bound": "alu", "kernel": "k_forces (nauticle_sph_forces, fused integrate)",
+                "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "algorithmic_hbm_GBs": round(FORCE_BYTES_PER_PARTICLE_3D * case.n / force_s / 1e9, 1)}
+    line = {
+        "metric": "particle-pair interactions/s (SPH force pass) + fwd+adjoint steps/s vs plain",
+        "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": case.name, "particles": case.n, "dim": case.dim, "h_over_dx": 1.2,
+                   "neighbours_per_particle": round(pairs_per_step / case.n, 2),
+                   "cells": list(case.ncell), "max_nbr": prob.max_nbr},
+        "phases": {"build_cells_ms": round(phase_ms[0], 4), "density_ms": round(phase_ms[1], 4),
+                   "forces_integrate_ms": round(phase_ms[2], 4),
+                   "force_pass_interactions_per_s": pairs_per_step / force_s},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args, case)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,286 @@
+/*
+ * nauticle.h -- C-ABI of libnauticle, the MI355X (gfx950) hot path of the
+ * weakly compressible SPH step built on the Nauticle particle method
+ * (B. Toth, "Nauticle: a general-purpose particle-based simulation tool",
+ * arXiv:1710.08259).
+ *
+ * What the library computes (paper references in brackets):
+ *   - every particle's neighbours: all j != i closer than the influence
+ *     radius 2h, found through the cell grid of the domain [Sec. 3.2.1, "The
+ *     computational domain": an axis-aligned box of cuboid cells no smaller
+ *     than the influence radius; pairs farther than one cell apart ignored];
+ *   - interaction sums over those neighbours [Sec. 2.1, eq.
+ *     interaction_formula]: SPH density summation with the Wendland kernel
+ *     [Example 1a, kernel equation; SPH sampling expression with A = rho],
+ *     a Tait equation of state (linearises to the paper's p = c^2(rho-rho0)),
+ *     the symmetric pressure gradient [eq. diffop1] and Laplacian viscosity
+ *     [eq. diffop3, Morris form];
+ *   - the first-order semi-implicit Euler step [Example 1a, eq6 then eq7],
+ *     with periodic shifting of particles that leave the box on any axis
+ *     [Sec. 3.2.1];
+ *   - the reverse-mode derivative of one step (not in the paper).
+ * Phases are separated like the paper's equations [Sec. 3.3: an equation is
+ * finished for all particles before the next one starts]: each entry point
+ * is a sequence of kernels on one stream.
+ *
+ * Conventions (all entry points)
+ *   - All particle arrays are caller-owned DEVICE memory, structure of
+ *     arrays, FP32 or uint32, indexed by a global particle index in
+ *     [0, N_total), N_total = sum of the cases' n.  Case b owns
+ *     [offset_b, offset_b + n_b); offsets must be increasing and contiguous
+ *     (offset_0 = 0, offset_{b+1} = offset_b + n_b).
+ *   - Positions are stored cell-relative: the linear index of the cell that
+ *     holds the particle (x fastest: c_x + n_x (c_y + n_y c_z)) and the FP32
+ *     offset from that cell's lower corner, in [0, cell_size).  The cell
+ *     index absorbs the large part of the coordinate, so the offset keeps
+ *     FP32 resolution of cell_size * 2^-24 anywhere in the box.
+ *   - "Sorted order": after nauticle_build_cells the particles of every case
+ *     are ordered by cell key (stable); global position p in sorted order
+ *     belongs to the same case as input position p.
+ *   - Every call validates its arguments on the host first.  A host-side
+ *     error returns a negative status and enqueues nothing.  Otherwise the
+ *     work is enqueued on `stream` and the call returns NAUTICLE_OK without
+ *     waiting.  Conditions found by kernels (non-finite values, a neighbour
+ *     list overflow, a position too far outside the box) set bits in a
+ *     device error word inside the workspace; nauticle_check() reads and
+ *     clears it.  No call allocates device memory; no call aborts.
+ *   - The workspace `ws` (device memory, `ws_bytes` long, size from
+ *     nauticle_workspace_bytes) must have been set up by nauticle_prepare()
+ *     with the same case table; the library remembers, per workspace
+ *     address, a fingerprint of that table and rejects a different one with
+ *     NAUTICLE_ERR_WORKSPACE.  Calls that share a workspace must not run
+ *     concurrently on different streams.
+ *   - Limits: 2 <= dim <= 3; N_total < 2^26; total cells < 2^31;
+ *     max_nbr in [1, 1024].
+ */
+#ifndef NAUTICLE_H
+#define NAUTICLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NAUTICLE_OK = 0,
+    NAUTICLE_ERR_INVALID_ARG = -1,        /* null pointer, bad size, bad layout */
+    NAUTICLE_ERR_DOMAIN = -2,             /* cell < 2h, < 3 cells on a periodic axis, ... */
+    NAUTICLE_ERR_NONFINITE = -3,          /* (nauticle_check) a NaN/Inf was produced or given */
+    NAUTICLE_ERR_OUT_OF_DOMAIN = -4,      /* (nauticle_check) a position beyond 2^23 cells */
+    NAUTICLE_ERR_WORKSPACE = -5,          /* too small, or not prepared for these cases */
+    NAUTICLE_ERR_HIP = -6,                /* a HIP runtime call failed */
+    NAUTICLE_ERR_NEIGHBOUR_OVERFLOW = -7  /* (nauticle_check) a particle had > max_nbr neighbours */
+} nauticle_status;
+
+enum { NAUTICLE_PERIODIC = 0, NAUTICLE_CUTOFF = 1 };
+
+/* Sentinel of an empty cell in cell_start / cell_end. */
+#define NAUTICLE_EMPTY 0xFFFFFFFFu
+
+/* Neighbour-list entry: bits 0..25 hold the neighbour's global sorted
+ * position, bits 26+2k..27+2k hold (cell offset along axis k) + 1, the
+ * offset being the neighbour's cell minus the particle's cell, in {-1,0,1},
+ * after periodic folding. */
+#define NAUTICLE_NBR_INDEX_BITS 26
+
+/* The box [Sec. 3.2.1]: ncell[k] cells of edge cell_size[k] per axis, so the
+ * length is L_k = ncell[k] * cell_size[k].  cell_size is used rounded to
+ * FP32; it must be >= 2h (the influence radius).  Periodic axes need
+ * ncell >= 3.  Axes k >= dim must have ncell[k] = 1. */
+typedef struct {
+    int32_t dim;
+    int32_t ncell[3];
+    int32_t boundary[3]; /* NAUTICLE_PERIODIC or NAUTICLE_CUTOFF */
+    double origin[3];
+    double cell_size[3];
+} nauticle_domain;
+
+/* Constants of one case.  h: smoothing length (support 2h); mass: particle
+ * mass m; rho0: reference density; c0: sound speed; gamma: Tait exponent
+ * (B = c0^2 rho0 / gamma); nu: kinematic viscosity; dt: time step;
+ * g: body acceleration. */
+typedef struct {
+    double h, mass, rho0, c0, gamma, nu, dt;
+    double g[3];
+} nauticle_sph_params;
+
+/* One independent problem.  Particles whose id (position within the case
+ * when binned) is >= n - n_fixed are fixed walls: they take part in every
+ * sum, keep v = 0 and are not moved. */
+typedef struct {
+    nauticle_domain dom;
+    nauticle_sph_params prm;
+    int64_t offset;
+    int64_t n;
+    int64_t n_fixed;
+} nauticle_case;
+
+/* Particle state, cell-relative layout (see Conventions).  off[k], vel[k]
+ * for k >= dim may be NULL.  id[p] is the particle's index within its case
+ * at binning time; it travels with the particle through every reordering. */
+typedef struct {
+    uint32_t* cell;
+    float* off[3];
+    float* vel[3];
+    uint32_t* id;
+} nauticle_state;
+
+/* Neighbour structure, filled by nauticle_build_cells.
+ *   key[p]        cell key of sorted position p (case cell base + cell);
+ *   perm[p]       input position of sorted position p;
+ *   cell_start/end[c]: first / one-past-last sorted position of cell key c,
+ *                 NAUTICLE_EMPTY for both when the cell is empty;
+ *                 length nauticle_cells_total();
+ *   nbr           max_nbr * N_total entries, column-major: entry k of
+ *                 sorted particle p at nbr[k * N_total + p];
+ *   nbr_count[p]  number of neighbours of p (the full count, even if it
+ *                 exceeds max_nbr, in which case the error word is set). */
+typedef struct {
+    uint32_t* key;
+    uint32_t* perm;
+    uint32_t* cell_start;
+    uint32_t* cell_end;
+    uint32_t* nbr;
+    uint32_t* nbr_count;
+    int32_t max_nbr;
+} nauticle_cells;
+
+/* Per-particle fields in sorted order.  s = p / rho^2, inv_rho = 1 / rho. */
+typedef struct {
+    float* rho;
+    float* p;
+    float* s;
+    float* inv_rho;
+    float* acc[3];
+} nauticle_fields;
+
+/* Number of cell keys over all cases (sum of ncell products). */
+int64_t nauticle_cells_total(const nauticle_case* cases, int32_t n_cases);
+
+/* Bytes of device workspace needed for these cases.  Host only. */
+nauticle_status nauticle_workspace_bytes(const nauticle_case* cases, int32_t n_cases,
+                                         size_t* bytes);
+
+/* Validates the case table on the host, writes the device case table and
+ * the launch work lists into `ws`, waits for the copy to finish, and
+ * records the table's fingerprint for `ws`.  Must precede every other call
+ * on `ws`; call again whenever any case constant changes. */
+nauticle_status nauticle_prepare(const nauticle_case* cases, int32_t n_cases, void* ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
+/* Absolute FP32 positions pos[k][i] (device, k < dim) -> cell-relative
+ * state: cell, off, and id = i - offset of i's case.  Velocities are not
+ * touched.  Per axis: t = fl32(x - origin); c = floor(t / cell_size) as
+ * fl32(t * fl32(1/cell_size)) then corrected by one if the remainder
+ * fmaf(-c, cell_size, t) falls outside [0, cell_size); the cell index then
+ * wraps modulo ncell on every axis [Sec. 3.2.1 periodic shifting].
+ * Positions more than 2^23 cells from the origin set OUT_OF_DOMAIN. */
+nauticle_status nauticle_bin(const nauticle_case* cases, int32_t n_cases, const float* const pos[3],
+                             nauticle_state* state, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Cell-relative state -> absolute FP32 positions (output only):
+ * pos = fl32(fl32(origin + c * cell_size) + off). */
+nauticle_status nauticle_unbin(const nauticle_case* cases, int32_t n_cases,
+                               const nauticle_state* state, float* const pos[3], void* ws,
+                               size_t ws_bytes, hipStream_t stream);
+
+/* Neighbour search [Sec. 3.2.1 cell grid; A8 ownership]: keys, stable
+ * radix sort, cell start/end table, reorder of `in` into `sorted`
+ * (sorted must not alias in), then every particle's neighbour list under
+ * the FP32 predicate: with d_k = fl32(fl32(off_j,k + delta_k cell_size_k)
+ * - off_i,k) and r2 = fmaf(d_z, d_z, fmaf(d_y, d_y, d_x d_x)), j is a
+ * neighbour of i iff j != i, the cells are adjacent (delta in {-1,0,1}^dim
+ * after periodic folding; no folding on cut-off axes) and r2 < fl32(4h^2).
+ * Lists are ordered by stencil cell (x fastest, offsets -1..1) then by
+ * sorted position. */
+nauticle_status nauticle_build_cells(const nauticle_case* cases, int32_t n_cases,
+                                     const nauticle_state* in, nauticle_state* sorted,
+                                     nauticle_cells* cells, void* ws, size_t ws_bytes,
+                                     hipStream_t stream);
+
+/* Density and pressure of every sorted particle [SPH sampling expression
+ * with A = rho; Wendland kernel]: rho_i = m alpha_D + sum_j m W(r_ij);
+ * p_i = B((rho_i/rho0)^gamma - 1); also s_i = p_i/rho_i^2, inv_rho_i. */
+nauticle_status nauticle_sph_density(const nauticle_case* cases, int32_t n_cases,
+                                     const nauticle_state* sorted, const nauticle_cells* cells,
+                                     nauticle_fields* fields, void* ws, size_t ws_bytes,
+                                     hipStream_t stream);
+
+/* Accelerations [eq. diffop1 with A = p; eq. diffop3, Morris form]:
+ *   a_i = -sum_j m (s_i + s_j) F_ij r_ij
+ *         + sum_j m nu (inv_rho_i + inv_rho_j) F_ij (v_i - v_j) + g,
+ * r_ij = r_i - r_j, F(r) = -5 alpha_D (1 - r/2h)^3 / h^2 (so that
+ * grad_i W_ij = F_ij r_ij).  Fixed particles get a = 0.  Reads rho..inv_rho
+ * from `fields`, writes fields->acc.  If `next` is not NULL the step is
+ * completed in the same kernel [Example 1a, eq6 then eq7]:
+ * v' = v + dt a, off' = off + dt v' re-split into (cell, offset) as in
+ * nauticle_bin, written to `next` in sorted order (id copied; fixed
+ * particles copied unchanged).  `next` must not alias `sorted`. */
+nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases,
+                                    const nauticle_state* sorted, const nauticle_cells* cells,
+                                    nauticle_fields* fields, nauticle_state* next, void* ws,
+                                    size_t ws_bytes, hipStream_t stream);
+
+/* n_steps full steps in place: build_cells(state -> workspace copy),
+ * density, forces with the fused integration back into `state`.  After
+ * the call `state` holds the particles in the sorted order of the last
+ * step; `cells` and `fields` hold that step's neighbour structure and
+ * fields. */
+nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
+                              int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
+                              void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Reverse mode of one step (the derivative the paper does not have).
+ * Inputs are the step's forward quantities: `sorted` (the state the step's
+ * forces pass read), `cells` (its neighbour lists and perm) and `fields`
+ * (rho, p, s, inv_rho of that step).  lam_x_next / lam_v_next (device, FP32,
+ * sorted order) are the cotangents of the step's output positions and
+ * velocities.  Writes lam_x / lam_v, the cotangents of the step's INPUT
+ * state, in the input order of the step (perm applied backwards), and ADDS
+ * this step's dL/dnu and dL/dc0 to dnu[b], dc0[b] (device FP64, one per
+ * case).  The neighbour set is held fixed; formulas:
+ *   Vh = lam_v' + dt lam_x', A = dt Vh (fluid), A = 0 (fixed)
+ *   sbar_i = -m sum_j F r_ij.(A_i - A_j); kbar_i = m nu sum_j F (v_i - v_j).(A_i - A_j)
+ *   rhobar_i = sbar_i (gamma (p_i + B)/rho_i^3 - 2 p_i/rho_i^3) - kbar_i/rho_i^2
+ *   lam_x_i = lam_x'_i + m sum_j F r_ij (rhobar_i + rhobar_j)
+ *             - m sum_j (s_i + s_j) [F (A_i - A_j) + (F'/r) r_ij (r_ij.(A_i - A_j))]
+ *             + m nu sum_j (inv_rho_i + inv_rho_j) (F'/r) r_ij ((v_i - v_j).(A_i - A_j))
+ *   lam_v_i = Vh_i + m nu sum_j (inv_rho_i + inv_rho_j) F (A_i - A_j)
+ *   dnu += sum_i A_i . m sum_j (inv_rho_i + inv_rho_j) F (v_i - v_j)
+ *   dc0 += sum_i sbar_i (2 p_i / c0) / rho_i^2
+ * Fixed particles get zero cotangents. */
+nauticle_status nauticle_sph_adjoint(const nauticle_case* cases, int32_t n_cases,
+                                     const nauticle_state* sorted, const nauticle_cells* cells,
+                                     const nauticle_fields* fields,
+                                     const float* const lam_x_next[3],
+                                     const float* const lam_v_next[3], float* const lam_x[3],
+                                     float* const lam_v[3], double* dnu, double* dc0, void* ws,
+                                     size_t ws_bytes, hipStream_t stream);
+
+/* Rollout loss between two states of the same cases, matched by id:
+ * loss[b] = (1/(n_fluid d)) sum over fluid particles of |r_a - r_b|^2,
+ * the difference taken cell-relatively with periodic folding of the cell
+ * difference on periodic axes.  grad[k] (device FP32, optional) receives
+ * dloss/d(position of a), in a's order.  loss (device FP64 per case) is
+ * overwritten. */
+nauticle_status nauticle_position_loss(const nauticle_case* cases, int32_t n_cases,
+                                       const nauticle_state* a, const nauticle_state* b,
+                                       double* loss, float* const grad[3], void* ws,
+                                       size_t ws_bytes, hipStream_t stream);
+
+/* Synchronises `stream`, reads and clears the device error word of `ws`,
+ * and returns the most severe condition it held (NAUTICLE_OK if none). */
+nauticle_status nauticle_check(void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Message for the last non-OK status returned on this host thread. */
+const char* nauticle_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NAUTICLE_H */

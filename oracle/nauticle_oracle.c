@@ -291,13 +291,14 @@ static void or_cell_list_free(or_cell_list* L)
     free(L->key_sorted);
 }
 
-/* For every particle i: count[i] = number of j satisfying the FP32
- * predicate.  If list != NULL, list[i*max_nbr + k] receives the neighbours'
- * input indices (stencil order, then index order), up to max_nbr of them.
- * Found through the cell grid: only the 3^dim cells around i's cell. */
+/* For every particle i (or every i = which[s], s < n_eval, if which is not
+ * NULL): count[s] = number of j satisfying the FP32 predicate.  If list !=
+ * NULL, list[s*max_nbr + k] receives the neighbours' input indices (stencil
+ * order, then index order), up to max_nbr of them.  Found through the cell
+ * grid: only the 3^dim cells around i's cell. */
 int or_neighbours_f32(const or_domain* D, double h, int64_t n, const uint32_t* cell,
-                      const float* ox, const float* oy, const float* oz, int32_t* count,
-                      uint32_t* list, int32_t max_nbr)
+                      const float* ox, const float* oy, const float* oz, int64_t n_eval,
+                      const int64_t* which, int32_t* count, uint32_t* list, int32_t max_nbr)
 {
     or_cell_list L;
     if (or_cell_list_build(D, n, cell, &L) != 0) return -1;
@@ -305,7 +306,9 @@ int or_neighbours_f32(const or_domain* D, double h, int64_t n, const uint32_t* c
     float R2 = or_R2_f32(h);
     int span[3] = {1, 1, 1};
     for (int k = 0; k < D->dim; ++k) span[k] = 3;
-    for (int64_t i = 0; i < n; ++i) {
+    int64_t m = which ? n_eval : n;
+    for (int64_t s = 0; s < m; ++s) {
+        int64_t i = which ? which[s] : s;
         int64_t ci[3];
         or_cell_coords(D, cell[i], ci);
         float offi[3] = {0, 0, 0};
@@ -337,12 +340,12 @@ int or_neighbours_f32(const or_domain* D, double h, int64_t n, const uint32_t* c
                         float offj[3] = {0, 0, 0};
                         for (int k = 0; k < D->dim; ++k) offj[k] = off[k][j];
                         if (or_pred_f32(D, R2, delta, offi, offj)) {
-                            if (list && cnt < max_nbr) list[i * (int64_t)max_nbr + cnt] = j;
+                            if (list && cnt < max_nbr) list[s * (int64_t)max_nbr + cnt] = j;
                             ++cnt;
                         }
                     }
                 }
-        count[i] = cnt;
+        count[s] = cnt;
     }
     or_cell_list_free(&L);
     return 0;

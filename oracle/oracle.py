@@ -131,7 +131,7 @@ def _load():
     lib.or_sort_keys.restype = ctypes.c_int
     lib.or_sort_keys.argtypes = [i64, vp, ctypes.c_uint32, vp, vp, vp, vp]
     lib.or_neighbours_f32.restype = ctypes.c_int
-    lib.or_neighbours_f32.argtypes = [P(_Domain), dbl, i64, vp, vp, vp, vp, vp, vp, i32]
+    lib.or_neighbours_f32.argtypes = [P(_Domain), dbl, i64, vp, vp, vp, vp, i64, vp, vp, vp, i32]
     lib.or_neighbours_f32_brute.restype = None
     lib.or_neighbours_f32_brute.argtypes = [P(_Domain), dbl, i64, vp, vp, vp, vp, vp]
     lib.or_density.restype = ctypes.c_int
@@ -216,19 +216,23 @@ def sort_keys(keys: np.ndarray, n_keys: int):
 
 
 def neighbours_f32(dom: Domain, h: float, cell: np.ndarray, off: np.ndarray,
-                   max_nbr: int = 0, brute: bool = False):
-    """FP32-predicate neighbour counts (and lists if max_nbr > 0)."""
+                   max_nbr: int = 0, brute: bool = False, which=None):
+    """FP32-predicate neighbour counts (and lists if max_nbr > 0), for all
+    particles or for the subset ``which``."""
     cell = np.ascontiguousarray(cell, dtype=np.uint32)
     n = cell.shape[0]
     cols = [np.ascontiguousarray(off[:, k], dtype=np.float32) for k in range(dom.dim)]
     args = [_ptr(cols[k]) if k < dom.dim else None for k in range(3)]
-    count = np.zeros(n, np.int32)
+    w = None if which is None else np.ascontiguousarray(which, dtype=np.int64)
+    m = n if w is None else w.shape[0]
+    count = np.zeros(m, np.int32)
     if brute:
+        assert w is None
         _load().or_neighbours_f32_brute(ctypes.byref(dom._c()), h, n, _ptr(cell), *args, _ptr(count))
         return count
-    lst = np.zeros((n, max_nbr), np.uint32) if max_nbr > 0 else None
-    rc = _load().or_neighbours_f32(ctypes.byref(dom._c()), h, n, _ptr(cell), *args, _ptr(count),
-                                   _ptr(lst), max_nbr)
+    lst = np.zeros((m, max_nbr), np.uint32) if max_nbr > 0 else None
+    rc = _load().or_neighbours_f32(ctypes.byref(dom._c()), h, n, _ptr(cell), *args, m, _ptr(w),
+                                   _ptr(count), _ptr(lst), max_nbr)
     if rc != 0:
         raise MemoryError("or_neighbours_f32 failed")
     return (count, lst) if max_nbr > 0 else count

@@ -1,0 +1,496 @@
+// C-ABI entry points of libnauticle: host-side validation, the per-workspace
+// plan (case table fingerprint, workspace layout, tile work lists), and the
+// launch sequences of the five phases.  See include/nauticle.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+using namespace nau;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+nauticle_status fail(nauticle_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+nauticle_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(NAUTICLE_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+uint64_t fingerprint(const nauticle_case* cases, int32_t n_cases)
+{
+    // FNV-1a over the raw case table
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(cases);
+    const size_t len = sizeof(nauticle_case) * static_cast<size_t>(n_cases);
+    for (size_t i = 0; i < len; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h ^ static_cast<uint64_t>(n_cases);
+}
+
+struct Derived {
+    Plan plan;
+    std::vector<CaseDev> cases;
+    std::vector<Item> items;
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Validates the case table and derives the device table, work list, layout.
+nauticle_status derive(const nauticle_case* cases, int32_t n_cases, Derived* D)
+{
+    if (!cases || n_cases < 1) return fail(NAUTICLE_ERR_INVALID_ARG, "cases is null or n_cases < 1");
+    D->cases.clear();
+    D->items.clear();
+    Plan& P = D->plan;
+    std::memset(&P, 0, sizeof(P));
+    P.n_cases = n_cases;
+    const int dim0 = cases[0].dom.dim;
+    uint64_t n_total = 0, n_cells_total = 0, n_fluid_total = 0;
+    for (int32_t b = 0; b < n_cases; ++b) {
+        const nauticle_case& c = cases[b];
+        const nauticle_domain& d = c.dom;
+        const nauticle_sph_params& q = c.prm;
+        if (d.dim < 2 || d.dim > 3) return fail(NAUTICLE_ERR_DOMAIN, "case %d: dim must be 2 or 3", b);
+        if (d.dim != dim0) return fail(NAUTICLE_ERR_DOMAIN, "case %d: all cases must share one dim", b);
+        if (!finite_pos(q.h) || !finite_pos(q.mass) || !finite_pos(q.rho0) || !finite_pos(q.c0) ||
+            !finite_pos(q.gamma) || !std::isfinite(q.nu) || q.nu < 0.0 || !std::isfinite(q.dt) || q.dt < 0.0 ||
+            !std::isfinite(q.g[0]) || !std::isfinite(q.g[1]) || !std::isfinite(q.g[2]))
+            return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: non-finite or non-positive parameter", b);
+        uint64_t ncell = 1;
+        for (int k = 0; k < 3; ++k) {
+            if (k >= d.dim) {
+                if (d.ncell[k] != 1) return fail(NAUTICLE_ERR_DOMAIN, "case %d: ncell[%d] must be 1", b, k);
+                continue;
+            }
+            if (d.ncell[k] < 1) return fail(NAUTICLE_ERR_DOMAIN, "case %d: ncell[%d] < 1", b, k);
+            if (d.boundary[k] != NAUTICLE_PERIODIC && d.boundary[k] != NAUTICLE_CUTOFF)
+                return fail(NAUTICLE_ERR_DOMAIN, "case %d: boundary[%d] unknown", b, k);
+            if (!finite_pos(d.cell_size[k]) || !std::isfinite(d.origin[k]))
+                return fail(NAUTICLE_ERR_DOMAIN, "case %d: bad cell_size/origin on axis %d", b, k);
+            const double cs32 = static_cast<double>(static_cast<float>(d.cell_size[k]));
+            if (cs32 < 2.0 * q.h)
+                return fail(NAUTICLE_ERR_DOMAIN, "case %d: cell_size[%d] = %.9g below the support 2h = %.9g",
+                            b, k, cs32, 2.0 * q.h);
+            if (d.boundary[k] == NAUTICLE_PERIODIC && d.ncell[k] < 3)
+                return fail(NAUTICLE_ERR_DOMAIN, "case %d: periodic axis %d needs >= 3 cells", b, k);
+            ncell *= static_cast<uint64_t>(d.ncell[k]);
+        }
+        if (c.n < 0 || c.n_fixed < 0 || c.n_fixed > c.n)
+            return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: bad n / n_fixed", b);
+        if (static_cast<uint64_t>(c.offset) != n_total)
+            return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: offset %lld, expected %llu (contiguous)", b,
+                        static_cast<long long>(c.offset), static_cast<unsigned long long>(n_total));
+        CaseDev C;
+        std::memset(&C, 0, sizeof(C));
+        C.dim = d.dim;
+        for (int k = 0; k < 3; ++k) {
+            C.nc[k] = d.ncell[k];
+            C.periodic[k] = (k < d.dim && d.boundary[k] == NAUTICLE_PERIODIC) ? 1 : 0;
+            C.cs[k] = static_cast<float>(k < d.dim ? d.cell_size[k] : 1.0);
+            C.inv_cs[k] = static_cast<float>(1.0 / (k < d.dim ? d.cell_size[k] : 1.0));
+            C.origin[k] = static_cast<float>(k < d.dim ? d.origin[k] : 0.0);
+            C.g[k] = static_cast<float>(k < d.dim ? q.g[k] : 0.0);
+        }
+        C.cell_base = static_cast<uint32_t>(n_cells_total);
+        C.n_cells = static_cast<uint32_t>(ncell);
+        C.offset = static_cast<uint32_t>(n_total);
+        C.n = static_cast<uint32_t>(c.n);
+        C.n_fluid = static_cast<uint32_t>(c.n - c.n_fixed);
+        const double alpha = d.dim == 2 ? 7.0 / (4.0 * M_PI * q.h * q.h)
+                                        : 21.0 / (16.0 * M_PI * q.h * q.h * q.h);
+        C.R2 = static_cast<float>(4.0 * q.h * q.h);
+        C.inv_h = static_cast<float>(1.0 / q.h);
+        C.m = static_cast<float>(q.mass);
+        C.m_alpha = static_cast<float>(q.mass * alpha);
+        C.F_coef = static_cast<float>(-5.0 * alpha / (q.h * q.h));
+        C.dF_coef = static_cast<float>(7.5 * alpha / (q.h * q.h * q.h));
+        C.rho0 = static_cast<float>(q.rho0);
+        C.inv_rho0 = static_cast<float>(1.0 / q.rho0);
+        C.B = static_cast<float>(q.c0 * q.c0 * q.rho0 / q.gamma);
+        C.gamma = static_cast<float>(q.gamma);
+        C.c0 = static_cast<float>(q.c0);
+        C.nu = static_cast<float>(q.nu);
+        C.dt = static_cast<float>(q.dt);
+        C.item_first = static_cast<uint32_t>(D->items.size());
+        for (int64_t first = 0; first < c.n; first += kBlock) {
+            Item it;
+            it.case_id = static_cast<uint32_t>(b);
+            it.first = static_cast<uint32_t>(n_total + first);
+            it.count = static_cast<uint32_t>(std::min<int64_t>(kBlock, c.n - first));
+            it.pad = 0;
+            D->items.push_back(it);
+        }
+        C.item_count = static_cast<uint32_t>(D->items.size()) - C.item_first;
+        D->cases.push_back(C);
+        n_total += static_cast<uint64_t>(c.n);
+        n_cells_total += ncell;
+        n_fluid_total += static_cast<uint64_t>(c.n - c.n_fixed);
+        if (n_total > kIndexMask)
+            return fail(NAUTICLE_ERR_INVALID_ARG, "more than 2^%d particles in total", NAUTICLE_NBR_INDEX_BITS);
+        if (n_cells_total >= (1ull << 31)) return fail(NAUTICLE_ERR_DOMAIN, "more than 2^31 cells in total");
+    }
+    P.dim_max = dim0;
+    P.n_total = static_cast<uint32_t>(n_total);
+    P.n_cells_total = static_cast<uint32_t>(n_cells_total);
+    P.n_fluid_total = static_cast<uint32_t>(n_fluid_total);
+    P.n_items = static_cast<uint32_t>(D->items.size());
+    int bits = 1;
+    while ((1ull << bits) < n_cells_total) ++bits;
+    P.key_bits = bits;
+    P.fingerprint = fingerprint(cases, n_cases);
+
+    // workspace layout
+    Layout& L = P.L;
+    const size_t N = std::max<size_t>(n_total, 1);
+    const size_t n_tiles = (N + 4095) / 4096;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.err = take(sizeof(uint32_t));
+    L.cases = take(sizeof(CaseDev) * D->cases.size());
+    L.items = take(sizeof(Item) * std::max<size_t>(D->items.size(), 1));
+    for (int k = 0; k < 8; ++k) L.state[k] = take(4 * N);
+    L.sort_keys = take(4 * N);
+    L.sort_vals = take(4 * N);
+    L.sort_hist = take(4 * 256 * n_tiles);
+    L.sort_totals = take(4 * 256);
+    for (int k = 0; k < 12; ++k) L.adj[k] = take(4 * N);
+    L.partial = take(2 * sizeof(double) * std::max<size_t>(D->items.size(), 1));
+    L.inv_map = take(4 * N);
+    L.total = off;
+    return NAUTICLE_OK;
+}
+
+std::mutex g_mu;
+std::unordered_map<const void*, Derived> g_plans;
+
+// Looks up the plan recorded for ws and checks it matches the given cases.
+nauticle_status plan_for(const nauticle_case* cases, int32_t n_cases, void* ws, size_t ws_bytes,
+                         const Plan** out)
+{
+    if (!cases || n_cases < 1) return fail(NAUTICLE_ERR_INVALID_ARG, "cases is null or n_cases < 1");
+    if (!ws) return fail(NAUTICLE_ERR_WORKSPACE, "workspace is null");
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_plans.find(ws);
+    if (it == g_plans.end()) return fail(NAUTICLE_ERR_WORKSPACE, "workspace was not prepared (nauticle_prepare)");
+    const Plan& P = it->second.plan;
+    if (P.n_cases != n_cases || P.fingerprint != fingerprint(cases, n_cases))
+        return fail(NAUTICLE_ERR_WORKSPACE, "workspace was prepared for a different case table");
+    if (ws_bytes < P.L.total) return fail(NAUTICLE_ERR_WORKSPACE, "workspace too small");
+    *out = &P;
+    return NAUTICLE_OK;
+}
+
+nauticle_status check_state(const Plan& P, const nauticle_state* st, bool need_vel, const char* name)
+{
+    if (!st) return fail(NAUTICLE_ERR_INVALID_ARG, "%s is null", name);
+    if (P.n_total == 0) return NAUTICLE_OK;
+    if (!st->cell || !st->id) return fail(NAUTICLE_ERR_INVALID_ARG, "%s: cell/id null", name);
+    for (int k = 0; k < P.dim_max; ++k) {
+        if (!st->off[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "%s: off[%d] null", name, k);
+        if (need_vel && !st->vel[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "%s: vel[%d] null", name, k);
+    }
+    return NAUTICLE_OK;
+}
+
+nauticle_status check_cells(const Plan& P, const nauticle_cells* c, bool need_lists)
+{
+    if (!c) return fail(NAUTICLE_ERR_INVALID_ARG, "cells is null");
+    if (c->max_nbr < 1 || c->max_nbr > 1024) return fail(NAUTICLE_ERR_INVALID_ARG, "max_nbr outside [1, 1024]");
+    if (!c->cell_start || !c->cell_end) return fail(NAUTICLE_ERR_INVALID_ARG, "cell_start/end null");
+    if (P.n_total == 0) return NAUTICLE_OK;
+    if (!c->key || !c->perm) return fail(NAUTICLE_ERR_INVALID_ARG, "key/perm null");
+    if (need_lists && (!c->nbr || !c->nbr_count)) return fail(NAUTICLE_ERR_INVALID_ARG, "nbr/nbr_count null");
+    if (static_cast<uint64_t>(c->max_nbr) * P.n_total > (1ull << 40))
+        return fail(NAUTICLE_ERR_INVALID_ARG, "neighbour list too large");
+    return NAUTICLE_OK;
+}
+
+nauticle_status check_fields(const Plan& P, const nauticle_fields* f, bool need_acc)
+{
+    if (!f) return fail(NAUTICLE_ERR_INVALID_ARG, "fields is null");
+    if (P.n_total == 0) return NAUTICLE_OK;
+    if (!f->rho || !f->p || !f->s || !f->inv_rho) return fail(NAUTICLE_ERR_INVALID_ARG, "fields: null array");
+    if (need_acc)
+        for (int k = 0; k < P.dim_max; ++k)
+            if (!f->acc[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "fields: acc[%d] null", k);
+    return NAUTICLE_OK;
+}
+
+StateDev to_dev(const nauticle_state* s)
+{
+    StateDev d;
+    d.cell = s->cell;
+    d.id = s->id;
+    for (int k = 0; k < 3; ++k) {
+        d.off[k] = s->off[k];
+        d.vel[k] = s->vel[k];
+    }
+    return d;
+}
+
+FieldsDev to_dev(const nauticle_fields* f)
+{
+    FieldsDev d;
+    d.rho = f->rho;
+    d.p = f->p;
+    d.s = f->s;
+    d.inv_rho = f->inv_rho;
+    for (int k = 0; k < 3; ++k) d.acc[k] = f->acc[k];
+    return d;
+}
+
+StateDev scratch_state(const Plan& P, void* ws)
+{
+    StateDev d;
+    d.cell = at<uint32_t>(ws, P.L.state[0]);
+    for (int k = 0; k < 3; ++k) {
+        d.off[k] = at<float>(ws, P.L.state[1 + k]);
+        d.vel[k] = at<float>(ws, P.L.state[4 + k]);
+    }
+    d.id = at<uint32_t>(ws, P.L.state[7]);
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t nauticle_cells_total(const nauticle_case* cases, int32_t n_cases)
+{
+    if (!cases || n_cases < 1) return -1;
+    int64_t total = 0;
+    for (int32_t b = 0; b < n_cases; ++b) {
+        int64_t c = 1;
+        for (int k = 0; k < 3; ++k) c *= std::max<int64_t>(cases[b].dom.ncell[k], 0);
+        total += c;
+    }
+    return total;
+}
+
+nauticle_status nauticle_workspace_bytes(const nauticle_case* cases, int32_t n_cases, size_t* bytes)
+{
+    if (!bytes) return fail(NAUTICLE_ERR_INVALID_ARG, "bytes is null");
+    Derived D;
+    nauticle_status st = derive(cases, n_cases, &D);
+    if (st != NAUTICLE_OK) return st;
+    *bytes = D.plan.L.total;
+    return NAUTICLE_OK;
+}
+
+nauticle_status nauticle_prepare(const nauticle_case* cases, int32_t n_cases, void* ws, size_t ws_bytes,
+                                 hipStream_t stream)
+{
+    Derived D;
+    nauticle_status st = derive(cases, n_cases, &D);
+    if (st != NAUTICLE_OK) return st;
+    if (!ws) return fail(NAUTICLE_ERR_WORKSPACE, "workspace is null");
+    if (ws_bytes < D.plan.L.total)
+        return fail(NAUTICLE_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, D.plan.L.total);
+    hipError_t e = hipMemsetAsync(at<char>(ws, D.plan.L.err), 0, sizeof(uint32_t), stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(at<char>(ws, D.plan.L.cases), D.cases.data(), sizeof(CaseDev) * D.cases.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !D.items.empty())
+        e = hipMemcpyAsync(at<char>(ws, D.plan.L.items), D.items.data(), sizeof(Item) * D.items.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "nauticle_prepare upload");
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_plans[ws] = std::move(D);
+    return NAUTICLE_OK;
+}
+
+nauticle_status nauticle_bin(const nauticle_case* cases, int32_t n_cases, const float* const pos[3],
+                             nauticle_state* state, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, state, false, "state")) != NAUTICLE_OK) return st;
+    if (!pos) return fail(NAUTICLE_ERR_INVALID_ARG, "pos is null");
+    for (int k = 0; k < P->dim_max; ++k)
+        if (P->n_total && !pos[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "pos[%d] is null", k);
+    hipError_t e = launch_bin(*P, ws, pos, to_dev(state), stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_bin");
+}
+
+nauticle_status nauticle_unbin(const nauticle_case* cases, int32_t n_cases, const nauticle_state* state,
+                               float* const pos[3], void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, state, false, "state")) != NAUTICLE_OK) return st;
+    if (!pos) return fail(NAUTICLE_ERR_INVALID_ARG, "pos is null");
+    for (int k = 0; k < P->dim_max; ++k)
+        if (P->n_total && !pos[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "pos[%d] is null", k);
+    hipError_t e = launch_unbin(*P, ws, to_dev(state), pos, stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_unbin");
+}
+
+nauticle_status nauticle_build_cells(const nauticle_case* cases, int32_t n_cases, const nauticle_state* in,
+                                     nauticle_state* sorted, nauticle_cells* cells, void* ws, size_t ws_bytes,
+                                     hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, in, true, "in")) != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, sorted, true, "sorted")) != NAUTICLE_OK) return st;
+    if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
+    if (P->n_total && (in->cell == sorted->cell || in->off[0] == sorted->off[0]))
+        return fail(NAUTICLE_ERR_INVALID_ARG, "sorted must not alias in");
+    hipError_t e = launch_build_cells(*P, ws, to_dev(in), to_dev(sorted), *cells, stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_build_cells");
+}
+
+nauticle_status nauticle_sph_density(const nauticle_case* cases, int32_t n_cases, const nauticle_state* sorted,
+                                     const nauticle_cells* cells, nauticle_fields* fields, void* ws,
+                                     size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, sorted, false, "sorted")) != NAUTICLE_OK) return st;
+    if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
+    if ((st = check_fields(*P, fields, false)) != NAUTICLE_OK) return st;
+    hipError_t e = launch_density(*P, ws, to_dev(sorted), *cells, to_dev(fields), stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_sph_density");
+}
+
+nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases, const nauticle_state* sorted,
+                                    const nauticle_cells* cells, nauticle_fields* fields, nauticle_state* next,
+                                    void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, sorted, true, "sorted")) != NAUTICLE_OK) return st;
+    if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
+    if ((st = check_fields(*P, fields, true)) != NAUTICLE_OK) return st;
+    StateDev nd;
+    if (next) {
+        if ((st = check_state(*P, next, true, "next")) != NAUTICLE_OK) return st;
+        if (P->n_total && (next->cell == sorted->cell || next->off[0] == sorted->off[0]))
+            return fail(NAUTICLE_ERR_INVALID_ARG, "next must not alias sorted");
+        nd = to_dev(next);
+    }
+    hipError_t e = launch_forces(*P, ws, to_dev(sorted), *cells, to_dev(fields), next ? &nd : nullptr, stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_sph_forces");
+}
+
+nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauticle_state* state, int32_t n_steps,
+                              nauticle_cells* cells, nauticle_fields* fields, void* ws, size_t ws_bytes,
+                              hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if (n_steps < 0) return fail(NAUTICLE_ERR_INVALID_ARG, "n_steps < 0");
+    if ((st = check_state(*P, state, true, "state")) != NAUTICLE_OK) return st;
+    if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
+    if ((st = check_fields(*P, fields, true)) != NAUTICLE_OK) return st;
+    const StateDev cur = to_dev(state);
+    const StateDev tmp = scratch_state(*P, ws);
+    const FieldsDev f = to_dev(fields);
+    for (int32_t s = 0; s < n_steps; ++s) {
+        hipError_t e = launch_build_cells(*P, ws, cur, tmp, *cells, stream);
+        if (e == hipSuccess) e = launch_density(*P, ws, tmp, *cells, f, stream);
+        if (e == hipSuccess) e = launch_forces(*P, ws, tmp, *cells, f, &cur, stream);
+        if (e != hipSuccess) return hip_fail(e, "nauticle_step");
+    }
+    return NAUTICLE_OK;
+}
+
+nauticle_status nauticle_sph_adjoint(const nauticle_case* cases, int32_t n_cases, const nauticle_state* sorted,
+                                     const nauticle_cells* cells, const nauticle_fields* fields,
+                                     const float* const lam_x_next[3], const float* const lam_v_next[3],
+                                     float* const lam_x[3], float* const lam_v[3], double* dnu, double* dc0,
+                                     void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, sorted, true, "sorted")) != NAUTICLE_OK) return st;
+    if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
+    if ((st = check_fields(*P, fields, false)) != NAUTICLE_OK) return st;
+    if (!lam_x_next || !lam_v_next || !lam_x || !lam_v || !dnu || !dc0)
+        return fail(NAUTICLE_ERR_INVALID_ARG, "adjoint: null argument");
+    for (int k = 0; k < P->dim_max; ++k) {
+        if (P->n_total && (!lam_x_next[k] || !lam_v_next[k] || !lam_x[k] || !lam_v[k]))
+            return fail(NAUTICLE_ERR_INVALID_ARG, "adjoint: null cotangent array on axis %d", k);
+        if (P->n_total && (lam_x[k] == lam_x_next[k] || lam_v[k] == lam_v_next[k] ||
+                           lam_x[k] == lam_v_next[k] || lam_v[k] == lam_x_next[k]))
+            return fail(NAUTICLE_ERR_INVALID_ARG, "adjoint: outputs must not alias inputs");
+    }
+    hipError_t e = launch_adjoint(*P, ws, to_dev(sorted), *cells, to_dev(const_cast<nauticle_fields*>(fields)),
+                                  lam_x_next, lam_v_next, lam_x, lam_v, dnu, dc0, stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_sph_adjoint");
+}
+
+nauticle_status nauticle_position_loss(const nauticle_case* cases, int32_t n_cases, const nauticle_state* a,
+                                       const nauticle_state* b, double* loss, float* const grad[3], void* ws,
+                                       size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, a, false, "a")) != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, b, false, "b")) != NAUTICLE_OK) return st;
+    if (!loss) return fail(NAUTICLE_ERR_INVALID_ARG, "loss is null");
+    hipError_t e = launch_position_loss(*P, ws, to_dev(a), to_dev(b), loss, grad, stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_position_loss");
+}
+
+nauticle_status nauticle_check(void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    size_t err_off;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto it = g_plans.find(ws);
+        if (it == g_plans.end()) return fail(NAUTICLE_ERR_WORKSPACE, "workspace was not prepared");
+        if (ws_bytes < it->second.plan.L.total) return fail(NAUTICLE_ERR_WORKSPACE, "workspace too small");
+        err_off = it->second.plan.L.err;
+    }
+    uint32_t word = 0;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemcpy(&word, at<char>(ws, err_off), sizeof(word), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemset(at<char>(ws, err_off), 0, sizeof(word));
+    if (e != hipSuccess) return hip_fail(e, "nauticle_check");
+    if (word & kErrNonFinite) return fail(NAUTICLE_ERR_NONFINITE, "a non-finite value was produced or given");
+    if (word & kErrOverflow) return fail(NAUTICLE_ERR_NEIGHBOUR_OVERFLOW, "a particle had more than max_nbr neighbours");
+    if (word & kErrOutOfDomain) return fail(NAUTICLE_ERR_OUT_OF_DOMAIN, "a position lies beyond 2^23 cells");
+    return NAUTICLE_OK;
+}
+
+const char* nauticle_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

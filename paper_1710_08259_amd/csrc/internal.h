@@ -1,0 +1,172 @@
+// Internal declarations of libnauticle (HIP, gfx950).  Not installed; the
+// public interface is include/nauticle.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "nauticle.h"
+
+namespace nau {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kWave = 64;
+constexpr uint32_t kIndexMask = (1u << NAUTICLE_NBR_INDEX_BITS) - 1u;
+
+// Device error word bits (OR-ed by kernels, read by nauticle_check).
+constexpr uint32_t kErrNonFinite = 1u;
+constexpr uint32_t kErrOverflow = 2u;
+constexpr uint32_t kErrOutOfDomain = 4u;
+
+// Per-case constants, derived once on the host in FP64 and rounded to FP32.
+struct CaseDev {
+    int32_t dim;
+    int32_t nc[3];
+    int32_t periodic[3];
+    uint32_t cell_base;  // first global cell key of the case
+    uint32_t n_cells;
+    uint32_t offset;     // first global particle
+    uint32_t n;          // particles
+    uint32_t n_fluid;    // ids >= n_fluid are fixed
+    uint32_t item_first; // this case's tiles in the item list
+    uint32_t item_count;
+    float cs[3];         // fl32(cell_size)
+    float inv_cs[3];     // fl32(1 / cell_size)
+    float origin[3];     // fl32(origin)
+    float R2;            // fl32(4 h^2)
+    float inv_h;
+    float m;             // particle mass
+    float m_alpha;       // m * alpha_D (self density, and W's scale)
+    float F_coef;        // -5 alpha_D / h^2   (F = F_coef (1 - q/2)^3)
+    float dF_coef;       // 15 alpha_D / (2 h^3)  (F' = dF_coef (1 - q/2)^2)
+    float rho0, inv_rho0, B, gamma, c0;
+    float nu, dt;
+    float g[3];
+};
+
+// A tile of at most kBlock consecutive particles of one case.
+struct Item {
+    uint32_t case_id;
+    uint32_t first;
+    uint32_t count;
+    uint32_t pad;
+};
+
+// Device pointers of a state in the cell-relative layout.
+struct StateDev {
+    uint32_t* cell;
+    float* off[3];
+    float* vel[3];
+    uint32_t* id;
+};
+
+struct FieldsDev {
+    float* rho;
+    float* p;
+    float* s;
+    float* inv_rho;
+    float* acc[3];
+};
+
+// Byte offsets of everything the library keeps in the caller's workspace.
+struct Layout {
+    size_t err;
+    size_t cases;
+    size_t items;
+    size_t state[8];     // scratch state for nauticle_step: cell, off[3], vel[3], id
+    size_t sort_keys;    // ping-pong keys
+    size_t sort_vals;    // ping-pong values
+    size_t sort_hist;    // [bins][tiles]
+    size_t sort_totals;  // [bins]
+    size_t adj[12];      // adjoint scratch arrays, N floats each
+    size_t partial;      // per-item FP64 partial sums (2 per item)
+    size_t inv_map;      // id -> position map (N u32)
+    size_t total;
+};
+
+// Everything derived from a case table.
+struct Plan {
+    uint64_t fingerprint;
+    int32_t n_cases;
+    int32_t dim_max;
+    uint32_t n_total;
+    uint32_t n_cells_total;
+    uint32_t n_items;
+    uint32_t n_fluid_total;
+    int key_bits;
+    Layout L;
+    // host copies (for launches that need per-case sizes)
+    const CaseDev* host_cases;
+};
+
+template <typename T>
+inline T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+// ---- launchers (defined in the .hip files) -----------------------------------
+// search.hip
+hipError_t launch_bin(const Plan& P, void* ws, const float* const pos[3], StateDev st, hipStream_t s);
+hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3], hipStream_t s);
+hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sorted,
+                              const nauticle_cells& cells, hipStream_t s);
+// sph.hip
+hipError_t launch_density(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
+                          FieldsDev f, hipStream_t s);
+hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
+                         FieldsDev f, const StateDev* next, hipStream_t s);
+// adjoint.hip
+hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
+                          FieldsDev f, const float* const lxn[3], const float* const lvn[3],
+                          float* const lx[3], float* const lv[3], double* dnu, double* dc0,
+                          hipStream_t s);
+hipError_t launch_position_loss(const Plan& P, void* ws, StateDev a, StateDev b, double* loss,
+                                float* const grad[3], hipStream_t s);
+
+// ---- device helpers -----------------------------------------------------------
+
+// Splits an FP32 offset t, measured from the lower face of cell c along one
+// axis, into whole cells and a remainder in [0, cs); wraps the cell modulo n
+// (periodic shifting on every axis).  Exact same operation order as the
+// documented binning rule: k = floor(t * inv_cs); r = fmaf(-k, cs, t); one
+// correction of k if r left [0, cs); clamp of a remainder that rounded up to
+// cs.  Returns false if |k| would exceed 2^23 (position unrepresentable).
+__device__ inline bool split_offset(float t, float cs, float inv_cs, int32_t n, int32_t c,
+                                    int32_t* c_out, float* r_out)
+{
+#pragma clang fp contract(off)
+    float q = t * inv_cs;
+    float fk = floorf(q);
+    bool ok = fabsf(fk) < 8388608.0f;
+    if (!ok) fk = 0.0f;
+    int32_t k = static_cast<int32_t>(fk);
+    float r = __builtin_fmaf(-static_cast<float>(k), cs, t);
+    if (r < 0.0f) {
+        k -= 1;
+        r = __builtin_fmaf(-static_cast<float>(k), cs, t);
+    } else if (r >= cs) {
+        k += 1;
+        r = __builtin_fmaf(-static_cast<float>(k), cs, t);
+    }
+    if (r < 0.0f) r = 0.0f;
+    if (r >= cs) r = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, cs) - 1u);
+    int32_t cc = (c + k) % n;
+    if (cc < 0) cc += n;
+    *c_out = cc;
+    *r_out = r;
+    return ok;
+}
+
+__device__ inline void cell_coords(const CaseDev& C, uint32_t cell, int32_t c[3])
+{
+    uint32_t nx = static_cast<uint32_t>(C.nc[0]);
+    uint32_t ny = static_cast<uint32_t>(C.nc[1]);
+    c[0] = static_cast<int32_t>(cell % nx);
+    uint32_t r = cell / nx;
+    c[1] = static_cast<int32_t>(r % ny);
+    c[2] = static_cast<int32_t>(r / ny);
+}
+
+__device__ inline void set_error(uint32_t* err, uint32_t bit) { atomicOr(err, bit); }
+
+}  // namespace nau

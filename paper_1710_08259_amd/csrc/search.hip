@@ -1,0 +1,431 @@
+// Neighbour search on gfx950: binning, cell keys, stable LSD radix sort,
+// cell start/end table, reorder, and the per-particle neighbour lists.
+//
+// The cell grid follows the paper's domain (Sec. 3.2.1): cuboid cells no
+// smaller than the influence radius, so every neighbour of a particle lies in
+// the 3^dim block of cells around its own.  Keys are linear cell indices with
+// x fastest, offset by the case's first key, so one global sort orders every
+// case of a batch at once and a row of cells along x is contiguous in sorted
+// order.
+#include "internal.h"
+
+namespace nau {
+
+// ----------------------------------------------------------------------------
+// binning: absolute FP32 positions -> (cell, offset), id
+// ----------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBlock)
+k_bin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, const float* __restrict__ px,
+      const float* __restrict__ py, const float* __restrict__ pz, StateDev st, uint32_t* err)
+{
+#pragma clang fp contract(off)
+    const Item it = items[blockIdx.x];
+    if (threadIdx.x >= it.count) return;
+    const CaseDev& C = cases[it.case_id];
+    const uint32_t i = it.first + threadIdx.x;
+    const float* pos[3] = {px, py, pz};
+    int32_t c[3] = {0, 0, 0};
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+        if (k >= C.dim) break;
+        float x = pos[k][i];
+        if (!isfinite(x)) {
+            set_error(err, kErrNonFinite);
+            x = C.origin[k];
+        }
+        float t = x - C.origin[k];
+        float r;
+        ok &= split_offset(t, C.cs[k], C.inv_cs[k], C.nc[k], 0, &c[k], &r);
+        st.off[k][i] = r;
+    }
+    if (!ok) set_error(err, kErrOutOfDomain);
+    st.cell[i] = static_cast<uint32_t>(c[0]) +
+                 static_cast<uint32_t>(C.nc[0]) * (static_cast<uint32_t>(c[1]) +
+                                                   static_cast<uint32_t>(C.nc[1]) * static_cast<uint32_t>(c[2]));
+    st.id[i] = i - C.offset;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_unbin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, StateDev st, float* px,
+        float* py, float* pz)
+{
+#pragma clang fp contract(off)
+    const Item it = items[blockIdx.x];
+    if (threadIdx.x >= it.count) return;
+    const CaseDev& C = cases[it.case_id];
+    const uint32_t i = it.first + threadIdx.x;
+    int32_t c[3];
+    cell_coords(C, st.cell[i], c);
+    float* pos[3] = {px, py, pz};
+    for (int k = 0; k < 3; ++k) {
+        if (k >= C.dim) break;
+        float corner = C.origin[k] + static_cast<float>(c[k]) * C.cs[k];
+        pos[k][i] = corner + st.off[k][i];
+    }
+}
+
+hipError_t launch_bin(const Plan& P, void* ws, const float* const pos[3], StateDev st, hipStream_t s)
+{
+    if (P.n_items == 0) return hipSuccess;
+    k_bin<<<P.n_items, kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), pos[0],
+                                       pos[1], pos[2], st, at<uint32_t>(ws, P.L.err));
+    return hipGetLastError();
+}
+
+hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3], hipStream_t s)
+{
+    if (P.n_items == 0) return hipSuccess;
+    k_unbin<<<P.n_items, kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), st,
+                                         pos[0], pos[1], pos[2]);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// keys
+// ----------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBlock)
+k_make_keys(const CaseDev* __restrict__ cases, const Item* __restrict__ items,
+            const uint32_t* __restrict__ cell, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    const Item it = items[blockIdx.x];
+    if (threadIdx.x >= it.count) return;
+    const uint32_t i = it.first + threadIdx.x;
+    uint32_t c = cell[i];
+    const CaseDev& C = cases[it.case_id];
+    // a corrupt cell index would index outside the cell table: clamp it
+    if (c >= C.n_cells) c = C.n_cells - 1;
+    keys[i] = C.cell_base + c;
+    vals[i] = i;
+}
+
+// ----------------------------------------------------------------------------
+// stable LSD radix sort of (key, value) pairs
+// ----------------------------------------------------------------------------
+// Per pass (digit of `bits` <= 8 bits at `shift`):
+//   1. k_rs_hist:    per tile of kTile keys, digit histogram -> hist[d][tile]
+//   2. k_rs_scan:    per digit, exclusive scan over tiles; digit totals
+//   3. k_rs_scatter: per tile, in input order, each key's rank among equal
+//                    digits (wave ballots for lanes of one wave, LDS counters
+//                    across waves and iterations) -> stable scatter.
+
+constexpr int kBins = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kBlock * kItems;
+
+__device__ inline uint32_t wave_lane() { return __lane_id(); }
+
+// Inclusive scan across a wave64 with shuffles.
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v)
+{
+    const uint32_t lane = wave_lane();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, kWave);
+        if (lane >= static_cast<uint32_t>(d)) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan over the 256 threads of a block; returns the block total in
+// *total.  `tmp` must hold kBlock / kWave words.  Contains barriers.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t* total)
+{
+    const uint32_t lane = wave_lane();
+    const uint32_t wave = threadIdx.x / kWave;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == kWave - 1) tmp[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        uint32_t t = tmp[w];
+        if (static_cast<uint32_t>(w) < wave) before += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_rs_hist(const uint32_t* __restrict__ keys, uint32_t n, int shift, uint32_t mask,
+          uint32_t* __restrict__ hist, uint32_t n_tiles)
+{
+    __shared__ uint32_t h[kBins];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kTile;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        uint32_t idx = base + k * kBlock + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_rs_scan(uint32_t* __restrict__ hist, uint32_t n_tiles, uint32_t* __restrict__ totals)
+{
+    __shared__ uint32_t tmp[kBlock / kWave];
+    uint32_t* row = hist + static_cast<size_t>(blockIdx.x) * n_tiles;
+    uint32_t running = 0;
+    constexpr int kPer = 4;
+    for (uint32_t base = 0; base < n_tiles; base += kBlock * kPer) {
+        uint32_t v[kPer];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            uint32_t idx = base + threadIdx.x * kPer + k;
+            v[k] = idx < n_tiles ? row[idx] : 0u;
+            sum += v[k];
+        }
+        uint32_t total;
+        uint32_t ex = block_exclusive_scan(sum, tmp, &total);
+        uint32_t acc = running + ex;
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            uint32_t idx = base + threadIdx.x * kPer + k;
+            if (idx < n_tiles) row[idx] = acc;
+            acc += v[k];
+        }
+        running += total;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = running;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_rs_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t n,
+             int shift, uint32_t mask, int bits, const uint32_t* __restrict__ hist,
+             const uint32_t* __restrict__ totals, uint32_t n_tiles, uint32_t* __restrict__ keys_out,
+             uint32_t* __restrict__ vals_out)
+{
+    __shared__ uint32_t digit_base[kBins];
+    __shared__ uint32_t wave_cnt[kBlock / kWave][kBins];
+    __shared__ uint32_t tmp[kBlock / kWave];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = wave_lane();
+    const uint32_t wave = tid / kWave;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+
+    // global start of each digit for this tile
+    uint32_t total;
+    uint32_t ex = block_exclusive_scan(totals[tid], tmp, &total);
+    digit_base[tid] = ex + hist[tid * n_tiles + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) wave_cnt[w][tid] = 0;
+    __syncthreads();
+
+    const uint32_t base = blockIdx.x * kTile;
+    for (int k = 0; k < kItems; ++k) {
+        const uint32_t idx = base + k * kBlock + tid;
+        const bool valid = idx < n;
+        const uint32_t key = valid ? keys_in[idx] : 0u;
+        const uint32_t val = valid ? vals_in[idx] : 0u;
+        const uint32_t d = (key >> shift) & mask;
+        // lanes of this wave holding the same digit
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < bits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0) wave_cnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = digit_base[d] + rank;
+            for (uint32_t w = 0; w < wave; ++w) pos += wave_cnt[w][d];
+            if (pos < n) {  // always true for a consistent histogram; guards memory
+                keys_out[pos] = key;
+                vals_out[pos] = val;
+            }
+        }
+        __syncthreads();
+        // advance each digit's base past this iteration's keys
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            add += wave_cnt[w][tid];
+            wave_cnt[w][tid] = 0;
+        }
+        digit_base[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// cell table, reorder
+// ----------------------------------------------------------------------------
+
+__global__ void k_fill_u32(uint32_t* __restrict__ a, uint32_t n, uint32_t v)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_cell_ranges(const uint32_t* __restrict__ keys, uint32_t n, uint32_t* __restrict__ start,
+              uint32_t* __restrict__ end)
+{
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t k = keys[p];
+    if (p == 0 || keys[p - 1] != k) start[k] = p;
+    if (p == n - 1 || keys[p + 1] != k) end[k] = p + 1;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_reorder(const uint32_t* __restrict__ perm, uint32_t n, int dim, StateDev in, StateDev out)
+{
+    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    uint32_t q = perm[p];
+    if (q >= n) q = p;  // never for a permutation; guards memory
+    out.cell[p] = in.cell[q];
+    out.id[p] = in.id[q];
+    for (int k = 0; k < 3; ++k) {
+        if (k >= dim) break;
+        out.off[k][p] = in.off[k][q];
+        out.vel[k][p] = in.vel[k][q];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// neighbour lists
+// ----------------------------------------------------------------------------
+// One lane per sorted particle.  For each of the 3^dim cells around the
+// particle's cell (x fastest, offsets -1..1), the candidates are that cell's
+// contiguous sorted range; each is tested with the FP32 predicate and, if
+// accepted, appended to the particle's column of the list.
+
+__global__ void __launch_bounds__(kBlock)
+k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, StateDev st,
+        const uint32_t* __restrict__ cell_start, const uint32_t* __restrict__ cell_end,
+        uint32_t* __restrict__ nbr, uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total,
+        uint32_t* err)
+{
+#pragma clang fp contract(off)
+    const Item it = items[blockIdx.x];
+    if (threadIdx.x >= it.count) return;
+    const CaseDev& C = cases[it.case_id];
+    const uint32_t p = it.first + threadIdx.x;
+    const int dim = C.dim;
+    int32_t c[3];
+    uint32_t own = st.cell[p];
+    if (own >= C.n_cells) {  // a corrupt state: keep every table access inside the case
+        own = C.n_cells - 1;
+        set_error(err, kErrOutOfDomain);
+    }
+    cell_coords(C, own, c);
+    float oi[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < 3; ++k)
+        if (k < dim) oi[k] = st.off[k][p];
+    const float R2 = C.R2;
+    uint32_t cnt = 0;
+    const int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+        int32_t cz = c[2] + dz;
+        if (dim == 3) {
+            if (C.periodic[2]) cz = cz < 0 ? cz + C.nc[2] : (cz >= C.nc[2] ? cz - C.nc[2] : cz);
+            else if (cz < 0 || cz >= C.nc[2]) continue;
+        }
+        for (int dy = -1; dy <= 1; ++dy) {
+            int32_t cy = c[1] + dy;
+            if (C.periodic[1]) cy = cy < 0 ? cy + C.nc[1] : (cy >= C.nc[1] ? cy - C.nc[1] : cy);
+            else if (cy < 0 || cy >= C.nc[1]) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                int32_t cx = c[0] + dx;
+                if (C.periodic[0]) cx = cx < 0 ? cx + C.nc[0] : (cx >= C.nc[0] ? cx - C.nc[0] : cx);
+                else if (cx < 0 || cx >= C.nc[0]) continue;
+                const uint32_t key = C.cell_base + static_cast<uint32_t>(cx) +
+                                     static_cast<uint32_t>(C.nc[0]) *
+                                         (static_cast<uint32_t>(cy) + static_cast<uint32_t>(C.nc[1]) * static_cast<uint32_t>(cz));
+                const uint32_t s = cell_start[key];
+                if (s == NAUTICLE_EMPTY) continue;
+                const uint32_t e = cell_end[key] < n_total ? cell_end[key] : n_total;
+                const float shx = static_cast<float>(dx) * C.cs[0];
+                const float shy = static_cast<float>(dy) * C.cs[1];
+                const float shz = dim == 3 ? static_cast<float>(dz) * C.cs[2] : 0.0f;
+                const uint32_t code = (static_cast<uint32_t>(dx + 1) << NAUTICLE_NBR_INDEX_BITS) |
+                                      (static_cast<uint32_t>(dy + 1) << (NAUTICLE_NBR_INDEX_BITS + 2)) |
+                                      (static_cast<uint32_t>(dz + 1) << (NAUTICLE_NBR_INDEX_BITS + 4));
+                for (uint32_t q = s; q < e; ++q) {
+                    if (q == p) continue;
+                    const float ddx = (st.off[0][q] + shx) - oi[0];
+                    const float ddy = (st.off[1][q] + shy) - oi[1];
+                    float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
+                    if (dim == 3) {
+                        const float ddz = (st.off[2][q] + shz) - oi[2];
+                        r2 = __builtin_fmaf(ddz, ddz, r2);
+                    }
+                    if (r2 < R2) {
+                        if (cnt < max_nbr) nbr[static_cast<size_t>(cnt) * n_total + p] = q | code;
+                        ++cnt;
+                    }
+                }
+            }
+        }
+    }
+    nbr_count[p] = cnt;
+    if (cnt > max_nbr) set_error(err, kErrOverflow);
+}
+
+// ----------------------------------------------------------------------------
+// build_cells
+// ----------------------------------------------------------------------------
+
+hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sorted,
+                              const nauticle_cells& cells, hipStream_t s)
+{
+    const uint32_t n = P.n_total;
+    const uint32_t nc = P.n_cells_total;
+    const CaseDev* cases = at<CaseDev>(ws, P.L.cases);
+    const Item* items = at<Item>(ws, P.L.items);
+    uint32_t* err = at<uint32_t>(ws, P.L.err);
+    const int fill_blocks = static_cast<int>((nc + kBlock - 1) / kBlock);
+    if (nc > 0) {
+        k_fill_u32<<<fill_blocks, kBlock, 0, s>>>(cells.cell_start, nc, NAUTICLE_EMPTY);
+        k_fill_u32<<<fill_blocks, kBlock, 0, s>>>(cells.cell_end, nc, NAUTICLE_EMPTY);
+    }
+    if (n == 0) return hipGetLastError();
+
+    // radix sort: passes of <= 8 bits, balanced
+    const int bits = P.key_bits;
+    const int passes = (bits + 7) / 8;
+    const int per = (bits + passes - 1) / passes;
+    // ping-pong so that the last pass lands in cells.key / cells.perm
+    uint32_t* ka = at<uint32_t>(ws, P.L.sort_keys);
+    uint32_t* va = at<uint32_t>(ws, P.L.sort_vals);
+    uint32_t* kb = cells.key;
+    uint32_t* vb = cells.perm;
+    if (passes % 2 == 0) {
+        uint32_t* t = ka; ka = kb; kb = t;
+        t = va; va = vb; vb = t;
+    }
+    k_make_keys<<<P.n_items, kBlock, 0, s>>>(cases, items, in.cell, ka, va);
+    const uint32_t n_tiles = (n + kTile - 1) / kTile;
+    uint32_t* hist = at<uint32_t>(ws, P.L.sort_hist);
+    uint32_t* totals = at<uint32_t>(ws, P.L.sort_totals);
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = pass * per;
+        const int b = (bits - shift) < per ? (bits - shift) : per;
+        const uint32_t mask = (1u << b) - 1u;
+        k_rs_hist<<<n_tiles, kBlock, 0, s>>>(ka, n, shift, mask, hist, n_tiles);
+        k_rs_scan<<<kBins, kBlock, 0, s>>>(hist, n_tiles, totals);
+        k_rs_scatter<<<n_tiles, kBlock, 0, s>>>(ka, va, n, shift, mask, b, hist, totals, n_tiles, kb, vb);
+        uint32_t* t = ka; ka = kb; kb = t;
+        t = va; va = vb; vb = t;
+    }
+    // now ka == cells.key, va == cells.perm
+    const int nb = static_cast<int>((n + kBlock - 1) / kBlock);
+    k_cell_ranges<<<nb, kBlock, 0, s>>>(cells.key, n, cells.cell_start, cells.cell_end);
+    k_reorder<<<nb, kBlock, 0, s>>>(cells.perm, n, P.dim_max, in, sorted);
+    k_nlist<<<P.n_items, kBlock, 0, s>>>(cases, items, sorted, cells.cell_start, cells.cell_end, cells.nbr,
+                                        cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), n, err);
+    return hipGetLastError();
+}
+
+}  // namespace nau

@@ -1,0 +1,388 @@
+"""ctypes binding of ``libnauticle.so`` (include/nauticle.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+kernels of the library.  PyTorch provides device memory (tensors) and the
+stream (``torch.cuda.current_stream().cuda_stream``).  There is no CPU
+fallback: if the library is missing, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnauticle.so")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_DOMAIN = -2
+ERR_NONFINITE = -3
+ERR_OUT_OF_DOMAIN = -4
+ERR_WORKSPACE = -5
+ERR_HIP = -6
+ERR_NEIGHBOUR_OVERFLOW = -7
+PERIODIC = 0
+CUTOFF = 1
+EMPTY = 0xFFFFFFFF
+NBR_INDEX_BITS = 26
+
+ENTRY_POINTS = (
+    "nauticle_cells_total", "nauticle_workspace_bytes", "nauticle_prepare", "nauticle_bin",
+    "nauticle_unbin", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_forces",
+    "nauticle_step", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
+    "nauticle_last_error",
+)
+
+
+class NauticleError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: status {status}: {message}")
+        self.status = status
+
+
+# ----------------------------------------------------------------------------
+# C structures (mirror include/nauticle.h)
+# ----------------------------------------------------------------------------
+
+class CDomain(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("ncell", ctypes.c_int32 * 3), ("boundary", ctypes.c_int32 * 3),
+                ("origin", ctypes.c_double * 3), ("cell_size", ctypes.c_double * 3)]
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("mass", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("c0", ctypes.c_double), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
+                ("dt", ctypes.c_double), ("g", ctypes.c_double * 3)]
+
+
+class CCase(ctypes.Structure):
+    _fields_ = [("dom", CDomain), ("prm", CParams), ("offset", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("n_fixed", ctypes.c_int64)]
+
+
+class CState(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_void_p), ("off", ctypes.c_void_p * 3), ("vel", ctypes.c_void_p * 3),
+                ("id", ctypes.c_void_p)]
+
+
+class CCells(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("perm", ctypes.c_void_p), ("cell_start", ctypes.c_void_p),
+                ("cell_end", ctypes.c_void_p), ("nbr", ctypes.c_void_p), ("nbr_count", ctypes.c_void_p),
+                ("max_nbr", ctypes.c_int32)]
+
+
+class CFields(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_void_p), ("p", ctypes.c_void_p), ("s", ctypes.c_void_p),
+                ("inv_rho", ctypes.c_void_p), ("acc", ctypes.c_void_p * 3)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1710_08259_amd/build.py "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i32, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int
+    ptr3 = ctypes.c_void_p * 3
+    L.nauticle_cells_total.restype = ctypes.c_int64
+    L.nauticle_cells_total.argtypes = [P(CCase), i32]
+    L.nauticle_workspace_bytes.restype = st
+    L.nauticle_workspace_bytes.argtypes = [P(CCase), i32, P(ctypes.c_size_t)]
+    L.nauticle_prepare.restype = st
+    L.nauticle_prepare.argtypes = [P(CCase), i32, vp, ctypes.c_size_t, vp]
+    L.nauticle_bin.restype = st
+    L.nauticle_bin.argtypes = [P(CCase), i32, P(ptr3), P(CState), vp, ctypes.c_size_t, vp]
+    L.nauticle_unbin.restype = st
+    L.nauticle_unbin.argtypes = [P(CCase), i32, P(CState), P(ptr3), vp, ctypes.c_size_t, vp]
+    L.nauticle_build_cells.restype = st
+    L.nauticle_build_cells.argtypes = [P(CCase), i32, P(CState), P(CState), P(CCells), vp, ctypes.c_size_t, vp]
+    L.nauticle_sph_density.restype = st
+    L.nauticle_sph_density.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CFields), vp, ctypes.c_size_t, vp]
+    L.nauticle_sph_forces.restype = st
+    L.nauticle_sph_forces.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CFields), P(CState), vp,
+                                      ctypes.c_size_t, vp]
+    L.nauticle_step.restype = st
+    L.nauticle_step.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), vp, ctypes.c_size_t, vp]
+    L.nauticle_sph_adjoint.restype = st
+    L.nauticle_sph_adjoint.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CFields), P(ptr3), P(ptr3),
+                                       P(ptr3), P(ptr3), vp, vp, vp, ctypes.c_size_t, vp]
+    L.nauticle_position_loss.restype = st
+    L.nauticle_position_loss.argtypes = [P(CCase), i32, P(CState), P(CState), vp, P(ptr3), vp,
+                                         ctypes.c_size_t, vp]
+    L.nauticle_check.restype = st
+    L.nauticle_check.argtypes = [vp, ctypes.c_size_t, vp]
+    L.nauticle_last_error.restype = ctypes.c_char_p
+    L.nauticle_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        msg = lib().nauticle_last_error().decode(errors="replace")
+        raise NauticleError(status, where, msg)
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr3(ts: Sequence[Optional[torch.Tensor]]):
+    arr = (ctypes.c_void_p * 3)()
+    for k in range(3):
+        arr[k] = ts[k].data_ptr() if k < len(ts) and ts[k] is not None else None
+    return arr
+
+
+# ----------------------------------------------------------------------------
+# Python-side containers
+# ----------------------------------------------------------------------------
+
+@dataclass
+class State:
+    """Particle state in the cell-relative layout (device tensors)."""
+
+    cell: torch.Tensor          # int32 (uint32 in C)
+    off: list                   # dim x float32
+    vel: list                   # dim x float32
+    id: torch.Tensor            # int32
+
+    def c(self) -> CState:
+        s = CState()
+        s.cell = self.cell.data_ptr()
+        s.id = self.id.data_ptr()
+        for k in range(3):
+            s.off[k] = self.off[k].data_ptr() if k < len(self.off) else None
+            s.vel[k] = self.vel[k].data_ptr() if k < len(self.vel) else None
+        return s
+
+    def clone(self) -> "State":
+        return State(self.cell.clone(), [t.clone() for t in self.off], [t.clone() for t in self.vel],
+                     self.id.clone())
+
+    def copy_(self, other: "State") -> "State":
+        self.cell.copy_(other.cell)
+        self.id.copy_(other.id)
+        for a, b in zip(self.off, other.off):
+            a.copy_(b)
+        for a, b in zip(self.vel, other.vel):
+            a.copy_(b)
+        return self
+
+
+@dataclass
+class Cells:
+    key: torch.Tensor
+    perm: torch.Tensor
+    cell_start: torch.Tensor
+    cell_end: torch.Tensor
+    nbr: torch.Tensor           # (max_nbr, N) int32
+    nbr_count: torch.Tensor
+    max_nbr: int
+
+    def c(self) -> CCells:
+        c = CCells()
+        c.key, c.perm = self.key.data_ptr(), self.perm.data_ptr()
+        c.cell_start, c.cell_end = self.cell_start.data_ptr(), self.cell_end.data_ptr()
+        c.nbr, c.nbr_count = self.nbr.data_ptr(), self.nbr_count.data_ptr()
+        c.max_nbr = self.max_nbr
+        return c
+
+
+@dataclass
+class Fields:
+    rho: torch.Tensor
+    p: torch.Tensor
+    s: torch.Tensor
+    inv_rho: torch.Tensor
+    acc: list
+
+    def c(self) -> CFields:
+        f = CFields()
+        f.rho, f.p, f.s, f.inv_rho = (self.rho.data_ptr(), self.p.data_ptr(), self.s.data_ptr(),
+                                      self.inv_rho.data_ptr())
+        for k in range(3):
+            f.acc[k] = self.acc[k].data_ptr() if k < len(self.acc) else None
+        return f
+
+
+def case_table(cases) -> "ctypes.Array":
+    """Case objects with the attributes of workloads.Case -> C case array."""
+    arr = (CCase * len(cases))()
+    offset = 0
+    for b, c in enumerate(cases):
+        d = arr[b].dom
+        d.dim = c.dim
+        for k in range(3):
+            d.ncell[k] = int(c.ncell[k])
+            d.boundary[k] = int(c.boundary[k])
+            d.origin[k] = float(c.origin[k])
+            d.cell_size[k] = float(c.cell_size[k])
+        p = arr[b].prm
+        p.h, p.mass, p.rho0, p.c0 = c.h, c.mass, c.rho0, c.c0
+        p.gamma, p.nu, p.dt = c.gamma, c.nu, c.dt
+        for k in range(3):
+            p.g[k] = float(c.g[k])
+        arr[b].offset = offset
+        arr[b].n = c.n
+        arr[b].n_fixed = c.n_fixed
+        offset += c.n
+    return arr
+
+
+def default_max_nbr(dim: int) -> int:
+    return 64 if dim == 2 else 128
+
+
+class Problem:
+    """A prepared set of independent cases on one device: owns the workspace,
+    the neighbour structure and the field arrays."""
+
+    def __init__(self, cases, device="cuda:0", max_nbr: Optional[int] = None):
+        self.cases = list(cases)
+        self.device = torch.device(device)
+        self.dim = self.cases[0].dim
+        self.table = case_table(self.cases)
+        self.n_cases = len(self.cases)
+        self.n = int(sum(c.n for c in self.cases))
+        self.n_cells = int(lib().nauticle_cells_total(self.table, self.n_cases))
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().nauticle_workspace_bytes(self.table, self.n_cases, ctypes.byref(nbytes)),
+               "nauticle_workspace_bytes")
+        self.ws_bytes = int(nbytes.value)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        _check(lib().nauticle_prepare(self.table, self.n_cases, _p(self.ws), self.ws_bytes, self.stream()),
+               "nauticle_prepare")
+        self.max_nbr = int(max_nbr or default_max_nbr(self.dim))
+        i32 = dict(dtype=torch.int32, device=self.device)
+        f32 = dict(dtype=torch.float32, device=self.device)
+        N = max(self.n, 1)
+        self.cells = Cells(torch.empty(N, **i32), torch.empty(N, **i32),
+                           torch.empty(max(self.n_cells, 1), **i32), torch.empty(max(self.n_cells, 1), **i32),
+                           torch.empty((self.max_nbr, N), **i32), torch.empty(N, **i32), self.max_nbr)
+        self.fields = Fields(torch.empty(N, **f32), torch.empty(N, **f32), torch.empty(N, **f32),
+                             torch.empty(N, **f32), [torch.empty(N, **f32) for _ in range(self.dim)])
+        self.sorted = self.new_state()
+
+    # -- helpers ----------------------------------------------------------------
+    def stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def new_state(self) -> State:
+        N = max(self.n, 1)
+        i32 = dict(dtype=torch.int32, device=self.device)
+        f32 = dict(dtype=torch.float32, device=self.device)
+        return State(torch.zeros(N, **i32), [torch.zeros(N, **f32) for _ in range(self.dim)],
+                     [torch.zeros(N, **f32) for _ in range(self.dim)], torch.zeros(N, **i32))
+
+    def _ws(self):
+        return _p(self.ws), self.ws_bytes, self.stream()
+
+    # -- entry points -------------------------------------------------------------
+    def bin(self, pos: Sequence[torch.Tensor], vel: Optional[Sequence[torch.Tensor]] = None) -> State:
+        """Absolute FP32 positions (per-axis device tensors) -> new state."""
+        st = self.new_state()
+        cs = st.c()
+        _check(lib().nauticle_bin(self.table, self.n_cases, ctypes.byref(_ptr3(pos)), ctypes.byref(cs),
+                                  *self._ws()), "nauticle_bin")
+        if vel is not None:
+            for k in range(self.dim):
+                st.vel[k].copy_(vel[k])
+        return st
+
+    def state_from_cases(self) -> State:
+        """Bins the cases' own positions and velocities (walls get v = 0)."""
+        pos = np.concatenate([c.pos for c in self.cases], axis=0)
+        vel = np.concatenate([np.where(c.fixed_mask()[:, None], 0.0, c.vel).astype(np.float32)
+                              for c in self.cases], axis=0)
+        pos_t = [torch.from_numpy(np.ascontiguousarray(pos[:, k])).to(self.device) for k in range(self.dim)]
+        vel_t = [torch.from_numpy(np.ascontiguousarray(vel[:, k])).to(self.device) for k in range(self.dim)]
+        return self.bin(pos_t, vel_t)
+
+    def unbin(self, st: State) -> list:
+        pos = [torch.empty(max(self.n, 1), dtype=torch.float32, device=self.device) for _ in range(self.dim)]
+        _check(lib().nauticle_unbin(self.table, self.n_cases, ctypes.byref(st.c()), ctypes.byref(_ptr3(pos)),
+                                    *self._ws()), "nauticle_unbin")
+        return pos
+
+    def build_cells(self, st: State, sorted_: Optional[State] = None, cells: Optional[Cells] = None) -> State:
+        out = self.sorted if sorted_ is None else sorted_
+        c = self.cells if cells is None else cells
+        _check(lib().nauticle_build_cells(self.table, self.n_cases, ctypes.byref(st.c()), ctypes.byref(out.c()),
+                                          ctypes.byref(c.c()), *self._ws()), "nauticle_build_cells")
+        return out
+
+    def density(self, sorted_: Optional[State] = None, cells: Optional[Cells] = None,
+                fields: Optional[Fields] = None):
+        s = self.sorted if sorted_ is None else sorted_
+        c = self.cells if cells is None else cells
+        f = self.fields if fields is None else fields
+        _check(lib().nauticle_sph_density(self.table, self.n_cases, ctypes.byref(s.c()), ctypes.byref(c.c()),
+                                          ctypes.byref(f.c()), *self._ws()), "nauticle_sph_density")
+        return f
+
+    def forces(self, sorted_: Optional[State] = None, next_: Optional[State] = None,
+               cells: Optional[Cells] = None, fields: Optional[Fields] = None):
+        s = self.sorted if sorted_ is None else sorted_
+        c = self.cells if cells is None else cells
+        f = self.fields if fields is None else fields
+        nxt = ctypes.byref(next_.c()) if next_ is not None else None
+        _check(lib().nauticle_sph_forces(self.table, self.n_cases, ctypes.byref(s.c()), ctypes.byref(c.c()),
+                                         ctypes.byref(f.c()), nxt, *self._ws()), "nauticle_sph_forces")
+        return f
+
+    def step(self, st: State, n_steps: int = 1) -> State:
+        _check(lib().nauticle_step(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
+                                   ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()), *self._ws()),
+               "nauticle_step")
+        return st
+
+    def adjoint(self, sorted_: State, cells: Cells, fields: Fields, lam_x_next, lam_v_next, lam_x, lam_v,
+                dnu: torch.Tensor, dc0: torch.Tensor):
+        _check(lib().nauticle_sph_adjoint(self.table, self.n_cases, ctypes.byref(sorted_.c()),
+                                          ctypes.byref(cells.c()), ctypes.byref(fields.c()),
+                                          ctypes.byref(_ptr3(lam_x_next)), ctypes.byref(_ptr3(lam_v_next)),
+                                          ctypes.byref(_ptr3(lam_x)), ctypes.byref(_ptr3(lam_v)),
+                                          _p(dnu), _p(dc0), *self._ws()), "nauticle_sph_adjoint")
+
+    def position_loss(self, a: State, b: State, grad: bool = True):
+        loss = torch.zeros(self.n_cases, dtype=torch.float64, device=self.device)
+        g = [torch.empty(max(self.n, 1), dtype=torch.float32, device=self.device) for _ in range(self.dim)] \
+            if grad else None
+        _check(lib().nauticle_position_loss(self.table, self.n_cases, ctypes.byref(a.c()), ctypes.byref(b.c()),
+                                            _p(loss), ctypes.byref(_ptr3(g)) if g else None, *self._ws()),
+               "nauticle_position_loss")
+        return loss, g
+
+    def check(self):
+        """Waits for the stream and raises on any condition the kernels flagged."""
+        _check(lib().nauticle_check(*self._ws()), "nauticle_check")
+
+    def new_cells(self) -> Cells:
+        i32 = dict(dtype=torch.int32, device=self.device)
+        N = max(self.n, 1)
+        return Cells(torch.empty(N, **i32), torch.empty(N, **i32), torch.empty(max(self.n_cells, 1), **i32),
+                     torch.empty(max(self.n_cells, 1), **i32), torch.empty((self.max_nbr, N), **i32),
+                     torch.empty(N, **i32), self.max_nbr)
+
+    def new_fields(self) -> Fields:
+        f32 = dict(dtype=torch.float32, device=self.device)
+        N = max(self.n, 1)
+        return Fields(torch.empty(N, **f32), torch.empty(N, **f32), torch.empty(N, **f32), torch.empty(N, **f32),
+                      [torch.empty(N, **f32) for _ in range(self.dim)])
+
+
+def to_numpy_u32(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint32)

@@ -1,0 +1,107 @@
+"""The C-ABI library loads, exports every entry point that include/nauticle.h
+declares, and validates case tables on the host (no GPU needed: these calls
+return before any HIP call)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1710_08259_amd import workloads as WL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nauticle.h")
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_1710_08259_amd import nauticle as N
+
+    if not os.path.exists(N.LIB_PATH):
+        from paper_1710_08259_amd import build
+
+        build.build()
+    N.lib()
+    return N
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nauticle_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    syms = declared_symbols()
+    for name in ("nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_forces", "nauticle_step",
+                 "nauticle_sph_adjoint"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol(N):
+    lib = ctypes.CDLL(N.LIB_PATH)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert set(declared_symbols()) == set(N.ENTRY_POINTS)
+
+
+def _ws_bytes(N, cases):
+    table = N.case_table(cases)
+    out = ctypes.c_size_t(0)
+    st = N.lib().nauticle_workspace_bytes(table, len(cases), ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_bytes_for_valid_cases(N):
+    st, nbytes = _ws_bytes(N, [WL.periodic_2d_4096()])
+    assert st == N.OK and nbytes > 4096 * 4 * 8
+    st, nbytes2 = _ws_bytes(N, WL.batched_2d(n_cases=5, seed=2, max_side_exp=6))
+    assert st == N.OK and nbytes2 > 0
+    assert N.lib().nauticle_cells_total(N.case_table([WL.periodic_2d_4096()]), 1) == 24 * 24
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda c: WL.scaled(c, cell_size=(0.02, 0.02, 1.0)), -2),                     # cell below 2h
+    (lambda c: WL.scaled(c, ncell=(2, 24, 1)), -2),                                 # periodic axis < 3 cells
+    (lambda c: WL.scaled(c, ncell=(24, 24, 2)), -2),                                # unused axis not 1
+    (lambda c: WL.scaled(c, h=-1.0), -1),                                           # bad parameter
+    (lambda c: WL.scaled(c, nu=float("nan")), -1),
+    (lambda c: WL.scaled(c, dim=4), -2),
+    (lambda c: WL.scaled(c, boundary=(7, 0, 0)), -2),
+])
+def test_invalid_cases_are_rejected_on_the_host(N, mutate, status):
+    st, _ = _ws_bytes(N, [mutate(WL.periodic_2d_4096())])
+    assert st == status
+    assert len(N.lib().nauticle_last_error()) > 0
+
+
+def test_mixed_dimensions_and_bad_offsets_are_rejected(N):
+    a = WL.periodic_2d_4096()
+    b = WL.lattice_case(3, (8, 8, 8), 0.01, 1.2, 0.0, 0.0, seed=0)
+    st, _ = _ws_bytes(N, [a, b])
+    assert st == N.ERR_DOMAIN
+    table = N.case_table([a, a])
+    table[1].offset = 5
+    out = ctypes.c_size_t(0)
+    assert N.lib().nauticle_workspace_bytes(table, 2, ctypes.byref(out)) == N.ERR_INVALID_ARG
+
+
+def test_unprepared_workspace_is_rejected_without_touching_the_device(N):
+    table = N.case_table([WL.periodic_2d_4096()])
+    assert N.lib().nauticle_prepare(table, 1, None, 0, None) == N.ERR_WORKSPACE
+    assert N.lib().nauticle_check(None, 0, None) == N.ERR_WORKSPACE
+    fake = ctypes.c_void_p(0x1000)
+    st = N.lib().nauticle_step(table, 1, None, 1, None, None, fake, 1 << 20, None)
+    assert st == N.ERR_WORKSPACE
+
+
+def test_the_oracle_is_not_reachable_from_the_package():
+    """The product path never imports, loads or calls the oracle."""
+    pat = re.compile(r"^\s*(from\s+oracle|import\s+oracle)|liboracle|\bor_[a-z_0-9]+\s*\(", re.M)
+    pkg = os.path.join(ROOT, "paper_1710_08259_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not pat.search(text), f

@@ -1,0 +1,315 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Bit-exact: binning, keys, sorted permutation, cell start/end table, sorted
+state, neighbour counts and neighbour sets.  Floating point: density,
+pressure and accelerations within 1e-5 of their scale per step, positions
+within 5e-4 of the box length after 100 steps (the bar the FP32 path is held
+to; the derivation of these bounds is in the design notes)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1710_08259_amd import workloads as WL
+from tests.gpu_common import (case_absolute_from_state, decode_nbr, f32, nauticle, norms, stack, u32)
+from tests.oracle_helpers import domain_of, params_of, v64, x64
+
+pytestmark = pytest.mark.gpu
+
+TOL_STEP = 1e-5      # per-step relative tolerance (scale-normalised)
+TOL_ROLLOUT = 5e-4   # after 100 steps
+
+
+def small_cases():
+    return {
+        "periodic_2d_4096": WL.periodic_2d_4096(),
+        "periodic_3d_ragged": WL.lattice_case(3, (23, 19, 17), 0.01, 1.2, 0.05, 0.05, seed=31),
+        "dam_break_small": WL.dam_break_case(dx=0.02),
+        "clustered_3d": _clustered(),
+    }
+
+
+def _clustered():
+    base = WL.lattice_case(3, (16, 15, 14), 0.01, 1.2, 0.0, 0.05, seed=41)
+    rng = np.random.default_rng(41)
+    L = base.length()[:3]
+    centres = rng.uniform(0, 1, (6, 3)) * L
+    pts = centres[rng.integers(0, 6, base.n)] + rng.normal(0, 1.5 * base.h, (base.n, 3))
+    return WL.scaled(base, pos=np.mod(pts, L).astype(np.float32))
+
+
+CASES = small_cases()
+NAMES = list(CASES)
+
+
+def run_search(N, case, max_nbr=None):
+    prob = N.Problem([case], max_nbr=max_nbr or (128 if case.dim == 3 else 64))
+    st = prob.state_from_cases()
+    prob.build_cells(st)
+    torch.cuda.synchronize()
+    prob.check()
+    return prob, st
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_bin_is_bit_exact(name):
+    N = nauticle()
+    case = CASES[name]
+    prob = N.Problem([case])
+    pos = case.pos.copy()
+    # box faces, cell faces and points outside the box
+    L = case.length()
+    extra = []
+    for k in range(case.dim):
+        for v in (case.origin[k], case.origin[k] + L[k], case.origin[k] + 2 * case.cell_size[k],
+                  case.origin[k] - 1e-7, case.origin[k] + L[k] + 3.5 * case.cell_size[k]):
+            row = pos[0].astype(np.float64)
+            row[k] = v
+            extra.append(row)
+    pos[: len(extra)] = np.array(extra, np.float32)
+    pos_t = [torch.from_numpy(np.ascontiguousarray(pos[:, k])).cuda() for k in range(case.dim)]
+    st = prob.bin(pos_t)
+    torch.cuda.synchronize()
+    cell_ref, off_ref = O.bin_f32(domain_of(case), pos)
+    np.testing.assert_array_equal(u32(st.cell)[: case.n], cell_ref)
+    np.testing.assert_array_equal(stack(st.off, case.n).view(np.uint32), off_ref.view(np.uint32))
+    np.testing.assert_array_equal(u32(st.id)[: case.n], np.arange(case.n, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_build_cells_is_bit_exact(name):
+    N = nauticle()
+    case = CASES[name]
+    prob, st = run_search(N, case)
+    n = case.n
+    cell_in = u32(st.cell)[:n]
+    ks, perm, start, end = O.sort_keys(cell_in, case.n_cells)
+    np.testing.assert_array_equal(u32(prob.cells.key)[:n], ks)
+    np.testing.assert_array_equal(u32(prob.cells.perm)[:n], perm)
+    np.testing.assert_array_equal(u32(prob.cells.cell_start)[: case.n_cells], start)
+    np.testing.assert_array_equal(u32(prob.cells.cell_end)[: case.n_cells], end)
+    # reorder
+    off_in = stack(st.off, n)
+    np.testing.assert_array_equal(u32(prob.sorted.cell)[:n], cell_in[perm])
+    np.testing.assert_array_equal(stack(prob.sorted.off, n).view(np.uint32), off_in[perm].view(np.uint32))
+    np.testing.assert_array_equal(u32(prob.sorted.id)[:n], perm)
+    # neighbour counts and sets under the FP32 predicate
+    cnt_ref, lst_ref = O.neighbours_f32(domain_of(case), case.h, cell_in, off_in, max_nbr=prob.max_nbr)
+    cnt = u32(prob.cells.nbr_count)[:n]
+    np.testing.assert_array_equal(cnt, cnt_ref[perm])
+    nbr = u32(prob.cells.nbr)[:, :n]
+    j, delta = decode_nbr(nbr)
+    coords = np.stack([cell_in % case.ncell[0], (cell_in // case.ncell[0]) % case.ncell[1],
+                       cell_in // (case.ncell[0] * case.ncell[1])], axis=1).astype(np.int64)
+    for p in range(n):
+        k = cnt[p]
+        got = perm[j[:k, p]]
+        assert sorted(got.tolist()) == sorted(lst_ref[perm[p], :k].tolist()), p
+        # the stored cell offset is the folded difference of the two cells
+        dc = coords[got] - coords[perm[p]]
+        for a in range(case.dim):
+            na = case.ncell[a]
+            if case.boundary[a] == WL.PERIODIC:
+                dc[:, a] = (dc[:, a] + na // 2) % na - na // 2 if na > 2 else dc[:, a]
+        np.testing.assert_array_equal(dc[:, : case.dim], delta[:k, p, : case.dim])
+
+
+def _fields(N, case):
+    prob, st = run_search(N, case)
+    prob.density()
+    prob.forces()
+    torch.cuda.synchronize()
+    prob.check()
+    perm = u32(prob.cells.perm)[: case.n]
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(case.n, dtype=np.uint32)
+    out = dict(rho=f32(prob.fields.rho)[: case.n][inv], p=f32(prob.fields.p)[: case.n][inv],
+               a=stack(prob.fields.acc, case.n)[inv])
+    return prob, st, out
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_density_pressure_acceleration_match_oracle(name):
+    N = nauticle()
+    case = CASES[name]
+    prob, st, g = _fields(N, case)
+    dom, prm = domain_of(case), params_of(case)
+    x, v = x64(case), v64(case)
+    rho, p = O.density(dom, prm, x)
+    a = O.forces(dom, prm, x, v, rho, p, fixed=case.fixed_mask())
+    S = norms(case)
+    err_rho = np.abs(g["rho"] - rho).max() / S["rho"]
+    err_p = np.abs(g["p"] - p).max() / S["p"]
+    fluid = ~case.fixed_mask()
+    err_a = np.abs(g["a"][fluid] - a[fluid]).max() / S["a"]
+    print(f"{name}: err rho {err_rho:.2e} p {err_p:.2e} a {err_a:.2e}")
+    assert err_rho < TOL_STEP and err_p < TOL_STEP and err_a < TOL_STEP
+    assert np.all(g["a"][~fluid] == 0.0)
+
+
+def test_rollout_100_steps_2d_matches_oracle():
+    N = nauticle()
+    case = WL.periodic_2d_4096()
+    prob = N.Problem([case])
+    st = prob.state_from_cases()
+    prob.step(st, 100)
+    torch.cuda.synchronize()
+    prob.check()
+    n = case.n
+    ids = u32(st.id)[:n]
+    x_gpu = np.empty((n, 2))
+    v_gpu = np.empty((n, 2))
+    x_gpu[ids] = case_absolute_from_state(case, u32(st.cell)[:n], stack(st.off, n))
+    v_gpu[ids] = stack(st.vel, n)
+    dom, prm = domain_of(case), params_of(case)
+    x, v, _, _, _ = O.step(dom, prm, x64(case), v64(case), n_steps=100)
+    dx = O.min_image(dom, x_gpu - x)
+    err_x = np.abs(dx).max() / norms(case)["x"]
+    err_v = np.abs(v_gpu - v).max() / np.abs(v).max()
+    print(f"100 steps: err x {err_x:.2e} (of L), err v {err_v:.2e} (of max |v|)")
+    assert err_x < TOL_ROLLOUT and err_v < TOL_ROLLOUT
+
+
+def test_rollout_dam_break_small_matches_oracle():
+    N = nauticle()
+    case = WL.dam_break_case(dx=0.02)
+    prob = N.Problem([case])
+    st = prob.state_from_cases()
+    steps = 20
+    prob.step(st, steps)
+    torch.cuda.synchronize()
+    prob.check()
+    n = case.n
+    ids = u32(st.id)[:n]
+    x_gpu = np.empty((n, 3))
+    x_gpu[ids] = case_absolute_from_state(case, u32(st.cell)[:n], stack(st.off, n))
+    v_gpu = np.empty((n, 3))
+    v_gpu[ids] = stack(st.vel, n)
+    dom, prm = domain_of(case), params_of(case)
+    x, v, _, _, _ = O.step(dom, prm, x64(case), v64(case), fixed=case.fixed_mask(), n_steps=steps)
+    err_x = np.abs(x_gpu - x).max() / norms(case)["x"]
+    vscale = max(np.abs(v).max(), 1e-30)
+    err_v = np.abs(v_gpu - v).max() / vscale
+    print(f"dam break {steps} steps: err x {err_x:.2e}, err v {err_v:.2e}")
+    assert err_x < TOL_ROLLOUT and err_v < TOL_ROLLOUT
+    # walls never move
+    wall = case.fixed_mask()
+    np.testing.assert_array_equal(x_gpu[wall], x64(case)[wall] * 0 + x_gpu[wall])
+    assert np.abs(x_gpu[wall] - x64(case)[wall]).max() < 1e-6
+    assert np.all(v_gpu[wall] == 0.0)
+
+
+def test_steps_are_deterministic():
+    N = nauticle()
+    case = CASES["periodic_3d_ragged"]
+    outs = []
+    for _ in range(2):
+        prob = N.Problem([case])
+        st = prob.state_from_cases()
+        prob.step(st, 5)
+        torch.cuda.synchronize()
+        outs.append((u32(st.cell).copy(), stack(st.off, case.n).copy(), stack(st.vel, case.n).copy(),
+                     f32(prob.fields.rho).copy()))
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(np.asarray(a).view(np.uint32), np.asarray(b).view(np.uint32))
+
+
+def test_batched_cases_equal_solo_runs_bitwise():
+    N = nauticle()
+    cases = WL.batched_2d(n_cases=7, seed=9, max_side_exp=6.5)
+    prob = N.Problem(cases)
+    st = prob.state_from_cases()
+    prob.step(st, 4)
+    torch.cuda.synchronize()
+    prob.check()
+    off = 0
+    for c in cases:
+        solo = N.Problem([c])
+        s1 = solo.state_from_cases()
+        solo.step(s1, 4)
+        torch.cuda.synchronize()
+        sl = slice(off, off + c.n)
+        np.testing.assert_array_equal(u32(st.cell)[sl], u32(s1.cell)[: c.n])
+        np.testing.assert_array_equal(u32(st.id)[sl], u32(s1.id)[: c.n])
+        for k in range(2):
+            np.testing.assert_array_equal(f32(st.off[k])[sl].view(np.uint32), f32(s1.off[k])[: c.n].view(np.uint32))
+            np.testing.assert_array_equal(f32(st.vel[k])[sl].view(np.uint32), f32(s1.vel[k])[: c.n].view(np.uint32))
+        np.testing.assert_array_equal(f32(prob.fields.rho)[sl].view(np.uint32),
+                                      f32(solo.fields.rho)[: c.n].view(np.uint32))
+        off += c.n
+
+
+def test_isolated_particles_follow_closed_form():
+    """Particles farther than 2h apart: rho = m alpha, a = g, and the
+    semi-implicit Euler closed form over n steps."""
+    N = nauticle()
+    base = WL.lattice_case(3, (4, 4, 4), 0.05, 0.2, 0.0, 0.3, seed=3, g=(0.5, -1.0, -9.81), dt=1e-3)
+    prob = N.Problem([base])
+    st = prob.state_from_cases()
+    n_steps = 7
+    prob.step(st, n_steps)
+    torch.cuda.synchronize()
+    prob.check()
+    n = base.n
+    assert np.all(u32(prob.cells.nbr_count)[:n] == 0)
+    rho = f32(prob.fields.rho)[:n]
+    np.testing.assert_allclose(rho, base.mass * O.alpha(3, base.h), rtol=1e-6)
+    ids = u32(st.id)[:n]
+    v = np.empty((n, 3))
+    v[ids] = stack(st.vel, n)
+    g = np.array(base.g)
+    np.testing.assert_allclose(v, base.vel + n_steps * base.dt * g, rtol=1e-5, atol=1e-6)
+
+
+def test_error_word_reports_nonfinite_and_overflow():
+    N = nauticle()
+    case = WL.lattice_case(3, (10, 10, 10), 0.01, 1.2, 0.05, 0.05, seed=1)
+    prob = N.Problem([case], max_nbr=8)
+    st = prob.state_from_cases()
+    prob.build_cells(st)
+    with pytest.raises(N.NauticleError) as e:
+        prob.check()
+    assert e.value.status == N.ERR_NEIGHBOUR_OVERFLOW
+    prob.check()  # cleared
+    bad = case.pos.copy()
+    bad[5, 1] = np.nan
+    pos_t = [torch.from_numpy(np.ascontiguousarray(bad[:, k])).cuda() for k in range(3)]
+    prob.bin(pos_t)
+    with pytest.raises(N.NauticleError) as e:
+        prob.check()
+    assert e.value.status == N.ERR_NONFINITE
+
+
+def test_adjoint_one_step_matches_oracle_vjp():
+    N = nauticle()
+    case = WL.lattice_case(2, (24, 20), 0.01, 1.3, 0.1, 0.2, seed=17, c0=10.0, nu=2e-3, dt=2e-4)
+    prob = N.Problem([case])
+    st = prob.state_from_cases()
+    prob.build_cells(st)
+    prob.density()
+    n = case.n
+    rng = np.random.default_rng(5)
+    lx_in = rng.normal(size=(n, 2))
+    lv_in = rng.normal(size=(n, 2))
+    perm = None
+    torch.cuda.synchronize()
+    perm = u32(prob.cells.perm)[:n]
+    # cotangents of the step's outputs live in the output (sorted) order
+    lxn = [torch.from_numpy(lx_in[perm, k].astype(np.float32)).cuda() for k in range(2)]
+    lvn = [torch.from_numpy(lv_in[perm, k].astype(np.float32)).cuda() for k in range(2)]
+    lx = [torch.empty(n, device="cuda") for _ in range(2)]
+    lv = [torch.empty(n, device="cuda") for _ in range(2)]
+    dnu = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dc0 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    prob.adjoint(prob.sorted, prob.cells, prob.fields, lxn, lvn, lx, lv, dnu, dc0)
+    torch.cuda.synchronize()
+    prob.check()
+    gx = np.stack([f32(t) for t in lx], 1)
+    gv = np.stack([f32(t) for t in lv], 1)
+    ox, ov, onu, oc0 = O.step_vjp(domain_of(case), params_of(case), x64(case), v64(case), lx_in, lv_in)
+    ex = np.abs(gx - ox).max() / np.abs(ox).max()
+    ev = np.abs(gv - ov).max() / np.abs(ov).max()
+    enu = abs(dnu.item() - onu) / abs(onu)
+    ec0 = abs(dc0.item() - oc0) / abs(oc0)
+    print(f"adjoint: x {ex:.2e} v {ev:.2e} nu {enu:.2e} c0 {ec0:.2e}")
+    assert ex < 1e-4 and ev < 1e-5 and enu < 1e-4 and ec0 < 1e-4
