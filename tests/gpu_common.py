@@ -52,8 +52,17 @@ def case_absolute_from_state(case, cell, off):
     return x
 
 
-def norms(case):
-    """Scale normalisers of the tolerance: rho0 for rho, c0^2 rho0 for p,
-    c0^2 / h for a, the box length for positions."""
-    return dict(rho=case.rho0, p=case.c0 ** 2 * case.rho0, a=case.c0 ** 2 / case.h,
-                x=float(np.max(case.length()[: case.dim])))
+def norms(case, rho=None, p=None, a=None):
+    """Scale normalisers of the tolerance: rho0 for rho, c0^2 rho0 (the
+    bulk modulus gamma B) for p, c0^2 / h for a, the box length for
+    positions; each raised to the reference field's own magnitude when that
+    is larger (strongly compressed states, where the Tait law amplifies)."""
+    S = dict(rho=case.rho0, p=case.c0 ** 2 * case.rho0, a=case.c0 ** 2 / case.h,
+             x=float(np.max(case.length()[: case.dim])))
+    if rho is not None:
+        S["rho"] = max(S["rho"], float(np.abs(rho).max()))
+    if p is not None:
+        S["p"] = max(S["p"], float(np.abs(p).max()))
+    if a is not None:
+        S["a"] = max(S["a"], float(np.abs(a).max()))
+    return S
