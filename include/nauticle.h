@@ -191,12 +191,14 @@ nauticle_status nauticle_unbin(const nauticle_case* cases, int32_t n_cases,
 /* Neighbour search [Sec. 3.2.1 cell grid; A8 ownership]: keys, stable
  * radix sort, cell start/end table, reorder of `in` into `sorted`
  * (sorted must not alias in), then every particle's neighbour list under
- * the FP32 predicate: with d_k = fl32(fl32(off_j,k + delta_k cell_size_k)
- * - off_i,k) and r2 = fmaf(d_z, d_z, fmaf(d_y, d_y, d_x d_x)), j is a
- * neighbour of i iff j != i, the cells are adjacent (delta in {-1,0,1}^dim
- * after periodic folding; no folding on cut-off axes) and r2 < fl32(4h^2).
- * Lists are ordered by stencil cell (x fastest, offsets -1..1) then by
- * sorted position. */
+ * the FP32 predicate: with delta = j's cell minus i's cell (in {-1,0,1}^dim
+ * after periodic folding; no folding on cut-off axes; other pairs are never
+ * neighbours), d_k = fl32(off_j,k - fl32(off_i,k - delta_k cell_size_k)) and
+ * r2 = fmaf(d_z, d_z, fmaf(d_y, d_y, d_x d_x)), j is a neighbour of i iff
+ * j != i and r2 < fl32(4h^2).
+ * Each list holds the neighbours row by row of the stencil (z offset
+ * outer, y offset inner, each -1..1), and within a row in ascending sorted
+ * position (the cell wrapped across a periodic x face after the others). */
 nauticle_status nauticle_build_cells(const nauticle_case* cases, int32_t n_cases,
                                      const nauticle_state* in, nauticle_state* sorted,
                                      nauticle_cells* cells, void* ws, size_t ws_bytes,
@@ -229,10 +231,12 @@ nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases,
  * density, forces with the fused integration back into `state`.  After
  * the call `state` holds the particles in the sorted order of the last
  * step; `cells` and `fields` hold that step's neighbour structure and
- * fields. */
+ * fields.  phase_events (optional, NULL or 4 * n_steps caller-created HIP
+ * events) are recorded on `stream` at the start of each step and after its
+ * search, density and force phases, for timing. */
 nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
                               int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
-                              void* ws, size_t ws_bytes, hipStream_t stream);
+                              hipEvent_t* phase_events, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Reverse mode of one step (the derivative the paper does not have).
  * Inputs are the step's forward quantities: `sorted` (the state the step's

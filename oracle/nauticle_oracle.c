@@ -204,9 +204,10 @@ static int or_cell_delta(const or_domain* D, int k, int64_t ci, int64_t cj)
 }
 
 /* FP32 neighbour predicate between particle i and j whose cells differ by
- * delta (each component in {-1,0,1}):
- *   s_k  = fl32(off_j,k + delta_k * cs_k)      (delta*cs is exact)
- *   d_k  = fl32(s_k - off_i,k)
+ * delta (j's cell minus i's, each component in {-1,0,1}): i's offset is
+ * moved into j's cell frame, then
+ *   t_k  = fl32(off_i,k - delta_k * cs_k)      (delta*cs is exact)
+ *   d_k  = fl32(off_j,k - t_k)                 (= r_j - r_i up to rounding)
  *   r2   = fmaf(d_z, d_z, fmaf(d_y, d_y, d_x * d_x))
  *   neighbour iff r2 < fl32(4 h^2) and j != i. */
 static int or_pred_f32(const or_domain* D, float R2, const int delta[3],
@@ -215,8 +216,8 @@ static int or_pred_f32(const or_domain* D, float R2, const int delta[3],
     float d[3] = {0.0f, 0.0f, 0.0f};
     for (int k = 0; k < D->dim; ++k) {
         float cs = (float)D->cs[k];
-        float s = offj[k] + (float)delta[k] * cs;
-        d[k] = s - offi[k];
+        float t = offi[k] - (float)delta[k] * cs;
+        d[k] = offj[k] - t;
     }
     float r2 = d[0] * d[0];
     if (D->dim >= 2) r2 = fmaf(d[1], d[1], r2);

@@ -7,18 +7,15 @@
 //           dnu and dc0 terms;
 //   pass B: lam_x (density geometry needs rhobar of the neighbours, so it
 //           runs after pass A has finished for every particle).
-// Per-case parameter gradients are reduced in FP64 in a fixed order (block
-// tree, then items in order), so results are bitwise reproducible.
+// Neighbour data is gathered as float4s in sorted order (offsets + s,
+// velocity + 1/rho, A + rhobar).  Per-case parameter gradients are reduced
+// in FP64 in a fixed order (block tree, then items in order), so results are
+// bitwise reproducible.
 #include "internal.h"
 
 namespace nau {
 
 namespace {
-
-struct AdjScratch {
-    float* A[3];     // dt (lam_v' + dt lam_x'), fluid only
-    float* rhobar;
-};
 
 __device__ inline void block_reduce2(double a, double b, double* sh_a, double* sh_b, double* out_a,
                                      double* out_b)
@@ -37,58 +34,71 @@ __device__ inline void block_reduce2(double a, double b, double* sh_a, double* s
     *out_b = sh_b[0];
 }
 
-__device__ inline uint32_t adj_pair(const CaseDev& C, int dim, uint32_t e, uint32_t n_total,
-                                    const StateDev& st, const float oi[3], float d[3], float* r2)
+// r_j - r_i as the neighbour predicate forms it (the particle moved into the
+// neighbour's cell frame, see sph.hip).
+__device__ inline float3 adj_d(const CaseDev& C, uint32_t e, const float4& oj, const float4& oi)
 {
 #pragma clang fp contract(off)
-    uint32_t j = e & kIndexMask;
-    if (j >= n_total) j = n_total - 1;  // never for lists built by the search; guards memory
-    d[2] = 0.0f;
-    for (int k = 0; k < 3; ++k) {
-        if (k >= dim) break;
-        const int32_t dk = static_cast<int32_t>((e >> (NAUTICLE_NBR_INDEX_BITS + 2 * k)) & 3u) - 1;
-        d[k] = (st.off[k][j] + static_cast<float>(dk) * C.cs[k]) - oi[k];
-    }
-    float s = __builtin_fmaf(d[1], d[1], d[0] * d[0]);
-    if (dim == 3) s = __builtin_fmaf(d[2], d[2], s);
-    *r2 = s;
-    return j;
+    const float sx = static_cast<float>(static_cast<int32_t>((e >> NAUTICLE_NBR_INDEX_BITS) & 3u) - 1) * C.cs[0];
+    const float sy = static_cast<float>(static_cast<int32_t>((e >> (NAUTICLE_NBR_INDEX_BITS + 2)) & 3u) - 1) * C.cs[1];
+    const float sz = static_cast<float>(static_cast<int32_t>((e >> (NAUTICLE_NBR_INDEX_BITS + 4)) & 3u) - 1) * C.cs[2];
+    return make_float3(oj.x - (oi.x - sx), oj.y - (oi.y - sy), oj.z - (oi.z - sz));
+}
+
+__device__ inline float adj_r2(const float3& d, int dim)
+{
+    float r2 = __builtin_fmaf(d.y, d.y, d.x * d.x);
+    if (dim == 3) r2 = __builtin_fmaf(d.z, d.z, r2);
+    return r2;
+}
+
+__device__ inline uint32_t adj_index(uint32_t e, uint32_t n_total)
+{
+    const uint32_t j = e & kIndexMask;
+    return j < n_total ? j : n_total - 1;  // never out of range for lists built by the search
 }
 
 }  // namespace
 
 // A_i = dt (lam_v'_i + dt lam_x'_i) for fluid particles, 0 for fixed ones.
 __global__ void __launch_bounds__(kBlock)
-k_adj_prep(const CaseDev* __restrict__ cases, const Item* __restrict__ items, StateDev st,
+k_adj_prep(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
            const float* __restrict__ lxn0, const float* __restrict__ lxn1, const float* __restrict__ lxn2,
            const float* __restrict__ lvn0, const float* __restrict__ lvn1, const float* __restrict__ lvn2,
-           AdjScratch S)
+           float4* __restrict__ adj4)
 {
-    const Item it = items[blockIdx.x];
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
     if (threadIdx.x >= it.count) return;
     const CaseDev& C = cases[it.case_id];
     const uint32_t i = it.first + threadIdx.x;
     const bool fixed = st.id[i] >= C.n_fluid;
     const float* lx[3] = {lxn0, lxn1, lxn2};
     const float* lv[3] = {lvn0, lvn1, lvn2};
+    float A[3] = {0.0f, 0.0f, 0.0f};
     for (int k = 0; k < 3; ++k) {
         if (k >= C.dim) break;
-        S.A[k][i] = fixed ? 0.0f : C.dt * fmaf(C.dt, lx[k][i], lv[k][i]);
+        A[k] = fixed ? 0.0f : C.dt * fmaf(C.dt, lx[k][i], lv[k][i]);
     }
+    adj4[i] = make_float4(A[0], A[1], A[2], 0.0f);
 }
 
 // Pass A.
 __global__ void __launch_bounds__(kBlock)
-k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, StateDev st,
+k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
+        const float4* __restrict__ a4, const float4* __restrict__ b4, const float4* __restrict__ adj4,
         const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count, uint32_t max_nbr,
-        uint32_t n_total, FieldsDev f, AdjScratch S, const uint32_t* __restrict__ perm,
-        const float* __restrict__ lxn0, const float* __restrict__ lxn1, const float* __restrict__ lxn2,
-        const float* __restrict__ lvn0, const float* __restrict__ lvn1, const float* __restrict__ lvn2,
-        float* lv0, float* lv1, float* lv2, double* __restrict__ partial)
+        uint32_t n_total, FieldsDev f, const uint32_t* __restrict__ perm, const float* __restrict__ lxn0,
+        const float* __restrict__ lxn1, const float* __restrict__ lxn2, const float* __restrict__ lvn0,
+        const float* __restrict__ lvn1, const float* __restrict__ lvn2, float* lv0, float* lv1, float* lv2,
+        float4* __restrict__ adj4b, double* __restrict__ partial)
 {
     __shared__ double sh_a[kBlock];
     __shared__ double sh_b[kBlock];
-    const Item it = items[blockIdx.x];
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;  // uniform over the block
+    const Item it = items[ix];
     const CaseDev& C = cases[it.case_id];
     const bool active = threadIdx.x < it.count;
     double nu_term = 0.0, c0_term = 0.0;
@@ -96,57 +106,48 @@ k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, State
         const uint32_t i = it.first + threadIdx.x;
         const int dim = C.dim;
         const bool fixed = st.id[i] >= C.n_fluid;
-        float oi[3] = {0.0f, 0.0f, 0.0f}, vi[3] = {0.0f, 0.0f, 0.0f}, Ai[3] = {0.0f, 0.0f, 0.0f};
-        for (int k = 0; k < 3; ++k)
-            if (k < dim) {
-                oi[k] = st.off[k][i];
-                vi[k] = fixed ? 0.0f : st.vel[k][i];
-                Ai[k] = S.A[k][i];
-            }
-        const float ki = f.inv_rho[i];
+        const float4 ai = a4[i], bi = b4[i], Ai = adj4[i];
         const float m = C.m, mnu = C.m * C.nu;
         uint32_t cnt = nbr_count[i];
         if (cnt > max_nbr) cnt = max_nbr;
         float sbar = 0.0f, kbar = 0.0f, nubar = 0.0f;
-        float vv[3] = {0.0f, 0.0f, 0.0f};
+        float vvx = 0.0f, vvy = 0.0f, vvz = 0.0f;
+        const uint32_t* col = nbr + i;
         for (uint32_t k = 0; k < cnt; ++k) {
-            float d[3], r2;
-            const uint32_t j = adj_pair(C, dim, nbr[static_cast<size_t>(k) * n_total + i], n_total, st, oi, d, &r2);
-            const float q = sqrtf(r2) * C.inv_h;
+            const uint32_t e = col[static_cast<size_t>(k) * n_total];
+            const uint32_t j = adj_index(e, n_total);
+            const float4 aj = a4[j], bj = b4[j], Aj = adj4[j];
+            const float3 d = adj_d(C, e, aj, ai);
+            const float q = sqrtf(adj_r2(d, dim)) * C.inv_h;
             const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
             const float F = C.F_coef * (t * t * t);
-            const bool jfixed = st.id[j] >= C.n_fluid;
-            float dA[3] = {0.0f, 0.0f, 0.0f}, dv[3] = {0.0f, 0.0f, 0.0f};
-            float ddA = 0.0f, dvdA = 0.0f, Aidv = 0.0f;
-            for (int c = 0; c < 3; ++c) {
-                if (c >= dim) break;
-                dA[c] = Ai[c] - S.A[c][j];
-                dv[c] = vi[c] - (jfixed ? 0.0f : st.vel[c][j]);
-                ddA = fmaf(d[c], dA[c], ddA);
-                dvdA = fmaf(dv[c], dA[c], dvdA);
-                Aidv = fmaf(Ai[c], dv[c], Aidv);
-            }
+            const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
+            const float dvx = bi.x - bj.x, dvy = bi.y - bj.y, dvz = bi.z - bj.z;
+            const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
+            const float dvdA = fmaf(dvz, dAz, fmaf(dvy, dAy, dvx * dAx));
+            const float Aidv = fmaf(Ai.z, dvz, fmaf(Ai.y, dvy, Ai.x * dvx));
             // r_ij = -d: sbar_i = -m sum F r_ij.dA = m sum F d.dA
             sbar = fmaf(m * F, ddA, sbar);
             kbar = fmaf(mnu * F, dvdA, kbar);
-            const float w = m * (ki + f.inv_rho[j]) * F;
-            for (int c = 0; c < 3; ++c)
-                if (c < dim) vv[c] = fmaf(C.nu * w, dA[c], vv[c]);
+            const float w = m * (bi.w + bj.w) * F;
+            const float wn = C.nu * w;
+            vvx = fmaf(wn, dAx, vvx);
+            vvy = fmaf(wn, dAy, vvy);
+            vvz = fmaf(wn, dAz, vvz);
             nubar = fmaf(w, Aidv, nubar);
         }
-        const float rho = f.rho[i], p = f.p[i];
-        const float inv_rho = ki;
-        const float inv_rho2 = inv_rho * inv_rho;
-        const float inv_rho3 = inv_rho2 * inv_rho;
-        S.rhobar[i] = sbar * (C.gamma * (p + C.B) - 2.0f * p) * inv_rho3 - kbar * inv_rho2;
-        (void)rho;
+        const float p = f.p[i];
+        const float inv_rho2 = bi.w * bi.w;
+        const float inv_rho3 = inv_rho2 * bi.w;
+        const float rhobar = sbar * (C.gamma * (p + C.B) - 2.0f * p) * inv_rho3 - kbar * inv_rho2;
+        adj4b[i] = make_float4(Ai.x, Ai.y, Ai.z, rhobar);
         nu_term = static_cast<double>(nubar);
-        c0_term = static_cast<double>(sbar) * (2.0 * static_cast<double>(p) / C.c0) *
-                  static_cast<double>(inv_rho2);
+        c0_term = static_cast<double>(sbar) * (2.0 * static_cast<double>(p) / C.c0) * static_cast<double>(inv_rho2);
         const uint32_t dst = perm[i] < n_total ? perm[i] : i;
         const float* lx[3] = {lxn0, lxn1, lxn2};
         const float* lvn[3] = {lvn0, lvn1, lvn2};
         float* lv[3] = {lv0, lv1, lv2};
+        const float vv[3] = {vvx, vvy, vvz};
         for (int c = 0; c < 3; ++c) {
             if (c >= dim) break;
             const float vh = fmaf(C.dt, lx[c][i], lvn[c][i]);
@@ -156,20 +157,22 @@ k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, State
     double sa, sb;
     block_reduce2(nu_term, c0_term, sh_a, sh_b, &sa, &sb);
     if (threadIdx.x == 0) {
-        partial[2 * blockIdx.x] = sa;
-        partial[2 * blockIdx.x + 1] = sb;
+        partial[2 * ix] = sa;
+        partial[2 * ix + 1] = sb;
     }
 }
 
 // Pass B.
 __global__ void __launch_bounds__(kBlock)
-k_adj_b(const CaseDev* __restrict__ cases, const Item* __restrict__ items, StateDev st,
+k_adj_b(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
+        const float4* __restrict__ a4, const float4* __restrict__ b4, const float4* __restrict__ adj4b,
         const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count, uint32_t max_nbr,
-        uint32_t n_total, FieldsDev f, AdjScratch S, const uint32_t* __restrict__ perm,
-        const float* __restrict__ lxn0, const float* __restrict__ lxn1, const float* __restrict__ lxn2,
-        float* lx0, float* lx1, float* lx2)
+        uint32_t n_total, const uint32_t* __restrict__ perm, const float* __restrict__ lxn0,
+        const float* __restrict__ lxn1, const float* __restrict__ lxn2, float* lx0, float* lx1, float* lx2)
 {
-    const Item it = items[blockIdx.x];
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
     if (threadIdx.x >= it.count) return;
     const CaseDev& C = cases[it.case_id];
     const uint32_t i = it.first + threadIdx.x;
@@ -182,56 +185,48 @@ k_adj_b(const CaseDev* __restrict__ cases, const Item* __restrict__ items, State
             if (c < dim) lx[c][dst] = 0.0f;
         return;
     }
-    float oi[3] = {0.0f, 0.0f, 0.0f}, vi[3] = {0.0f, 0.0f, 0.0f}, Ai[3] = {0.0f, 0.0f, 0.0f};
-    for (int k = 0; k < 3; ++k)
-        if (k < dim) {
-            oi[k] = st.off[k][i];
-            vi[k] = st.vel[k][i];
-            Ai[k] = S.A[k][i];
-        }
-    const float si = f.s[i], ki = f.inv_rho[i], rbi = S.rhobar[i];
+    const float4 ai = a4[i], bi = b4[i], Ai = adj4b[i];
     const float m = C.m, mnu = C.m * C.nu;
     uint32_t cnt = nbr_count[i];
     if (cnt > max_nbr) cnt = max_nbr;
-    float acc[3] = {0.0f, 0.0f, 0.0f};
+    float accx = 0.0f, accy = 0.0f, accz = 0.0f;
+    const uint32_t* col = nbr + i;
     for (uint32_t k = 0; k < cnt; ++k) {
-        float d[3], r2;
-        const uint32_t j = adj_pair(C, dim, nbr[static_cast<size_t>(k) * n_total + i], n_total, st, oi, d, &r2);
-        const float r = sqrtf(r2);
+        const uint32_t e = col[static_cast<size_t>(k) * n_total];
+        const uint32_t j = adj_index(e, n_total);
+        const float4 aj = a4[j], bj = b4[j], Aj = adj4b[j];
+        const float3 d = adj_d(C, e, aj, ai);
+        const float r = sqrtf(adj_r2(d, dim));
         const float q = r * C.inv_h;
         const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
         const float F = C.F_coef * (t * t * t);
         const float Fp_r = r > 0.0f ? C.dF_coef * (t * t) / r : 0.0f;
-        const bool jfixed = st.id[j] >= C.n_fluid;
-        float dA[3] = {0.0f, 0.0f, 0.0f};
-        float ddA = 0.0f, dvdA = 0.0f;
-        for (int c = 0; c < 3; ++c) {
-            if (c >= dim) break;
-            dA[c] = Ai[c] - S.A[c][j];
-            const float dv = vi[c] - (jfixed ? 0.0f : st.vel[c][j]);
-            ddA = fmaf(d[c], dA[c], ddA);
-            dvdA = fmaf(dv, dA[c], dvdA);
-        }
+        const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
+        const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
+        const float dvdA = fmaf(bi.z - bj.z, dAz, fmaf(bi.y - bj.y, dAy, (bi.x - bj.x) * dAx));
         // with r_ij = -d:
-        //   density geometry  m F r_ij (rhobar_i + rhobar_j)           = -m F (rb) d
+        //   density geometry  m F r_ij (rhobar_i + rhobar_j)             = -m F (rb) d
         //   pressure Hessian -m (s_i+s_j) [F dA + (F'/r) r_ij (r_ij.dA)] = -m (s) [F dA + (F'/r) d (d.dA)]
-        //   viscous geometry  m nu (k_i+k_j) (F'/r) r_ij (dv.dA)        = -m nu (k) (F'/r) d (dv.dA)
-        const float rb = rbi + S.rhobar[j];
-        const float cs_ = m * (si + f.s[j]);
-        const float ck = mnu * (ki + f.inv_rho[j]);
+        //   viscous geometry  m nu (k_i+k_j) (F'/r) r_ij (dv.dA)          = -m nu (k) (F'/r) d (dv.dA)
+        const float rb = Ai.w + Aj.w;
+        const float cs_ = m * (ai.w + aj.w);
+        const float ck = mnu * (bi.w + bj.w);
         const float coef_d = -m * F * rb - cs_ * Fp_r * ddA - ck * Fp_r * dvdA;
         const float coef_a = -cs_ * F;
-        for (int c = 0; c < 3; ++c)
-            if (c < dim) acc[c] = fmaf(coef_d, d[c], fmaf(coef_a, dA[c], acc[c]));
+        accx = fmaf(coef_d, d.x, fmaf(coef_a, dAx, accx));
+        accy = fmaf(coef_d, d.y, fmaf(coef_a, dAy, accy));
+        accz = fmaf(coef_d, d.z, fmaf(coef_a, dAz, accz));
     }
     const float* lxn[3] = {lxn0, lxn1, lxn2};
+    const float acc[3] = {accx, accy, accz};
     for (int c = 0; c < 3; ++c)
         if (c < dim) lx[c][dst] = lxn[c][i] + acc[c];
 }
 
 // Adds each case's sum of item partials (in item order) to out_a / out_b.
+// With per_case_mean, out_a gets the sum divided by (n_fluid * dim).
 __global__ void k_reduce_cases(const CaseDev* __restrict__ cases, int n_cases, const double* __restrict__ partial,
-                               double* out_a, double* out_b, int accumulate, double scale_a_by_case)
+                               double* out_a, double* out_b, int accumulate, int per_case_mean)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n_cases) return;
@@ -241,7 +236,7 @@ __global__ void k_reduce_cases(const CaseDev* __restrict__ cases, int n_cases, c
         sa += partial[2 * it];
         sb += partial[2 * it + 1];
     }
-    if (scale_a_by_case != 0.0) {
+    if (per_case_mean) {
         const double nf = static_cast<double>(C.n_fluid) * C.dim;
         sa = nf > 0.0 ? sa / nf : 0.0;
     }
@@ -257,20 +252,22 @@ hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nautic
     if (P.n_items == 0) return hipSuccess;
     const CaseDev* cases = at<CaseDev>(ws, P.L.cases);
     const Item* items = at<Item>(ws, P.L.items);
-    AdjScratch S;
-    for (int k = 0; k < 3; ++k) S.A[k] = at<float>(ws, P.L.adj[k]);
-    S.rhobar = at<float>(ws, P.L.adj[3]);
+    const Packed pk = packed(P, ws);
     double* partial = at<double>(ws, P.L.partial);
     const uint32_t mx = static_cast<uint32_t>(cells.max_nbr);
-    k_adj_prep<<<P.n_items, kBlock, 0, s>>>(cases, items, sorted, lxn[0], lxn[1], lxn[2], lvn[0], lvn[1],
-                                            lvn[2], S);
-    k_adj_a<<<P.n_items, kBlock, 0, s>>>(cases, items, sorted, cells.nbr, cells.nbr_count, mx, P.n_total, f, S,
-                                         cells.perm, lxn[0], lxn[1], lxn[2], lvn[0], lvn[1], lvn[2], lv[0],
-                                         lv[1], lv[2], partial);
-    k_adj_b<<<P.n_items, kBlock, 0, s>>>(cases, items, sorted, cells.nbr, cells.nbr_count, mx, P.n_total, f, S,
-                                         cells.perm, lxn[0], lxn[1], lxn[2], lx[0], lx[1], lx[2]);
+    const uint32_t grid = xcd_grid(P.n_items);
+    hipError_t e = launch_pack_fields(P, ws, sorted, f, s);
+    if (e != hipSuccess) return e;
+    k_adj_prep<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, lxn[0], lxn[1], lxn[2], lvn[0], lvn[1],
+                                       lvn[2], pk.adj4);
+    k_adj_a<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, pk.a4, pk.b4, pk.adj4, cells.nbr,
+                                    cells.nbr_count, mx, P.n_total, f, cells.perm, lxn[0], lxn[1], lxn[2], lvn[0],
+                                    lvn[1], lvn[2], lv[0], lv[1], lv[2], pk.adj4b, partial);
+    k_adj_b<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, pk.a4, pk.b4, pk.adj4b, cells.nbr,
+                                    cells.nbr_count, mx, P.n_total, cells.perm, lxn[0], lxn[1], lxn[2], lx[0],
+                                    lx[1], lx[2]);
     const int nb = (P.n_cases + kBlock - 1) / kBlock;
-    k_reduce_cases<<<nb, kBlock, 0, s>>>(cases, P.n_cases, partial, dnu, dc0, 1, 0.0);
+    k_reduce_cases<<<nb, kBlock, 0, s>>>(cases, P.n_cases, partial, dnu, dc0, 1, 0);
     return hipGetLastError();
 }
 
@@ -279,10 +276,12 @@ hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nautic
 // ----------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kBlock)
-k_inverse_id(const CaseDev* __restrict__ cases, const Item* __restrict__ items, const uint32_t* __restrict__ id,
-             uint32_t* __restrict__ inv)
+k_inverse_id(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
+             const uint32_t* __restrict__ id, uint32_t* __restrict__ inv)
 {
-    const Item it = items[blockIdx.x];
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
     if (threadIdx.x >= it.count) return;
     const CaseDev& C = cases[it.case_id];
     const uint32_t p = it.first + threadIdx.x;
@@ -292,12 +291,15 @@ k_inverse_id(const CaseDev* __restrict__ cases, const Item* __restrict__ items, 
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_position_loss(const CaseDev* __restrict__ cases, const Item* __restrict__ items, StateDev a, StateDev b,
-                const uint32_t* __restrict__ inv_b, float* g0, float* g1, float* g2, double* __restrict__ partial)
+k_position_loss(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev a,
+                StateDev b, const uint32_t* __restrict__ inv_b, float* g0, float* g1, float* g2,
+                double* __restrict__ partial)
 {
     __shared__ double sh_a[kBlock];
     __shared__ double sh_b[kBlock];
-    const Item it = items[blockIdx.x];
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;  // uniform over the block
+    const Item it = items[ix];
     const CaseDev& C = cases[it.case_id];
     double sq = 0.0;
     if (threadIdx.x < it.count) {
@@ -327,8 +329,8 @@ k_position_loss(const CaseDev* __restrict__ cases, const Item* __restrict__ item
     double sa, sb;
     block_reduce2(sq, 0.0, sh_a, sh_b, &sa, &sb);
     if (threadIdx.x == 0) {
-        partial[2 * blockIdx.x] = sa;
-        partial[2 * blockIdx.x + 1] = 0.0;
+        partial[2 * ix] = sa;
+        partial[2 * ix + 1] = 0.0;
     }
 }
 
@@ -340,11 +342,12 @@ hipError_t launch_position_loss(const Plan& P, void* ws, StateDev a, StateDev b,
     const Item* items = at<Item>(ws, P.L.items);
     uint32_t* inv = at<uint32_t>(ws, P.L.inv_map);
     double* partial = at<double>(ws, P.L.partial);
-    k_inverse_id<<<P.n_items, kBlock, 0, s>>>(cases, items, b.id, inv);
-    k_position_loss<<<P.n_items, kBlock, 0, s>>>(cases, items, a, b, inv, grad ? grad[0] : nullptr,
-                                                 grad ? grad[1] : nullptr, grad ? grad[2] : nullptr, partial);
+    const uint32_t grid = xcd_grid(P.n_items);
+    k_inverse_id<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, b.id, inv);
+    k_position_loss<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, a, b, inv, grad ? grad[0] : nullptr,
+                                            grad ? grad[1] : nullptr, grad ? grad[2] : nullptr, partial);
     const int nb = (P.n_cases + kBlock - 1) / kBlock;
-    k_reduce_cases<<<nb, kBlock, 0, s>>>(cases, P.n_cases, partial, loss, nullptr, 0, 1.0);
+    k_reduce_cases<<<nb, kBlock, 0, s>>>(cases, P.n_cases, partial, loss, nullptr, 0, 1);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // C-ABI entry points of libnauticle: host-side validation, the per-workspace
-// plan (case table fingerprint, workspace layout, tile work lists), and the
+// plan (case table fingerprint, workspace layout, particle-block work lists), and the
 // launch sequences of the five phases.  See include/nauticle.h.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -181,7 +182,12 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, Derived* D)
     L.sort_vals = take(4 * N);
     L.sort_hist = take(4 * 256 * n_tiles);
     L.sort_totals = take(4 * 256);
-    for (int k = 0; k < 12; ++k) L.adj[k] = take(4 * N);
+    L.cell_first = take(4 * (static_cast<size_t>(n_cells_total) + 1));
+    L.pos4 = take(16 * N);
+    L.a4 = take(16 * N);
+    L.b4 = take(16 * N);
+    L.adj4 = take(16 * N);
+    L.adj4b = take(16 * N);
     L.partial = take(2 * sizeof(double) * std::max<size_t>(D->items.size(), 1));
     L.inv_map = take(4 * N);
     L.total = off;
@@ -382,7 +388,9 @@ nauticle_status nauticle_sph_density(const nauticle_case* cases, int32_t n_cases
     if ((st = check_state(*P, sorted, false, "sorted")) != NAUTICLE_OK) return st;
     if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
     if ((st = check_fields(*P, fields, false)) != NAUTICLE_OK) return st;
-    hipError_t e = launch_density(*P, ws, to_dev(sorted), *cells, to_dev(fields), stream);
+    hipError_t e = launch_cell_first(*P, ws, *cells, stream);
+    if (e == hipSuccess) e = launch_pack_positions(*P, ws, to_dev(sorted), stream);
+    if (e == hipSuccess) e = launch_density(*P, ws, to_dev(sorted), *cells, to_dev(fields), stream);
     return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_sph_density");
 }
 
@@ -403,13 +411,16 @@ nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases,
             return fail(NAUTICLE_ERR_INVALID_ARG, "next must not alias sorted");
         nd = to_dev(next);
     }
-    hipError_t e = launch_forces(*P, ws, to_dev(sorted), *cells, to_dev(fields), next ? &nd : nullptr, stream);
+    hipError_t e = launch_cell_first(*P, ws, *cells, stream);
+    if (e == hipSuccess) e = launch_pack_fields(*P, ws, to_dev(sorted), to_dev(fields), stream);
+    if (e == hipSuccess)
+        e = launch_forces(*P, ws, to_dev(sorted), *cells, to_dev(fields), next ? &nd : nullptr, stream);
     return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_sph_forces");
 }
 
 nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauticle_state* state, int32_t n_steps,
-                              nauticle_cells* cells, nauticle_fields* fields, void* ws, size_t ws_bytes,
-                              hipStream_t stream)
+                              nauticle_cells* cells, nauticle_fields* fields, hipEvent_t* phase_events, void* ws,
+                              size_t ws_bytes, hipStream_t stream)
 {
     const Plan* P;
     nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
@@ -421,10 +432,19 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
     const StateDev cur = to_dev(state);
     const StateDev tmp = scratch_state(*P, ws);
     const FieldsDev f = to_dev(fields);
+    // build_cells leaves packed positions for density, and density leaves
+    // packed fields for forces, so the step needs no separate packing
+    auto mark = [&](int32_t s, int k) {
+        return phase_events ? hipEventRecord(phase_events[4 * s + k], stream) : hipSuccess;
+    };
     for (int32_t s = 0; s < n_steps; ++s) {
-        hipError_t e = launch_build_cells(*P, ws, cur, tmp, *cells, stream);
+        hipError_t e = mark(s, 0);
+        if (e == hipSuccess) e = launch_build_cells(*P, ws, cur, tmp, *cells, stream);
+        if (e == hipSuccess) e = mark(s, 1);
         if (e == hipSuccess) e = launch_density(*P, ws, tmp, *cells, f, stream);
+        if (e == hipSuccess) e = mark(s, 2);
         if (e == hipSuccess) e = launch_forces(*P, ws, tmp, *cells, f, &cur, stream);
+        if (e == hipSuccess) e = mark(s, 3);
         if (e != hipSuccess) return hip_fail(e, "nauticle_step");
     }
     return NAUTICLE_OK;

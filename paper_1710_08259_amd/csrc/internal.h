@@ -13,6 +13,7 @@ namespace nau {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
+constexpr uint32_t kGroup = 4;     // list entries in flight per lane in the pair loops
 constexpr uint32_t kIndexMask = (1u << NAUTICLE_NBR_INDEX_BITS) - 1u;
 
 // Device error word bits (OR-ed by kernels, read by nauticle_check).
@@ -30,7 +31,7 @@ struct CaseDev {
     uint32_t offset;     // first global particle
     uint32_t n;          // particles
     uint32_t n_fluid;    // ids >= n_fluid are fixed
-    uint32_t item_first; // this case's tiles in the item list
+    uint32_t item_first; // this case's blocks of particles in the item list
     uint32_t item_count;
     float cs[3];         // fl32(cell_size)
     float inv_cs[3];     // fl32(1 / cell_size)
@@ -80,10 +81,25 @@ struct Layout {
     size_t sort_vals;    // ping-pong values
     size_t sort_hist;    // [bins][tiles]
     size_t sort_totals;  // [bins]
-    size_t adj[12];      // adjoint scratch arrays, N floats each
+    size_t cell_first;   // n_cells_total + 1: first sorted position with key >= c
+    size_t pos4;         // float4 per sorted particle: offsets, bits of the cell's x index
+    size_t a4;           // float4: offsets, s = p / rho^2
+    size_t b4;           // float4: velocity (0 for fixed particles), 1 / rho
+    size_t adj4;         // float4: adjoint A = dt (lam_v' + dt lam_x'), 0
+    size_t adj4b;        // float4: A, rhobar (after adjoint pass A)
     size_t partial;      // per-item FP64 partial sums (2 per item)
     size_t inv_map;      // id -> position map (N u32)
     size_t total;
+};
+
+// Packed per-particle arrays in sorted order (workspace).
+struct Packed {
+    float4* pos4;
+    float4* a4;
+    float4* b4;
+    float4* adj4;
+    float4* adj4b;
+    uint32_t* cell_first;
 };
 
 // Everything derived from a case table.
@@ -104,15 +120,42 @@ struct Plan {
 template <typename T>
 inline T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
 
+inline Packed packed(const Plan& P, void* ws)
+{
+    return Packed{at<float4>(ws, P.L.pos4), at<float4>(ws, P.L.a4), at<float4>(ws, P.L.b4),
+                  at<float4>(ws, P.L.adj4), at<float4>(ws, P.L.adj4b), at<uint32_t>(ws, P.L.cell_first)};
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X, each
+// with its own L2.  Tiles are consecutive in space, so giving every XCD one
+// contiguous run of tiles keeps neighbouring tiles (which read the same
+// neighbour cells) on one L2.  Grid = kXcds * ceil(n_items / kXcds).
+constexpr uint32_t kXcds = 8;
+
+inline uint32_t xcd_grid(uint32_t n_items) { return (n_items + kXcds - 1) / kXcds * kXcds; }
+
+__device__ inline uint32_t xcd_item(uint32_t n_items)
+{
+    const uint32_t per = (n_items + kXcds - 1) / kXcds;
+    return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
 // ---- launchers (defined in the .hip files) -----------------------------------
 // search.hip
 hipError_t launch_bin(const Plan& P, void* ws, const float* const pos[3], StateDev st, hipStream_t s);
 hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3], hipStream_t s);
 hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sorted,
                               const nauticle_cells& cells, hipStream_t s);
+hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipStream_t s);
+// cell_first (the tiles' particle ranges) from the sorted keys of `cells`
+hipError_t launch_cell_first(const Plan& P, void* ws, const nauticle_cells& cells, hipStream_t s);
 // sph.hip
+hipError_t launch_pack_fields(const Plan& P, void* ws, StateDev sorted, FieldsDev f, hipStream_t s);
+// density reads pos4 (written by build_cells or launch_pack_positions) and
+// writes the fields plus a4/b4 for the force pass
 hipError_t launch_density(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                           FieldsDev f, hipStream_t s);
+// forces read a4/b4 (written by density or launch_pack_fields)
 hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                          FieldsDev f, const StateDev* next, hipStream_t s);
 // adjoint.hip

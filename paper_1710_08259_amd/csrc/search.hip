@@ -16,11 +16,14 @@ namespace nau {
 // ----------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kBlock)
-k_bin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, const float* __restrict__ px,
-      const float* __restrict__ py, const float* __restrict__ pz, StateDev st, uint32_t* err)
+k_bin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
+      const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz, StateDev st,
+      uint32_t* err)
 {
 #pragma clang fp contract(off)
-    const Item it = items[blockIdx.x];
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
     if (threadIdx.x >= it.count) return;
     const CaseDev& C = cases[it.case_id];
     const uint32_t i = it.first + threadIdx.x;
@@ -47,11 +50,13 @@ k_bin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, const f
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_unbin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, StateDev st, float* px,
-        float* py, float* pz)
+k_unbin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
+        float* px, float* py, float* pz)
 {
 #pragma clang fp contract(off)
-    const Item it = items[blockIdx.x];
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
     if (threadIdx.x >= it.count) return;
     const CaseDev& C = cases[it.case_id];
     const uint32_t i = it.first + threadIdx.x;
@@ -68,16 +73,17 @@ k_unbin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, State
 hipError_t launch_bin(const Plan& P, void* ws, const float* const pos[3], StateDev st, hipStream_t s)
 {
     if (P.n_items == 0) return hipSuccess;
-    k_bin<<<P.n_items, kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), pos[0],
-                                       pos[1], pos[2], st, at<uint32_t>(ws, P.L.err));
+    k_bin<<<xcd_grid(P.n_items), kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
+                                                 P.n_items, pos[0], pos[1], pos[2], st,
+                                                 at<uint32_t>(ws, P.L.err));
     return hipGetLastError();
 }
 
 hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3], hipStream_t s)
 {
     if (P.n_items == 0) return hipSuccess;
-    k_unbin<<<P.n_items, kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), st,
-                                         pos[0], pos[1], pos[2]);
+    k_unbin<<<xcd_grid(P.n_items), kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
+                                                   P.n_items, st, pos[0], pos[1], pos[2]);
     return hipGetLastError();
 }
 
@@ -86,10 +92,12 @@ hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3
 // ----------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kBlock)
-k_make_keys(const CaseDev* __restrict__ cases, const Item* __restrict__ items,
+k_make_keys(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
             const uint32_t* __restrict__ cell, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
 {
-    const Item it = items[blockIdx.x];
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
     if (threadIdx.x >= it.count) return;
     const uint32_t i = it.first + threadIdx.x;
     uint32_t c = cell[i];
@@ -277,53 +285,126 @@ k_cell_ranges(const uint32_t* __restrict__ keys, uint32_t n, uint32_t* __restric
     if (p == n - 1 || keys[p + 1] != k) end[k] = p + 1;
 }
 
+// cell_first[c] = first sorted position whose key is >= c, for every key c in
+// [0, n_cells] (binary search in the sorted keys).  Unlike cell_start it is
+// defined for empty cells too, so [cell_first[a], cell_first[b + 1]) is the
+// sorted range of the cells a..b.
 __global__ void __launch_bounds__(kBlock)
-k_reorder(const uint32_t* __restrict__ perm, uint32_t n, int dim, StateDev in, StateDev out)
+k_cell_first(const uint32_t* __restrict__ keys, uint32_t n, uint32_t n_cells, uint32_t* __restrict__ first)
 {
-    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > n_cells) return;
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] < c) lo = mid + 1;
+        else hi = mid;
+    }
+    first[c] = lo;
+}
+
+// Gathers the state into sorted order and packs each particle's offsets into
+// one float4 for the neighbour search and the density pass.
+__global__ void __launch_bounds__(kBlock)
+k_reorder(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
+          const uint32_t* __restrict__ perm, uint32_t n, StateDev in, StateDev out, float4* __restrict__ pos4)
+{
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
+    if (threadIdx.x >= it.count) return;
+    const CaseDev& C = cases[it.case_id];
+    const uint32_t p = it.first + threadIdx.x;
     uint32_t q = perm[p];
     if (q >= n) q = p;  // never for a permutation; guards memory
-    out.cell[p] = in.cell[q];
+    const uint32_t cell = in.cell[q];
+    out.cell[p] = cell;
     out.id[p] = in.id[q];
+    float o[3] = {0.0f, 0.0f, 0.0f};
     for (int k = 0; k < 3; ++k) {
-        if (k >= dim) break;
-        out.off[k][p] = in.off[k][q];
+        if (k >= C.dim) break;
+        o[k] = in.off[k][q];
+        out.off[k][p] = o[k];
         out.vel[k][p] = in.vel[k][q];
     }
+    pos4[p] = make_float4(o[0], o[1], o[2], 0.0f);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_pack_positions(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
+                 StateDev st, float4* __restrict__ pos4)
+{
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
+    if (threadIdx.x >= it.count) return;
+    const CaseDev& C = cases[it.case_id];
+    const uint32_t p = it.first + threadIdx.x;
+    float o[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < 3; ++k)
+        if (k < C.dim) o[k] = st.off[k][p];
+    pos4[p] = make_float4(o[0], o[1], o[2], 0.0f);
+}
+
+hipError_t launch_cell_first(const Plan& P, void* ws, const nauticle_cells& cells, hipStream_t s)
+{
+    if (P.n_total == 0) return hipSuccess;
+    const uint32_t nc = P.n_cells_total;
+    k_cell_first<<<(nc + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(cells.key, P.n_total, nc, packed(P, ws).cell_first);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipStream_t s)
+{
+    if (P.n_items == 0) return hipSuccess;
+    k_pack_positions<<<xcd_grid(P.n_items), kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
+                                                            P.n_items, sorted, packed(P, ws).pos4);
+    return hipGetLastError();
 }
 
 // ----------------------------------------------------------------------------
 // neighbour lists
 // ----------------------------------------------------------------------------
-// One lane per sorted particle.  For each of the 3^dim cells around the
-// particle's cell (x fastest, offsets -1..1), the candidates are that cell's
-// contiguous sorted range; each is tested with the FP32 predicate and, if
-// accepted, appended to the particle's column of the list.
+// One lane per sorted particle.  The 3^dim stencil is walked as 3^(dim-1)
+// rows of three cells along x; since keys run x fastest, a row's three cells
+// are one contiguous sorted range (two pieces where a periodic x axis wraps).
+// The predicate moves the particle into the candidate's cell frame,
+// t = off_i - delta cs: the y and z parts of t are fixed per row, and within a
+// piece the x part takes one of three values, selected by the piece's cell
+// boundaries.  Candidates are read as float4s, kUnroll at a time; those that
+// pass set a bit in a 64-candidate mask, which is then emitted into the
+// particle's list column in ascending order.  Lanes of one home cell read the
+// same candidate at the same time, so a wave's load touches only a handful of
+// cache lines.
+
+constexpr uint32_t kUnroll = 8;
 
 __global__ void __launch_bounds__(kBlock)
-k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, StateDev st,
-        const uint32_t* __restrict__ cell_start, const uint32_t* __restrict__ cell_end,
-        uint32_t* __restrict__ nbr, uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total,
-        uint32_t* err)
+k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
+        const float4* __restrict__ pos4, const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
+        uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total, uint32_t* err)
 {
 #pragma clang fp contract(off)
-    const Item it = items[blockIdx.x];
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
     if (threadIdx.x >= it.count) return;
     const CaseDev& C = cases[it.case_id];
     const uint32_t p = it.first + threadIdx.x;
     const int dim = C.dim;
-    int32_t c[3];
     uint32_t own = st.cell[p];
     if (own >= C.n_cells) {  // a corrupt state: keep every table access inside the case
         own = C.n_cells - 1;
         set_error(err, kErrOutOfDomain);
     }
+    int32_t c[3];
     cell_coords(C, own, c);
-    float oi[3] = {0.0f, 0.0f, 0.0f};
-    for (int k = 0; k < 3; ++k)
-        if (k < dim) oi[k] = st.off[k][p];
+    const float4 me = pos4[p];
     const float R2 = C.R2;
+    const int32_t nx = C.nc[0];
+    const bool px = C.periodic[0] != 0;
+    const float csx = C.cs[0];
+    uint32_t* col = nbr + p;
     uint32_t cnt = 0;
     const int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
     for (int dz = zlo; dz <= zhi; ++dz) {
@@ -332,37 +413,71 @@ k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, State
             if (C.periodic[2]) cz = cz < 0 ? cz + C.nc[2] : (cz >= C.nc[2] ? cz - C.nc[2] : cz);
             else if (cz < 0 || cz >= C.nc[2]) continue;
         }
+        const float tz = me.z - static_cast<float>(dz) * C.cs[2];
         for (int dy = -1; dy <= 1; ++dy) {
             int32_t cy = c[1] + dy;
             if (C.periodic[1]) cy = cy < 0 ? cy + C.nc[1] : (cy >= C.nc[1] ? cy - C.nc[1] : cy);
             else if (cy < 0 || cy >= C.nc[1]) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                int32_t cx = c[0] + dx;
-                if (C.periodic[0]) cx = cx < 0 ? cx + C.nc[0] : (cx >= C.nc[0] ? cx - C.nc[0] : cx);
-                else if (cx < 0 || cx >= C.nc[0]) continue;
-                const uint32_t key = C.cell_base + static_cast<uint32_t>(cx) +
-                                     static_cast<uint32_t>(C.nc[0]) *
-                                         (static_cast<uint32_t>(cy) + static_cast<uint32_t>(C.nc[1]) * static_cast<uint32_t>(cz));
-                const uint32_t s = cell_start[key];
-                if (s == NAUTICLE_EMPTY) continue;
-                const uint32_t e = cell_end[key] < n_total ? cell_end[key] : n_total;
-                const float shx = static_cast<float>(dx) * C.cs[0];
-                const float shy = static_cast<float>(dy) * C.cs[1];
-                const float shz = dim == 3 ? static_cast<float>(dz) * C.cs[2] : 0.0f;
-                const uint32_t code = (static_cast<uint32_t>(dx + 1) << NAUTICLE_NBR_INDEX_BITS) |
-                                      (static_cast<uint32_t>(dy + 1) << (NAUTICLE_NBR_INDEX_BITS + 2)) |
-                                      (static_cast<uint32_t>(dz + 1) << (NAUTICLE_NBR_INDEX_BITS + 4));
-                for (uint32_t q = s; q < e; ++q) {
-                    if (q == p) continue;
-                    const float ddx = (st.off[0][q] + shx) - oi[0];
-                    const float ddy = (st.off[1][q] + shy) - oi[1];
-                    float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
-                    if (dim == 3) {
-                        const float ddz = (st.off[2][q] + shz) - oi[2];
-                        r2 = __builtin_fmaf(ddz, ddz, r2);
+            const uint32_t row = C.cell_base + static_cast<uint32_t>(nx) *
+                                                   (static_cast<uint32_t>(cy) + static_cast<uint32_t>(C.nc[1]) * static_cast<uint32_t>(cz));
+            const float ty = me.y - static_cast<float>(dy) * C.cs[1];
+            // the row's x span [c-1, c+1] as up to two contiguous pieces of cells
+            int32_t lo0 = c[0] - 1, hi0 = c[0] + 1, lo1 = 0, hi1 = -1;
+            if (px) {
+                if (lo0 < 0) { lo1 = nx - 1; hi1 = nx - 1; lo0 = 0; }
+                if (hi0 >= nx) { lo1 = 0; hi1 = 0; hi0 = nx - 1; }
+            } else {
+                if (lo0 < 0) lo0 = 0;
+                if (hi0 >= nx) hi0 = nx - 1;
+            }
+            const uint32_t code_yz = (static_cast<uint32_t>(dy + 1) << (NAUTICLE_NBR_INDEX_BITS + 2)) |
+                                     (static_cast<uint32_t>(dz + 1) << (NAUTICLE_NBR_INDEX_BITS + 4));
+            for (int piece = 0; piece < 2; ++piece) {
+                const int32_t xa = piece == 0 ? lo0 : lo1;
+                const int32_t xb = piece == 0 ? hi0 : hi1;
+                if (xb < xa) continue;
+                const uint32_t q_begin = min(cell_first[row + static_cast<uint32_t>(xa)], n_total);
+                const uint32_t q_end = min(cell_first[row + static_cast<uint32_t>(xb) + 1], n_total);
+                // cell x offset of the piece's first cell, where its next cells
+                // start, and the particle's x in each of those cells' frames
+                int32_t dx0 = xa - c[0];
+                if (dx0 > 1) dx0 -= nx;
+                else if (dx0 < -1) dx0 += nx;
+                const uint32_t b1 = xa + 1 <= xb ? cell_first[row + static_cast<uint32_t>(xa) + 1] : q_end;
+                const uint32_t b2 = xa + 2 <= xb ? cell_first[row + static_cast<uint32_t>(xa) + 2] : q_end;
+                const float tx0 = me.x - static_cast<float>(dx0) * csx;
+                const float tx1 = me.x - static_cast<float>(dx0 + 1) * csx;
+                const float tx2 = me.x - static_cast<float>(dx0 + 2) * csx;
+                for (uint32_t q0 = q_begin; q0 < q_end; q0 += 64) {
+                    const uint32_t m = min(q_end - q0, 64u);
+                    uint64_t hits = 0;
+                    for (uint32_t b = 0; b < m; b += kUnroll) {
+                        float4 o[kUnroll];
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) o[u] = pos4[min(q0 + b + u, q_end - 1)];
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) {
+                            const uint32_t q = q0 + b + u;
+                            const float tx = q < b1 ? tx0 : (q < b2 ? tx1 : tx2);
+                            const float ddx = o[u].x - tx;
+                            const float ddy = o[u].y - ty;
+                            float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
+                            if (dim == 3) {
+                                const float ddz = o[u].z - tz;
+                                r2 = __builtin_fmaf(ddz, ddz, r2);
+                            }
+                            const bool hit = (b + u < m) && (r2 < R2) && (q != p);
+                            hits |= static_cast<uint64_t>(hit) << (b + u);
+                        }
                     }
-                    if (r2 < R2) {
-                        if (cnt < max_nbr) nbr[static_cast<size_t>(cnt) * n_total + p] = q | code;
+                    while (hits) {
+                        const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(hits));
+                        hits &= hits - 1;
+                        const uint32_t q = q0 + b;
+                        const int32_t dx = dx0 + static_cast<int32_t>(q >= b1) + static_cast<int32_t>(q >= b2);
+                        if (cnt < max_nbr)
+                            col[static_cast<size_t>(cnt) * n_total] =
+                                q | code_yz | (static_cast<uint32_t>(dx + 1) << NAUTICLE_NBR_INDEX_BITS);
                         ++cnt;
                     }
                 }
@@ -385,6 +500,7 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     const CaseDev* cases = at<CaseDev>(ws, P.L.cases);
     const Item* items = at<Item>(ws, P.L.items);
     uint32_t* err = at<uint32_t>(ws, P.L.err);
+    const Packed pk = packed(P, ws);
     const int fill_blocks = static_cast<int>((nc + kBlock - 1) / kBlock);
     if (nc > 0) {
         k_fill_u32<<<fill_blocks, kBlock, 0, s>>>(cells.cell_start, nc, NAUTICLE_EMPTY);
@@ -405,7 +521,8 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
         uint32_t* t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
-    k_make_keys<<<P.n_items, kBlock, 0, s>>>(cases, items, in.cell, ka, va);
+    const uint32_t grid = xcd_grid(P.n_items);
+    k_make_keys<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, in.cell, ka, va);
     const uint32_t n_tiles = (n + kTile - 1) / kTile;
     uint32_t* hist = at<uint32_t>(ws, P.L.sort_hist);
     uint32_t* totals = at<uint32_t>(ws, P.L.sort_totals);
@@ -422,9 +539,10 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     // now ka == cells.key, va == cells.perm
     const int nb = static_cast<int>((n + kBlock - 1) / kBlock);
     k_cell_ranges<<<nb, kBlock, 0, s>>>(cells.key, n, cells.cell_start, cells.cell_end);
-    k_reorder<<<nb, kBlock, 0, s>>>(cells.perm, n, P.dim_max, in, sorted);
-    k_nlist<<<P.n_items, kBlock, 0, s>>>(cases, items, sorted, cells.cell_start, cells.cell_end, cells.nbr,
-                                        cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), n, err);
+    k_cell_first<<<(nc + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(cells.key, n, nc, pk.cell_first);
+    k_reorder<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, cells.perm, n, in, sorted, pk.pos4);
+    k_nlist<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, pk.pos4, pk.cell_first, cells.nbr,
+                                    cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), n, err);
     return hipGetLastError();
 }
 

@@ -2,39 +2,65 @@
 // state, and accelerations with the fused semi-implicit Euler update.
 //
 // Both passes walk the neighbour lists built by the search (column-major, so
-// the 64 lanes of a wave read 64 consecutive words per list row) and gather
-// the neighbours' data from sorted SoA arrays, which keeps the gathers
-// spatially local (neighbours are within one cell row of each other in
-// sorted order) and mostly L2 hits.  Every sum is a gather in a fixed order:
-// no atomics, so results are bitwise reproducible.
+// the 64 lanes of a wave read 64 consecutive words per list row).  Each
+// neighbour costs one float4 gather in the density pass (offsets) and two in
+// the force pass (offsets + s, velocity + 1/rho), from arrays in sorted order,
+// so the gathers of a wave stay within a few cells.  Every sum is a gather in
+// list order: no atomics, so results are bitwise reproducible.
 #include "internal.h"
 
 namespace nau {
 
-struct PairGeom {
-    float d[3];  // r_j - r_i (FP32, cell-relative arithmetic)
-    float r2;
+// The cell shift of a list entry, delta * cell_size, looked up by the entry's
+// 6-bit offset code (bits 26..31) in a per-block LDS table.
+struct ShiftTable {
+    float4 v[64];
 };
 
-// Decodes a list entry and forms r_j - r_i exactly as the neighbour
-// predicate did: d_k = fl32(fl32(off_j,k + delta_k cs_k) - off_i,k).
-__device__ inline uint32_t pair_geom(const CaseDev& C, int dim, uint32_t e, uint32_t n_total,
-                                     const StateDev& st, const float oi[3], PairGeom* g)
+// Every thread of the block must call it (contains a barrier).
+__device__ inline void fill_shift_table(const CaseDev& C, ShiftTable* tab)
+{
+    if (threadIdx.x < 64) {
+        const uint32_t code = threadIdx.x;
+        const float sx = static_cast<float>(static_cast<int32_t>(code & 3u) - 1) * C.cs[0];
+        const float sy = static_cast<float>(static_cast<int32_t>((code >> 2) & 3u) - 1) * C.cs[1];
+        const float sz = static_cast<float>(static_cast<int32_t>((code >> 4) & 3u) - 1) * C.cs[2];
+        tab->v[code] = make_float4(sx, sy, sz, 0.0f);
+    }
+    __syncthreads();
+}
+
+// r_j - r_i as the neighbour predicate forms it: the particle is moved into
+// the neighbour's cell frame, d_k = fl32(off_j,k - fl32(off_i,k - shift_k)).
+__device__ inline float3 pair_d(const float4& sh, float ojx, float ojy, float ojz, float oix, float oiy, float oiz)
 {
 #pragma clang fp contract(off)
-    uint32_t j = e & kIndexMask;
-    if (j >= n_total) j = n_total - 1;  // never for lists built by the search; guards memory
-    g->d[2] = 0.0f;
-    for (int k = 0; k < 3; ++k) {
-        if (k >= dim) break;
-        const int32_t dk = static_cast<int32_t>((e >> (NAUTICLE_NBR_INDEX_BITS + 2 * k)) & 3u) - 1;
-        const float sh = static_cast<float>(dk) * C.cs[k];
-        g->d[k] = (st.off[k][j] + sh) - oi[k];
-    }
-    float r2 = __builtin_fmaf(g->d[1], g->d[1], g->d[0] * g->d[0]);
-    if (dim == 3) r2 = __builtin_fmaf(g->d[2], g->d[2], r2);
-    g->r2 = r2;
-    return j;
+    return make_float3(ojx - (oix - sh.x), ojy - (oiy - sh.y), ojz - (oiz - sh.z));
+}
+
+__device__ inline float pair_r2(const float3& d, int dim)
+{
+    float r2 = __builtin_fmaf(d.y, d.y, d.x * d.x);
+    if (dim == 3) r2 = __builtin_fmaf(d.z, d.z, r2);
+    return r2;
+}
+
+__device__ inline uint32_t entry_index(uint32_t e, uint32_t n_total)
+{
+    const uint32_t j = e & kIndexMask;
+    return j < n_total ? j : n_total - 1;  // never out of range for lists built by the search
+}
+
+// Entries of list rows k .. k + kGroup - 1 of particle i (column-major lists,
+// so a wave reads kGroup runs of 64 consecutive words).  Rows at or past
+// max_nbr are not read; rows past the particle's own count hold stale entries,
+// whose contribution the caller masks.
+__device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t k, uint32_t max_nbr,
+                                    uint32_t n_total, uint32_t* e)
+{
+#pragma unroll
+    for (uint32_t u = 0; u < kGroup; ++u)
+        e[u] = k + u < max_nbr ? nbr[static_cast<size_t>(k + u) * n_total + i] : 0u;
 }
 
 // ----------------------------------------------------------------------------
@@ -43,40 +69,65 @@ __device__ inline uint32_t pair_geom(const CaseDev& C, int dim, uint32_t e, uint
 // rho_i = m alpha + sum_j m alpha (1 - q/2)^4 (2q + 1),  q = r_ij / h
 // p_i   = B ((rho_i / rho0)^gamma - 1), evaluated as B expm1(gamma log1p(delta))
 //         with delta = (rho_i - rho0) / rho0 (no cancellation near rho0)
+// Also packs (offsets, s) and (velocity, 1/rho) for the force pass; fixed
+// particles get velocity 0 there.
 
 __global__ void __launch_bounds__(kBlock)
-k_density(const CaseDev* __restrict__ cases, const Item* __restrict__ items, StateDev st,
-          const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count, uint32_t max_nbr,
-          uint32_t n_total, FieldsDev f, uint32_t* err)
+k_density(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
+          const float4* __restrict__ pos4, const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count,
+          uint32_t max_nbr, uint32_t n_total, FieldsDev f, float4* __restrict__ a4, float4* __restrict__ b4,
+          uint32_t* err)
 {
-    const Item it = items[blockIdx.x];
-    if (threadIdx.x >= it.count) return;
+    __shared__ ShiftTable tab;
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
     const CaseDev& C = cases[it.case_id];
+    fill_shift_table(C, &tab);
+    if (threadIdx.x >= it.count) return;
     const uint32_t i = it.first + threadIdx.x;
     const int dim = C.dim;
-    float oi[3] = {0.0f, 0.0f, 0.0f};
-    for (int k = 0; k < 3; ++k)
-        if (k < dim) oi[k] = st.off[k][i];
+    const float4 me = pos4[i];
     uint32_t cnt = nbr_count[i];
     if (cnt > max_nbr) cnt = max_nbr;
     const float inv_h = C.inv_h;
     float sum = 0.0f;
-    for (uint32_t k = 0; k < cnt; ++k) {
-        PairGeom g;
-        pair_geom(C, dim, nbr[static_cast<size_t>(k) * n_total + i], n_total, st, oi, &g);
-        const float q = sqrtf(g.r2) * inv_h;
-        const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
-        const float t2 = t * t;
-        sum = fmaf(t2 * t2, fmaf(2.0f, q, 1.0f), sum);
+    // groups of kGroup pairs; the next group's entries load while this
+    // group's neighbours are gathered
+    uint32_t e[kGroup], en[kGroup];
+    load_entries(nbr, i, 0, max_nbr, n_total, e);
+    for (uint32_t k = 0; k < cnt; k += kGroup) {
+        load_entries(nbr, i, k + kGroup, max_nbr, n_total, en);
+        float4 o[kGroup];
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u) o[u] = pos4[entry_index(e[u], n_total)];
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u) {
+            const float3 d = pair_d(tab.v[e[u] >> NAUTICLE_NBR_INDEX_BITS], o[u].x, o[u].y, o[u].z, me.x, me.y, me.z);
+            const float q = sqrtf(pair_r2(d, dim)) * inv_h;
+            const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
+            const float t2 = t * t;
+            const float w = t2 * t2 * fmaf(2.0f, q, 1.0f);
+            sum += k + u < cnt ? w : 0.0f;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u) e[u] = en[u];
     }
     const float rho = C.m_alpha * (1.0f + sum);
     const float delta = (rho - C.rho0) * C.inv_rho0;
     const float p = C.B * expm1f(C.gamma * log1pf(delta));
     const float inv_rho = 1.0f / rho;
+    const float s = p * inv_rho * inv_rho;
     f.rho[i] = rho;
     f.p[i] = p;
     f.inv_rho[i] = inv_rho;
-    f.s[i] = p * inv_rho * inv_rho;
+    f.s[i] = s;
+    const bool fixed = st.id[i] >= C.n_fluid;
+    float v[3] = {0.0f, 0.0f, 0.0f};
+    for (int c = 0; c < 3; ++c)
+        if (c < dim && !fixed) v[c] = st.vel[c][i];
+    a4[i] = make_float4(me.x, me.y, me.z, s);
+    b4[i] = make_float4(v[0], v[1], v[2], inv_rho);
     if (!isfinite(rho) || !isfinite(p)) set_error(err, kErrNonFinite);
 }
 
@@ -84,9 +135,43 @@ hipError_t launch_density(const Plan& P, void* ws, StateDev sorted, const nautic
                           FieldsDev f, hipStream_t s)
 {
     if (P.n_items == 0) return hipSuccess;
-    k_density<<<P.n_items, kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), sorted,
-                                           cells.nbr, cells.nbr_count, static_cast<uint32_t>(cells.max_nbr),
-                                           P.n_total, f, at<uint32_t>(ws, P.L.err));
+    const Packed pk = packed(P, ws);
+    k_density<<<xcd_grid(P.n_items), kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), P.n_items,
+                                                     sorted, pk.pos4, cells.nbr, cells.nbr_count,
+                                                     static_cast<uint32_t>(cells.max_nbr), P.n_total, f, pk.a4,
+                                                     pk.b4, at<uint32_t>(ws, P.L.err));
+    return hipGetLastError();
+}
+
+// Packs (offsets, s) and (velocity, 1/rho) from caller-provided fields, for
+// a force pass that does not follow a density pass on this workspace.
+__global__ void __launch_bounds__(kBlock)
+k_pack_fields(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
+              FieldsDev f, float4* __restrict__ a4, float4* __restrict__ b4)
+{
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
+    if (threadIdx.x >= it.count) return;
+    const CaseDev& C = cases[it.case_id];
+    const uint32_t i = it.first + threadIdx.x;
+    const bool fixed = st.id[i] >= C.n_fluid;
+    float o[3] = {0.0f, 0.0f, 0.0f}, v[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < 3; ++k)
+        if (k < C.dim) {
+            o[k] = st.off[k][i];
+            v[k] = fixed ? 0.0f : st.vel[k][i];
+        }
+    a4[i] = make_float4(o[0], o[1], o[2], f.s[i]);
+    b4[i] = make_float4(v[0], v[1], v[2], f.inv_rho[i]);
+}
+
+hipError_t launch_pack_fields(const Plan& P, void* ws, StateDev sorted, FieldsDev f, hipStream_t s)
+{
+    if (P.n_items == 0) return hipSuccess;
+    const Packed pk = packed(P, ws);
+    k_pack_fields<<<xcd_grid(P.n_items), kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
+                                                         P.n_items, sorted, f, pk.a4, pk.b4);
     return hipGetLastError();
 }
 
@@ -98,48 +183,64 @@ hipError_t launch_density(const Plan& P, void* ws, StateDev sorted, const nautic
 
 template <bool kIntegrate>
 __global__ void __launch_bounds__(kBlock)
-k_forces(const CaseDev* __restrict__ cases, const Item* __restrict__ items, StateDev st,
-         const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count, uint32_t max_nbr,
-         uint32_t n_total, FieldsDev f, StateDev next, uint32_t* err)
+k_forces(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
+         const float4* __restrict__ a4, const float4* __restrict__ b4, const uint32_t* __restrict__ nbr,
+         const uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total, FieldsDev f, StateDev next,
+         uint32_t* err)
 {
-    const Item it = items[blockIdx.x];
-    if (threadIdx.x >= it.count) return;
+    __shared__ ShiftTable tab;
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
     const CaseDev& C = cases[it.case_id];
+    fill_shift_table(C, &tab);
+    if (threadIdx.x >= it.count) return;
     const uint32_t i = it.first + threadIdx.x;
     const int dim = C.dim;
-    const bool fixed = st.id[i] >= C.n_fluid;
-    float oi[3] = {0.0f, 0.0f, 0.0f}, vi[3] = {0.0f, 0.0f, 0.0f};
-    for (int k = 0; k < 3; ++k)
-        if (k < dim) {
-            oi[k] = st.off[k][i];
-            vi[k] = fixed ? 0.0f : st.vel[k][i];
-        }
-    const float si = f.s[i];
-    const float ki = f.inv_rho[i];
+    const float4 ai4 = a4[i];
+    const float4 bi4 = b4[i];
     const float inv_h = C.inv_h;
     const float m = C.m;
     const float mnu = C.m * C.nu;
     uint32_t cnt = nbr_count[i];
     if (cnt > max_nbr) cnt = max_nbr;
-    float a[3] = {0.0f, 0.0f, 0.0f};
-    for (uint32_t k = 0; k < cnt; ++k) {
-        PairGeom g;
-        const uint32_t j = pair_geom(C, dim, nbr[static_cast<size_t>(k) * n_total + i], n_total, st, oi, &g);
-        const float q = sqrtf(g.r2) * inv_h;
-        const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
-        const float F = C.F_coef * (t * t * t);
-        const bool jfixed = st.id[j] >= C.n_fluid;
-        // pressure: -m (s_i + s_j) F r_ij = +m (s_i + s_j) F d
-        const float cp = m * (si + f.s[j]) * F;
-        // viscosity: m nu (k_i + k_j) F (v_i - v_j)
-        const float cv = mnu * (ki + f.inv_rho[j]) * F;
-        for (int c = 0; c < 3; ++c) {
-            if (c >= dim) break;
-            const float vj = jfixed ? 0.0f : st.vel[c][j];
-            a[c] = fmaf(cp, g.d[c], a[c]);
-            a[c] = fmaf(cv, vi[c] - vj, a[c]);
+    float ax = 0.0f, ay = 0.0f, az = 0.0f;
+    // groups of kGroup pairs; the next group's entries load while this
+    // group's neighbours are gathered
+    uint32_t e[kGroup], en[kGroup];
+    load_entries(nbr, i, 0, max_nbr, n_total, e);
+    for (uint32_t k = 0; k < cnt; k += kGroup) {
+        load_entries(nbr, i, k + kGroup, max_nbr, n_total, en);
+        float4 aj[kGroup], bj[kGroup];
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u) {
+            const uint32_t j = entry_index(e[u], n_total);
+            aj[u] = a4[j];
+            bj[u] = b4[j];
         }
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u) {
+            const float3 d = pair_d(tab.v[e[u] >> NAUTICLE_NBR_INDEX_BITS], aj[u].x, aj[u].y, aj[u].z, ai4.x, ai4.y,
+                                    ai4.z);
+            const float q = sqrtf(pair_r2(d, dim)) * inv_h;
+            const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
+            // a pair past the end of the list contributes nothing
+            const float F = k + u < cnt ? C.F_coef * (t * t * t) : 0.0f;
+            // pressure: -m (s_i + s_j) F r_ij = +m (s_i + s_j) F d
+            const float cp = m * (ai4.w + aj[u].w) * F;
+            // viscosity: m nu (k_i + k_j) F (v_i - v_j)
+            const float cv = mnu * (bi4.w + bj[u].w) * F;
+            ax = fmaf(cp, d.x, fmaf(cv, bi4.x - bj[u].x, ax));
+            ay = fmaf(cp, d.y, fmaf(cv, bi4.y - bj[u].y, ay));
+            az = fmaf(cp, d.z, fmaf(cv, bi4.z - bj[u].z, az));
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u) e[u] = en[u];
     }
+    const bool fixed = st.id[i] >= C.n_fluid;
+    float a[3] = {ax, ay, az};
+    const float vi[3] = {bi4.x, bi4.y, bi4.z};
+    const float oi[3] = {ai4.x, ai4.y, ai4.z};
     bool finite = true;
     for (int c = 0; c < 3; ++c) {
         if (c >= dim) break;
@@ -181,14 +282,16 @@ hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticl
     const CaseDev* cases = at<CaseDev>(ws, P.L.cases);
     const Item* items = at<Item>(ws, P.L.items);
     uint32_t* err = at<uint32_t>(ws, P.L.err);
+    const Packed pk = packed(P, ws);
     const uint32_t mx = static_cast<uint32_t>(cells.max_nbr);
+    const uint32_t grid = xcd_grid(P.n_items);
     if (next) {
-        k_forces<true><<<P.n_items, kBlock, 0, s>>>(cases, items, sorted, cells.nbr, cells.nbr_count, mx,
-                                                    P.n_total, f, *next, err);
+        k_forces<true><<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, pk.a4, pk.b4, cells.nbr,
+                                               cells.nbr_count, mx, P.n_total, f, *next, err);
     } else {
         StateDev none{};
-        k_forces<false><<<P.n_items, kBlock, 0, s>>>(cases, items, sorted, cells.nbr, cells.nbr_count, mx,
-                                                     P.n_total, f, none, err);
+        k_forces<false><<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, pk.a4, pk.b4, cells.nbr,
+                                                cells.nbr_count, mx, P.n_total, f, none, err);
     }
     return hipGetLastError();
 }

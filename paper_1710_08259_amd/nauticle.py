@@ -114,7 +114,8 @@ def lib():
     L.nauticle_sph_forces.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CFields), P(CState), vp,
                                       ctypes.c_size_t, vp]
     L.nauticle_step.restype = st
-    L.nauticle_step.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), vp, ctypes.c_size_t, vp]
+    L.nauticle_step.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(vp), vp,
+                                ctypes.c_size_t, vp]
     L.nauticle_sph_adjoint.restype = st
     L.nauticle_sph_adjoint.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CFields), P(ptr3), P(ptr3),
                                        P(ptr3), P(ptr3), vp, vp, vp, ctypes.c_size_t, vp]
@@ -343,9 +344,20 @@ class Problem:
                                          ctypes.byref(f.c()), nxt, *self._ws()), "nauticle_sph_forces")
         return f
 
-    def step(self, st: State, n_steps: int = 1) -> State:
+    def step(self, st: State, n_steps: int = 1, events=None) -> State:
+        """n_steps steps in place.  `events` (optional): 4 * n_steps
+        torch.cuda.Event(enable_timing=True) recorded at each step's start
+        and after its search, density and force phases."""
+        ev = None
+        if events is not None:
+            if len(events) != 4 * n_steps:
+                raise ValueError("need 4 events per step")
+            for e in events:  # torch creates the HIP event on first record
+                if e.cuda_event == 0:
+                    e.record(torch.cuda.current_stream(self.device))
+            ev = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
         _check(lib().nauticle_step(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
-                                   ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()), *self._ws()),
+                                   ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()), ev, *self._ws()),
                "nauticle_step")
         return st
 

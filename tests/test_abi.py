@@ -92,7 +92,7 @@ def test_unprepared_workspace_is_rejected_without_touching_the_device(N):
     assert N.lib().nauticle_prepare(table, 1, None, 0, None) == N.ERR_WORKSPACE
     assert N.lib().nauticle_check(None, 0, None) == N.ERR_WORKSPACE
     fake = ctypes.c_void_p(0x1000)
-    st = N.lib().nauticle_step(table, 1, None, 1, None, None, fake, 1 << 20, None)
+    st = N.lib().nauticle_step(table, 1, None, 1, None, None, None, fake, 1 << 20, None)
     assert st == N.ERR_WORKSPACE
 
 
