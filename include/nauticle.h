@@ -158,19 +158,39 @@ typedef struct {
     float* acc[3];
 } nauticle_fields;
 
+/* Launch shape of the neighbour loops (search, density, forces, adjoint),
+ * chosen per workload by the autotuner; results do not depend on it.
+ *   block:         particles per work item = threads per workgroup, one of
+ *                  64, 128, 256 (0 = 256);
+ *   persistent:    0 = one workgroup per item; 1 = a persistent grid of
+ *                  groups_per_cu workgroups per compute unit pulls items
+ *                  from a queue ordered by decreasing estimated cost
+ *                  (particles x expected neighbours), one atomic counter per
+ *                  launch;
+ *   groups_per_cu: persistent grid size per compute unit (0 = 4). */
+typedef struct {
+    int32_t block;
+    int32_t persistent;
+    int32_t groups_per_cu;
+    int32_t reserved;
+} nauticle_tuning;
+
 /* Number of cell keys over all cases (sum of ncell products). */
 int64_t nauticle_cells_total(const nauticle_case* cases, int32_t n_cases);
 
-/* Bytes of device workspace needed for these cases.  Host only. */
+/* Bytes of device workspace needed for these cases (with any tuning).
+ * Host only. */
 nauticle_status nauticle_workspace_bytes(const nauticle_case* cases, int32_t n_cases,
                                          size_t* bytes);
 
 /* Validates the case table on the host, writes the device case table and
  * the launch work lists into `ws`, waits for the copy to finish, and
- * records the table's fingerprint for `ws`.  Must precede every other call
- * on `ws`; call again whenever any case constant changes. */
-nauticle_status nauticle_prepare(const nauticle_case* cases, int32_t n_cases, void* ws,
-                                 size_t ws_bytes, hipStream_t stream);
+ * records the table's fingerprint and the tuning (NULL = defaults) for
+ * `ws`.  Must precede every other call on `ws`; call again whenever any
+ * case constant or the tuning changes. */
+nauticle_status nauticle_prepare(const nauticle_case* cases, int32_t n_cases,
+                                 const nauticle_tuning* tuning, void* ws, size_t ws_bytes,
+                                 hipStream_t stream);
 
 /* Absolute FP32 positions pos[k][i] (device, k < dim) -> cell-relative
  * state: cell, off, and id = i - offset of i's case.  Velocities are not

@@ -1,0 +1,82 @@
+"""Autotuner for the launch shape of the neighbour loops.
+
+For a set of cases it times a short run of full steps under every candidate
+tuning (particles per work item / threads per workgroup, grid vs persistent
+launch, persistent workgroups per compute unit) with HIP events on the
+library's stream, and keeps the fastest.  Results are cached as JSON per
+workload bucket: dimension, log2 of particles per cell, log2 of the total
+particle count and log2 of the number of cases.  The tuning changes only how
+work is distributed, never the arithmetic: every candidate gives bitwise the
+same results.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Optional
+
+import torch
+
+from . import nauticle as N
+
+CANDIDATES = tuple(N.Tuning(block=b, persistent=p, groups_per_cu=g)
+                   for b in (64, 128, 256)
+                   for (p, g) in ((0, 4), (1, 2), (1, 4), (1, 8)))
+
+
+def bucket(cases) -> str:
+    n = sum(c.n for c in cases)
+    cells = sum(c.n_cells for c in cases)
+    ppc = max(n / max(cells, 1), 1e-3)
+    return (f"d{cases[0].dim}-ppc{round(math.log2(ppc))}-n{round(math.log2(max(n, 1)))}"
+            f"-c{round(math.log2(len(cases)))}")
+
+
+def default_cache_path() -> str:
+    base = os.environ.get("NAUTICLE_TUNE_CACHE")
+    if base:
+        return base
+    return os.path.join(os.path.expanduser("~"), ".cache", "nauticle", "tuning.json")
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def time_tuning(cases, tuning: N.Tuning, steps: int = 3, warmup: int = 1, device="cuda:0") -> float:
+    """Mean GPU milliseconds per full step under `tuning`."""
+    prob = N.Problem(cases, device=device, tuning=tuning)
+    st = prob.state_from_cases()
+    prob.step(st, warmup)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * steps)]
+    prob.step(st, steps, events=ev)
+    torch.cuda.synchronize()
+    prob.check()
+    return sum(ev[4 * k].elapsed_time(ev[4 * k + 3]) for k in range(steps)) / steps
+
+
+def tune(cases, steps: int = 3, candidates=CANDIDATES, cache_path: Optional[str] = None, device="cuda:0",
+         force: bool = False):
+    """Best tuning for `cases` (from the cache unless `force`), and the table
+    of timings {tuning: ms per step} when it was measured now."""
+    path = cache_path or default_cache_path()
+    key = bucket(cases)
+    cache = _load(path)
+    if key in cache and not force:
+        return N.Tuning(**cache[key]["tuning"]), None
+    timings = {}
+    for cand in candidates:
+        timings[cand] = time_tuning(cases, cand, steps=steps, device=device)
+    best = min(timings, key=timings.get)
+    cache[key] = {"tuning": {"block": best.block, "persistent": best.persistent,
+                             "groups_per_cu": best.groups_per_cu},
+                  "ms_per_step": timings[best]}
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    return best, timings

@@ -23,7 +23,7 @@ __device__ inline void block_reduce2(double a, double b, double* sh_a, double* s
     sh_a[threadIdx.x] = a;
     sh_b[threadIdx.x] = b;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
+    for (int s = static_cast<int>(blockDim.x) / 2; s > 0; s >>= 1) {
         if (threadIdx.x < static_cast<unsigned>(s)) {
             sh_a[threadIdx.x] += sh_a[threadIdx.x + s];
             sh_b[threadIdx.x] += sh_b[threadIdx.x + s];
@@ -61,7 +61,7 @@ __device__ inline uint32_t adj_index(uint32_t e, uint32_t n_total)
 }  // namespace
 
 // A_i = dt (lam_v'_i + dt lam_x'_i) for fluid particles, 0 for fixed ones.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxBlock)
 k_adj_prep(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
            const float* __restrict__ lxn0, const float* __restrict__ lxn1, const float* __restrict__ lxn2,
            const float* __restrict__ lvn0, const float* __restrict__ lvn1, const float* __restrict__ lvn2,
@@ -85,8 +85,8 @@ k_adj_prep(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ui
 }
 
 // Pass A.
-__global__ void __launch_bounds__(kBlock)
-k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
+__global__ void __launch_bounds__(kMaxBlock)
+k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
         const float4* __restrict__ a4, const float4* __restrict__ b4, const float4* __restrict__ adj4,
         const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count, uint32_t max_nbr,
         uint32_t n_total, FieldsDev f, const uint32_t* __restrict__ perm, const float* __restrict__ lxn0,
@@ -94,88 +94,83 @@ k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint3
         const float* __restrict__ lvn1, const float* __restrict__ lvn2, float* lv0, float* lv1, float* lv2,
         float4* __restrict__ adj4b, double* __restrict__ partial)
 {
-    __shared__ double sh_a[kBlock];
-    __shared__ double sh_b[kBlock];
-    const uint32_t ix = xcd_item(n_items);
-    if (ix >= n_items) return;  // uniform over the block
-    const Item it = items[ix];
-    const CaseDev& C = cases[it.case_id];
-    const bool active = threadIdx.x < it.count;
-    double nu_term = 0.0, c0_term = 0.0;
-    if (active) {
-        const uint32_t i = it.first + threadIdx.x;
-        const int dim = C.dim;
-        const bool fixed = st.id[i] >= C.n_fluid;
-        const float4 ai = a4[i], bi = b4[i], Ai = adj4[i];
-        const float m = C.m, mnu = C.m * C.nu;
-        uint32_t cnt = nbr_count[i];
-        if (cnt > max_nbr) cnt = max_nbr;
-        float sbar = 0.0f, kbar = 0.0f, nubar = 0.0f;
-        float vvx = 0.0f, vvy = 0.0f, vvz = 0.0f;
-        const uint32_t* col = nbr + i;
-        for (uint32_t k = 0; k < cnt; ++k) {
-            const uint32_t e = col[static_cast<size_t>(k) * n_total];
-            const uint32_t j = adj_index(e, n_total);
-            const float4 aj = a4[j], bj = b4[j], Aj = adj4[j];
-            const float3 d = adj_d(C, e, aj, ai);
-            const float q = sqrtf(adj_r2(d, dim)) * C.inv_h;
-            const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
-            const float F = C.F_coef * (t * t * t);
-            const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
-            const float dvx = bi.x - bj.x, dvy = bi.y - bj.y, dvz = bi.z - bj.z;
-            const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
-            const float dvdA = fmaf(dvz, dAz, fmaf(dvy, dAy, dvx * dAx));
-            const float Aidv = fmaf(Ai.z, dvz, fmaf(Ai.y, dvy, Ai.x * dvx));
-            // r_ij = -d: sbar_i = -m sum F r_ij.dA = m sum F d.dA
-            sbar = fmaf(m * F, ddA, sbar);
-            kbar = fmaf(mnu * F, dvdA, kbar);
-            const float w = m * (bi.w + bj.w) * F;
-            const float wn = C.nu * w;
-            vvx = fmaf(wn, dAx, vvx);
-            vvy = fmaf(wn, dAy, vvy);
-            vvz = fmaf(wn, dAz, vvz);
-            nubar = fmaf(w, Aidv, nubar);
+    __shared__ double sh_a[kMaxBlock];
+    __shared__ double sh_b[kMaxBlock];
+    __shared__ uint32_t s_pos;
+    for_each_item(Q, &s_pos, [&](uint32_t ix) {
+        const Item it = items[ix];
+        const CaseDev& C = cases[it.case_id];
+        const bool active = threadIdx.x < it.count;
+        double nu_term = 0.0, c0_term = 0.0;
+        if (active) {
+            const uint32_t i = it.first + threadIdx.x;
+            const int dim = C.dim;
+            const bool fixed = st.id[i] >= C.n_fluid;
+            const float4 ai = a4[i], bi = b4[i], Ai = adj4[i];
+            const float m = C.m, mnu = C.m * C.nu;
+            uint32_t cnt = nbr_count[i];
+            if (cnt > max_nbr) cnt = max_nbr;
+            float sbar = 0.0f, kbar = 0.0f, nubar = 0.0f;
+            float vvx = 0.0f, vvy = 0.0f, vvz = 0.0f;
+            const uint32_t* col = nbr + i;
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const uint32_t e = col[static_cast<size_t>(k) * n_total];
+                const uint32_t j = adj_index(e, n_total);
+                const float4 aj = a4[j], bj = b4[j], Aj = adj4[j];
+                const float3 d = adj_d(C, e, aj, ai);
+                const float q = sqrtf(adj_r2(d, dim)) * C.inv_h;
+                const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
+                const float F = C.F_coef * (t * t * t);
+                const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
+                const float dvx = bi.x - bj.x, dvy = bi.y - bj.y, dvz = bi.z - bj.z;
+                const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
+                const float dvdA = fmaf(dvz, dAz, fmaf(dvy, dAy, dvx * dAx));
+                const float Aidv = fmaf(Ai.z, dvz, fmaf(Ai.y, dvy, Ai.x * dvx));
+                // r_ij = -d: sbar_i = -m sum F r_ij.dA = m sum F d.dA
+                sbar = fmaf(m * F, ddA, sbar);
+                kbar = fmaf(mnu * F, dvdA, kbar);
+                const float w = m * (bi.w + bj.w) * F;
+                const float wn = C.nu * w;
+                vvx = fmaf(wn, dAx, vvx);
+                vvy = fmaf(wn, dAy, vvy);
+                vvz = fmaf(wn, dAz, vvz);
+                nubar = fmaf(w, Aidv, nubar);
+            }
+            const float p = f.p[i];
+            const float inv_rho2 = bi.w * bi.w;
+            const float inv_rho3 = inv_rho2 * bi.w;
+            const float rhobar = sbar * (C.gamma * (p + C.B) - 2.0f * p) * inv_rho3 - kbar * inv_rho2;
+            adj4b[i] = make_float4(Ai.x, Ai.y, Ai.z, rhobar);
+            nu_term = static_cast<double>(nubar);
+            c0_term = static_cast<double>(sbar) * (2.0 * static_cast<double>(p) / C.c0) * static_cast<double>(inv_rho2);
+            const uint32_t dst = perm[i] < n_total ? perm[i] : i;
+            const float* lx[3] = {lxn0, lxn1, lxn2};
+            const float* lvn[3] = {lvn0, lvn1, lvn2};
+            float* lv[3] = {lv0, lv1, lv2};
+            const float vv[3] = {vvx, vvy, vvz};
+            for (int c = 0; c < 3; ++c) {
+                if (c >= dim) break;
+                const float vh = fmaf(C.dt, lx[c][i], lvn[c][i]);
+                lv[c][dst] = fixed ? 0.0f : vh + vv[c];
+            }
         }
-        const float p = f.p[i];
-        const float inv_rho2 = bi.w * bi.w;
-        const float inv_rho3 = inv_rho2 * bi.w;
-        const float rhobar = sbar * (C.gamma * (p + C.B) - 2.0f * p) * inv_rho3 - kbar * inv_rho2;
-        adj4b[i] = make_float4(Ai.x, Ai.y, Ai.z, rhobar);
-        nu_term = static_cast<double>(nubar);
-        c0_term = static_cast<double>(sbar) * (2.0 * static_cast<double>(p) / C.c0) * static_cast<double>(inv_rho2);
-        const uint32_t dst = perm[i] < n_total ? perm[i] : i;
-        const float* lx[3] = {lxn0, lxn1, lxn2};
-        const float* lvn[3] = {lvn0, lvn1, lvn2};
-        float* lv[3] = {lv0, lv1, lv2};
-        const float vv[3] = {vvx, vvy, vvz};
-        for (int c = 0; c < 3; ++c) {
-            if (c >= dim) break;
-            const float vh = fmaf(C.dt, lx[c][i], lvn[c][i]);
-            lv[c][dst] = fixed ? 0.0f : vh + vv[c];
+        double sa, sb;
+        block_reduce2(nu_term, c0_term, sh_a, sh_b, &sa, &sb);
+        if (threadIdx.x == 0) {
+            partial[2 * ix] = sa;
+            partial[2 * ix + 1] = sb;
         }
-    }
-    double sa, sb;
-    block_reduce2(nu_term, c0_term, sh_a, sh_b, &sa, &sb);
-    if (threadIdx.x == 0) {
-        partial[2 * ix] = sa;
-        partial[2 * ix + 1] = sb;
-    }
+    });
 }
 
 // Pass B.
-__global__ void __launch_bounds__(kBlock)
-k_adj_b(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
-        const float4* __restrict__ a4, const float4* __restrict__ b4, const float4* __restrict__ adj4b,
-        const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count, uint32_t max_nbr,
-        uint32_t n_total, const uint32_t* __restrict__ perm, const float* __restrict__ lxn0,
-        const float* __restrict__ lxn1, const float* __restrict__ lxn2, float* lx0, float* lx1, float* lx2)
+__device__ inline void adj_b_particle(const CaseDev& C, uint32_t i, StateDev st, const float4* __restrict__ a4,
+                                      const float4* __restrict__ b4, const float4* __restrict__ adj4b,
+                                      const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count,
+                                      uint32_t max_nbr, uint32_t n_total, const uint32_t* __restrict__ perm,
+                                      const float* __restrict__ lxn0, const float* __restrict__ lxn1,
+                                      const float* __restrict__ lxn2, float* lx0, float* lx1, float* lx2)
 {
-    const uint32_t ix = xcd_item(n_items);
-    if (ix >= n_items) return;
-    const Item it = items[ix];
-    if (threadIdx.x >= it.count) return;
-    const CaseDev& C = cases[it.case_id];
-    const uint32_t i = it.first + threadIdx.x;
     const int dim = C.dim;
     const bool fixed = st.id[i] >= C.n_fluid;
     const uint32_t dst = perm[i] < n_total ? perm[i] : i;
@@ -223,6 +218,22 @@ k_adj_b(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint3
         if (c < dim) lx[c][dst] = lxn[c][i] + acc[c];
 }
 
+__global__ void __launch_bounds__(kMaxBlock)
+k_adj_b(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
+        const float4* __restrict__ a4, const float4* __restrict__ b4, const float4* __restrict__ adj4b,
+        const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count, uint32_t max_nbr,
+        uint32_t n_total, const uint32_t* __restrict__ perm, const float* __restrict__ lxn0,
+        const float* __restrict__ lxn1, const float* __restrict__ lxn2, float* lx0, float* lx1, float* lx2)
+{
+    __shared__ uint32_t s_pos;
+    for_each_item(Q, &s_pos, [&](uint32_t ix) {
+        const Item it = items[ix];
+        if (threadIdx.x < it.count)
+            adj_b_particle(cases[it.case_id], it.first + threadIdx.x, st, a4, b4, adj4b, nbr, nbr_count, max_nbr,
+                           n_total, perm, lxn0, lxn1, lxn2, lx0, lx1, lx2);
+    });
+}
+
 // Adds each case's sum of item partials (in item order) to out_a / out_b.
 // With per_case_mean, out_a gets the sum divided by (n_fluid * dim).
 __global__ void k_reduce_cases(const CaseDev* __restrict__ cases, int n_cases, const double* __restrict__ partial,
@@ -258,14 +269,17 @@ hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nautic
     const uint32_t grid = xcd_grid(P.n_items);
     hipError_t e = launch_pack_fields(P, ws, sorted, f, s);
     if (e != hipSuccess) return e;
-    k_adj_prep<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, lxn[0], lxn[1], lxn[2], lvn[0], lvn[1],
-                                       lvn[2], pk.adj4);
-    k_adj_a<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, pk.a4, pk.b4, pk.adj4, cells.nbr,
-                                    cells.nbr_count, mx, P.n_total, f, cells.perm, lxn[0], lxn[1], lxn[2], lvn[0],
-                                    lvn[1], lvn[2], lv[0], lv[1], lv[2], pk.adj4b, partial);
-    k_adj_b<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, pk.a4, pk.b4, pk.adj4b, cells.nbr,
-                                    cells.nbr_count, mx, P.n_total, cells.perm, lxn[0], lxn[1], lxn[2], lx[0],
-                                    lx[1], lx[2]);
+    k_adj_prep<<<grid, P.block, 0, s>>>(cases, items, P.n_items, sorted, lxn[0], lxn[1], lxn[2], lvn[0], lvn[1],
+                                        lvn[2], pk.adj4);
+    ItemQueue Qa, Qb;
+    if ((e = item_queue(P, ws, 3, s, &Qa)) != hipSuccess) return e;
+    k_adj_a<<<grid_for(P), P.block, 0, s>>>(cases, items, Qa, sorted, pk.a4, pk.b4, pk.adj4, cells.nbr,
+                                            cells.nbr_count, mx, P.n_total, f, cells.perm, lxn[0], lxn[1], lxn[2],
+                                            lvn[0], lvn[1], lvn[2], lv[0], lv[1], lv[2], pk.adj4b, partial);
+    if ((e = item_queue(P, ws, 4, s, &Qb)) != hipSuccess) return e;
+    k_adj_b<<<grid_for(P), P.block, 0, s>>>(cases, items, Qb, sorted, pk.a4, pk.b4, pk.adj4b, cells.nbr,
+                                            cells.nbr_count, mx, P.n_total, cells.perm, lxn[0], lxn[1], lxn[2],
+                                            lx[0], lx[1], lx[2]);
     const int nb = (P.n_cases + kBlock - 1) / kBlock;
     k_reduce_cases<<<nb, kBlock, 0, s>>>(cases, P.n_cases, partial, dnu, dc0, 1, 0);
     return hipGetLastError();
@@ -275,7 +289,7 @@ hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nautic
 // rollout loss between two states matched by id
 // ----------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxBlock)
 k_inverse_id(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
              const uint32_t* __restrict__ id, uint32_t* __restrict__ inv)
 {
@@ -290,13 +304,13 @@ k_inverse_id(const CaseDev* __restrict__ cases, const Item* __restrict__ items, 
     inv[C.offset + k] = p;
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxBlock)
 k_position_loss(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev a,
                 StateDev b, const uint32_t* __restrict__ inv_b, float* g0, float* g1, float* g2,
                 double* __restrict__ partial)
 {
-    __shared__ double sh_a[kBlock];
-    __shared__ double sh_b[kBlock];
+    __shared__ double sh_a[kMaxBlock];
+    __shared__ double sh_b[kMaxBlock];
     const uint32_t ix = xcd_item(n_items);
     if (ix >= n_items) return;  // uniform over the block
     const Item it = items[ix];
@@ -343,8 +357,8 @@ hipError_t launch_position_loss(const Plan& P, void* ws, StateDev a, StateDev b,
     uint32_t* inv = at<uint32_t>(ws, P.L.inv_map);
     double* partial = at<double>(ws, P.L.partial);
     const uint32_t grid = xcd_grid(P.n_items);
-    k_inverse_id<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, b.id, inv);
-    k_position_loss<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, a, b, inv, grad ? grad[0] : nullptr,
+    k_inverse_id<<<grid, P.block, 0, s>>>(cases, items, P.n_items, b.id, inv);
+    k_position_loss<<<grid, P.block, 0, s>>>(cases, items, P.n_items, a, b, inv, grad ? grad[0] : nullptr,
                                             grad ? grad[1] : nullptr, grad ? grad[2] : nullptr, partial);
     const int nb = (P.n_cases + kBlock - 1) / kBlock;
     k_reduce_cases<<<nb, kBlock, 0, s>>>(cases, P.n_cases, partial, loss, nullptr, 0, 1);

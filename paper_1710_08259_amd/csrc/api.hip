@@ -56,21 +56,38 @@ struct Derived {
     Plan plan;
     std::vector<CaseDev> cases;
     std::vector<Item> items;
+    std::vector<uint32_t> queue;
 };
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// Validates the case table and derives the device table, work list, layout.
-nauticle_status derive(const nauticle_case* cases, int32_t n_cases, Derived* D)
+// Validates the case table and tuning and derives the device table, the
+// work list (blocks of tuning.block particles), the cost-ordered queue and
+// the workspace layout.  The layout is sized for the smallest block, so one
+// workspace size serves every tuning.
+nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nauticle_tuning* tuning, Derived* D)
 {
+    nauticle_tuning tn{256, 0, 4, 0};
+    if (tuning) {
+        tn = *tuning;
+        if (tn.block == 0) tn.block = 256;
+        if (tn.groups_per_cu == 0) tn.groups_per_cu = 4;
+        if ((tn.block != 64 && tn.block != 128 && tn.block != 256) || (tn.persistent != 0 && tn.persistent != 1) ||
+            tn.groups_per_cu < 1 || tn.groups_per_cu > 64)
+            return fail(NAUTICLE_ERR_INVALID_ARG, "tuning: block in {64,128,256}, persistent in {0,1}, groups_per_cu in [1,64]");
+    }
+    const int64_t block = tn.block;
     if (!cases || n_cases < 1) return fail(NAUTICLE_ERR_INVALID_ARG, "cases is null or n_cases < 1");
     D->cases.clear();
     D->items.clear();
+    D->queue.clear();
     Plan& P = D->plan;
     std::memset(&P, 0, sizeof(P));
     P.n_cases = n_cases;
     const int dim0 = cases[0].dom.dim;
     uint64_t n_total = 0, n_cells_total = 0, n_fluid_total = 0;
+    int64_t worst_items = 0;
+    std::vector<double> nbr_per_particle;
     for (int32_t b = 0; b < n_cases; ++b) {
         const nauticle_case& c = cases[b];
         const nauticle_domain& d = c.dom;
@@ -137,14 +154,20 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, Derived* D)
         C.nu = static_cast<float>(q.nu);
         C.dt = static_cast<float>(q.dt);
         C.item_first = static_cast<uint32_t>(D->items.size());
-        for (int64_t first = 0; first < c.n; first += kBlock) {
+        for (int64_t first = 0; first < c.n; first += block) {
             Item it;
             it.case_id = static_cast<uint32_t>(b);
             it.first = static_cast<uint32_t>(n_total + first);
-            it.count = static_cast<uint32_t>(std::min<int64_t>(kBlock, c.n - first));
+            it.count = static_cast<uint32_t>(std::min<int64_t>(block, c.n - first));
             it.pad = 0;
             D->items.push_back(it);
         }
+        worst_items += (c.n + 63) / 64;
+        // expected neighbours per particle at the case's mean number density
+        double volume = 1.0;
+        for (int k = 0; k < d.dim; ++k) volume *= d.ncell[k] * d.cell_size[k];
+        const double ball = d.dim == 2 ? M_PI * 4.0 * q.h * q.h : 4.0 / 3.0 * M_PI * 8.0 * q.h * q.h * q.h;
+        nbr_per_particle.push_back(static_cast<double>(c.n) / volume * ball);
         C.item_count = static_cast<uint32_t>(D->items.size()) - C.item_first;
         D->cases.push_back(C);
         n_total += static_cast<uint64_t>(c.n);
@@ -159,6 +182,24 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, Derived* D)
     P.n_cells_total = static_cast<uint32_t>(n_cells_total);
     P.n_fluid_total = static_cast<uint32_t>(n_fluid_total);
     P.n_items = static_cast<uint32_t>(D->items.size());
+    P.block = static_cast<uint32_t>(block);
+    P.persistent = static_cast<uint32_t>(tn.persistent);
+    int cus = 256;
+    if (tn.persistent) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            return fail(NAUTICLE_ERR_HIP, "could not query the number of compute units");
+    }
+    P.persistent_grid = static_cast<uint32_t>(cus * tn.groups_per_cu);
+    // queue: items by decreasing estimated cost (particles x expected neighbours), ties in item order
+    D->queue.resize(D->items.size());
+    for (size_t k = 0; k < D->queue.size(); ++k) D->queue[k] = static_cast<uint32_t>(k);
+    std::stable_sort(D->queue.begin(), D->queue.end(), [&](uint32_t a, uint32_t b) {
+        const Item& A = D->items[a];
+        const Item& B = D->items[b];
+        return A.count * nbr_per_particle[A.case_id] > B.count * nbr_per_particle[B.case_id];
+    });
     int bits = 1;
     while ((1ull << bits) < n_cells_total) ++bits;
     P.key_bits = bits;
@@ -176,7 +217,10 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, Derived* D)
     };
     L.err = take(sizeof(uint32_t));
     L.cases = take(sizeof(CaseDev) * D->cases.size());
-    L.items = take(sizeof(Item) * std::max<size_t>(D->items.size(), 1));
+    const size_t n_items_max = std::max<size_t>(static_cast<size_t>(worst_items), 1);
+    L.items = take(sizeof(Item) * n_items_max);
+    L.queue = take(sizeof(uint32_t) * n_items_max);
+    L.counters = take(sizeof(uint32_t) * kCounters);
     for (int k = 0; k < 8; ++k) L.state[k] = take(4 * N);
     L.sort_keys = take(4 * N);
     L.sort_vals = take(4 * N);
@@ -188,7 +232,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, Derived* D)
     L.b4 = take(16 * N);
     L.adj4 = take(16 * N);
     L.adj4b = take(16 * N);
-    L.partial = take(2 * sizeof(double) * std::max<size_t>(D->items.size(), 1));
+    L.partial = take(2 * sizeof(double) * n_items_max);
     L.inv_map = take(4 * N);
     L.total = off;
     return NAUTICLE_OK;
@@ -305,17 +349,17 @@ nauticle_status nauticle_workspace_bytes(const nauticle_case* cases, int32_t n_c
 {
     if (!bytes) return fail(NAUTICLE_ERR_INVALID_ARG, "bytes is null");
     Derived D;
-    nauticle_status st = derive(cases, n_cases, &D);
+    nauticle_status st = derive(cases, n_cases, nullptr, &D);
     if (st != NAUTICLE_OK) return st;
     *bytes = D.plan.L.total;
     return NAUTICLE_OK;
 }
 
-nauticle_status nauticle_prepare(const nauticle_case* cases, int32_t n_cases, void* ws, size_t ws_bytes,
-                                 hipStream_t stream)
+nauticle_status nauticle_prepare(const nauticle_case* cases, int32_t n_cases, const nauticle_tuning* tuning,
+                                 void* ws, size_t ws_bytes, hipStream_t stream)
 {
     Derived D;
-    nauticle_status st = derive(cases, n_cases, &D);
+    nauticle_status st = derive(cases, n_cases, tuning, &D);
     if (st != NAUTICLE_OK) return st;
     if (!ws) return fail(NAUTICLE_ERR_WORKSPACE, "workspace is null");
     if (ws_bytes < D.plan.L.total)
@@ -326,6 +370,9 @@ nauticle_status nauticle_prepare(const nauticle_case* cases, int32_t n_cases, vo
                            hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && !D.items.empty())
         e = hipMemcpyAsync(at<char>(ws, D.plan.L.items), D.items.data(), sizeof(Item) * D.items.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !D.queue.empty())
+        e = hipMemcpyAsync(at<char>(ws, D.plan.L.queue), D.queue.data(), sizeof(uint32_t) * D.queue.size(),
                            hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "nauticle_prepare upload");

@@ -76,6 +76,8 @@ struct Layout {
     size_t err;
     size_t cases;
     size_t items;
+    size_t queue;        // item indices in decreasing estimated cost (persistent launches)
+    size_t counters;     // one queue counter per neighbour-loop launch of a step
     size_t state[8];     // scratch state for nauticle_step: cell, off[3], vel[3], id
     size_t sort_keys;    // ping-pong keys
     size_t sort_vals;    // ping-pong values
@@ -112,6 +114,9 @@ struct Plan {
     uint32_t n_items;
     uint32_t n_fluid_total;
     int key_bits;
+    uint32_t block;          // threads per workgroup = particles per item
+    uint32_t persistent;     // neighbour loops as persistent grids
+    uint32_t persistent_grid;
     Layout L;
     // host copies (for launches that need per-case sizes)
     const CaseDev* host_cases;
@@ -126,6 +131,17 @@ inline Packed packed(const Plan& P, void* ws)
                   at<float4>(ws, P.L.adj4), at<float4>(ws, P.L.adj4b), at<uint32_t>(ws, P.L.cell_first)};
 }
 
+// How a neighbour-loop kernel finds its work items.
+struct ItemQueue {
+    uint32_t n_items;
+    uint32_t persistent;
+    const uint32_t* order;  // queue position -> item index
+    uint32_t* counter;      // next queue position (zeroed before the launch)
+};
+
+constexpr int kMaxBlock = 256;
+constexpr int kCounters = 8;  // queue counters in the workspace
+
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X, each
 // with its own L2.  Tiles are consecutive in space, so giving every XCD one
 // contiguous run of tiles keeps neighbouring tiles (which read the same
@@ -139,6 +155,37 @@ __device__ inline uint32_t xcd_item(uint32_t n_items)
     const uint32_t per = (n_items + kXcds - 1) / kXcds;
     return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
 }
+
+// Runs body(item) for the items this workgroup owns: its one XCD-mapped
+// item (grid launch), or items pulled from the cost-ordered queue until the
+// queue is empty (persistent launch; every workgroup reaches the end).
+// Every thread of the block must call it; body may contain barriers.
+template <typename Body>
+__device__ inline void for_each_item(const ItemQueue& Q, uint32_t* s_pos, Body&& body)
+{
+    if (!Q.persistent) {
+        const uint32_t ix = xcd_item(Q.n_items);
+        if (ix < Q.n_items) body(ix);
+        return;
+    }
+    for (;;) {
+        if (threadIdx.x == 0) *s_pos = atomicAdd(Q.counter, 1u);
+        __syncthreads();
+        const uint32_t pos = *s_pos;
+        __syncthreads();
+        if (pos >= Q.n_items) break;
+        body(Q.order[pos]);
+    }
+}
+
+inline uint32_t grid_for(const Plan& P)
+{
+    return P.persistent ? P.persistent_grid : xcd_grid(P.n_items);
+}
+
+// Queue for the c-th neighbour-loop launch of a sequence (counter c, reset
+// on `s` by this call when the plan is persistent).
+hipError_t item_queue(const Plan& P, void* ws, int c, hipStream_t s, ItemQueue* Q);
 
 // ---- launchers (defined in the .hip files) -----------------------------------
 // search.hip

@@ -15,7 +15,7 @@ namespace nau {
 // binning: absolute FP32 positions -> (cell, offset), id
 // ----------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxBlock)
 k_bin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
       const float* __restrict__ px, const float* __restrict__ py, const float* __restrict__ pz, StateDev st,
       uint32_t* err)
@@ -49,7 +49,7 @@ k_bin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_
     st.id[i] = i - C.offset;
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxBlock)
 k_unbin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
         float* px, float* py, float* pz)
 {
@@ -73,7 +73,7 @@ k_unbin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint3
 hipError_t launch_bin(const Plan& P, void* ws, const float* const pos[3], StateDev st, hipStream_t s)
 {
     if (P.n_items == 0) return hipSuccess;
-    k_bin<<<xcd_grid(P.n_items), kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
+    k_bin<<<xcd_grid(P.n_items), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
                                                  P.n_items, pos[0], pos[1], pos[2], st,
                                                  at<uint32_t>(ws, P.L.err));
     return hipGetLastError();
@@ -82,7 +82,7 @@ hipError_t launch_bin(const Plan& P, void* ws, const float* const pos[3], StateD
 hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3], hipStream_t s)
 {
     if (P.n_items == 0) return hipSuccess;
-    k_unbin<<<xcd_grid(P.n_items), kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
+    k_unbin<<<xcd_grid(P.n_items), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
                                                    P.n_items, st, pos[0], pos[1], pos[2]);
     return hipGetLastError();
 }
@@ -91,7 +91,7 @@ hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3
 // keys
 // ----------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxBlock)
 k_make_keys(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
             const uint32_t* __restrict__ cell, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
 {
@@ -305,7 +305,7 @@ k_cell_first(const uint32_t* __restrict__ keys, uint32_t n, uint32_t n_cells, ui
 
 // Gathers the state into sorted order and packs each particle's offsets into
 // one float4 for the neighbour search and the density pass.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxBlock)
 k_reorder(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
           const uint32_t* __restrict__ perm, uint32_t n, StateDev in, StateDev out, float4* __restrict__ pos4)
 {
@@ -330,7 +330,7 @@ k_reorder(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uin
     pos4[p] = make_float4(o[0], o[1], o[2], 0.0f);
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxBlock)
 k_pack_positions(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
                  StateDev st, float4* __restrict__ pos4)
 {
@@ -346,6 +346,17 @@ k_pack_positions(const CaseDev* __restrict__ cases, const Item* __restrict__ ite
     pos4[p] = make_float4(o[0], o[1], o[2], 0.0f);
 }
 
+hipError_t item_queue(const Plan& P, void* ws, int c, hipStream_t s, ItemQueue* Q)
+{
+    Q->n_items = P.n_items;
+    Q->persistent = P.persistent;
+    Q->order = at<uint32_t>(ws, P.L.queue);
+    Q->counter = at<uint32_t>(ws, P.L.counters) + (c % kCounters);
+    if (!P.persistent) return hipSuccess;
+    k_fill_u32<<<1, 64, 0, s>>>(Q->counter, 1, 0u);  // a kernel, not a memset: safe under graph capture
+    return hipGetLastError();
+}
+
 hipError_t launch_cell_first(const Plan& P, void* ws, const nauticle_cells& cells, hipStream_t s)
 {
     if (P.n_total == 0) return hipSuccess;
@@ -357,7 +368,7 @@ hipError_t launch_cell_first(const Plan& P, void* ws, const nauticle_cells& cell
 hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipStream_t s)
 {
     if (P.n_items == 0) return hipSuccess;
-    k_pack_positions<<<xcd_grid(P.n_items), kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
+    k_pack_positions<<<xcd_grid(P.n_items), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
                                                             P.n_items, sorted, packed(P, ws).pos4);
     return hipGetLastError();
 }
@@ -379,17 +390,12 @@ hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipSt
 
 constexpr uint32_t kUnroll = 8;
 
-__global__ void __launch_bounds__(kBlock)
-k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
-        const float4* __restrict__ pos4, const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
-        uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total, uint32_t* err)
+__device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev st, const float4* __restrict__ pos4,
+                                      const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
+                                      uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total,
+                                      uint32_t* err)
 {
 #pragma clang fp contract(off)
-    const uint32_t ix = xcd_item(n_items);
-    if (ix >= n_items) return;
-    const Item it = items[ix];
-    if (threadIdx.x >= it.count) return;
-    const CaseDev& C = cases[it.case_id];
     const uint32_t p = it.first + threadIdx.x;
     const int dim = C.dim;
     uint32_t own = st.cell[p];
@@ -488,6 +494,19 @@ k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint3
     if (cnt > max_nbr) set_error(err, kErrOverflow);
 }
 
+__global__ void __launch_bounds__(kMaxBlock)
+k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
+        const float4* __restrict__ pos4, const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
+        uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total, uint32_t* err)
+{
+    __shared__ uint32_t s_pos;
+    for_each_item(Q, &s_pos, [&](uint32_t ix) {
+        const Item it = items[ix];
+        if (threadIdx.x < it.count)
+            nlist_particle(cases[it.case_id], it, st, pos4, cell_first, nbr, nbr_count, max_nbr, n_total, err);
+    });
+}
+
 // ----------------------------------------------------------------------------
 // build_cells
 // ----------------------------------------------------------------------------
@@ -522,7 +541,7 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
         t = va; va = vb; vb = t;
     }
     const uint32_t grid = xcd_grid(P.n_items);
-    k_make_keys<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, in.cell, ka, va);
+    k_make_keys<<<grid, P.block, 0, s>>>(cases, items, P.n_items, in.cell, ka, va);
     const uint32_t n_tiles = (n + kTile - 1) / kTile;
     uint32_t* hist = at<uint32_t>(ws, P.L.sort_hist);
     uint32_t* totals = at<uint32_t>(ws, P.L.sort_totals);
@@ -540,9 +559,12 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     const int nb = static_cast<int>((n + kBlock - 1) / kBlock);
     k_cell_ranges<<<nb, kBlock, 0, s>>>(cells.key, n, cells.cell_start, cells.cell_end);
     k_cell_first<<<(nc + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(cells.key, n, nc, pk.cell_first);
-    k_reorder<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, cells.perm, n, in, sorted, pk.pos4);
-    k_nlist<<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, pk.pos4, pk.cell_first, cells.nbr,
-                                    cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), n, err);
+    k_reorder<<<grid, P.block, 0, s>>>(cases, items, P.n_items, cells.perm, n, in, sorted, pk.pos4);
+    ItemQueue Q;
+    hipError_t e = item_queue(P, ws, 0, s, &Q);
+    if (e != hipSuccess) return e;
+    k_nlist<<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
+                                            cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), n, err);
     return hipGetLastError();
 }
 

@@ -17,11 +17,11 @@ struct ShiftTable {
     float4 v[64];
 };
 
-// Every thread of the block must call it (contains a barrier).
+// Every thread of the block must call it (contains a barrier; the caller's
+// queue loop separates successive fills by barriers).
 __device__ inline void fill_shift_table(const CaseDev& C, ShiftTable* tab)
 {
-    if (threadIdx.x < 64) {
-        const uint32_t code = threadIdx.x;
+    for (uint32_t code = threadIdx.x; code < 64; code += blockDim.x) {
         const float sx = static_cast<float>(static_cast<int32_t>(code & 3u) - 1) * C.cs[0];
         const float sy = static_cast<float>(static_cast<int32_t>((code >> 2) & 3u) - 1) * C.cs[1];
         const float sz = static_cast<float>(static_cast<int32_t>((code >> 4) & 3u) - 1) * C.cs[2];
@@ -72,20 +72,11 @@ __device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i
 // Also packs (offsets, s) and (velocity, 1/rho) for the force pass; fixed
 // particles get velocity 0 there.
 
-__global__ void __launch_bounds__(kBlock)
-k_density(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
-          const float4* __restrict__ pos4, const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count,
-          uint32_t max_nbr, uint32_t n_total, FieldsDev f, float4* __restrict__ a4, float4* __restrict__ b4,
-          uint32_t* err)
+__device__ inline void density_particle(const CaseDev& C, const ShiftTable& tab, uint32_t i, StateDev st,
+                                        const float4* __restrict__ pos4, const uint32_t* __restrict__ nbr,
+                                        const uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total,
+                                        FieldsDev f, float4* __restrict__ a4, float4* __restrict__ b4, uint32_t* err)
 {
-    __shared__ ShiftTable tab;
-    const uint32_t ix = xcd_item(n_items);
-    if (ix >= n_items) return;
-    const Item it = items[ix];
-    const CaseDev& C = cases[it.case_id];
-    fill_shift_table(C, &tab);
-    if (threadIdx.x >= it.count) return;
-    const uint32_t i = it.first + threadIdx.x;
     const int dim = C.dim;
     const float4 me = pos4[i];
     uint32_t cnt = nbr_count[i];
@@ -131,21 +122,42 @@ k_density(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uin
     if (!isfinite(rho) || !isfinite(p)) set_error(err, kErrNonFinite);
 }
 
+__global__ void __launch_bounds__(kMaxBlock)
+k_density(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
+          const float4* __restrict__ pos4, const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count,
+          uint32_t max_nbr, uint32_t n_total, FieldsDev f, float4* __restrict__ a4, float4* __restrict__ b4,
+          uint32_t* err)
+{
+    __shared__ ShiftTable tab;
+    __shared__ uint32_t s_pos;
+    for_each_item(Q, &s_pos, [&](uint32_t ix) {
+        const Item it = items[ix];
+        const CaseDev& C = cases[it.case_id];
+        fill_shift_table(C, &tab);
+        if (threadIdx.x < it.count)
+            density_particle(C, tab, it.first + threadIdx.x, st, pos4, nbr, nbr_count, max_nbr, n_total, f, a4, b4,
+                             err);
+    });
+}
+
 hipError_t launch_density(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                           FieldsDev f, hipStream_t s)
 {
     if (P.n_items == 0) return hipSuccess;
     const Packed pk = packed(P, ws);
-    k_density<<<xcd_grid(P.n_items), kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), P.n_items,
-                                                     sorted, pk.pos4, cells.nbr, cells.nbr_count,
-                                                     static_cast<uint32_t>(cells.max_nbr), P.n_total, f, pk.a4,
-                                                     pk.b4, at<uint32_t>(ws, P.L.err));
+    ItemQueue Q;
+    hipError_t e = item_queue(P, ws, 1, s, &Q);
+    if (e != hipSuccess) return e;
+    k_density<<<grid_for(P), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), Q, sorted,
+                                              pk.pos4, cells.nbr, cells.nbr_count,
+                                              static_cast<uint32_t>(cells.max_nbr), P.n_total, f, pk.a4, pk.b4,
+                                              at<uint32_t>(ws, P.L.err));
     return hipGetLastError();
 }
 
 // Packs (offsets, s) and (velocity, 1/rho) from caller-provided fields, for
 // a force pass that does not follow a density pass on this workspace.
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kMaxBlock)
 k_pack_fields(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
               FieldsDev f, float4* __restrict__ a4, float4* __restrict__ b4)
 {
@@ -170,7 +182,7 @@ hipError_t launch_pack_fields(const Plan& P, void* ws, StateDev sorted, FieldsDe
 {
     if (P.n_items == 0) return hipSuccess;
     const Packed pk = packed(P, ws);
-    k_pack_fields<<<xcd_grid(P.n_items), kBlock, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
+    k_pack_fields<<<xcd_grid(P.n_items), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
                                                          P.n_items, sorted, f, pk.a4, pk.b4);
     return hipGetLastError();
 }
@@ -182,20 +194,11 @@ hipError_t launch_pack_fields(const Plan& P, void* ws, StateDev sorted, FieldsDe
 // with r_ij = -d, F = F_coef (1 - q/2)^3, k = 1/rho.
 
 template <bool kIntegrate>
-__global__ void __launch_bounds__(kBlock)
-k_forces(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
-         const float4* __restrict__ a4, const float4* __restrict__ b4, const uint32_t* __restrict__ nbr,
-         const uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total, FieldsDev f, StateDev next,
-         uint32_t* err)
+__device__ inline void forces_particle(const CaseDev& C, const ShiftTable& tab, uint32_t i, StateDev st,
+                                       const float4* __restrict__ a4, const float4* __restrict__ b4,
+                                       const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count,
+                                       uint32_t max_nbr, uint32_t n_total, FieldsDev f, StateDev next, uint32_t* err)
 {
-    __shared__ ShiftTable tab;
-    const uint32_t ix = xcd_item(n_items);
-    if (ix >= n_items) return;
-    const Item it = items[ix];
-    const CaseDev& C = cases[it.case_id];
-    fill_shift_table(C, &tab);
-    if (threadIdx.x >= it.count) return;
-    const uint32_t i = it.first + threadIdx.x;
     const int dim = C.dim;
     const float4 ai4 = a4[i];
     const float4 bi4 = b4[i];
@@ -275,6 +278,25 @@ k_forces(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint
     }
 }
 
+template <bool kIntegrate>
+__global__ void __launch_bounds__(kMaxBlock)
+k_forces(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
+         const float4* __restrict__ a4, const float4* __restrict__ b4, const uint32_t* __restrict__ nbr,
+         const uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total, FieldsDev f, StateDev next,
+         uint32_t* err)
+{
+    __shared__ ShiftTable tab;
+    __shared__ uint32_t s_pos;
+    for_each_item(Q, &s_pos, [&](uint32_t ix) {
+        const Item it = items[ix];
+        const CaseDev& C = cases[it.case_id];
+        fill_shift_table(C, &tab);
+        if (threadIdx.x < it.count)
+            forces_particle<kIntegrate>(C, tab, it.first + threadIdx.x, st, a4, b4, nbr, nbr_count, max_nbr, n_total,
+                                        f, next, err);
+    });
+}
+
 hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                          FieldsDev f, const StateDev* next, hipStream_t s)
 {
@@ -284,14 +306,16 @@ hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticl
     uint32_t* err = at<uint32_t>(ws, P.L.err);
     const Packed pk = packed(P, ws);
     const uint32_t mx = static_cast<uint32_t>(cells.max_nbr);
-    const uint32_t grid = xcd_grid(P.n_items);
+    ItemQueue Q;
+    hipError_t e = item_queue(P, ws, 2, s, &Q);
+    if (e != hipSuccess) return e;
     if (next) {
-        k_forces<true><<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, pk.a4, pk.b4, cells.nbr,
-                                               cells.nbr_count, mx, P.n_total, f, *next, err);
+        k_forces<true><<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.a4, pk.b4, cells.nbr,
+                                                       cells.nbr_count, mx, P.n_total, f, *next, err);
     } else {
         StateDev none{};
-        k_forces<false><<<grid, kBlock, 0, s>>>(cases, items, P.n_items, sorted, pk.a4, pk.b4, cells.nbr,
-                                                cells.nbr_count, mx, P.n_total, f, none, err);
+        k_forces<false><<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.a4, pk.b4, cells.nbr,
+                                                        cells.nbr_count, mx, P.n_total, f, none, err);
     }
     return hipGetLastError();
 }

@@ -76,6 +76,25 @@ class CCells(ctypes.Structure):
                 ("max_nbr", ctypes.c_int32)]
 
 
+class CTuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("persistent", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+@dataclass(frozen=True)
+class Tuning:
+    """Launch shape of the neighbour loops (results do not depend on it)."""
+
+    block: int = 256
+    persistent: int = 0
+    groups_per_cu: int = 4
+
+    def c(self) -> CTuning:
+        t = CTuning()
+        t.block, t.persistent, t.groups_per_cu, t.reserved = self.block, self.persistent, self.groups_per_cu, 0
+        return t
+
+
 class CFields(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_void_p), ("p", ctypes.c_void_p), ("s", ctypes.c_void_p),
                 ("inv_rho", ctypes.c_void_p), ("acc", ctypes.c_void_p * 3)]
@@ -101,7 +120,7 @@ def lib():
     L.nauticle_workspace_bytes.restype = st
     L.nauticle_workspace_bytes.argtypes = [P(CCase), i32, P(ctypes.c_size_t)]
     L.nauticle_prepare.restype = st
-    L.nauticle_prepare.argtypes = [P(CCase), i32, vp, ctypes.c_size_t, vp]
+    L.nauticle_prepare.argtypes = [P(CCase), i32, P(CTuning), vp, ctypes.c_size_t, vp]
     L.nauticle_bin.restype = st
     L.nauticle_bin.argtypes = [P(CCase), i32, P(ptr3), P(CState), vp, ctypes.c_size_t, vp]
     L.nauticle_unbin.restype = st
@@ -251,8 +270,9 @@ class Problem:
     """A prepared set of independent cases on one device: owns the workspace,
     the neighbour structure and the field arrays."""
 
-    def __init__(self, cases, device="cuda:0", max_nbr: Optional[int] = None):
+    def __init__(self, cases, device="cuda:0", max_nbr: Optional[int] = None, tuning: Optional[Tuning] = None):
         self.cases = list(cases)
+        self.tuning = tuning or Tuning()
         self.device = torch.device(device)
         self.dim = self.cases[0].dim
         self.table = case_table(self.cases)
@@ -264,8 +284,8 @@ class Problem:
                "nauticle_workspace_bytes")
         self.ws_bytes = int(nbytes.value)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
-        _check(lib().nauticle_prepare(self.table, self.n_cases, _p(self.ws), self.ws_bytes, self.stream()),
-               "nauticle_prepare")
+        _check(lib().nauticle_prepare(self.table, self.n_cases, ctypes.byref(self.tuning.c()), _p(self.ws),
+                                      self.ws_bytes, self.stream()), "nauticle_prepare")
         self.max_nbr = int(max_nbr or default_max_nbr(self.dim))
         i32 = dict(dtype=torch.int32, device=self.device)
         f32 = dict(dtype=torch.float32, device=self.device)

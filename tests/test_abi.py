@@ -89,7 +89,7 @@ def test_mixed_dimensions_and_bad_offsets_are_rejected(N):
 
 def test_unprepared_workspace_is_rejected_without_touching_the_device(N):
     table = N.case_table([WL.periodic_2d_4096()])
-    assert N.lib().nauticle_prepare(table, 1, None, 0, None) == N.ERR_WORKSPACE
+    assert N.lib().nauticle_prepare(table, 1, None, None, 0, None) == N.ERR_WORKSPACE
     assert N.lib().nauticle_check(None, 0, None) == N.ERR_WORKSPACE
     fake = ctypes.c_void_p(0x1000)
     st = N.lib().nauticle_step(table, 1, None, 1, None, None, None, fake, 1 << 20, None)
@@ -105,3 +105,9 @@ def test_the_oracle_is_not_reachable_from_the_package():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert not pat.search(text), f
+
+
+def test_invalid_tuning_is_rejected_on_the_host(N):
+    table = N.case_table([WL.periodic_2d_4096()])
+    for bad in (N.Tuning(block=96), N.Tuning(persistent=2), N.Tuning(persistent=1, groups_per_cu=100)):
+        assert N.lib().nauticle_prepare(table, 1, ctypes.byref(bad.c()), None, 0, None) == N.ERR_INVALID_ARG
