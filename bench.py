@@ -1,17 +1,21 @@
 """Benchmark of the WCSPH hot path on one MI355X.
 
 A step is one pass of the whole hot path over the 3-D periodic jittered
-lattice of 8,388,608 particles (256 x 256 x 128, h = 1.2 dx, ~56
+lattice of 8,388,608 particles (256 x 256 x 128, h = 1.2 dx, ~57
 neighbours): neighbour search (keys, radix sort, cell table, reorder,
 neighbour lists), density + Tait pressure, accelerations with the fused
 semi-implicit Euler update.  Inputs are resident in HBM before timing.
 
 Prints ONE JSON line.  `value` is pair interactions per second over the
-whole step (each ordered neighbour pair counted once per step); the force
-pass alone is reported under `phases`.  `roofline` is for the force kernel
-(its launch is timed alone with HIP events on the library's stream).
-`cpu_baseline` times the FP64 oracle on a bounded sample of the same
-workload (a smaller box of the same lattice recipe).
+whole step (each ordered neighbour pair counted once per step).  Phase times
+come from HIP events recorded on the library's stream between the kernels.
+`roofline` is for the dominant kernel (the neighbour-list search);
+`extra.roofline_force_pass` for the force kernel.  `cpu_baseline` times the
+FP64 oracle on a bounded sample of the same workload (a smaller box of the
+same lattice recipe).  `extra` also carries the forward + adjoint step rate
+of the 262,144-particle differentiation case (with the oracle's rate on the
+same case: the "vs plain" figure), the 256-case batched workload and the
+3-D dam-break workload.
 """
 import argparse
 import json
@@ -22,11 +26,29 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# per-interaction algorithmic work of the force kernel (3-D), see the design notes
-FORCE_FLOP_PER_PAIR_3D = 39
-FORCE_BYTES_PER_PARTICLE_3D = 4 * (3 + 3 + 1 + 1 + 1 + 1) + 4 * (3 + 3 + 3 + 1 + 1)  # in: off,v,s,k,cell,id,count; out: a,off',v',cell',id'
-PEAK_FP32_TFLOPS = 157.3
+# Algorithmic work per unit (see the design notes):
+#  search: per candidate tested, d = off_j - t (3), r^2 (3 mul/fma = 5 flops), compare (1)
+#  force pass: per neighbour pair, 40 flops (FMA = 2)
+SEARCH_FLOP_PER_CANDIDATE = 9
+FORCE_FLOP_PER_PAIR = 40
+PEAK_FP32_TFLOPS = 157.3            # published MI355X FP32 vector peak (packed FP32)
+PEAK_FP32_TFLOPS_UNPACKED = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz: packed FP32 is disabled in this build
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per k_nlist launch from the FETCH_SIZE / WRITE_SIZE counter runs
+# summarised in profiles/neighbour_kernels_periodic_3d_8388608_traffic.md
+# (scaled by a plain 1 GiB copy); valid only for the search source the
+# counters were taken on, reported as null otherwise.
+NLIST_TRAFFIC_BYTES = 6.020e9
+NLIST_TRAFFIC_SOURCE_SHA256 = "1d258b93426d23be"
+
+
+def nlist_traffic():
+    import hashlib
+
+    src = os.path.join(ROOT, "paper_1710_08259_amd", "csrc", "search.hip")
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()[:16]
+    return NLIST_TRAFFIC_BYTES if digest == NLIST_TRAFFIC_SOURCE_SHA256 else None
 
 
 def parse():
@@ -34,23 +56,70 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="periodic_3d_8388608",
-                    choices=["periodic_3d_8388608", "periodic_3d_262144", "periodic_2d_4096", "dam_break_3d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="only the main workload")
     ap.add_argument("--cpu-sample", default="128x128x64", help="oracle sample box (lattice sites per axis)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB of a plain device copy run before timing (counter calibration runs)")
     return ap.parse_args()
 
 
-def make_case(name):
-    from paper_1710_08259_amd import workloads as WL
+def candidates_per_step(prob, case):
+    """Candidates the search tests per step: sum over particles of the
+    occupancy of the 3^dim cells around theirs (periodic box)."""
+    import torch
 
-    return {"periodic_3d_8388608": WL.periodic_3d_8m, "periodic_3d_262144": WL.periodic_3d_262k,
-            "periodic_2d_4096": WL.periodic_2d_4096, "dam_break_3d": WL.dam_break_3d}[name]()
+    nc = case.ncell
+    start = prob.cells.cell_start[: case.n_cells].to(torch.int64)
+    end = prob.cells.cell_end[: case.n_cells].to(torch.int64)
+    cnt = torch.where(start < 0, torch.zeros_like(start), end - start)
+    grid = cnt.reshape(nc[2], nc[1], nc[0]).double()
+    s = torch.zeros_like(grid)
+    for dz in (-1, 0, 1) if case.dim == 3 else (0,):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                s += torch.roll(grid, shifts=(dz, dy, dx), dims=(0, 1, 2))
+    return float((grid * s).sum().item())
+
+
+def timed_steps(prob, st, steps, warmup):
+    """Runs warmup + steps full steps; returns (wall s, per-phase ms [4], pairs)."""
+    import numpy as np
+    import torch
+
+    n = prob.n
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(5 * steps)]
+    for e in evs:  # create the HIP events before the timed region
+        e.record(stream)
+    pairs = torch.zeros((), dtype=torch.int64, device=prob.device)
+
+    def body(k):
+        prob.step(st, 1, events=evs[5 * k: 5 * k + 5])
+        pairs.add_(prob.cells.nbr_count[:n].sum(dtype=torch.int64))
+
+    for k in range(warmup):  # the timed body itself, so every kernel module is loaded
+        body(k % steps)
+    torch.cuda.synchronize()
+    prob.check()
+    pairs.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        body(k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prob.check()
+    phase = np.zeros(4)
+    for k in range(steps):
+        e = evs[5 * k: 5 * k + 5]
+        phase += [e[i].elapsed_time(e[i + 1]) for i in range(4)]
+    return wall, phase / steps, int(pairs.item())
 
 
 def cpu_baseline(args, case):
     """The oracle, as it stands, on a smaller box of the same lattice recipe:
-    one full step (density, pressure, accelerations, integration)."""
+    one full FP64 step (density, pressure, accelerations, integration)."""
     import numpy as np
 
     from oracle import oracle as O
@@ -74,74 +143,167 @@ def cpu_baseline(args, case):
                       f"{pairs} interactions) of the same lattice recipe, {dt:.2f} s"}
 
 
+def adjoint_extra(device):
+    """Forward and forward+adjoint steps/s of the 262,144-particle 3-D case
+    (one checkpoint segment of 20 steps: forward, then recompute with stored
+    step records and 20 adjoint steps), next to the FP64 oracle's forward +
+    adjoint step on the same case."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as O
+    from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
+    from paper_1710_08259_amd.rollout import _StepRecord
+
+    case = WL.periodic_3d_262k()
+    prob = N.Problem([case], device=device)
+    st = prob.state_from_cases()
+    K = 20
+    prob.step(st, 2)
+    torch.cuda.synchronize()
+    ck = st.clone()
+    t0 = time.perf_counter()
+    prob.step(st, K)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    lam = {"x": [torch.full((prob.n,), 1e-3, device=device) for _ in range(3)],
+           "v": [torch.zeros(prob.n, device=device) for _ in range(3)],
+           "ox": [torch.empty(prob.n, device=device) for _ in range(3)],
+           "ov": [torch.empty(prob.n, device=device) for _ in range(3)]}
+    dnu = torch.zeros(1, dtype=torch.float64, device=device)
+    dc0 = torch.zeros(1, dtype=torch.float64, device=device)
+    records = [_StepRecord(prob.new_state(), prob.new_cells(), prob.new_fields()) for _ in range(K)]
+
+    def reverse_segment():
+        cur = ck.clone()
+        for rec in records:
+            prob.build_cells(cur, rec.sorted, rec.cells)
+            prob.density(rec.sorted, rec.cells, rec.fields)
+            prob.forces(rec.sorted, cur, rec.cells, rec.fields)
+        for rec in reversed(records):
+            prob.adjoint(rec.sorted, rec.cells, rec.fields, lam["x"], lam["v"], lam["ox"], lam["ov"], dnu, dc0)
+            lam["x"], lam["ox"] = lam["ox"], lam["x"]
+            lam["v"], lam["ov"] = lam["ov"], lam["v"]
+
+    reverse_segment()  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reverse_segment()
+    torch.cuda.synchronize()
+    t_rev = time.perf_counter() - t0
+    prob.check()
+    # the oracle: one FP64 forward step and one step VJP on the same case
+    dom = O.Domain(dim=3, n=case.ncell, cs=case.cell_size, origin=case.origin)
+    prm = O.Params(h=case.h, mass=case.mass, rho0=case.rho0, c0=case.c0, gamma=case.gamma, nu=case.nu,
+                   dt=case.dt, g=case.g)
+    x, v = case.pos.astype(np.float64), case.vel.astype(np.float64)
+    threads = O.default_threads()
+    t0 = time.perf_counter()
+    O.step(dom, prm, x, v, n_steps=1, nthreads=threads)
+    O.step_vjp(dom, prm, x, v, np.ones_like(x), np.zeros_like(v), nthreads=threads)
+    t_or = time.perf_counter() - t0
+    fa_sps = K / (t_fwd + t_rev)
+    return {"workload": case.name, "particles": case.n, "checkpoint_every": K,
+            "forward_steps_per_s": K / t_fwd, "adjoint_steps_per_s": K / t_rev,
+            "adjoint_over_forward": t_rev / t_fwd, "fwd_plus_adjoint_steps_per_s": fa_sps,
+            "oracle_fwd_plus_adjoint_steps_per_s": 1.0 / t_or, "oracle_cores": threads,
+            "fwd_plus_adjoint_vs_oracle": fa_sps * t_or}
+
+
+def batched_extra(device, steps=10):
+    """The 256-case batched workload, launch shape picked by the autotuner."""
+    from paper_1710_08259_amd import autotune
+    from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
+
+    cases = WL.batched_2d()
+    cands = (N.Tuning(), N.Tuning(block=128, persistent=1, groups_per_cu=4),
+             N.Tuning(block=256, persistent=1, groups_per_cu=4), N.Tuning(block=128))
+    best, timings = autotune.tune(cases, steps=2, candidates=cands,
+                                  cache_path=os.path.join(ROOT, "gpurun_out", "tuning.json"), force=True)
+    prob = N.Problem(cases, device=device, tuning=best)
+    st = prob.state_from_cases()
+    wall, phase, pairs = timed_steps(prob, st, steps, 2)
+    return {"workload": f"batched_2d_{len(cases)}_cases", "particles": prob.n, "cases": len(cases),
+            "tuning": best.__dict__, "steps_per_s": steps / wall, "interactions_per_s": pairs / wall,
+            "tuning_ms_per_step": {f"{t.block}/{t.persistent}/{t.groups_per_cu}": round(v, 4)
+                                   for t, v in timings.items()}}
+
+
+def dam_break_extra(device, steps=10):
+    from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
+
+    case = WL.dam_break_3d()
+    prob = N.Problem([case], device=device)
+    st = prob.state_from_cases()
+    wall, phase, pairs = timed_steps(prob, st, steps, 2)
+    return {"workload": case.name, "particles": case.n, "fixed": case.n_fixed, "steps_per_s": steps / wall,
+            "interactions_per_s": pairs / wall, "ms_per_step": wall * 1e3 / steps}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is "
               f"described in the design notes but not built", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
 
-    case = make_case(args.workload)
-    prob = N.Problem([case])
+    device = "cuda:0"
+    if args.calibrate_copy:
+        nb = args.calibrate_copy << 20
+        a = torch.empty(nb // 4, dtype=torch.float32, device=device).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    case = WL.periodic_3d_8m()
+    prob = N.Problem([case], device=device)
     st = prob.state_from_cases()
-    stream = torch.cuda.current_stream()
-    n = case.n
-
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(4 * args.steps)]
-    for e in evs:  # create the HIP events before the timed region
-        e.record(stream)
-    pairs = torch.zeros((), dtype=torch.int64, device=prob.device)
-
-    def body(k):
-        prob.step(st, 1, events=evs[4 * k: 4 * k + 4])
-        pairs.add_(prob.cells.nbr_count[:n].sum(dtype=torch.int64))
-
-    # warmup runs the timed body itself, so every kernel module is loaded
-    for k in range(args.warmup):
-        body(k % args.steps)
-    torch.cuda.synchronize()
-    prob.check()
-    pairs.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        body(k)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    prob.check()
-    phase = np.zeros(3)
-    for k in range(args.steps):
-        e = evs[4 * k: 4 * k + 4]
-        phase += [e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])]
-    phase_ms = phase / args.steps
-    total_pairs = int(pairs.item())
+    wall, phase_ms, total_pairs = timed_steps(prob, st, args.steps, args.warmup)
     pairs_per_step = total_pairs / args.steps
-    ms_step = wall * 1e3 / args.steps
-    value = total_pairs / wall
-    force_s = phase_ms[2] * 1e-3
-    flops = FORCE_FLOP_PER_PAIR_3D * pairs_per_step
-    achieved_tflops = flops / force_s / 1e12
-    roofline = {"bound": "alu", "kernel": "k_forces<true> (force pass with fused integration)",
-                "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "algorithmic_hbm_GBs": round(FORCE_BYTES_PER_PARTICLE_3D * case.n / force_s / 1e9, 1)}
+    cand = candidates_per_step(prob, case)
+    search_s = phase_ms[1] * 1e-3
+    force_s = phase_ms[3] * 1e-3
+    search_tflops = SEARCH_FLOP_PER_CANDIDATE * cand / search_s / 1e12
+    force_tflops = FORCE_FLOP_PER_PAIR * pairs_per_step / force_s / 1e12
+    roofline = {"bound": "alu", "kernel": "k_nlist (neighbour-list search)",
+                "achieved": round(search_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(search_tflops / PEAK_FP32_TFLOPS, 4), "traffic": nlist_traffic(),
+                "peak_without_packed_fp32": PEAK_FP32_TFLOPS_UNPACKED,
+                "candidates_per_step": cand, "ms": round(phase_ms[1], 4)}
     line = {
         "metric": "particle-pair interactions/s (SPH force pass) + fwd+adjoint steps/s vs plain",
-        "value": value, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "value": total_pairs / wall, "unit": "interactions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": case.name, "particles": case.n, "dim": case.dim, "h_over_dx": 1.2,
                    "neighbours_per_particle": round(pairs_per_step / case.n, 2),
+                   "candidates_per_particle": round(cand / case.n, 1),
                    "cells": list(case.ncell), "max_nbr": prob.max_nbr},
-        "phases": {"build_cells_ms": round(phase_ms[0], 4), "density_ms": round(phase_ms[1], 4),
-                   "forces_integrate_ms": round(phase_ms[2], 4), "gpu_ms_per_step": round(float(phase_ms.sum()), 4),
+        "phases": {"sort_reorder_ms": round(phase_ms[0], 4), "neighbour_lists_ms": round(phase_ms[1], 4),
+                   "density_ms": round(phase_ms[2], 4), "forces_integrate_ms": round(phase_ms[3], 4),
+                   "gpu_ms_per_step": round(float(phase_ms.sum()), 4),
                    "force_pass_interactions_per_s": pairs_per_step / force_s},
         "roofline": roofline,
+        "extra": {"roofline_force_pass": {
+            "bound": "alu", "kernel": "k_forces<true> (force pass with fused integration)",
+            "achieved": round(force_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(force_tflops / PEAK_FP32_TFLOPS, 4), "ms": round(phase_ms[3], 4)}},
     }
+    del prob, st
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        line["extra"]["adjoint"] = adjoint_extra(device)
+        torch.cuda.empty_cache()
+        line["extra"]["batched"] = batched_extra(device)
+        torch.cuda.empty_cache()
+        line["extra"]["dam_break"] = dam_break_extra(device)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args, case)
     print(json.dumps(line), flush=True)

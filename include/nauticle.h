@@ -251,9 +251,10 @@ nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases,
  * density, forces with the fused integration back into `state`.  After
  * the call `state` holds the particles in the sorted order of the last
  * step; `cells` and `fields` hold that step's neighbour structure and
- * fields.  phase_events (optional, NULL or 4 * n_steps caller-created HIP
- * events) are recorded on `stream` at the start of each step and after its
- * search, density and force phases, for timing. */
+ * fields.  phase_events (optional, NULL or 5 * n_steps caller-created HIP
+ * events) are recorded on `stream` at the start of each step, after its
+ * sort and reorder, after its neighbour lists, after density and after
+ * forces, for timing. */
 nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
                               int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
                               hipEvent_t* phase_events, void* ws, size_t ws_bytes, hipStream_t stream);

@@ -53,11 +53,11 @@ def time_tuning(cases, tuning: N.Tuning, steps: int = 3, warmup: int = 1, device
     prob = N.Problem(cases, device=device, tuning=tuning)
     st = prob.state_from_cases()
     prob.step(st, warmup)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4 * steps)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5 * steps)]
     prob.step(st, steps, events=ev)
     torch.cuda.synchronize()
     prob.check()
-    return sum(ev[4 * k].elapsed_time(ev[4 * k + 3]) for k in range(steps)) / steps
+    return sum(ev[5 * k].elapsed_time(ev[5 * k + 4]) for k in range(steps)) / steps
 
 
 def tune(cases, steps: int = 3, candidates=CANDIDATES, cache_path: Optional[str] = None, device="cuda:0",

@@ -482,16 +482,17 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
     // build_cells leaves packed positions for density, and density leaves
     // packed fields for forces, so the step needs no separate packing
     auto mark = [&](int32_t s, int k) {
-        return phase_events ? hipEventRecord(phase_events[4 * s + k], stream) : hipSuccess;
+        return phase_events ? hipEventRecord(phase_events[5 * s + k], stream) : hipSuccess;
     };
     for (int32_t s = 0; s < n_steps; ++s) {
         hipError_t e = mark(s, 0);
-        if (e == hipSuccess) e = launch_build_cells(*P, ws, cur, tmp, *cells, stream);
-        if (e == hipSuccess) e = mark(s, 1);
-        if (e == hipSuccess) e = launch_density(*P, ws, tmp, *cells, f, stream);
+        if (e == hipSuccess)
+            e = launch_build_cells(*P, ws, cur, tmp, *cells, stream, phase_events ? phase_events[5 * s + 1] : nullptr);
         if (e == hipSuccess) e = mark(s, 2);
-        if (e == hipSuccess) e = launch_forces(*P, ws, tmp, *cells, f, &cur, stream);
+        if (e == hipSuccess) e = launch_density(*P, ws, tmp, *cells, f, stream);
         if (e == hipSuccess) e = mark(s, 3);
+        if (e == hipSuccess) e = launch_forces(*P, ws, tmp, *cells, f, &cur, stream);
+        if (e == hipSuccess) e = mark(s, 4);
         if (e != hipSuccess) return hip_fail(e, "nauticle_step");
     }
     return NAUTICLE_OK;

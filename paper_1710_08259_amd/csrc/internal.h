@@ -191,8 +191,9 @@ hipError_t item_queue(const Plan& P, void* ws, int c, hipStream_t s, ItemQueue* 
 // search.hip
 hipError_t launch_bin(const Plan& P, void* ws, const float* const pos[3], StateDev st, hipStream_t s);
 hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3], hipStream_t s);
+// mid (optional) is recorded between the sort/reorder and the neighbour lists
 hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sorted,
-                              const nauticle_cells& cells, hipStream_t s);
+                              const nauticle_cells& cells, hipStream_t s, hipEvent_t mid = nullptr);
 hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipStream_t s);
 // cell_first (the tiles' particle ranges) from the sorted keys of `cells`
 hipError_t launch_cell_first(const Plan& P, void* ws, const nauticle_cells& cells, hipStream_t s);

@@ -512,7 +512,7 @@ k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
 // ----------------------------------------------------------------------------
 
 hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sorted,
-                              const nauticle_cells& cells, hipStream_t s)
+                              const nauticle_cells& cells, hipStream_t s, hipEvent_t mid)
 {
     const uint32_t n = P.n_total;
     const uint32_t nc = P.n_cells_total;
@@ -562,6 +562,7 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     k_reorder<<<grid, P.block, 0, s>>>(cases, items, P.n_items, cells.perm, n, in, sorted, pk.pos4);
     ItemQueue Q;
     hipError_t e = item_queue(P, ws, 0, s, &Q);
+    if (e == hipSuccess && mid) e = hipEventRecord(mid, s);
     if (e != hipSuccess) return e;
     k_nlist<<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
                                             cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), n, err);

@@ -365,13 +365,13 @@ class Problem:
         return f
 
     def step(self, st: State, n_steps: int = 1, events=None) -> State:
-        """n_steps steps in place.  `events` (optional): 4 * n_steps
-        torch.cuda.Event(enable_timing=True) recorded at each step's start
-        and after its search, density and force phases."""
+        """n_steps steps in place.  `events` (optional): 5 * n_steps
+        torch.cuda.Event(enable_timing=True) recorded at each step's start,
+        after its sort/reorder, its neighbour lists, density and forces."""
         ev = None
         if events is not None:
-            if len(events) != 4 * n_steps:
-                raise ValueError("need 4 events per step")
+            if len(events) != 5 * n_steps:
+                raise ValueError("need 5 events per step")
             for e in events:  # torch creates the HIP event on first record
                 if e.cuda_event == 0:
                     e.record(torch.cuda.current_stream(self.device))
