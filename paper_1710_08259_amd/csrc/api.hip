@@ -227,7 +227,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     L.sort_hist = take(4 * 256 * n_tiles);
     L.sort_totals = take(4 * 256);
     L.cell_first = take(4 * (static_cast<size_t>(n_cells_total) + 1));
-    L.pos4 = take(16 * N);
+    L.pos4 = take(16 * (N + kPosPad));
     L.a4 = take(16 * N);
     L.b4 = take(16 * N);
     L.adj4 = take(16 * N);

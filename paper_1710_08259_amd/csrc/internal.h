@@ -13,7 +13,7 @@ namespace nau {
 
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
-constexpr uint32_t kGroup = 4;     // list entries in flight per lane in the pair loops
+constexpr uint32_t kPosPad = 64;   // float4s readable past the end of the packed position array
 constexpr uint32_t kIndexMask = (1u << NAUTICLE_NBR_INDEX_BITS) - 1u;
 
 // Device error word bits (OR-ed by kernels, read by nauticle_check).
@@ -163,18 +163,21 @@ __device__ inline uint32_t xcd_item(uint32_t n_items)
 template <typename Body>
 __device__ inline void for_each_item(const ItemQueue& Q, uint32_t* s_pos, Body&& body)
 {
-    if (!Q.persistent) {
-        const uint32_t ix = xcd_item(Q.n_items);
-        if (ix < Q.n_items) body(ix);
-        return;
-    }
-    for (;;) {
-        if (threadIdx.x == 0) *s_pos = atomicAdd(Q.counter, 1u);
-        __syncthreads();
-        const uint32_t pos = *s_pos;
-        __syncthreads();
-        if (pos >= Q.n_items) break;
-        body(Q.order[pos]);
+    // one loop for both launch modes, so the body is instantiated once
+    for (uint32_t iter = 0;; ++iter) {
+        uint32_t ix;
+        if (Q.persistent) {
+            if (threadIdx.x == 0) *s_pos = atomicAdd(Q.counter, 1u);
+            __syncthreads();
+            const uint32_t pos = *s_pos;
+            __syncthreads();
+            if (pos >= Q.n_items) break;
+            ix = Q.order[pos];
+        } else {
+            ix = xcd_item(Q.n_items);
+            if (iter > 0 || ix >= Q.n_items) break;
+        }
+        body(ix);
     }
 }
 

@@ -382,14 +382,45 @@ hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipSt
 // The predicate moves the particle into the candidate's cell frame,
 // t = off_i - delta cs: the y and z parts of t are fixed per row, and within a
 // piece the x part takes one of three values, selected by the piece's cell
-// boundaries.  Candidates are read as float4s, kUnroll at a time; those that
-// pass set a bit in a 64-candidate mask, which is then emitted into the
+// boundaries.  Candidates are read as float4s, kUnroll at a time, with the
+// next kUnroll already in flight (the loop is bound by load latency); those
+// that pass set a bit in a 64-candidate mask, which is then emitted into the
 // particle's list column in ascending order.  Lanes of one home cell read the
 // same candidate at the same time, so a wave's load touches only a handful of
-// cache lines.
+// cache lines.  Reads may run up to 2 kUnroll - 1 candidates past a piece
+// (the packed positions are padded for it); such candidates are masked off.
 
-constexpr uint32_t kUnroll = 8;
+constexpr uint32_t kUnroll = 4;
+static_assert(2 * kUnroll <= kPosPad && 64 % (2 * kUnroll) == 0, "candidate groups must tile the 64-bit mask");
 
+// Bit u set iff candidate q + u passes the distance test (FP32, the frame
+// shift applied to the particle; see the predicate above).
+template <int DIM>
+__device__ inline uint32_t test_group(const float4* o, uint32_t q, uint32_t b1, uint32_t b2, float tx0, float tx1,
+                                      float tx2, float ty, float tz, float R2)
+{
+#pragma clang fp contract(off)
+    // candidate positions relative to the piece's cell boundaries
+    const int32_t r1 = static_cast<int32_t>(b1 - q);
+    const int32_t r2b = static_cast<int32_t>(b2 - q);
+    uint32_t bits = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+        const int32_t iu = static_cast<int32_t>(u);
+        const float tx = iu < r1 ? tx0 : (iu < r2b ? tx1 : tx2);
+        const float ddx = o[u].x - tx;
+        const float ddy = o[u].y - ty;
+        float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
+        if constexpr (DIM == 3) {
+            const float ddz = o[u].z - tz;
+            r2 = __builtin_fmaf(ddz, ddz, r2);
+        }
+        bits |= r2 < R2 ? (1u << u) : 0u;
+    }
+    return bits;
+}
+
+template <int DIM>
 __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev st, const float4* __restrict__ pos4,
                                       const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
                                       uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total,
@@ -397,7 +428,6 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
 {
 #pragma clang fp contract(off)
     const uint32_t p = it.first + threadIdx.x;
-    const int dim = C.dim;
     uint32_t own = st.cell[p];
     if (own >= C.n_cells) {  // a corrupt state: keep every table access inside the case
         own = C.n_cells - 1;
@@ -412,10 +442,10 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
     const float csx = C.cs[0];
     uint32_t* col = nbr + p;
     uint32_t cnt = 0;
-    const int zlo = dim == 3 ? -1 : 0, zhi = dim == 3 ? 1 : 0;
-    for (int dz = zlo; dz <= zhi; ++dz) {
+    constexpr int kZ = DIM == 3 ? 1 : 0;
+    for (int dz = -kZ; dz <= kZ; ++dz) {
         int32_t cz = c[2] + dz;
-        if (dim == 3) {
+        if constexpr (DIM == 3) {
             if (C.periodic[2]) cz = cz < 0 ? cz + C.nc[2] : (cz >= C.nc[2] ? cz - C.nc[2] : cz);
             else if (cz < 0 || cz >= C.nc[2]) continue;
         }
@@ -451,31 +481,39 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
                 else if (dx0 < -1) dx0 += nx;
                 const uint32_t b1 = xa + 1 <= xb ? cell_first[row + static_cast<uint32_t>(xa) + 1] : q_end;
                 const uint32_t b2 = xa + 2 <= xb ? cell_first[row + static_cast<uint32_t>(xa) + 2] : q_end;
-                const float tx0 = me.x - static_cast<float>(dx0) * csx;
-                const float tx1 = me.x - static_cast<float>(dx0 + 1) * csx;
-                const float tx2 = me.x - static_cast<float>(dx0 + 2) * csx;
+                float tx0 = me.x - static_cast<float>(dx0) * csx;
+                float tx1 = me.x - static_cast<float>(dx0 + 1) * csx;
+                float tx2 = me.x - static_cast<float>(dx0 + 2) * csx;
+                // opaque to the optimiser, so the per-candidate choice stays a
+                // select of these three values instead of being recomputed
+                asm volatile("" : "+v"(tx0), "+v"(tx1), "+v"(tx2));
                 for (uint32_t q0 = q_begin; q0 < q_end; q0 += 64) {
                     const uint32_t m = min(q_end - q0, 64u);
+                    const float4* src = pos4 + q0;
                     uint64_t hits = 0;
-                    for (uint32_t b = 0; b < m; b += kUnroll) {
-                        float4 o[kUnroll];
+                    // two groups per iteration, in ping-pong registers: group A
+                    // is tested while group B loads, then B while the next A loads
+                    float4 oa[kUnroll], ob[kUnroll];
 #pragma unroll
-                        for (uint32_t u = 0; u < kUnroll; ++u) o[u] = pos4[min(q0 + b + u, q_end - 1)];
+                    for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[u];
+                    for (uint32_t b = 0; b < m; b += 2 * kUnroll) {
 #pragma unroll
-                        for (uint32_t u = 0; u < kUnroll; ++u) {
-                            const uint32_t q = q0 + b + u;
-                            const float tx = q < b1 ? tx0 : (q < b2 ? tx1 : tx2);
-                            const float ddx = o[u].x - tx;
-                            const float ddy = o[u].y - ty;
-                            float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
-                            if (dim == 3) {
-                                const float ddz = o[u].z - tz;
-                                r2 = __builtin_fmaf(ddz, ddz, r2);
-                            }
-                            const bool hit = (b + u < m) && (r2 < R2) && (q != p);
-                            hits |= static_cast<uint64_t>(hit) << (b + u);
-                        }
+                        for (uint32_t u = 0; u < kUnroll; ++u) ob[u] = src[b + kUnroll + u];
+                        __builtin_amdgcn_sched_barrier(0);
+                        hits |= static_cast<uint64_t>(test_group<DIM>(oa, q0 + b, b1, b2, tx0, tx1, tx2, ty, tz, R2)) << b;
+                        // the next A group, or this one again past the piece's end
+                        // (keeps the address inside the padded array)
+                        const uint32_t na = b + 2 * kUnroll < m ? b + 2 * kUnroll : b;
+#pragma unroll
+                        for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[na + u];
+                        __builtin_amdgcn_sched_barrier(0);
+                        hits |= static_cast<uint64_t>(
+                                    test_group<DIM>(ob, q0 + b + kUnroll, b1, b2, tx0, tx1, tx2, ty, tz, R2))
+                                << (b + kUnroll);
                     }
+                    // drop candidates past the piece and the particle itself
+                    if (m < 64) hits &= (uint64_t{1} << m) - 1u;
+                    if (p - q0 < 64u) hits &= ~(uint64_t{1} << (p - q0));
                     while (hits) {
                         const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(hits));
                         hits &= hits - 1;
@@ -494,6 +532,7 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
     if (cnt > max_nbr) set_error(err, kErrOverflow);
 }
 
+template <int DIM>
 __global__ void __launch_bounds__(kMaxBlock)
 k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
         const float4* __restrict__ pos4, const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
@@ -503,7 +542,7 @@ k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
     for_each_item(Q, &s_pos, [&](uint32_t ix) {
         const Item it = items[ix];
         if (threadIdx.x < it.count)
-            nlist_particle(cases[it.case_id], it, st, pos4, cell_first, nbr, nbr_count, max_nbr, n_total, err);
+            nlist_particle<DIM>(cases[it.case_id], it, st, pos4, cell_first, nbr, nbr_count, max_nbr, n_total, err);
     });
 }
 
@@ -564,8 +603,13 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     hipError_t e = item_queue(P, ws, 0, s, &Q);
     if (e == hipSuccess && mid) e = hipEventRecord(mid, s);
     if (e != hipSuccess) return e;
-    k_nlist<<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
-                                            cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), n, err);
+    const uint32_t mx = static_cast<uint32_t>(cells.max_nbr);
+    if (P.dim_max == 3)
+        k_nlist<3><<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
+                                                   cells.nbr_count, mx, n, err);
+    else
+        k_nlist<2><<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
+                                                   cells.nbr_count, mx, n, err);
     return hipGetLastError();
 }
 

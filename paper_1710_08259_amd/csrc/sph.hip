@@ -51,17 +51,26 @@ __device__ inline uint32_t entry_index(uint32_t e, uint32_t n_total)
     return j < n_total ? j : n_total - 1;  // never out of range for lists built by the search
 }
 
-// Entries of list rows k .. k + kGroup - 1 of particle i (column-major lists,
-// so a wave reads kGroup runs of 64 consecutive words).  Rows at or past
-// max_nbr are not read; rows past the particle's own count hold stale entries,
-// whose contribution the caller masks.
-__device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t k, uint32_t max_nbr,
+// Entries of list rows k .. k + G - 1 of particle i (column-major lists, so a
+// wave reads G runs of 64 consecutive words).  Rows at or past the particle's
+// own count are not read (their entry is 0, i.e. particle 0 with no shift;
+// the caller masks the contribution of such pairs).
+template <uint32_t G>
+__device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t k, uint32_t cnt,
                                     uint32_t n_total, uint32_t* e)
 {
 #pragma unroll
-    for (uint32_t u = 0; u < kGroup; ++u)
-        e[u] = k + u < max_nbr ? nbr[static_cast<size_t>(k + u) * n_total + i] : 0u;
+    for (uint32_t u = 0; u < G; ++u)
+        e[u] = k + u < cnt ? nbr[static_cast<size_t>(k + u) * n_total + i] : 0u;
 }
+
+// The pair loops are bound by the latency of their gathers, not by issue:
+// each loop is software-pipelined so that the gathers of group g + 1 (and
+// the list entries of group g + 2) are in flight while group g is summed.
+// The scheduling barrier keeps the compiler from sinking those loads below
+// the arithmetic they are meant to overlap.
+constexpr uint32_t kDensityGroup = 8;
+constexpr uint32_t kForceGroup = 4;
 
 // ----------------------------------------------------------------------------
 // density + equation of state
@@ -83,17 +92,22 @@ __device__ inline void density_particle(const CaseDev& C, const ShiftTable& tab,
     if (cnt > max_nbr) cnt = max_nbr;
     const float inv_h = C.inv_h;
     float sum = 0.0f;
-    // groups of kGroup pairs; the next group's entries load while this
-    // group's neighbours are gathered
-    uint32_t e[kGroup], en[kGroup];
-    load_entries(nbr, i, 0, max_nbr, n_total, e);
-    for (uint32_t k = 0; k < cnt; k += kGroup) {
-        load_entries(nbr, i, k + kGroup, max_nbr, n_total, en);
-        float4 o[kGroup];
+    constexpr uint32_t G = kDensityGroup;
+    uint32_t e[G], en[G];
+    float4 o[G];
+    load_entries<G>(nbr, i, 0, cnt, n_total, e);
 #pragma unroll
-        for (uint32_t u = 0; u < kGroup; ++u) o[u] = pos4[entry_index(e[u], n_total)];
+    for (uint32_t u = 0; u < G; ++u) o[u] = pos4[entry_index(e[u], n_total)];
+    load_entries<G>(nbr, i, G, cnt, n_total, en);
+    for (uint32_t k = 0; k < cnt; k += G) {
+        float4 on[G];
+        uint32_t enn[G];
 #pragma unroll
-        for (uint32_t u = 0; u < kGroup; ++u) {
+        for (uint32_t u = 0; u < G; ++u) on[u] = pos4[entry_index(en[u], n_total)];
+        load_entries<G>(nbr, i, k + 2 * G, cnt, n_total, enn);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (uint32_t u = 0; u < G; ++u) {
             const float3 d = pair_d(tab.v[e[u] >> NAUTICLE_NBR_INDEX_BITS], o[u].x, o[u].y, o[u].z, me.x, me.y, me.z);
             const float q = sqrtf(pair_r2(d, dim)) * inv_h;
             const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
@@ -102,7 +116,11 @@ __device__ inline void density_particle(const CaseDev& C, const ShiftTable& tab,
             sum += k + u < cnt ? w : 0.0f;
         }
 #pragma unroll
-        for (uint32_t u = 0; u < kGroup; ++u) e[u] = en[u];
+        for (uint32_t u = 0; u < G; ++u) {
+            e[u] = en[u];
+            en[u] = enn[u];
+            o[u] = on[u];
+        }
     }
     const float rho = C.m_alpha * (1.0f + sum);
     const float delta = (rho - C.rho0) * C.inv_rho0;
@@ -208,21 +226,30 @@ __device__ inline void forces_particle(const CaseDev& C, const ShiftTable& tab, 
     uint32_t cnt = nbr_count[i];
     if (cnt > max_nbr) cnt = max_nbr;
     float ax = 0.0f, ay = 0.0f, az = 0.0f;
-    // groups of kGroup pairs; the next group's entries load while this
-    // group's neighbours are gathered
-    uint32_t e[kGroup], en[kGroup];
-    load_entries(nbr, i, 0, max_nbr, n_total, e);
-    for (uint32_t k = 0; k < cnt; k += kGroup) {
-        load_entries(nbr, i, k + kGroup, max_nbr, n_total, en);
-        float4 aj[kGroup], bj[kGroup];
+    constexpr uint32_t G = kForceGroup;
+    uint32_t e[G], en[G];
+    float4 aj[G], bj[G];
+    load_entries<G>(nbr, i, 0, cnt, n_total, e);
 #pragma unroll
-        for (uint32_t u = 0; u < kGroup; ++u) {
-            const uint32_t j = entry_index(e[u], n_total);
-            aj[u] = a4[j];
-            bj[u] = b4[j];
+    for (uint32_t u = 0; u < G; ++u) {
+        const uint32_t j = entry_index(e[u], n_total);
+        aj[u] = a4[j];
+        bj[u] = b4[j];
+    }
+    load_entries<G>(nbr, i, G, cnt, n_total, en);
+    for (uint32_t k = 0; k < cnt; k += G) {
+        float4 ajn[G], bjn[G];
+        uint32_t enn[G];
+#pragma unroll
+        for (uint32_t u = 0; u < G; ++u) {
+            const uint32_t j = entry_index(en[u], n_total);
+            ajn[u] = a4[j];
+            bjn[u] = b4[j];
         }
+        load_entries<G>(nbr, i, k + 2 * G, cnt, n_total, enn);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (uint32_t u = 0; u < kGroup; ++u) {
+        for (uint32_t u = 0; u < G; ++u) {
             const float3 d = pair_d(tab.v[e[u] >> NAUTICLE_NBR_INDEX_BITS], aj[u].x, aj[u].y, aj[u].z, ai4.x, ai4.y,
                                     ai4.z);
             const float q = sqrtf(pair_r2(d, dim)) * inv_h;
@@ -238,7 +265,12 @@ __device__ inline void forces_particle(const CaseDev& C, const ShiftTable& tab, 
             az = fmaf(cp, d.z, fmaf(cv, bi4.z - bj[u].z, az));
         }
 #pragma unroll
-        for (uint32_t u = 0; u < kGroup; ++u) e[u] = en[u];
+        for (uint32_t u = 0; u < G; ++u) {
+            e[u] = en[u];
+            en[u] = enn[u];
+            aj[u] = ajn[u];
+            bj[u] = bjn[u];
+        }
     }
     const bool fixed = st.id[i] >= C.n_fluid;
     float a[3] = {ax, ay, az};
