@@ -135,8 +135,13 @@ typedef struct {
  *   cell_start/end[c]: first / one-past-last sorted position of cell key c,
  *                 NAUTICLE_EMPTY for both when the cell is empty;
  *                 length nauticle_cells_total();
- *   nbr           max_nbr * N_total entries, column-major: entry k of
- *                 sorted particle p at nbr[k * N_total + p];
+ *   nbr           max_nbr * N_total entries in chunks of four, chunk-major:
+ *                 entry k of sorted particle p at
+ *                 nbr[4 * ((k / 4) * N_total + p) + k % 4]
+ *                 (so one 16-byte load gives four consecutive entries of a
+ *                 particle and the lanes of a wave read adjacent chunks);
+ *                 max_nbr is a multiple of 4 and nbr is 16-byte aligned;
+ *                 entries past a particle's count are unspecified;
  *   nbr_count[p]  number of neighbours of p (the full count, even if it
  *                 exceeds max_nbr, in which case the error word is set). */
 typedef struct {

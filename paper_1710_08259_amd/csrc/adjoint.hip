@@ -112,9 +112,8 @@ k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
             if (cnt > max_nbr) cnt = max_nbr;
             float sbar = 0.0f, kbar = 0.0f, nubar = 0.0f;
             float vvx = 0.0f, vvy = 0.0f, vvz = 0.0f;
-            const uint32_t* col = nbr + i;
             for (uint32_t k = 0; k < cnt; ++k) {
-                const uint32_t e = col[static_cast<size_t>(k) * n_total];
+                const uint32_t e = list_entry(nbr, k, i, n_total);
                 const uint32_t j = adj_index(e, n_total);
                 const float4 aj = a4[j], bj = b4[j], Aj = adj4[j];
                 const float3 d = adj_d(C, e, aj, ai);
@@ -185,9 +184,8 @@ __device__ inline void adj_b_particle(const CaseDev& C, uint32_t i, StateDev st,
     uint32_t cnt = nbr_count[i];
     if (cnt > max_nbr) cnt = max_nbr;
     float accx = 0.0f, accy = 0.0f, accz = 0.0f;
-    const uint32_t* col = nbr + i;
     for (uint32_t k = 0; k < cnt; ++k) {
-        const uint32_t e = col[static_cast<size_t>(k) * n_total];
+        const uint32_t e = list_entry(nbr, k, i, n_total);
         const uint32_t j = adj_index(e, n_total);
         const float4 aj = a4[j], bj = b4[j], Aj = adj4b[j];
         const float3 d = adj_d(C, e, aj, ai);

@@ -273,11 +273,14 @@ nauticle_status check_state(const Plan& P, const nauticle_state* st, bool need_v
 nauticle_status check_cells(const Plan& P, const nauticle_cells* c, bool need_lists)
 {
     if (!c) return fail(NAUTICLE_ERR_INVALID_ARG, "cells is null");
-    if (c->max_nbr < 1 || c->max_nbr > 1024) return fail(NAUTICLE_ERR_INVALID_ARG, "max_nbr outside [1, 1024]");
+    if (c->max_nbr < kChunk || c->max_nbr > 1024 || c->max_nbr % kChunk != 0)
+        return fail(NAUTICLE_ERR_INVALID_ARG, "max_nbr must be a multiple of 4 in [4, 1024]");
     if (!c->cell_start || !c->cell_end) return fail(NAUTICLE_ERR_INVALID_ARG, "cell_start/end null");
     if (P.n_total == 0) return NAUTICLE_OK;
     if (!c->key || !c->perm) return fail(NAUTICLE_ERR_INVALID_ARG, "key/perm null");
     if (need_lists && (!c->nbr || !c->nbr_count)) return fail(NAUTICLE_ERR_INVALID_ARG, "nbr/nbr_count null");
+    if (need_lists && reinterpret_cast<uintptr_t>(c->nbr) % 16 != 0)
+        return fail(NAUTICLE_ERR_INVALID_ARG, "nbr must be 16-byte aligned");
     if (static_cast<uint64_t>(c->max_nbr) * P.n_total > (1ull << 40))
         return fail(NAUTICLE_ERR_INVALID_ARG, "neighbour list too large");
     return NAUTICLE_OK;

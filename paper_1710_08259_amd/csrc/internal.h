@@ -15,6 +15,19 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
 constexpr uint32_t kPosPad = 64;   // float4s readable past the end of the packed position array
 constexpr uint32_t kIndexMask = (1u << NAUTICLE_NBR_INDEX_BITS) - 1u;
+constexpr int32_t kChunk = 4;      // list entries per 16-byte chunk
+
+// Chunk c (entries 4c .. 4c + 3) of sorted particle p's neighbour list.
+__device__ inline const uint4* nbr_chunk(const uint32_t* nbr, uint32_t c, uint32_t p, uint32_t n_total)
+{
+    return reinterpret_cast<const uint4*>(nbr) + (static_cast<size_t>(c) * n_total + p);
+}
+
+// Entry k of sorted particle p's neighbour list.
+__device__ inline uint32_t list_entry(const uint32_t* nbr, uint32_t k, uint32_t p, uint32_t n_total)
+{
+    return nbr[(static_cast<size_t>(k / kChunk) * n_total + p) * kChunk + k % kChunk];
+}
 
 // Device error word bits (OR-ed by kernels, read by nauticle_check).
 constexpr uint32_t kErrNonFinite = 1u;

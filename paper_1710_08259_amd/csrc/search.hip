@@ -384,8 +384,9 @@ hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipSt
 // piece the x part takes one of three values, selected by the piece's cell
 // boundaries.  Candidates are read as float4s, kUnroll at a time, with the
 // next kUnroll already in flight (the loop is bound by load latency); those
-// that pass set a bit in a 64-candidate mask, which is then emitted into the
-// particle's list column in ascending order.  Lanes of one home cell read the
+// that pass set a bit in a 64-candidate mask, which is then emitted in
+// ascending order into a four-entry register buffer that is stored as one
+// 16-byte chunk when full.  Lanes of one home cell read the
 // same candidate at the same time, so a wave's load touches only a handful of
 // cache lines.  Reads may run up to 2 kUnroll - 1 candidates past a piece
 // (the packed positions are padded for it); such candidates are masked off.
@@ -440,7 +441,9 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
     const int32_t nx = C.nc[0];
     const bool px = C.periodic[0] != 0;
     const float csx = C.cs[0];
-    uint32_t* col = nbr + p;
+    uint4* col = reinterpret_cast<uint4*>(nbr) + p;  // chunk c at col[c * n_total]
+    const uint32_t max_chunks = max_nbr / kChunk;
+    uint4 buf = make_uint4(0u, 0u, 0u, 0u);  // the last four entries, newest in w
     uint32_t cnt = 0;
     constexpr int kZ = DIM == 3 ? 1 : 0;
     for (int dz = -kZ; dz <= kZ; ++dz) {
@@ -519,14 +522,24 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
                         hits &= hits - 1;
                         const uint32_t q = q0 + b;
                         const int32_t dx = dx0 + static_cast<int32_t>(q >= b1) + static_cast<int32_t>(q >= b2);
-                        if (cnt < max_nbr)
-                            col[static_cast<size_t>(cnt) * n_total] =
-                                q | code_yz | (static_cast<uint32_t>(dx + 1) << NAUTICLE_NBR_INDEX_BITS);
+                        buf.x = buf.y;
+                        buf.y = buf.z;
+                        buf.z = buf.w;
+                        buf.w = q | code_yz | (static_cast<uint32_t>(dx + 1) << NAUTICLE_NBR_INDEX_BITS);
                         ++cnt;
+                        const uint32_t chunk = (cnt >> 2) - 1u;
+                        if ((cnt & 3u) == 0u && chunk < max_chunks) col[static_cast<size_t>(chunk) * n_total] = buf;
                     }
                 }
             }
         }
+    }
+    // the last, partial chunk: its r entries are the newest r of the buffer
+    const uint32_t r = cnt & 3u;
+    if (r != 0u && (cnt >> 2) < max_chunks) {
+        const uint4 out = r == 1u ? make_uint4(buf.w, 0u, 0u, 0u)
+                                  : (r == 2u ? make_uint4(buf.z, buf.w, 0u, 0u) : make_uint4(buf.y, buf.z, buf.w, 0u));
+        col[static_cast<size_t>(cnt >> 2) * n_total] = out;
     }
     nbr_count[p] = cnt;
     if (cnt > max_nbr) set_error(err, kErrOverflow);

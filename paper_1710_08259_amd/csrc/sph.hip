@@ -51,24 +51,95 @@ __device__ inline uint32_t entry_index(uint32_t e, uint32_t n_total)
     return j < n_total ? j : n_total - 1;  // never out of range for lists built by the search
 }
 
-// Entries of list rows k .. k + G - 1 of particle i (column-major lists, so a
-// wave reads G runs of 64 consecutive words).  Rows at or past the particle's
-// own count are not read (their entry is 0, i.e. particle 0 with no shift;
-// the caller masks the contribution of such pairs).
+// Entries k .. k + G - 1 of particle i's list (k a multiple of G, G a
+// multiple of the four-entry chunk): one 16-byte load per chunk, and the 64
+// lanes of a wave read 64 adjacent chunks.  Chunks past the particle's last
+// one (`last`) are not read: the last chunk is read again instead (a cache
+// hit, and no divergent branch that would hold up the pipelined gathers);
+// the caller masks the contribution of entries at or past the count.
 template <uint32_t G>
-__device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t k, uint32_t cnt,
+__device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t k, uint32_t last,
                                     uint32_t n_total, uint32_t* e)
 {
+    static_assert(G % kChunk == 0, "groups are whole chunks");
 #pragma unroll
-    for (uint32_t u = 0; u < G; ++u)
-        e[u] = k + u < cnt ? nbr[static_cast<size_t>(k + u) * n_total + i] : 0u;
+    for (uint32_t c = 0; c < G / kChunk; ++c) {
+        const uint4 v = *nbr_chunk(nbr, min(k / kChunk + c, last), i, n_total);
+        e[c * kChunk + 0] = v.x;
+        e[c * kChunk + 1] = v.y;
+        e[c * kChunk + 2] = v.z;
+        e[c * kChunk + 3] = v.w;
+    }
 }
 
-// The pair loops are bound by the latency of their gathers, not by issue:
-// each loop is software-pipelined so that the gathers of group g + 1 (and
-// the list entries of group g + 2) are in flight while group g is summed.
-// The scheduling barrier keeps the compiler from sinking those loads below
-// the arithmetic they are meant to overlap.
+// Index of the last chunk holding any of a particle's cnt entries (0 when
+// there are none; its entries are then all masked).
+__device__ inline uint32_t last_chunk(uint32_t cnt)
+{
+    return cnt > 0u ? (cnt - 1u) / kChunk : 0u;
+}
+
+// The pair loops are bound by the latency of their gathers, not by issue.
+// walk_pairs runs a particle's list through a two-stage load pipeline, in
+// groups of G pairs held in two register stages (A, B) that alternate
+// without copies:
+//
+//   entries(g + 2) ; gathers(g + 1) -> B ; sum group g from A
+//   entries(g + 3) ; gathers(g + 2) -> A ; sum group g + 1 from B
+//
+// Loads complete in issue order as far as the wait counter is concerned, so
+// each group's entries are issued ahead of the gathers of the group before
+// it: waiting for the entries then never waits for gathers still in flight,
+// and a group is summed while the next group's gathers are outstanding.
+// The scheduling barriers keep the compiler from moving the sums across the
+// loads they are meant to overlap.  `gather(j, v)` fills the NA float4s of
+// neighbour j; `body(k, v, code)` adds pair k (k >= cnt must be masked by
+// the body) with the 6-bit cell-shift code of its entry.
+template <uint32_t G, uint32_t NA>
+struct PairStage {
+    float4 v[G][NA];
+    uint32_t code[G];
+};
+
+template <uint32_t G, uint32_t NA, typename Gather>
+__device__ inline void gather_stage(const uint32_t* e, uint32_t n_total, Gather&& gather, PairStage<G, NA>& S)
+{
+#pragma unroll
+    for (uint32_t u = 0; u < G; ++u) {
+        gather(entry_index(e[u], n_total), S.v[u]);
+        S.code[u] = e[u] >> NAUTICLE_NBR_INDEX_BITS;
+    }
+}
+
+template <uint32_t G, uint32_t NA, typename Gather, typename Body>
+__device__ inline void walk_pairs(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t cnt, uint32_t n_total,
+                                  Gather&& gather, Body&& body)
+{
+    const uint32_t last = last_chunk(cnt);
+    uint32_t ex[G], ey[G];
+    PairStage<G, NA> A, B;
+    load_entries<G>(nbr, i, 0, last, n_total, ex);
+    __builtin_amdgcn_sched_barrier(0);
+    load_entries<G>(nbr, i, G, last, n_total, ey);
+    __builtin_amdgcn_sched_barrier(0);
+    gather_stage<G, NA>(ex, n_total, gather, A);
+    __builtin_amdgcn_sched_barrier(0);
+    for (uint32_t k = 0; k < cnt; k += 2 * G) {
+        load_entries<G>(nbr, i, k + 2 * G, last, n_total, ex);
+        gather_stage<G, NA>(ey, n_total, gather, B);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (uint32_t u = 0; u < G; ++u) body(k + u, A.v[u], A.code[u]);
+        __builtin_amdgcn_sched_barrier(0);
+        load_entries<G>(nbr, i, k + 3 * G, last, n_total, ey);
+        gather_stage<G, NA>(ex, n_total, gather, A);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (uint32_t u = 0; u < G; ++u) body(k + G + u, B.v[u], B.code[u]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 constexpr uint32_t kDensityGroup = 8;
 constexpr uint32_t kForceGroup = 4;
 
@@ -92,36 +163,18 @@ __device__ inline void density_particle(const CaseDev& C, const ShiftTable& tab,
     if (cnt > max_nbr) cnt = max_nbr;
     const float inv_h = C.inv_h;
     float sum = 0.0f;
-    constexpr uint32_t G = kDensityGroup;
-    uint32_t e[G], en[G];
-    float4 o[G];
-    load_entries<G>(nbr, i, 0, cnt, n_total, e);
-#pragma unroll
-    for (uint32_t u = 0; u < G; ++u) o[u] = pos4[entry_index(e[u], n_total)];
-    load_entries<G>(nbr, i, G, cnt, n_total, en);
-    for (uint32_t k = 0; k < cnt; k += G) {
-        float4 on[G];
-        uint32_t enn[G];
-#pragma unroll
-        for (uint32_t u = 0; u < G; ++u) on[u] = pos4[entry_index(en[u], n_total)];
-        load_entries<G>(nbr, i, k + 2 * G, cnt, n_total, enn);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (uint32_t u = 0; u < G; ++u) {
-            const float3 d = pair_d(tab.v[e[u] >> NAUTICLE_NBR_INDEX_BITS], o[u].x, o[u].y, o[u].z, me.x, me.y, me.z);
+    walk_pairs<kDensityGroup, 1>(
+        nbr, i, cnt, n_total, [&](uint32_t j, float4* v) { v[0] = pos4[j]; },
+        [&](uint32_t k, const float4* v, uint32_t code) {
+            const float3 d = pair_d(tab.v[code], v[0].x, v[0].y, v[0].z, me.x, me.y, me.z);
             const float q = sqrtf(pair_r2(d, dim)) * inv_h;
             const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
             const float t2 = t * t;
             const float w = t2 * t2 * fmaf(2.0f, q, 1.0f);
-            sum += k + u < cnt ? w : 0.0f;
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < G; ++u) {
-            e[u] = en[u];
-            en[u] = enn[u];
-            o[u] = on[u];
-        }
-    }
+            // a pair past the end of the list contributes nothing (a factor,
+            // not a branch: the loop body stays one basic block)
+            sum = fmaf(k < cnt ? 1.0f : 0.0f, w, sum);
+        });
     const float rho = C.m_alpha * (1.0f + sum);
     const float delta = (rho - C.rho0) * C.inv_rho0;
     const float p = C.B * expm1f(C.gamma * log1pf(delta));
@@ -226,52 +279,29 @@ __device__ inline void forces_particle(const CaseDev& C, const ShiftTable& tab, 
     uint32_t cnt = nbr_count[i];
     if (cnt > max_nbr) cnt = max_nbr;
     float ax = 0.0f, ay = 0.0f, az = 0.0f;
-    constexpr uint32_t G = kForceGroup;
-    uint32_t e[G], en[G];
-    float4 aj[G], bj[G];
-    load_entries<G>(nbr, i, 0, cnt, n_total, e);
-#pragma unroll
-    for (uint32_t u = 0; u < G; ++u) {
-        const uint32_t j = entry_index(e[u], n_total);
-        aj[u] = a4[j];
-        bj[u] = b4[j];
-    }
-    load_entries<G>(nbr, i, G, cnt, n_total, en);
-    for (uint32_t k = 0; k < cnt; k += G) {
-        float4 ajn[G], bjn[G];
-        uint32_t enn[G];
-#pragma unroll
-        for (uint32_t u = 0; u < G; ++u) {
-            const uint32_t j = entry_index(en[u], n_total);
-            ajn[u] = a4[j];
-            bjn[u] = b4[j];
-        }
-        load_entries<G>(nbr, i, k + 2 * G, cnt, n_total, enn);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (uint32_t u = 0; u < G; ++u) {
-            const float3 d = pair_d(tab.v[e[u] >> NAUTICLE_NBR_INDEX_BITS], aj[u].x, aj[u].y, aj[u].z, ai4.x, ai4.y,
-                                    ai4.z);
+    walk_pairs<kForceGroup, 2>(
+        nbr, i, cnt, n_total,
+        [&](uint32_t j, float4* v) {
+            v[0] = a4[j];
+            v[1] = b4[j];
+        },
+        [&](uint32_t k, const float4* v, uint32_t code) {
+            const float4& aj = v[0];
+            const float4& bj = v[1];
+            const float3 d = pair_d(tab.v[code], aj.x, aj.y, aj.z, ai4.x, ai4.y, ai4.z);
             const float q = sqrtf(pair_r2(d, dim)) * inv_h;
             const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
-            // a pair past the end of the list contributes nothing
-            const float F = k + u < cnt ? C.F_coef * (t * t * t) : 0.0f;
+            // a pair past the end of the list contributes nothing (a factor,
+            // not a branch: the loop body stays one basic block)
+            const float F = (k < cnt ? C.F_coef : 0.0f) * (t * t * t);
             // pressure: -m (s_i + s_j) F r_ij = +m (s_i + s_j) F d
-            const float cp = m * (ai4.w + aj[u].w) * F;
+            const float cp = m * (ai4.w + aj.w) * F;
             // viscosity: m nu (k_i + k_j) F (v_i - v_j)
-            const float cv = mnu * (bi4.w + bj[u].w) * F;
-            ax = fmaf(cp, d.x, fmaf(cv, bi4.x - bj[u].x, ax));
-            ay = fmaf(cp, d.y, fmaf(cv, bi4.y - bj[u].y, ay));
-            az = fmaf(cp, d.z, fmaf(cv, bi4.z - bj[u].z, az));
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < G; ++u) {
-            e[u] = en[u];
-            en[u] = enn[u];
-            aj[u] = ajn[u];
-            bj[u] = bjn[u];
-        }
-    }
+            const float cv = mnu * (bi4.w + bj.w) * F;
+            ax = fmaf(cp, d.x, fmaf(cv, bi4.x - bj.x, ax));
+            ay = fmaf(cp, d.y, fmaf(cv, bi4.y - bj.y, ay));
+            az = fmaf(cp, d.z, fmaf(cv, bi4.z - bj.z, az));
+        });
     const bool fixed = st.id[i] >= C.n_fluid;
     float a[3] = {ax, ay, az};
     const float vi[3] = {bi4.x, bi4.y, bi4.z};

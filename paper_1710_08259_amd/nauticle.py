@@ -208,9 +208,14 @@ class Cells:
     perm: torch.Tensor
     cell_start: torch.Tensor
     cell_end: torch.Tensor
-    nbr: torch.Tensor           # (max_nbr, N) int32
+    nbr: torch.Tensor           # (max_nbr / 4, N, 4) int32: chunks of four entries
     nbr_count: torch.Tensor
     max_nbr: int
+
+    def entries(self) -> torch.Tensor:
+        """The lists as (max_nbr, N): entry k of sorted particle p at [k, p]."""
+        n_chunks, N, w = self.nbr.shape
+        return self.nbr.permute(0, 2, 1).reshape(n_chunks * w, N)
 
     def c(self) -> CCells:
         c = CCells()
@@ -266,6 +271,13 @@ def default_max_nbr(dim: int) -> int:
     return 64 if dim == 2 else 128
 
 
+def _list_shape(max_nbr: int, n: int):
+    """Storage of the neighbour lists: chunks of four entries, chunk-major.
+    A max_nbr that is not a multiple of 4 is passed through for the library
+    to reject."""
+    return (max(max_nbr // 4, 1), n, 4) if max_nbr % 4 == 0 else (max_nbr, n)
+
+
 class Problem:
     """A prepared set of independent cases on one device: owns the workspace,
     the neighbour structure and the field arrays."""
@@ -292,7 +304,7 @@ class Problem:
         N = max(self.n, 1)
         self.cells = Cells(torch.empty(N, **i32), torch.empty(N, **i32),
                            torch.empty(max(self.n_cells, 1), **i32), torch.empty(max(self.n_cells, 1), **i32),
-                           torch.empty((self.max_nbr, N), **i32), torch.empty(N, **i32), self.max_nbr)
+                           torch.empty(_list_shape(self.max_nbr, N), **i32), torch.empty(N, **i32), self.max_nbr)
         self.fields = Fields(torch.empty(N, **f32), torch.empty(N, **f32), torch.empty(N, **f32),
                              torch.empty(N, **f32), [torch.empty(N, **f32) for _ in range(self.dim)])
         self.sorted = self.new_state()
@@ -406,7 +418,7 @@ class Problem:
         i32 = dict(dtype=torch.int32, device=self.device)
         N = max(self.n, 1)
         return Cells(torch.empty(N, **i32), torch.empty(N, **i32), torch.empty(max(self.n_cells, 1), **i32),
-                     torch.empty(max(self.n_cells, 1), **i32), torch.empty((self.max_nbr, N), **i32),
+                     torch.empty(max(self.n_cells, 1), **i32), torch.empty(_list_shape(self.max_nbr, N), **i32),
                      torch.empty(N, **i32), self.max_nbr)
 
     def new_fields(self) -> Fields:

@@ -100,7 +100,7 @@ def test_build_cells_is_bit_exact(name):
     cnt_ref, lst_ref = O.neighbours_f32(domain_of(case), case.h, cell_in, off_in, max_nbr=prob.max_nbr)
     cnt = u32(prob.cells.nbr_count)[:n]
     np.testing.assert_array_equal(cnt, cnt_ref[perm])
-    nbr = u32(prob.cells.nbr)[:, :n]
+    nbr = u32(prob.cells.entries())[:, :n]
     j, delta = decode_nbr(nbr)
     coords = np.stack([cell_in % case.ncell[0], (cell_in // case.ncell[0]) % case.ncell[1],
                        cell_in // (case.ncell[0] * case.ncell[1])], axis=1).astype(np.int64)
@@ -281,6 +281,30 @@ def test_error_word_reports_nonfinite_and_overflow():
     with pytest.raises(N.NauticleError) as e:
         prob.check()
     assert e.value.status == N.ERR_NONFINITE
+
+
+def test_list_storage_must_be_whole_aligned_chunks():
+    """The lists are stored as 16-byte chunks of four entries: a max_nbr
+    that is not a multiple of 4, or a misaligned list pointer, is rejected
+    on the host before any kernel runs."""
+    N = nauticle()
+    case = WL.lattice_case(3, (10, 10, 10), 0.01, 1.2, 0.05, 0.05, seed=2)
+    prob = N.Problem([case], max_nbr=6)
+    st = prob.state_from_cases()
+    with pytest.raises(N.NauticleError) as e:
+        prob.build_cells(st)
+    assert e.value.status == N.ERR_INVALID_ARG
+    prob = N.Problem([case], max_nbr=128)
+    st = prob.state_from_cases()
+    cells = prob.new_cells()
+    flat = torch.empty(128 * case.n + 4, dtype=torch.int32, device=cells.nbr.device)
+    cells.nbr = flat[1:]  # 4-byte aligned, not 16
+    with pytest.raises(N.NauticleError) as e:
+        prob.build_cells(st, cells=cells)
+    assert e.value.status == N.ERR_INVALID_ARG
+    prob.build_cells(st)
+    torch.cuda.synchronize()
+    prob.check()
 
 
 def test_adjoint_one_step_matches_oracle_vjp():
