@@ -87,6 +87,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     const int dim0 = cases[0].dom.dim;
     uint64_t n_total = 0, n_cells_total = 0, n_fluid_total = 0;
     int64_t worst_items = 0;
+    double halo_need = 0.0;
     std::vector<double> nbr_per_particle;
     for (int32_t b = 0; b < n_cases; ++b) {
         const nauticle_case& c = cases[b];
@@ -168,6 +169,15 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         for (int k = 0; k < d.dim; ++k) volume *= d.ncell[k] * d.cell_size[k];
         const double ball = d.dim == 2 ? M_PI * 4.0 * q.h * q.h : 4.0 / 3.0 * M_PI * 8.0 * q.h * q.h * q.h;
         nbr_per_particle.push_back(static_cast<double>(c.n) / volume * ball);
+        // LDS records for an item's neighbourhood at the reference density
+        // (particle volume m / rho0): 3^(dim-1) rows of the item's cells plus
+        // one on each side, with 10% slack; the rest takes the global path
+        double cell_volume = 1.0;
+        for (int k = 0; k < d.dim; ++k) cell_volume *= d.cell_size[k];
+        const double ppc = cell_volume / (q.mass / q.rho0);
+        const double rows = d.dim == 3 ? 9.0 : 3.0;
+        const double need = rows * (std::ceil(static_cast<double>(block) / ppc) + 3.0) * ppc * 1.1 + 32.0;
+        halo_need = std::max(halo_need, need);
         C.item_count = static_cast<uint32_t>(D->items.size()) - C.item_first;
         D->cases.push_back(C);
         n_total += static_cast<uint64_t>(c.n);
@@ -183,6 +193,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     P.n_fluid_total = static_cast<uint32_t>(n_fluid_total);
     P.n_items = static_cast<uint32_t>(D->items.size());
     P.block = static_cast<uint32_t>(block);
+    P.halo_cap = static_cast<uint32_t>(std::min<double>(std::max<double>(halo_need, 256.0), kHaloMaxRecords));
     P.persistent = static_cast<uint32_t>(tn.persistent);
     int cus = 256;
     if (tn.persistent) {

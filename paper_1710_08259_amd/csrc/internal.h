@@ -130,6 +130,7 @@ struct Plan {
     uint32_t block;          // threads per workgroup = particles per item
     uint32_t persistent;     // neighbour loops as persistent grids
     uint32_t persistent_grid;
+    uint32_t halo_cap;       // LDS records staged per work item (neighbour loops)
     Layout L;
     // host copies (for launches that need per-case sizes)
     const CaseDev* host_cases;
@@ -192,6 +193,94 @@ __device__ inline void for_each_item(const ItemQueue& Q, uint32_t* s_pos, Body&&
         }
         body(ix);
     }
+}
+
+// ---- block neighbourhood staging (LDS) ---------------------------------------
+// The neighbour loops are bound by the rate at which the vector L1 cache
+// serves scattered 16-byte gathers.  A work item's particles are one sorted
+// range, in case cells c_lo..c_hi; every neighbour of theirs with cell
+// offset (dx, dy, dz) and no periodic fold lies in the cells
+// [c_lo - 1, c_hi + 1] shifted by dy rows and dz planes, which is one
+// contiguous sorted range per (dy, dz).  Those 3^(dim-1) ranges are copied
+// (coalesced) into LDS, and a neighbour j of row r is read from LDS slot
+// j + shift[r] when it falls inside the staged range, else from global
+// memory (folded neighbours, rows that did not fit).  Which copy is read
+// never changes a value.
+constexpr uint32_t kHaloRows = 9;
+constexpr uint32_t kHaloPad = 16;  // LDS records readable past the staged data
+constexpr uint32_t kHaloMaxRecords = 3072 - kHaloPad;  // 48 KB of float4 records
+
+struct HaloRows {
+    uint32_t lo[kHaloRows];    // staged sorted range [lo, hi) of row r
+    uint32_t hi[kHaloRows];    // hi == lo: nothing staged for the row
+    int32_t shift[kHaloRows];  // LDS record of sorted index j: j + shift
+    uint32_t total;
+};
+
+// Row of a (dy, dz) cell offset: r = (dy + 1) + 3 (dz + 1) in 3-D, dy + 1 in 2-D.
+template <int DIM>
+__device__ inline uint32_t halo_row(int32_t dy, int32_t dz)
+{
+    return static_cast<uint32_t>(dy + 1) + (DIM == 3 ? 3u * static_cast<uint32_t>(dz + 1) : 0u);
+}
+
+// Plans the staged ranges of an item (cap records at most; rows that do not
+// fit whole are left to the global path).  Every thread of the block calls it.
+template <int DIM>
+__device__ inline void halo_plan(const CaseDev& C, const Item& it, const uint32_t* __restrict__ cell,
+                                 const uint32_t* __restrict__ cell_first, uint32_t n_total, uint32_t cap,
+                                 HaloRows* H)
+{
+    constexpr uint32_t rows = DIM == 3 ? 9u : 3u;
+    if (threadIdx.x < rows) {
+        const uint32_t r = threadIdx.x;
+        const int64_t dy = static_cast<int64_t>(r % 3u) - 1;
+        const int64_t dz = DIM == 3 ? static_cast<int64_t>(r / 3u) - 1 : 0;
+        const int64_t S = dy * C.nc[0] + dz * static_cast<int64_t>(C.nc[0]) * C.nc[1];
+        const int64_t last = static_cast<int64_t>(C.n_cells) - 1;
+        int64_t a = static_cast<int64_t>(min(cell[it.first], C.n_cells - 1)) - 1 + S;
+        int64_t b = static_cast<int64_t>(min(cell[it.first + it.count - 1], C.n_cells - 1)) + 1 + S;
+        a = a < 0 ? 0 : a;
+        b = b > last ? last : b;
+        uint32_t lo = 0, hi = 0;
+        if (a <= b) {
+            lo = min(cell_first[C.cell_base + static_cast<uint32_t>(a)], n_total);
+            hi = min(cell_first[C.cell_base + static_cast<uint32_t>(b) + 1u], n_total);
+            hi = hi < lo ? lo : hi;
+        }
+        H->lo[r] = lo;
+        H->hi[r] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t used = 0;
+        for (uint32_t r = 0; r < rows; ++r) {
+            const uint32_t len = H->hi[r] - H->lo[r];
+            if (len <= cap - used) {
+                H->shift[r] = static_cast<int32_t>(used) - static_cast<int32_t>(H->lo[r]);
+                used += len;
+            } else {
+                H->hi[r] = H->lo[r];
+                H->shift[r] = 0;
+            }
+        }
+        H->total = used;
+    }
+    __syncthreads();
+}
+
+// Copies the planned ranges of `src` (one float4 per sorted particle) into
+// `dst` and waits for the whole block.  Every thread of the block calls it.
+template <int DIM>
+__device__ inline void halo_copy(const HaloRows& H, const float4* __restrict__ src, float4* dst)
+{
+    constexpr uint32_t rows = DIM == 3 ? 9u : 3u;
+    for (uint32_t r = 0; r < rows; ++r) {
+        const uint32_t lo = H.lo[r], len = H.hi[r] - H.lo[r];
+        float4* d = dst + (static_cast<int64_t>(lo) + H.shift[r]);
+        for (uint32_t t = threadIdx.x; t < len; t += blockDim.x) d[t] = src[lo + t];
+    }
+    __syncthreads();
 }
 
 inline uint32_t grid_for(const Plan& P)

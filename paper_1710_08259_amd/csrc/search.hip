@@ -304,7 +304,9 @@ k_cell_first(const uint32_t* __restrict__ keys, uint32_t n, uint32_t n_cells, ui
 }
 
 // Gathers the state into sorted order and packs each particle's offsets into
-// one float4 for the neighbour search and the density pass.
+// one float4 for the neighbour search and the density pass; w holds the x
+// index of the particle's cell (exact in FP32), from which the search forms
+// its cell frame shift.
 __global__ void __launch_bounds__(kMaxBlock)
 k_reorder(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
           const uint32_t* __restrict__ perm, uint32_t n, StateDev in, StateDev out, float4* __restrict__ pos4)
@@ -327,7 +329,7 @@ k_reorder(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uin
         out.off[k][p] = o[k];
         out.vel[k][p] = in.vel[k][q];
     }
-    pos4[p] = make_float4(o[0], o[1], o[2], 0.0f);
+    pos4[p] = make_float4(o[0], o[1], o[2], static_cast<float>(cell % static_cast<uint32_t>(C.nc[0])));
 }
 
 __global__ void __launch_bounds__(kMaxBlock)
@@ -343,7 +345,7 @@ k_pack_positions(const CaseDev* __restrict__ cases, const Item* __restrict__ ite
     float o[3] = {0.0f, 0.0f, 0.0f};
     for (int k = 0; k < 3; ++k)
         if (k < C.dim) o[k] = st.off[k][p];
-    pos4[p] = make_float4(o[0], o[1], o[2], 0.0f);
+    pos4[p] = make_float4(o[0], o[1], o[2], static_cast<float>(st.cell[p] % static_cast<uint32_t>(C.nc[0])));
 }
 
 hipError_t item_queue(const Plan& P, void* ws, int c, hipStream_t s, ItemQueue* Q)
@@ -380,35 +382,33 @@ hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipSt
 // rows of three cells along x; since keys run x fastest, a row's three cells
 // are one contiguous sorted range (two pieces where a periodic x axis wraps).
 // The predicate moves the particle into the candidate's cell frame,
-// t = off_i - delta cs: the y and z parts of t are fixed per row, and within a
-// piece the x part takes one of three values, selected by the piece's cell
-// boundaries.  Candidates are read as float4s, kUnroll at a time, with the
-// next kUnroll already in flight (the loop is bound by load latency); those
+// t = off_i - delta cs: the y and z parts of t are fixed per row, and the x
+// part follows from the candidate's cell x index, packed with its offsets.
+// Candidates come from the item's neighbourhood staged in LDS (global memory
+// for folded pieces), kUnroll at a time with the next kUnroll in flight; those
 // that pass set a bit in a 64-candidate mask, which is then emitted in
 // ascending order into a four-entry register buffer that is stored as one
-// 16-byte chunk when full.  Lanes of one home cell read the
-// same candidate at the same time, so a wave's load touches only a handful of
-// cache lines.  Reads may run up to 2 kUnroll - 1 candidates past a piece
-// (the packed positions are padded for it); such candidates are masked off.
+// 16-byte chunk when full.  Lanes of one home cell read the same candidate at
+// the same time.  Reads may run up to 2 kUnroll - 1 candidates past a piece
+// (LDS and the packed positions are padded for it); such candidates are
+// masked off.
 
 constexpr uint32_t kUnroll = 4;
 static_assert(2 * kUnroll <= kPosPad && 64 % (2 * kUnroll) == 0, "candidate groups must tile the 64-bit mask");
 
-// Bit u set iff candidate q + u passes the distance test (FP32, the frame
-// shift applied to the particle; see the predicate above).
+// Bit u set iff candidate u of the group passes the distance test (FP32,
+// the frame shift applied to the particle).  The candidate's cell x index
+// (o.w) against the piece's reference gives delta_x in {-1, 0, 1}, so
+// tx = fl(me.x - delta_x cs) is one fused multiply-add of an exact product.
 template <int DIM>
-__device__ inline uint32_t test_group(const float4* o, uint32_t q, uint32_t b1, uint32_t b2, float tx0, float tx1,
-                                      float tx2, float ty, float tz, float R2)
+__device__ inline uint32_t test_group(const float4* o, float cref, float mex, float csx, float ty, float tz,
+                                      float R2)
 {
 #pragma clang fp contract(off)
-    // candidate positions relative to the piece's cell boundaries
-    const int32_t r1 = static_cast<int32_t>(b1 - q);
-    const int32_t r2b = static_cast<int32_t>(b2 - q);
     uint32_t bits = 0;
 #pragma unroll
     for (uint32_t u = 0; u < kUnroll; ++u) {
-        const int32_t iu = static_cast<int32_t>(u);
-        const float tx = iu < r1 ? tx0 : (iu < r2b ? tx1 : tx2);
+        const float tx = __builtin_fmaf(cref - o[u].w, csx, mex);
         const float ddx = o[u].x - tx;
         const float ddy = o[u].y - ty;
         float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
@@ -421,8 +421,36 @@ __device__ inline uint32_t test_group(const float4* o, uint32_t q, uint32_t b1, 
     return bits;
 }
 
+// Hit mask of the candidates q0 .. q0 + m - 1 (m <= 64) read from `src`
+// (src[k] = candidate q0 + k; readable up to 2 kUnroll - 1 past m).  Two
+// groups per iteration in ping-pong registers: group A is tested while group
+// B loads, then B while the next A loads.
+template <int DIM>
+__device__ inline uint64_t scan_chunk(const float4* src, uint32_t m, float cref, float mex, float csx, float ty,
+                                      float tz, float R2)
+{
+    uint64_t hits = 0;
+    float4 oa[kUnroll], ob[kUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[u];
+    for (uint32_t b = 0; b < m; b += 2 * kUnroll) {
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) ob[u] = src[b + kUnroll + u];
+        __builtin_amdgcn_sched_barrier(0);
+        hits |= static_cast<uint64_t>(test_group<DIM>(oa, cref, mex, csx, ty, tz, R2)) << b;
+        // the next A group, or this one again past the end (stays readable)
+        const uint32_t na = b + 2 * kUnroll < m ? b + 2 * kUnroll : b;
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[na + u];
+        __builtin_amdgcn_sched_barrier(0);
+        hits |= static_cast<uint64_t>(test_group<DIM>(ob, cref, mex, csx, ty, tz, R2)) << (b + kUnroll);
+    }
+    return hits;
+}
+
 template <int DIM>
 __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev st, const float4* __restrict__ pos4,
+                                      const HaloRows& H, const float4* halo,
                                       const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
                                       uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total,
                                       uint32_t* err)
@@ -484,36 +512,20 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
                 else if (dx0 < -1) dx0 += nx;
                 const uint32_t b1 = xa + 1 <= xb ? cell_first[row + static_cast<uint32_t>(xa) + 1] : q_end;
                 const uint32_t b2 = xa + 2 <= xb ? cell_first[row + static_cast<uint32_t>(xa) + 2] : q_end;
-                float tx0 = me.x - static_cast<float>(dx0) * csx;
-                float tx1 = me.x - static_cast<float>(dx0 + 1) * csx;
-                float tx2 = me.x - static_cast<float>(dx0 + 2) * csx;
-                // opaque to the optimiser, so the per-candidate choice stays a
-                // select of these three values instead of being recomputed
-                asm volatile("" : "+v"(tx0), "+v"(tx1), "+v"(tx2));
+                // candidate cell x index - cref = delta_x (the wrapped piece's
+                // single cell included)
+                const float cref = static_cast<float>(xa - dx0);
+                // the piece from LDS when it lies in the row's staged range
+                const uint32_t hr = halo_row<DIM>(dy, dz);
+                const bool staged = q_begin >= H.lo[hr] && q_end <= H.hi[hr];
+                const int32_t hshift = H.shift[hr];
                 for (uint32_t q0 = q_begin; q0 < q_end; q0 += 64) {
                     const uint32_t m = min(q_end - q0, 64u);
-                    const float4* src = pos4 + q0;
-                    uint64_t hits = 0;
-                    // two groups per iteration, in ping-pong registers: group A
-                    // is tested while group B loads, then B while the next A loads
-                    float4 oa[kUnroll], ob[kUnroll];
-#pragma unroll
-                    for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[u];
-                    for (uint32_t b = 0; b < m; b += 2 * kUnroll) {
-#pragma unroll
-                        for (uint32_t u = 0; u < kUnroll; ++u) ob[u] = src[b + kUnroll + u];
-                        __builtin_amdgcn_sched_barrier(0);
-                        hits |= static_cast<uint64_t>(test_group<DIM>(oa, q0 + b, b1, b2, tx0, tx1, tx2, ty, tz, R2)) << b;
-                        // the next A group, or this one again past the piece's end
-                        // (keeps the address inside the padded array)
-                        const uint32_t na = b + 2 * kUnroll < m ? b + 2 * kUnroll : b;
-#pragma unroll
-                        for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[na + u];
-                        __builtin_amdgcn_sched_barrier(0);
-                        hits |= static_cast<uint64_t>(
-                                    test_group<DIM>(ob, q0 + b + kUnroll, b1, b2, tx0, tx1, tx2, ty, tz, R2))
-                                << (b + kUnroll);
-                    }
+                    const uint64_t hits_all =
+                        staged ? scan_chunk<DIM>(halo + (static_cast<int32_t>(q0) + hshift), m, cref, me.x, csx, ty,
+                                                 tz, R2)
+                               : scan_chunk<DIM>(pos4 + q0, m, cref, me.x, csx, ty, tz, R2);
+                    uint64_t hits = hits_all;
                     // drop candidates past the piece and the particle itself
                     if (m < 64) hits &= (uint64_t{1} << m) - 1u;
                     if (p - q0 < 64u) hits &= ~(uint64_t{1} << (p - q0));
@@ -549,13 +561,19 @@ template <int DIM>
 __global__ void __launch_bounds__(kMaxBlock)
 k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
         const float4* __restrict__ pos4, const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
-        uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total, uint32_t* err)
+        uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total, uint32_t halo_cap, uint32_t* err)
 {
+    extern __shared__ float4 s_halo[];  // halo_cap + kHaloPad records
+    __shared__ HaloRows s_rows;
     __shared__ uint32_t s_pos;
     for_each_item(Q, &s_pos, [&](uint32_t ix) {
         const Item it = items[ix];
+        const CaseDev& C = cases[it.case_id];
+        halo_plan<DIM>(C, it, st.cell, cell_first, n_total, halo_cap, &s_rows);
+        halo_copy<DIM>(s_rows, pos4, s_halo);
         if (threadIdx.x < it.count)
-            nlist_particle<DIM>(cases[it.case_id], it, st, pos4, cell_first, nbr, nbr_count, max_nbr, n_total, err);
+            nlist_particle<DIM>(C, it, st, pos4, s_rows, s_halo, cell_first, nbr, nbr_count, max_nbr, n_total, err);
+        __syncthreads();  // the next item's staging overwrites the LDS
     });
 }
 
@@ -617,12 +635,13 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     if (e == hipSuccess && mid) e = hipEventRecord(mid, s);
     if (e != hipSuccess) return e;
     const uint32_t mx = static_cast<uint32_t>(cells.max_nbr);
+    const size_t lds = sizeof(float4) * (P.halo_cap + kHaloPad);
     if (P.dim_max == 3)
-        k_nlist<3><<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
-                                                   cells.nbr_count, mx, n, err);
+        k_nlist<3><<<grid_for(P), P.block, lds, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
+                                                     cells.nbr_count, mx, n, P.halo_cap, err);
     else
-        k_nlist<2><<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
-                                                   cells.nbr_count, mx, n, err);
+        k_nlist<2><<<grid_for(P), P.block, lds, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
+                                                     cells.nbr_count, mx, n, P.halo_cap, err);
     return hipGetLastError();
 }
 
