@@ -193,7 +193,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     P.n_fluid_total = static_cast<uint32_t>(n_fluid_total);
     P.n_items = static_cast<uint32_t>(D->items.size());
     P.block = static_cast<uint32_t>(block);
-    P.halo_cap = static_cast<uint32_t>(std::min<double>(std::max<double>(halo_need, 256.0), kHaloMaxRecords));
+    P.halo_cap = static_cast<uint32_t>(std::min<double>(std::max<double>(halo_need, 256.0), 1u << 20));
     P.persistent = static_cast<uint32_t>(tn.persistent);
     int cus = 256;
     if (tn.persistent) {

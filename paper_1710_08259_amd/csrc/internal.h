@@ -208,7 +208,15 @@ __device__ inline void for_each_item(const ItemQueue& Q, uint32_t* s_pos, Body&&
 // never changes a value.
 constexpr uint32_t kHaloRows = 9;
 constexpr uint32_t kHaloPad = 16;  // LDS records readable past the staged data
-constexpr uint32_t kHaloMaxRecords = 3072 - kHaloPad;  // 48 KB of float4 records
+
+// Records an item may stage for a kernel whose records are na float4s and
+// whose LDS budget is `bytes` (the planned need, or what fits).
+inline uint32_t halo_records(uint32_t planned, uint32_t na, uint32_t bytes)
+{
+    const uint32_t fit = bytes / (16u * na) - kHaloPad;
+    return planned < fit ? planned : fit;
+}
+constexpr uint32_t kHaloBytes = 48u * 1024u;  // 3 items of 256 per CU
 
 struct HaloRows {
     uint32_t lo[kHaloRows];    // staged sorted range [lo, hi) of row r
@@ -269,16 +277,20 @@ __device__ inline void halo_plan(const CaseDev& C, const Item& it, const uint32_
     __syncthreads();
 }
 
-// Copies the planned ranges of `src` (one float4 per sorted particle) into
-// `dst` and waits for the whole block.  Every thread of the block calls it.
-template <int DIM>
-__device__ inline void halo_copy(const HaloRows& H, const float4* __restrict__ src, float4* dst)
+// Copies the planned ranges of NA per-particle float4 arrays into `dst`, as
+// records of NA float4s (record of sorted index j at dst[(j + shift) NA]),
+// and waits for the whole block.  Every thread of the block calls it.
+template <int DIM, int NA>
+__device__ inline void halo_copy(const HaloRows& H, const float4* const (&src)[NA], float4* dst)
 {
     constexpr uint32_t rows = DIM == 3 ? 9u : 3u;
     for (uint32_t r = 0; r < rows; ++r) {
         const uint32_t lo = H.lo[r], len = H.hi[r] - H.lo[r];
-        float4* d = dst + (static_cast<int64_t>(lo) + H.shift[r]);
-        for (uint32_t t = threadIdx.x; t < len; t += blockDim.x) d[t] = src[lo + t];
+        float4* d = dst + (static_cast<int64_t>(lo) + H.shift[r]) * NA;
+        for (uint32_t t = threadIdx.x; t < len; t += blockDim.x) {
+#pragma unroll
+            for (int a = 0; a < NA; ++a) d[t * NA + a] = src[a][lo + t];
+        }
     }
     __syncthreads();
 }

@@ -570,7 +570,8 @@ k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
         const Item it = items[ix];
         const CaseDev& C = cases[it.case_id];
         halo_plan<DIM>(C, it, st.cell, cell_first, n_total, halo_cap, &s_rows);
-        halo_copy<DIM>(s_rows, pos4, s_halo);
+        const float4* const src[1] = {pos4};
+        halo_copy<DIM, 1>(s_rows, src, s_halo);
         if (threadIdx.x < it.count)
             nlist_particle<DIM>(C, it, st, pos4, s_rows, s_halo, cell_first, nbr, nbr_count, max_nbr, n_total, err);
         __syncthreads();  // the next item's staging overwrites the LDS
@@ -635,13 +636,14 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     if (e == hipSuccess && mid) e = hipEventRecord(mid, s);
     if (e != hipSuccess) return e;
     const uint32_t mx = static_cast<uint32_t>(cells.max_nbr);
-    const size_t lds = sizeof(float4) * (P.halo_cap + kHaloPad);
+    const uint32_t cap = halo_records(P.halo_cap, 1, kHaloBytes);
+    const size_t lds = sizeof(float4) * (cap + kHaloPad);
     if (P.dim_max == 3)
         k_nlist<3><<<grid_for(P), P.block, lds, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
-                                                     cells.nbr_count, mx, n, P.halo_cap, err);
+                                                     cells.nbr_count, mx, n, cap, err);
     else
         k_nlist<2><<<grid_for(P), P.block, lds, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
-                                                     cells.nbr_count, mx, n, P.halo_cap, err);
+                                                     cells.nbr_count, mx, n, cap, err);
     return hipGetLastError();
 }
 

@@ -53,30 +53,23 @@ __device__ inline uint32_t entry_index(uint32_t e, uint32_t n_total)
 
 // Entries k .. k + G - 1 of particle i's list (k a multiple of G, G a
 // multiple of the four-entry chunk): one 16-byte load per chunk, and the 64
-// lanes of a wave read 64 adjacent chunks.  Chunks past the particle's last
-// one (`last`) are not read: the last chunk is read again instead (a cache
-// hit, and no divergent branch that would hold up the pipelined gathers);
-// the caller masks the contribution of entries at or past the count.
+// lanes of a wave read 64 adjacent chunks.  Chunks at or past the particle's
+// count are not read (their entries are 0: particle 0 with no shift, one
+// address for every such lane); the caller masks those pairs.
 template <uint32_t G>
-__device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t k, uint32_t last,
+__device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t k, uint32_t cnt,
                                     uint32_t n_total, uint32_t* e)
 {
     static_assert(G % kChunk == 0, "groups are whole chunks");
 #pragma unroll
     for (uint32_t c = 0; c < G / kChunk; ++c) {
-        const uint4 v = *nbr_chunk(nbr, min(k / kChunk + c, last), i, n_total);
+        const uint32_t kc = k + c * kChunk;
+        const uint4 v = kc < cnt ? *nbr_chunk(nbr, kc / kChunk, i, n_total) : make_uint4(0u, 0u, 0u, 0u);
         e[c * kChunk + 0] = v.x;
         e[c * kChunk + 1] = v.y;
         e[c * kChunk + 2] = v.z;
         e[c * kChunk + 3] = v.w;
     }
-}
-
-// Index of the last chunk holding any of a particle's cnt entries (0 when
-// there are none; its entries are then all masked).
-__device__ inline uint32_t last_chunk(uint32_t cnt)
-{
-    return cnt > 0u ? (cnt - 1u) / kChunk : 0u;
 }
 
 // The pair loops are bound by the latency of their gathers, not by issue.
@@ -115,23 +108,22 @@ template <uint32_t G, uint32_t NA, typename Gather, typename Body>
 __device__ inline void walk_pairs(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t cnt, uint32_t n_total,
                                   Gather&& gather, Body&& body)
 {
-    const uint32_t last = last_chunk(cnt);
     uint32_t ex[G], ey[G];
     PairStage<G, NA> A, B;
-    load_entries<G>(nbr, i, 0, last, n_total, ex);
+    load_entries<G>(nbr, i, 0, cnt, n_total, ex);
     __builtin_amdgcn_sched_barrier(0);
-    load_entries<G>(nbr, i, G, last, n_total, ey);
+    load_entries<G>(nbr, i, G, cnt, n_total, ey);
     __builtin_amdgcn_sched_barrier(0);
     gather_stage<G, NA>(ex, n_total, gather, A);
     __builtin_amdgcn_sched_barrier(0);
     for (uint32_t k = 0; k < cnt; k += 2 * G) {
-        load_entries<G>(nbr, i, k + 2 * G, last, n_total, ex);
+        load_entries<G>(nbr, i, k + 2 * G, cnt, n_total, ex);
         gather_stage<G, NA>(ey, n_total, gather, B);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (uint32_t u = 0; u < G; ++u) body(k + u, A.v[u], A.code[u]);
         __builtin_amdgcn_sched_barrier(0);
-        load_entries<G>(nbr, i, k + 3 * G, last, n_total, ey);
+        load_entries<G>(nbr, i, k + 3 * G, cnt, n_total, ey);
         gather_stage<G, NA>(ex, n_total, gather, A);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -141,7 +133,7 @@ __device__ inline void walk_pairs(const uint32_t* __restrict__ nbr, uint32_t i, 
 }
 
 constexpr uint32_t kDensityGroup = 8;
-constexpr uint32_t kForceGroup = 4;
+constexpr uint32_t kForceGroup = 8;
 
 // ----------------------------------------------------------------------------
 // density + equation of state

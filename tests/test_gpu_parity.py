@@ -202,6 +202,37 @@ def test_rollout_dam_break_small_matches_oracle():
     assert np.all(v_gpu[wall] == 0.0)
 
 
+@pytest.mark.parametrize("name", NAMES)
+def test_step_equals_separate_passes_bitwise(name):
+    """nauticle_step (one launch sequence, packed arrays handed from pass to
+    pass) and the separate entry points (build_cells, density, forces with
+    integration) give the same fields and the same next state, bit for bit."""
+    N = nauticle()
+    case = CASES[name]
+    mx = MAX_NBR.get(case.name)
+    whole = N.Problem([case], max_nbr=mx)
+    st = whole.state_from_cases()
+    whole.step(st, 1)
+    torch.cuda.synchronize()
+    whole.check()
+    sep = N.Problem([case], max_nbr=mx)
+    st0 = sep.state_from_cases()
+    sep.build_cells(st0)
+    sep.density()
+    nxt = sep.new_state()
+    sep.forces(next_=nxt)
+    torch.cuda.synchronize()
+    sep.check()
+    n = case.n
+    for a, b in [(whole.fields.rho, sep.fields.rho), (whole.fields.p, sep.fields.p), (whole.fields.s, sep.fields.s),
+                 (whole.fields.inv_rho, sep.fields.inv_rho)] + list(zip(whole.fields.acc, sep.fields.acc)):
+        np.testing.assert_array_equal(f32(a)[:n].view(np.uint32), f32(b)[:n].view(np.uint32))
+    np.testing.assert_array_equal(u32(st.cell)[:n], u32(nxt.cell)[:n])
+    np.testing.assert_array_equal(u32(st.id)[:n], u32(nxt.id)[:n])
+    for a, b in zip(st.off + st.vel, nxt.off + nxt.vel):
+        np.testing.assert_array_equal(f32(a)[:n].view(np.uint32), f32(b)[:n].view(np.uint32))
+
+
 def test_steps_are_deterministic():
     N = nauticle()
     case = CASES["periodic_3d_ragged"]
