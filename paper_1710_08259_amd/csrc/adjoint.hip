@@ -12,6 +12,7 @@
 // in FP64 in a fixed order (block tree, then items in order), so results are
 // bitwise reproducible.
 #include "internal.h"
+#include "pairs.h"
 
 namespace nau {
 
@@ -35,13 +36,13 @@ __device__ inline void block_reduce2(double a, double b, double* sh_a, double* s
 }
 
 // r_j - r_i as the neighbour predicate forms it (the particle moved into the
-// neighbour's cell frame, see sph.hip).
-__device__ inline float3 adj_d(const CaseDev& C, uint32_t e, const float4& oj, const float4& oi)
+// neighbour's cell frame, see sph.hip), from the entry's 6-bit offset code.
+__device__ inline float3 adj_d(const CaseDev& C, uint32_t code, const float4& oj, const float4& oi)
 {
 #pragma clang fp contract(off)
-    const float sx = static_cast<float>(static_cast<int32_t>((e >> NAUTICLE_NBR_INDEX_BITS) & 3u) - 1) * C.cs[0];
-    const float sy = static_cast<float>(static_cast<int32_t>((e >> (NAUTICLE_NBR_INDEX_BITS + 2)) & 3u) - 1) * C.cs[1];
-    const float sz = static_cast<float>(static_cast<int32_t>((e >> (NAUTICLE_NBR_INDEX_BITS + 4)) & 3u) - 1) * C.cs[2];
+    const float sx = static_cast<float>(static_cast<int32_t>(code & 3u) - 1) * C.cs[0];
+    const float sy = static_cast<float>(static_cast<int32_t>((code >> 2) & 3u) - 1) * C.cs[1];
+    const float sz = static_cast<float>(static_cast<int32_t>((code >> 4) & 3u) - 1) * C.cs[2];
     return make_float3(oj.x - (oi.x - sx), oj.y - (oi.y - sy), oj.z - (oi.z - sz));
 }
 
@@ -52,11 +53,8 @@ __device__ inline float adj_r2(const float3& d, int dim)
     return r2;
 }
 
-__device__ inline uint32_t adj_index(uint32_t e, uint32_t n_total)
-{
-    const uint32_t j = e & kIndexMask;
-    return j < n_total ? j : n_total - 1;  // never out of range for lists built by the search
-}
+// Pairs per pipeline stage: three float4 records per neighbour.
+constexpr uint32_t kAdjGroup = 4;
 
 }  // namespace
 
@@ -112,29 +110,37 @@ k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
             if (cnt > max_nbr) cnt = max_nbr;
             float sbar = 0.0f, kbar = 0.0f, nubar = 0.0f;
             float vvx = 0.0f, vvy = 0.0f, vvz = 0.0f;
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const uint32_t e = list_entry(nbr, k, i, n_total);
-                const uint32_t j = adj_index(e, n_total);
-                const float4 aj = a4[j], bj = b4[j], Aj = adj4[j];
-                const float3 d = adj_d(C, e, aj, ai);
-                const float q = sqrtf(adj_r2(d, dim)) * C.inv_h;
-                const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
-                const float F = C.F_coef * (t * t * t);
-                const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
-                const float dvx = bi.x - bj.x, dvy = bi.y - bj.y, dvz = bi.z - bj.z;
-                const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
-                const float dvdA = fmaf(dvz, dAz, fmaf(dvy, dAy, dvx * dAx));
-                const float Aidv = fmaf(Ai.z, dvz, fmaf(Ai.y, dvy, Ai.x * dvx));
-                // r_ij = -d: sbar_i = -m sum F r_ij.dA = m sum F d.dA
-                sbar = fmaf(m * F, ddA, sbar);
-                kbar = fmaf(mnu * F, dvdA, kbar);
-                const float w = m * (bi.w + bj.w) * F;
-                const float wn = C.nu * w;
-                vvx = fmaf(wn, dAx, vvx);
-                vvy = fmaf(wn, dAy, vvy);
-                vvz = fmaf(wn, dAz, vvz);
-                nubar = fmaf(w, Aidv, nubar);
-            }
+            walk_pairs<kAdjGroup, 3>(
+                nbr, i, cnt, n_total,
+                [&](uint32_t j, float4* v) {
+                    v[0] = a4[j];
+                    v[1] = b4[j];
+                    v[2] = adj4[j];
+                },
+                [&](uint32_t k, const float4* v, uint32_t code) {
+                    const float4& aj = v[0];
+                    const float4& bj = v[1];
+                    const float4& Aj = v[2];
+                    const float3 d = adj_d(C, code, aj, ai);
+                    const float q = sqrtf(adj_r2(d, dim)) * C.inv_h;
+                    const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
+                    // pairs past the end of the list contribute nothing
+                    const float F = (k < cnt ? C.F_coef : 0.0f) * (t * t * t);
+                    const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
+                    const float dvx = bi.x - bj.x, dvy = bi.y - bj.y, dvz = bi.z - bj.z;
+                    const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
+                    const float dvdA = fmaf(dvz, dAz, fmaf(dvy, dAy, dvx * dAx));
+                    const float Aidv = fmaf(Ai.z, dvz, fmaf(Ai.y, dvy, Ai.x * dvx));
+                    // r_ij = -d: sbar_i = -m sum F r_ij.dA = m sum F d.dA
+                    sbar = fmaf(m * F, ddA, sbar);
+                    kbar = fmaf(mnu * F, dvdA, kbar);
+                    const float w = m * (bi.w + bj.w) * F;
+                    const float wn = C.nu * w;
+                    vvx = fmaf(wn, dAx, vvx);
+                    vvy = fmaf(wn, dAy, vvy);
+                    vvz = fmaf(wn, dAz, vvz);
+                    nubar = fmaf(w, Aidv, nubar);
+                });
             const float p = f.p[i];
             const float inv_rho2 = bi.w * bi.w;
             const float inv_rho3 = inv_rho2 * bi.w;
@@ -184,32 +190,41 @@ __device__ inline void adj_b_particle(const CaseDev& C, uint32_t i, StateDev st,
     uint32_t cnt = nbr_count[i];
     if (cnt > max_nbr) cnt = max_nbr;
     float accx = 0.0f, accy = 0.0f, accz = 0.0f;
-    for (uint32_t k = 0; k < cnt; ++k) {
-        const uint32_t e = list_entry(nbr, k, i, n_total);
-        const uint32_t j = adj_index(e, n_total);
-        const float4 aj = a4[j], bj = b4[j], Aj = adj4b[j];
-        const float3 d = adj_d(C, e, aj, ai);
-        const float r = sqrtf(adj_r2(d, dim));
-        const float q = r * C.inv_h;
-        const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
-        const float F = C.F_coef * (t * t * t);
-        const float Fp_r = r > 0.0f ? C.dF_coef * (t * t) / r : 0.0f;
-        const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
-        const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
-        const float dvdA = fmaf(bi.z - bj.z, dAz, fmaf(bi.y - bj.y, dAy, (bi.x - bj.x) * dAx));
-        // with r_ij = -d:
-        //   density geometry  m F r_ij (rhobar_i + rhobar_j)             = -m F (rb) d
-        //   pressure Hessian -m (s_i+s_j) [F dA + (F'/r) r_ij (r_ij.dA)] = -m (s) [F dA + (F'/r) d (d.dA)]
-        //   viscous geometry  m nu (k_i+k_j) (F'/r) r_ij (dv.dA)          = -m nu (k) (F'/r) d (dv.dA)
-        const float rb = Ai.w + Aj.w;
-        const float cs_ = m * (ai.w + aj.w);
-        const float ck = mnu * (bi.w + bj.w);
-        const float coef_d = -m * F * rb - cs_ * Fp_r * ddA - ck * Fp_r * dvdA;
-        const float coef_a = -cs_ * F;
-        accx = fmaf(coef_d, d.x, fmaf(coef_a, dAx, accx));
-        accy = fmaf(coef_d, d.y, fmaf(coef_a, dAy, accy));
-        accz = fmaf(coef_d, d.z, fmaf(coef_a, dAz, accz));
-    }
+    walk_pairs<kAdjGroup, 3>(
+        nbr, i, cnt, n_total,
+        [&](uint32_t j, float4* v) {
+            v[0] = a4[j];
+            v[1] = b4[j];
+            v[2] = adj4b[j];
+        },
+        [&](uint32_t k, const float4* v, uint32_t code) {
+            const float4& aj = v[0];
+            const float4& bj = v[1];
+            const float4& Aj = v[2];
+            const float3 d = adj_d(C, code, aj, ai);
+            const float r = sqrtf(adj_r2(d, dim));
+            const float q = r * C.inv_h;
+            const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
+            // pairs past the end of the list contribute nothing
+            const float live = k < cnt ? 1.0f : 0.0f;
+            const float F = (live * C.F_coef) * (t * t * t);
+            const float Fp_r = r > 0.0f ? (live * C.dF_coef) * (t * t) / r : 0.0f;
+            const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
+            const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
+            const float dvdA = fmaf(bi.z - bj.z, dAz, fmaf(bi.y - bj.y, dAy, (bi.x - bj.x) * dAx));
+            // with r_ij = -d:
+            //   density geometry  m F r_ij (rhobar_i + rhobar_j)             = -m F (rb) d
+            //   pressure Hessian -m (s_i+s_j) [F dA + (F'/r) r_ij (r_ij.dA)] = -m (s) [F dA + (F'/r) d (d.dA)]
+            //   viscous geometry  m nu (k_i+k_j) (F'/r) r_ij (dv.dA)          = -m nu (k) (F'/r) d (dv.dA)
+            const float rb = Ai.w + Aj.w;
+            const float cs_ = m * (ai.w + aj.w);
+            const float ck = mnu * (bi.w + bj.w);
+            const float coef_d = -m * F * rb - cs_ * Fp_r * ddA - ck * Fp_r * dvdA;
+            const float coef_a = -cs_ * F;
+            accx = fmaf(coef_d, d.x, fmaf(coef_a, dAx, accx));
+            accy = fmaf(coef_d, d.y, fmaf(coef_a, dAy, accy));
+            accz = fmaf(coef_d, d.z, fmaf(coef_a, dAz, accz));
+        });
     const float* lxn[3] = {lxn0, lxn1, lxn2};
     const float acc[3] = {accx, accy, accz};
     for (int c = 0; c < 3; ++c)

@@ -23,12 +23,6 @@ __device__ inline const uint4* nbr_chunk(const uint32_t* nbr, uint32_t c, uint32
     return reinterpret_cast<const uint4*>(nbr) + (static_cast<size_t>(c) * n_total + p);
 }
 
-// Entry k of sorted particle p's neighbour list.
-__device__ inline uint32_t list_entry(const uint32_t* nbr, uint32_t k, uint32_t p, uint32_t n_total)
-{
-    return nbr[(static_cast<size_t>(k / kChunk) * n_total + p) * kChunk + k % kChunk];
-}
-
 // Device error word bits (OR-ed by kernels, read by nauticle_check).
 constexpr uint32_t kErrNonFinite = 1u;
 constexpr uint32_t kErrOverflow = 2u;
