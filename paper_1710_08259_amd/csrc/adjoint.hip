@@ -110,19 +110,21 @@ k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
             if (cnt > max_nbr) cnt = max_nbr;
             float sbar = 0.0f, kbar = 0.0f, nubar = 0.0f;
             float vvx = 0.0f, vvy = 0.0f, vvz = 0.0f;
+            const __amdgpu_buffer_rsrc_t ra = float4_rsrc(a4, n_total), rb = float4_rsrc(b4, n_total),
+                                         rA = float4_rsrc(adj4, n_total);
             walk_pairs<kAdjGroup, 3>(
                 nbr, i, cnt, n_total,
-                [&](uint32_t j, float4* v) {
-                    v[0] = a4[j];
-                    v[1] = b4[j];
-                    v[2] = adj4[j];
+                [&](uint32_t e, float4* v) {
+                    v[0] = gather4(ra, e);
+                    v[1] = gather4(rb, e);
+                    v[2] = gather4(rA, e);
                 },
                 [&](uint32_t k, const float4* v, uint32_t code) {
                     const float4& aj = v[0];
                     const float4& bj = v[1];
                     const float4& Aj = v[2];
                     const float3 d = adj_d(C, code, aj, ai);
-                    const float q = sqrtf(adj_r2(d, dim)) * C.inv_h;
+                    const float q = pair_sqrt(adj_r2(d, dim)) * C.inv_h;
                     const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
                     // pairs past the end of the list contribute nothing
                     const float F = (k < cnt ? C.F_coef : 0.0f) * (t * t * t);
@@ -190,25 +192,28 @@ __device__ inline void adj_b_particle(const CaseDev& C, uint32_t i, StateDev st,
     uint32_t cnt = nbr_count[i];
     if (cnt > max_nbr) cnt = max_nbr;
     float accx = 0.0f, accy = 0.0f, accz = 0.0f;
+    const __amdgpu_buffer_rsrc_t ra = float4_rsrc(a4, n_total), rb = float4_rsrc(b4, n_total),
+                                 rA = float4_rsrc(adj4b, n_total);
     walk_pairs<kAdjGroup, 3>(
         nbr, i, cnt, n_total,
-        [&](uint32_t j, float4* v) {
-            v[0] = a4[j];
-            v[1] = b4[j];
-            v[2] = adj4b[j];
+        [&](uint32_t e, float4* v) {
+            v[0] = gather4(ra, e);
+            v[1] = gather4(rb, e);
+            v[2] = gather4(rA, e);
         },
         [&](uint32_t k, const float4* v, uint32_t code) {
             const float4& aj = v[0];
             const float4& bj = v[1];
             const float4& Aj = v[2];
             const float3 d = adj_d(C, code, aj, ai);
-            const float r = sqrtf(adj_r2(d, dim));
+            const float r = pair_sqrt(adj_r2(d, dim));
             const float q = r * C.inv_h;
             const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
             // pairs past the end of the list contribute nothing
             const float live = k < cnt ? 1.0f : 0.0f;
             const float F = (live * C.F_coef) * (t * t * t);
-            const float Fp_r = r > 0.0f ? (live * C.dF_coef) * (t * t) / r : 0.0f;
+            // F'/r with the hardware reciprocal (1 ulp)
+            const float Fp_r = r > 0.0f ? (live * C.dF_coef) * (t * t) * __builtin_amdgcn_rcpf(r) : 0.0f;
             const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
             const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
             const float dvdA = fmaf(bi.z - bj.z, dAz, fmaf(bi.y - bj.y, dAy, (bi.x - bj.x) * dAx));

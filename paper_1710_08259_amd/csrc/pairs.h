@@ -6,10 +6,59 @@
 
 namespace nau {
 
+// The cell shift of a list entry, delta * cell_size, looked up by the entry's
+// 6-bit offset code (bits 26..31) in a per-block LDS table.
+struct ShiftTable {
+    float4 v[64];
+};
+
+// Every thread of the block must call it (contains a barrier; the caller's
+// queue loop separates successive fills by barriers).
+__device__ inline void fill_shift_table(const CaseDev& C, ShiftTable* tab)
+{
+    for (uint32_t code = threadIdx.x; code < 64; code += blockDim.x) {
+        const float sx = static_cast<float>(static_cast<int32_t>(code & 3u) - 1) * C.cs[0];
+        const float sy = static_cast<float>(static_cast<int32_t>((code >> 2) & 3u) - 1) * C.cs[1];
+        const float sz = static_cast<float>(static_cast<int32_t>((code >> 4) & 3u) - 1) * C.cs[2];
+        tab->v[code] = make_float4(sx, sy, sz, 0.0f);
+    }
+    __syncthreads();
+}
+
+// r_j - r_i as the neighbour predicate forms it: the particle is moved into
+// the neighbour's cell frame, d_k = fl32(off_j,k - fl32(off_i,k - shift_k)).
+__device__ inline float3 pair_d(const float4& sh, float ojx, float ojy, float ojz, float oix, float oiy, float oiz)
+{
+#pragma clang fp contract(off)
+    return make_float3(ojx - (oix - sh.x), ojy - (oiy - sh.y), ojz - (oiz - sh.z));
+}
+
+__device__ inline float pair_r2(const float3& d, int dim)
+{
+    float r2 = __builtin_fmaf(d.y, d.y, d.x * d.x);
+    if (dim == 3) r2 = __builtin_fmaf(d.z, d.z, r2);
+    return r2;
+}
+
 __device__ inline uint32_t entry_index(uint32_t e, uint32_t n_total)
 {
     const uint32_t j = e & kIndexMask;
     return j < n_total ? j : n_total - 1;  // never out of range for lists built by the search
+}
+
+// Neighbour records are gathered with bounds-checked buffer loads: the byte
+// offset is the entry's index times 16 (one shift), the range check is the
+// buffer's own (a corrupt index reads zeros instead of faulting), so no
+// clamp or 64-bit address arithmetic is spent per pair.
+__device__ inline __amdgpu_buffer_rsrc_t float4_rsrc(const float4* p, uint32_t n)
+{
+    // word 3 0x00020000: raw dword access on CDNA
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(p), 0, static_cast<int32_t>(n * 16u), 0x00020000);
+}
+
+__device__ inline float4 gather4(__amdgpu_buffer_rsrc_t r, uint32_t e)
+{
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (e & kIndexMask) << 4, 0, 0));
 }
 
 // Entries k .. k + G - 1 of particle i's list (k a multiple of G, G a
@@ -47,9 +96,9 @@ __device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i
 // it: waiting for the entries then never waits for gathers still in flight,
 // and a group is summed while the next group's gathers are outstanding.
 // The scheduling barriers keep the compiler from moving the sums across the
-// loads they are meant to overlap.  `gather(j, v)` fills the NA float4s of
-// neighbour j; `body(k, v, code)` adds pair k (k >= cnt must be masked by
-// the body) with the 6-bit cell-shift code of its entry.
+// loads they are meant to overlap.  `gather(e, v)` fills the NA float4s of
+// the neighbour of list entry e; `body(k, v, code)` adds pair k (k >= cnt
+// must be masked by the body) with the 6-bit cell-offset code of its entry.
 template <uint32_t G, uint32_t NA>
 struct PairStage {
     float4 v[G][NA];
@@ -57,11 +106,11 @@ struct PairStage {
 };
 
 template <uint32_t G, uint32_t NA, typename Gather>
-__device__ inline void gather_stage(const uint32_t* e, uint32_t n_total, Gather&& gather, PairStage<G, NA>& S)
+__device__ inline void gather_stage(const uint32_t* e, Gather&& gather, PairStage<G, NA>& S)
 {
 #pragma unroll
     for (uint32_t u = 0; u < G; ++u) {
-        gather(entry_index(e[u], n_total), S.v[u]);
+        gather(e[u], S.v[u]);
         S.code[u] = e[u] >> NAUTICLE_NBR_INDEX_BITS;
     }
 }
@@ -76,22 +125,88 @@ __device__ inline void walk_pairs(const uint32_t* __restrict__ nbr, uint32_t i, 
     __builtin_amdgcn_sched_barrier(0);
     load_entries<G>(nbr, i, G, cnt, n_total, ey);
     __builtin_amdgcn_sched_barrier(0);
-    gather_stage<G, NA>(ex, n_total, gather, A);
+    gather_stage<G, NA>(ex, gather, A);
     __builtin_amdgcn_sched_barrier(0);
     for (uint32_t k = 0; k < cnt; k += 2 * G) {
         load_entries<G>(nbr, i, k + 2 * G, cnt, n_total, ex);
-        gather_stage<G, NA>(ey, n_total, gather, B);
+        gather_stage<G, NA>(ey, gather, B);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (uint32_t u = 0; u < G; ++u) body(k + u, A.v[u], A.code[u]);
         __builtin_amdgcn_sched_barrier(0);
         load_entries<G>(nbr, i, k + 3 * G, cnt, n_total, ey);
-        gather_stage<G, NA>(ex, n_total, gather, A);
+        gather_stage<G, NA>(ex, gather, A);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (uint32_t u = 0; u < G; ++u) body(k + G + u, B.v[u], B.code[u]);
         __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+
+// ---- density summation ---------------------------------------------------------
+// rho_i = m alpha (1 + sum_j (1 - q/2)^4 (2q + 1)),  q = r_ij / h, summed in
+// list order.
+constexpr uint32_t kDensityGroup = 8;
+
+// Square root for the pair loops: the hardware instruction (1 ulp).  The
+// correctly rounded sqrtf costs a dozen more instructions per pair, and the
+// pair sums are held to 1e-5 of their scale, where 1 ulp (6e-8) is invisible.
+__device__ inline float pair_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Kernel term of one pair at squared distance r2 (0.5 q is exact, so
+// 1 - 0.5 q rounds once however it is evaluated).
+__device__ inline float density_term(float r2, float inv_h)
+{
+#pragma clang fp contract(off)
+    const float q = pair_sqrt(r2) * inv_h;
+    const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
+    const float t2 = t * t;
+    return t2 * t2 * __builtin_fmaf(2.0f, q, 1.0f);
+}
+
+// Sum of the kernel terms of sorted particle i (offsets `me`) over its first
+// cnt list entries; gather(e, v) puts the neighbour's offsets in v[0].
+// (G pairs per pipeline stage: the order of the sum does not depend on it.)
+template <int DIM, uint32_t G = kDensityGroup, typename Gather>
+__device__ inline float density_sum(const CaseDev& C, const ShiftTable& tab, uint32_t i, const float4& me,
+                                    const uint32_t* __restrict__ nbr, uint32_t cnt, uint32_t n_total, Gather&& gather)
+{
+    const float inv_h = C.inv_h;
+    float sum = 0.0f;
+    walk_pairs<G, 1>(nbr, i, cnt, n_total, gather, [&](uint32_t k, const float4* v, uint32_t code) {
+        const float3 d = pair_d(tab.v[code], v[0].x, v[0].y, v[0].z, me.x, me.y, me.z);
+        // a pair past the end of the list contributes nothing (a factor, not
+        // a branch: the loop body stays one basic block)
+        sum = __fadd_rn(sum, density_term(pair_r2(d, DIM), inv_h) * (k < cnt ? 1.0f : 0.0f));
+    });
+    return sum;
+}
+
+// rho, the Tait pressure p = B ((rho / rho0)^gamma - 1) evaluated as
+// B expm1(gamma log1p(delta)) with delta = (rho - rho0) / rho0 (no
+// cancellation near rho0), s = p / rho^2 and 1 / rho of sorted particle i;
+// also packs (offsets, s) and (velocity, or 0 for fixed particles, 1 / rho)
+// for the force pass.
+__device__ inline void density_finish(const CaseDev& C, uint32_t i, float sum, const float4& me, StateDev st,
+                                      FieldsDev f, float4* __restrict__ a4, float4* __restrict__ b4, uint32_t* err)
+{
+    const float rho = C.m_alpha * (1.0f + sum);
+    const float delta = (rho - C.rho0) * C.inv_rho0;
+    const float p = C.B * expm1f(C.gamma * log1pf(delta));
+    const float inv_rho = 1.0f / rho;
+    const float s = p * inv_rho * inv_rho;
+    f.rho[i] = rho;
+    f.p[i] = p;
+    f.inv_rho[i] = inv_rho;
+    f.s[i] = s;
+    const bool fixed = st.id[i] >= C.n_fluid;
+    float v[3] = {0.0f, 0.0f, 0.0f};
+    for (int c = 0; c < 3; ++c)
+        if (c < C.dim && !fixed) v[c] = st.vel[c][i];
+    a4[i] = make_float4(me.x, me.y, me.z, s);
+    b4[i] = make_float4(v[0], v[1], v[2], inv_rho);
+    if (!isfinite(rho) || !isfinite(p)) set_error(err, kErrNonFinite);
 }
 
 }  // namespace nau

@@ -12,45 +12,10 @@
 
 namespace nau {
 
-// The cell shift of a list entry, delta * cell_size, looked up by the entry's
-// 6-bit offset code (bits 26..31) in a per-block LDS table.
-struct ShiftTable {
-    float4 v[64];
-};
-
-// Every thread of the block must call it (contains a barrier; the caller's
-// queue loop separates successive fills by barriers).
-__device__ inline void fill_shift_table(const CaseDev& C, ShiftTable* tab)
-{
-    for (uint32_t code = threadIdx.x; code < 64; code += blockDim.x) {
-        const float sx = static_cast<float>(static_cast<int32_t>(code & 3u) - 1) * C.cs[0];
-        const float sy = static_cast<float>(static_cast<int32_t>((code >> 2) & 3u) - 1) * C.cs[1];
-        const float sz = static_cast<float>(static_cast<int32_t>((code >> 4) & 3u) - 1) * C.cs[2];
-        tab->v[code] = make_float4(sx, sy, sz, 0.0f);
-    }
-    __syncthreads();
-}
-
-// r_j - r_i as the neighbour predicate forms it: the particle is moved into
-// the neighbour's cell frame, d_k = fl32(off_j,k - fl32(off_i,k - shift_k)).
-__device__ inline float3 pair_d(const float4& sh, float ojx, float ojy, float ojz, float oix, float oiy, float oiz)
-{
-#pragma clang fp contract(off)
-    return make_float3(ojx - (oix - sh.x), ojy - (oiy - sh.y), ojz - (oiz - sh.z));
-}
-
-__device__ inline float pair_r2(const float3& d, int dim)
-{
-    float r2 = __builtin_fmaf(d.y, d.y, d.x * d.x);
-    if (dim == 3) r2 = __builtin_fmaf(d.z, d.z, r2);
-    return r2;
-}
-
-constexpr uint32_t kDensityGroup = 8;
 constexpr uint32_t kForceGroup = 8;
 
 // ----------------------------------------------------------------------------
-// density + equation of state
+// density + equation of state (arithmetic in pairs.h)
 // ----------------------------------------------------------------------------
 // rho_i = m alpha + sum_j m alpha (1 - q/2)^4 (2q + 1),  q = r_ij / h
 // p_i   = B ((rho_i / rho0)^gamma - 1), evaluated as B expm1(gamma log1p(delta))
@@ -63,40 +28,14 @@ __device__ inline void density_particle(const CaseDev& C, const ShiftTable& tab,
                                         const uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total,
                                         FieldsDev f, float4* __restrict__ a4, float4* __restrict__ b4, uint32_t* err)
 {
-    const int dim = C.dim;
     const float4 me = pos4[i];
     uint32_t cnt = nbr_count[i];
     if (cnt > max_nbr) cnt = max_nbr;
-    const float inv_h = C.inv_h;
-    float sum = 0.0f;
-    walk_pairs<kDensityGroup, 1>(
-        nbr, i, cnt, n_total, [&](uint32_t j, float4* v) { v[0] = pos4[j]; },
-        [&](uint32_t k, const float4* v, uint32_t code) {
-            const float3 d = pair_d(tab.v[code], v[0].x, v[0].y, v[0].z, me.x, me.y, me.z);
-            const float q = sqrtf(pair_r2(d, dim)) * inv_h;
-            const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
-            const float t2 = t * t;
-            const float w = t2 * t2 * fmaf(2.0f, q, 1.0f);
-            // a pair past the end of the list contributes nothing (a factor,
-            // not a branch: the loop body stays one basic block)
-            sum = fmaf(k < cnt ? 1.0f : 0.0f, w, sum);
-        });
-    const float rho = C.m_alpha * (1.0f + sum);
-    const float delta = (rho - C.rho0) * C.inv_rho0;
-    const float p = C.B * expm1f(C.gamma * log1pf(delta));
-    const float inv_rho = 1.0f / rho;
-    const float s = p * inv_rho * inv_rho;
-    f.rho[i] = rho;
-    f.p[i] = p;
-    f.inv_rho[i] = inv_rho;
-    f.s[i] = s;
-    const bool fixed = st.id[i] >= C.n_fluid;
-    float v[3] = {0.0f, 0.0f, 0.0f};
-    for (int c = 0; c < 3; ++c)
-        if (c < dim && !fixed) v[c] = st.vel[c][i];
-    a4[i] = make_float4(me.x, me.y, me.z, s);
-    b4[i] = make_float4(v[0], v[1], v[2], inv_rho);
-    if (!isfinite(rho) || !isfinite(p)) set_error(err, kErrNonFinite);
+    const __amdgpu_buffer_rsrc_t rpos = float4_rsrc(pos4, n_total);
+    auto gather = [&](uint32_t e, float4* v) { v[0] = gather4(rpos, e); };
+    const float sum = C.dim == 3 ? density_sum<3>(C, tab, i, me, nbr, cnt, n_total, gather)
+                                 : density_sum<2>(C, tab, i, me, nbr, cnt, n_total, gather);
+    density_finish(C, i, sum, me, st, f, a4, b4, err);
 }
 
 __global__ void __launch_bounds__(kMaxBlock)
@@ -185,17 +124,18 @@ __device__ inline void forces_particle(const CaseDev& C, const ShiftTable& tab, 
     uint32_t cnt = nbr_count[i];
     if (cnt > max_nbr) cnt = max_nbr;
     float ax = 0.0f, ay = 0.0f, az = 0.0f;
+    const __amdgpu_buffer_rsrc_t ra = float4_rsrc(a4, n_total), rb = float4_rsrc(b4, n_total);
     walk_pairs<kForceGroup, 2>(
         nbr, i, cnt, n_total,
-        [&](uint32_t j, float4* v) {
-            v[0] = a4[j];
-            v[1] = b4[j];
+        [&](uint32_t e, float4* v) {
+            v[0] = gather4(ra, e);
+            v[1] = gather4(rb, e);
         },
         [&](uint32_t k, const float4* v, uint32_t code) {
             const float4& aj = v[0];
             const float4& bj = v[1];
             const float3 d = pair_d(tab.v[code], aj.x, aj.y, aj.z, ai4.x, ai4.y, ai4.z);
-            const float q = sqrtf(pair_r2(d, dim)) * inv_h;
+            const float q = pair_sqrt(pair_r2(d, dim)) * inv_h;
             const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
             // a pair past the end of the list contributes nothing (a factor,
             // not a branch: the loop body stays one basic block)
