@@ -471,6 +471,7 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
     const float csx = C.cs[0];
     uint4* col = reinterpret_cast<uint4*>(nbr) + p;  // chunk c at col[c * n_total]
     const uint32_t max_chunks = max_nbr / kChunk;
+    uint4* dst = col;  // where the next full chunk goes (advanced by n_total chunks)
     uint4 buf = make_uint4(0u, 0u, 0u, 0u);  // the last four entries, newest in w
     uint32_t cnt = 0;
     constexpr int kZ = DIM == 3 ? 1 : 0;
@@ -529,18 +530,26 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
                     // drop candidates past the piece and the particle itself
                     if (m < 64) hits &= (uint64_t{1} << m) - 1u;
                     if (p - q0 < 64u) hits &= ~(uint64_t{1} << (p - q0));
+                    // entry of candidate q0 + b: the index plus the piece's first-cell
+                    // code (the fields do not overlap), plus one x step per cell
+                    // boundary at or before it
+                    const uint32_t e0 =
+                        q0 + (code_yz | (static_cast<uint32_t>(dx0 + 1) << NAUTICLE_NBR_INDEX_BITS));
+                    const uint32_t r1 = b1 - q0, r2 = b2 - q0;  // boundaries relative to q0 (wrap if before)
                     while (hits) {
                         const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(hits));
                         hits &= hits - 1;
-                        const uint32_t q = q0 + b;
-                        const int32_t dx = dx0 + static_cast<int32_t>(q >= b1) + static_cast<int32_t>(q >= b2);
+                        const uint32_t step = (static_cast<int32_t>(b) >= static_cast<int32_t>(r1) ? 1u : 0u) +
+                                              (static_cast<int32_t>(b) >= static_cast<int32_t>(r2) ? 1u : 0u);
                         buf.x = buf.y;
                         buf.y = buf.z;
                         buf.z = buf.w;
-                        buf.w = q | code_yz | (static_cast<uint32_t>(dx + 1) << NAUTICLE_NBR_INDEX_BITS);
+                        buf.w = e0 + b + (step << NAUTICLE_NBR_INDEX_BITS);
                         ++cnt;
-                        const uint32_t chunk = (cnt >> 2) - 1u;
-                        if ((cnt & 3u) == 0u && chunk < max_chunks) col[static_cast<size_t>(chunk) * n_total] = buf;
+                        if ((cnt & 3u) == 0u && cnt <= max_nbr) {
+                            *dst = buf;
+                            dst += n_total;
+                        }
                     }
                 }
             }
