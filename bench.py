@@ -38,8 +38,8 @@ PEAK_HBM_GBS = 8000.0
 # summarised in profiles/neighbour_kernels_periodic_3d_8388608_traffic.md
 # (scaled by a plain 1 GiB copy); valid only for the search source the
 # counters were taken on, reported as null otherwise.
-NLIST_TRAFFIC_BYTES = 6.020e9
-NLIST_TRAFFIC_SOURCE_SHA256 = "1d258b93426d23be"
+NLIST_TRAFFIC_BYTES = 3.385e9
+NLIST_TRAFFIC_SOURCE_SHA256 = "acb0c13d28071c2c"
 
 
 def nlist_traffic():

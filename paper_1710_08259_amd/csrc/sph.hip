@@ -1,12 +1,13 @@
 // Interaction sums of the WCSPH step on gfx950: density + Tait equation of
 // state, and accelerations with the fused semi-implicit Euler update.
 //
-// Both passes walk the neighbour lists built by the search (column-major, so
-// the 64 lanes of a wave read 64 consecutive words per list row).  Each
-// neighbour costs one float4 gather in the density pass (offsets) and two in
-// the force pass (offsets + s, velocity + 1/rho), from arrays in sorted order,
-// so the gathers of a wave stay within a few cells.  Every sum is a gather in
-// list order: no atomics, so results are bitwise reproducible.
+// Both passes walk the neighbour lists built by the search (16-byte chunks of
+// four entries, so the 64 lanes of a wave read 1 KB contiguous per chunk
+// row) with the pipelined walk of pairs.h.  Each neighbour costs one float4
+// gather in the density pass (offsets) and two in the force pass (offsets +
+// s, velocity + 1/rho), from arrays in sorted order, so the gathers of a wave
+// stay within a few cells.  Every sum is taken in list order: no atomics, so
+// results are bitwise reproducible.
 #include "internal.h"
 #include "pairs.h"
 
