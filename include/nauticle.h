@@ -141,7 +141,12 @@ typedef struct {
  *                 (so one 16-byte load gives four consecutive entries of a
  *                 particle and the lanes of a wave read adjacent chunks);
  *                 max_nbr is a multiple of 4 and nbr is 16-byte aligned;
- *                 entries past a particle's count are unspecified;
+ *                 the entries from a particle's count to the end of its
+ *                 last chunk hold a padding entry (the particle itself with
+ *                 cell offset -1 on every axis of the case, whose kernel
+ *                 terms are exactly zero) on which the density, force and
+ *                 adjoint passes rely; entries in later chunks are
+ *                 unspecified;
  *   nbr_count[p]  number of neighbours of p (the full count, even if it
  *                 exceeds max_nbr, in which case the error word is set). */
 typedef struct {

@@ -113,21 +113,20 @@ k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
             const __amdgpu_buffer_rsrc_t ra = float4_rsrc(a4, n_total), rb = float4_rsrc(b4, n_total),
                                          rA = float4_rsrc(adj4, n_total);
             walk_pairs<kAdjGroup, 3>(
-                nbr, i, cnt, n_total,
+                nbr, i, cnt, n_total, dim,
                 [&](uint32_t e, float4* v) {
                     v[0] = gather4(ra, e);
                     v[1] = gather4(rb, e);
                     v[2] = gather4(rA, e);
                 },
-                [&](uint32_t k, const float4* v, uint32_t code) {
+                [&](uint32_t, const float4* v, uint32_t code) {
                     const float4& aj = v[0];
                     const float4& bj = v[1];
                     const float4& Aj = v[2];
                     const float3 d = adj_d(C, code, aj, ai);
                     const float q = pair_sqrt(adj_r2(d, dim)) * C.inv_h;
                     const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
-                    // pairs past the end of the list contribute nothing
-                    const float F = (k < cnt ? C.F_coef : 0.0f) * (t * t * t);
+                    const float F = C.F_coef * (t * t * t);  // 0 for padding pairs (t = 0)
                     const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
                     const float dvx = bi.x - bj.x, dvy = bi.y - bj.y, dvz = bi.z - bj.z;
                     const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
@@ -195,13 +194,13 @@ __device__ inline void adj_b_particle(const CaseDev& C, uint32_t i, StateDev st,
     const __amdgpu_buffer_rsrc_t ra = float4_rsrc(a4, n_total), rb = float4_rsrc(b4, n_total),
                                  rA = float4_rsrc(adj4b, n_total);
     walk_pairs<kAdjGroup, 3>(
-        nbr, i, cnt, n_total,
+        nbr, i, cnt, n_total, dim,
         [&](uint32_t e, float4* v) {
             v[0] = gather4(ra, e);
             v[1] = gather4(rb, e);
             v[2] = gather4(rA, e);
         },
-        [&](uint32_t k, const float4* v, uint32_t code) {
+        [&](uint32_t, const float4* v, uint32_t code) {
             const float4& aj = v[0];
             const float4& bj = v[1];
             const float4& Aj = v[2];
@@ -209,11 +208,9 @@ __device__ inline void adj_b_particle(const CaseDev& C, uint32_t i, StateDev st,
             const float r = pair_sqrt(adj_r2(d, dim));
             const float q = r * C.inv_h;
             const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
-            // pairs past the end of the list contribute nothing
-            const float live = k < cnt ? 1.0f : 0.0f;
-            const float F = (live * C.F_coef) * (t * t * t);
-            // F'/r with the hardware reciprocal (1 ulp)
-            const float Fp_r = r > 0.0f ? (live * C.dF_coef) * (t * t) * __builtin_amdgcn_rcpf(r) : 0.0f;
+            // both 0 for padding pairs (t = 0); F'/r with the hardware reciprocal (1 ulp)
+            const float F = C.F_coef * (t * t * t);
+            const float Fp_r = r > 0.0f ? C.dF_coef * (t * t) * __builtin_amdgcn_rcpf(r) : 0.0f;
             const float dAx = Ai.x - Aj.x, dAy = Ai.y - Aj.y, dAz = Ai.z - Aj.z;
             const float ddA = fmaf(d.z, dAz, fmaf(d.y, dAy, d.x * dAx));
             const float dvdA = fmaf(bi.z - bj.z, dAz, fmaf(bi.y - bj.y, dAy, (bi.x - bj.x) * dAx));

@@ -17,6 +17,16 @@ constexpr uint32_t kPosPad = 64;   // float4s readable past the end of the packe
 constexpr uint32_t kIndexMask = (1u << NAUTICLE_NBR_INDEX_BITS) - 1u;
 constexpr int32_t kChunk = 4;      // list entries per 16-byte chunk
 
+// The entry that fills a particle's list from its count to the end of the
+// last chunk: the particle itself, one cell away along every axis of the
+// case (offset code (-1, -1, -1), or (-1, -1, 0) in 2-D).  Its distance is
+// at least sqrt(2) cell sizes > 2h, so every kernel term of such a pair is
+// exactly zero and the pair loops need no per-pair mask.
+__device__ inline uint32_t pad_entry(uint32_t p, int dim)
+{
+    return p | (dim == 3 ? 0u : (1u << (NAUTICLE_NBR_INDEX_BITS + 4)));
+}
+
 // Chunk c (entries 4c .. 4c + 3) of sorted particle p's neighbour list.
 __device__ inline const uint4* nbr_chunk(const uint32_t* nbr, uint32_t c, uint32_t p, uint32_t n_total)
 {

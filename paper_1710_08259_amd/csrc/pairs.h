@@ -64,17 +64,17 @@ __device__ inline float4 gather4(__amdgpu_buffer_rsrc_t r, uint32_t e)
 // Entries k .. k + G - 1 of particle i's list (k a multiple of G, G a
 // multiple of the four-entry chunk): one 16-byte load per chunk, and the 64
 // lanes of a wave read 64 adjacent chunks.  Chunks at or past the particle's
-// count are not read (their entries are 0: particle 0 with no shift, one
-// address for every such lane); the caller masks those pairs.
+// count are not read: they are all padding (pad_entry), so such lanes gather
+// their own record again.
 template <uint32_t G>
 __device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t k, uint32_t cnt,
-                                    uint32_t n_total, uint32_t* e)
+                                    uint32_t n_total, uint32_t pad, uint32_t* e)
 {
     static_assert(G % kChunk == 0, "groups are whole chunks");
 #pragma unroll
     for (uint32_t c = 0; c < G / kChunk; ++c) {
         const uint32_t kc = k + c * kChunk;
-        const uint4 v = kc < cnt ? *nbr_chunk(nbr, kc / kChunk, i, n_total) : make_uint4(0u, 0u, 0u, 0u);
+        const uint4 v = kc < cnt ? *nbr_chunk(nbr, kc / kChunk, i, n_total) : make_uint4(pad, pad, pad, pad);
         e[c * kChunk + 0] = v.x;
         e[c * kChunk + 1] = v.y;
         e[c * kChunk + 2] = v.z;
@@ -97,8 +97,9 @@ __device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i
 // and a group is summed while the next group's gathers are outstanding.
 // The scheduling barriers keep the compiler from moving the sums across the
 // loads they are meant to overlap.  `gather(e, v)` fills the NA float4s of
-// the neighbour of list entry e; `body(k, v, code)` adds pair k (k >= cnt
-// must be masked by the body) with the 6-bit cell-offset code of its entry.
+// the neighbour of list entry e; `body(k, v, code)` adds pair k with the
+// 6-bit cell-offset code of its entry.  Pairs k >= cnt (up to the end of the
+// last group) are padding pairs, whose terms are exactly zero.
 template <uint32_t G, uint32_t NA>
 struct PairStage {
     float4 v[G][NA];
@@ -117,24 +118,25 @@ __device__ inline void gather_stage(const uint32_t* e, Gather&& gather, PairStag
 
 template <uint32_t G, uint32_t NA, typename Gather, typename Body>
 __device__ inline void walk_pairs(const uint32_t* __restrict__ nbr, uint32_t i, uint32_t cnt, uint32_t n_total,
-                                  Gather&& gather, Body&& body)
+                                  int dim, Gather&& gather, Body&& body)
 {
+    const uint32_t pad = pad_entry(i, dim);
     uint32_t ex[G], ey[G];
     PairStage<G, NA> A, B;
-    load_entries<G>(nbr, i, 0, cnt, n_total, ex);
+    load_entries<G>(nbr, i, 0, cnt, n_total, pad, ex);
     __builtin_amdgcn_sched_barrier(0);
-    load_entries<G>(nbr, i, G, cnt, n_total, ey);
+    load_entries<G>(nbr, i, G, cnt, n_total, pad, ey);
     __builtin_amdgcn_sched_barrier(0);
     gather_stage<G, NA>(ex, gather, A);
     __builtin_amdgcn_sched_barrier(0);
     for (uint32_t k = 0; k < cnt; k += 2 * G) {
-        load_entries<G>(nbr, i, k + 2 * G, cnt, n_total, ex);
+        load_entries<G>(nbr, i, k + 2 * G, cnt, n_total, pad, ex);
         gather_stage<G, NA>(ey, gather, B);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (uint32_t u = 0; u < G; ++u) body(k + u, A.v[u], A.code[u]);
         __builtin_amdgcn_sched_barrier(0);
-        load_entries<G>(nbr, i, k + 3 * G, cnt, n_total, ey);
+        load_entries<G>(nbr, i, k + 3 * G, cnt, n_total, pad, ey);
         gather_stage<G, NA>(ex, gather, A);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -174,11 +176,9 @@ __device__ inline float density_sum(const CaseDev& C, const ShiftTable& tab, uin
 {
     const float inv_h = C.inv_h;
     float sum = 0.0f;
-    walk_pairs<G, 1>(nbr, i, cnt, n_total, gather, [&](uint32_t k, const float4* v, uint32_t code) {
+    walk_pairs<G, 1>(nbr, i, cnt, n_total, DIM, gather, [&](uint32_t, const float4* v, uint32_t code) {
         const float3 d = pair_d(tab.v[code], v[0].x, v[0].y, v[0].z, me.x, me.y, me.z);
-        // a pair past the end of the list contributes nothing (a factor, not
-        // a branch: the loop body stays one basic block)
-        sum = __fadd_rn(sum, density_term(pair_r2(d, DIM), inv_h) * (k < cnt ? 1.0f : 0.0f));
+        sum = __fadd_rn(sum, density_term(pair_r2(d, DIM), inv_h));  // + 0 for padding pairs
     });
     return sum;
 }

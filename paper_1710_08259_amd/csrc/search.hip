@@ -555,11 +555,13 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
             }
         }
     }
-    // the last, partial chunk: its r entries are the newest r of the buffer
+    // the last, partial chunk: its r entries are the newest r of the buffer,
+    // the rest padding
     const uint32_t r = cnt & 3u;
     if (r != 0u && (cnt >> 2) < max_chunks) {
-        const uint4 out = r == 1u ? make_uint4(buf.w, 0u, 0u, 0u)
-                                  : (r == 2u ? make_uint4(buf.z, buf.w, 0u, 0u) : make_uint4(buf.y, buf.z, buf.w, 0u));
+        const uint32_t z = pad_entry(p, DIM);
+        const uint4 out = r == 1u ? make_uint4(buf.w, z, z, z)
+                                  : (r == 2u ? make_uint4(buf.z, buf.w, z, z) : make_uint4(buf.y, buf.z, buf.w, z));
         col[static_cast<size_t>(cnt >> 2) * n_total] = out;
     }
     nbr_count[p] = cnt;

@@ -127,20 +127,18 @@ __device__ inline void forces_particle(const CaseDev& C, const ShiftTable& tab, 
     float ax = 0.0f, ay = 0.0f, az = 0.0f;
     const __amdgpu_buffer_rsrc_t ra = float4_rsrc(a4, n_total), rb = float4_rsrc(b4, n_total);
     walk_pairs<kForceGroup, 2>(
-        nbr, i, cnt, n_total,
+        nbr, i, cnt, n_total, dim,
         [&](uint32_t e, float4* v) {
             v[0] = gather4(ra, e);
             v[1] = gather4(rb, e);
         },
-        [&](uint32_t k, const float4* v, uint32_t code) {
+        [&](uint32_t, const float4* v, uint32_t code) {
             const float4& aj = v[0];
             const float4& bj = v[1];
             const float3 d = pair_d(tab.v[code], aj.x, aj.y, aj.z, ai4.x, ai4.y, ai4.z);
             const float q = pair_sqrt(pair_r2(d, dim)) * inv_h;
             const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
-            // a pair past the end of the list contributes nothing (a factor,
-            // not a branch: the loop body stays one basic block)
-            const float F = (k < cnt ? C.F_coef : 0.0f) * (t * t * t);
+            const float F = C.F_coef * (t * t * t);  // 0 for padding pairs (t = 0)
             // pressure: -m (s_i + s_j) F r_ij = +m (s_i + s_j) F d
             const float cp = m * (ai4.w + aj.w) * F;
             // viscosity: m nu (k_i + k_j) F (v_i - v_j)
