@@ -38,17 +38,38 @@ PEAK_HBM_GBS = 8000.0
 # summarised in profiles/neighbour_kernels_periodic_3d_8388608_traffic.md
 # (scaled by a plain 1 GiB copy); valid only for the search source the
 # counters were taken on, reported as null otherwise.
-NLIST_TRAFFIC_BYTES = 3.385e9
-NLIST_TRAFFIC_SOURCE_SHA256 = "acb0c13d28071c2c"
+NLIST_TRAFFIC_BYTES = 3.367e9
+NLIST_TRAFFIC_SOURCE_SHA256 = "120523f890ad3cc6"
+
+
+# Issue-slot and vector-L1 figures from the counter runs summarised in
+# profiles/neighbour_kernels_periodic_3d_8388608_issue.md, guarded the same
+# way (by the sources of the kernels they were taken on).
+NLIST_VALU_ISSUE_FRAC = 0.874
+FORCE_L1_ACCESS_RATE = 1.00   # accesses per CU per clock; the vector L1 serves about one
+FORCE_SOURCES_SHA256 = "755bdf5d7744380a"
+
+
+def _digest(*rel):
+    import hashlib
+
+    h = hashlib.sha256()
+    for r in rel:
+        with open(os.path.join(ROOT, "paper_1710_08259_amd", "csrc", r), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def nlist_traffic():
-    import hashlib
+    return NLIST_TRAFFIC_BYTES if _digest("search.hip") == NLIST_TRAFFIC_SOURCE_SHA256 else None
 
-    src = os.path.join(ROOT, "paper_1710_08259_amd", "csrc", "search.hip")
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()[:16]
-    return NLIST_TRAFFIC_BYTES if digest == NLIST_TRAFFIC_SOURCE_SHA256 else None
+
+def nlist_issue_frac():
+    return NLIST_VALU_ISSUE_FRAC if _digest("search.hip") == NLIST_TRAFFIC_SOURCE_SHA256 else None
+
+
+def force_l1_rate():
+    return FORCE_L1_ACCESS_RATE if _digest("sph.hip", "pairs.h") == FORCE_SOURCES_SHA256 else None
 
 
 def parse():
@@ -276,6 +297,7 @@ def main():
                 "achieved": round(search_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(search_tflops / PEAK_FP32_TFLOPS, 4), "traffic": nlist_traffic(),
                 "peak_without_packed_fp32": PEAK_FP32_TFLOPS_UNPACKED,
+                "valu_issue_frac": nlist_issue_frac(),
                 "candidates_per_step": cand, "ms": round(phase_ms[1], 4)}
     line = {
         "metric": "particle-pair interactions/s (SPH force pass) + fwd+adjoint steps/s vs plain",
@@ -294,7 +316,8 @@ def main():
         "extra": {"roofline_force_pass": {
             "bound": "alu", "kernel": "k_forces<true> (force pass with fused integration)",
             "achieved": round(force_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(force_tflops / PEAK_FP32_TFLOPS, 4), "ms": round(phase_ms[3], 4)}},
+            "frac": round(force_tflops / PEAK_FP32_TFLOPS, 4), "ms": round(phase_ms[3], 4),
+            "l1_accesses_per_cu_clock": force_l1_rate()}},
     }
     del prob, st
     torch.cuda.empty_cache()
