@@ -136,6 +136,7 @@ __device__ inline void walk_pairs(const uint32_t* __restrict__ nbr, uint32_t i, 
 #pragma unroll
         for (uint32_t u = 0; u < G; ++u) body(k + u, A.v[u], A.code[u]);
         __builtin_amdgcn_sched_barrier(0);
+        if (k + G >= cnt) break;  // the second half would be padding only
         load_entries<G>(nbr, i, k + 3 * G, cnt, n_total, pad, ey);
         gather_stage<G, NA>(ex, gather, A);
         __builtin_amdgcn_sched_barrier(0);
