@@ -281,22 +281,30 @@ __device__ inline void halo_plan(const CaseDev& C, const Item& it, const uint32_
     __syncthreads();
 }
 
-// Copies the planned ranges of NA per-particle float4 arrays into `dst`, as
-// records of NA float4s (record of sorted index j at dst[(j + shift) NA]),
-// and waits for the whole block.  Every thread of the block calls it.
-template <int DIM, int NA>
-__device__ inline void halo_copy(const HaloRows& H, const float4* const (&src)[NA], float4* dst)
+// Copies the planned ranges of a per-particle float4 array into `dst`
+// (record of sorted index j at dst[j + shift]) and waits for the whole
+// block.  Every thread of the block calls it.  Each row is a contiguous run
+// in both places, so the copy goes straight from global memory to LDS
+// (gfx950 global_load_lds, 16 bytes per lane): the waves share out the
+// 64-record pieces of all rows, issue every load before waiting once, and
+// the data never passes through registers.
+template <int DIM>
+__device__ inline void halo_copy(const HaloRows& H, const float4* __restrict__ src, float4* dst)
 {
     constexpr uint32_t rows = DIM == 3 ? 9u : 3u;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+    uint32_t piece = 0;  // running index over the 64-record pieces of all rows (wave-uniform)
     for (uint32_t r = 0; r < rows; ++r) {
         const uint32_t lo = H.lo[r], len = H.hi[r] - H.lo[r];
-        float4* d = dst + (static_cast<int64_t>(lo) + H.shift[r]) * NA;
-        for (uint32_t t = threadIdx.x; t < len; t += blockDim.x) {
-#pragma unroll
-            for (int a = 0; a < NA; ++a) d[t * NA + a] = src[a][lo + t];
+        const uint32_t slot = lo + static_cast<uint32_t>(H.shift[r]);  // LDS record of sorted index lo
+        for (uint32_t o = 0; o < len; o += 64u, ++piece) {
+            if (piece % n_waves != wave) continue;
+            if (o + lane < len)
+                __builtin_amdgcn_global_load_lds(src + lo + o + lane, (__attribute__((address_space(3))) void*)(dst + slot + o),
+                                                 16, 0, 0);
         }
     }
-    __syncthreads();
+    __syncthreads();  // waits for the loads (vmcnt) before the barrier
 }
 
 inline uint32_t grid_for(const Plan& P)

@@ -581,8 +581,7 @@ k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
         const Item it = items[ix];
         const CaseDev& C = cases[it.case_id];
         halo_plan<DIM>(C, it, st.cell, cell_first, n_total, halo_cap, &s_rows);
-        const float4* const src[1] = {pos4};
-        halo_copy<DIM, 1>(s_rows, src, s_halo);
+        halo_copy<DIM>(s_rows, pos4, s_halo);
         if (threadIdx.x < it.count)
             nlist_particle<DIM>(C, it, st, pos4, s_rows, s_halo, cell_first, nbr, nbr_count, max_nbr, n_total, err);
         __syncthreads();  // the next item's staging overwrites the LDS
