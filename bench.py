@@ -38,16 +38,16 @@ PEAK_HBM_GBS = 8000.0
 # summarised in profiles/neighbour_kernels_periodic_3d_8388608_traffic.md
 # (scaled by a plain 1 GiB copy); valid only for the search source the
 # counters were taken on, reported as null otherwise.
-NLIST_TRAFFIC_BYTES = 3.367e9
-NLIST_TRAFFIC_SOURCE_SHA256 = "120523f890ad3cc6"
+NLIST_TRAFFIC_BYTES = 3.389e9
+NLIST_TRAFFIC_SOURCE_SHA256 = "4e5e2f0cd99971c0"
 
 
 # Issue-slot and vector-L1 figures from the counter runs summarised in
 # profiles/neighbour_kernels_periodic_3d_8388608_issue.md, guarded the same
 # way (by the sources of the kernels they were taken on).
-NLIST_VALU_ISSUE_FRAC = 0.874
-FORCE_L1_ACCESS_RATE = 1.00   # accesses per CU per clock; the vector L1 serves about one
-FORCE_SOURCES_SHA256 = "755bdf5d7744380a"
+NLIST_VALU_ISSUE_FRAC = 0.947
+FORCE_L1_ACCESS_RATE = 1.06   # accesses per CU per clock; the vector L1 serves about one
+FORCE_SOURCES_SHA256 = "e8befa2a4e43ad45"
 
 
 def _digest(*rel):
@@ -61,15 +61,15 @@ def _digest(*rel):
 
 
 def nlist_traffic():
-    return NLIST_TRAFFIC_BYTES if _digest("search.hip") == NLIST_TRAFFIC_SOURCE_SHA256 else None
+    return NLIST_TRAFFIC_BYTES if _digest("search.hip", "internal.h") == NLIST_TRAFFIC_SOURCE_SHA256 else None
 
 
 def nlist_issue_frac():
-    return NLIST_VALU_ISSUE_FRAC if _digest("search.hip") == NLIST_TRAFFIC_SOURCE_SHA256 else None
+    return NLIST_VALU_ISSUE_FRAC if _digest("search.hip", "internal.h") == NLIST_TRAFFIC_SOURCE_SHA256 else None
 
 
 def force_l1_rate():
-    return FORCE_L1_ACCESS_RATE if _digest("sph.hip", "pairs.h") == FORCE_SOURCES_SHA256 else None
+    return FORCE_L1_ACCESS_RATE if _digest("sph.hip", "pairs.h", "internal.h") == FORCE_SOURCES_SHA256 else None
 
 
 def parse():
