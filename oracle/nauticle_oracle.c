@@ -39,7 +39,16 @@
  *   - first-order semi-implicit Euler: v <- v + dt a, then r <- r + dt v
  *     with the new v (Example 1a, equations eq6 and eq7);
  *   - particles leaving the box are shifted periodically on every axis
- *     (Sec. 3.2.1).
+ *     (Sec. 3.2.1);
+ *   - symmetric boundaries (Sec. 3.2.1): a particle within the influence
+ *     radius of a symmetric face interacts with the mirror images of the
+ *     particles near that face (its own included), positions reflected in
+ *     the face and the normal velocity component reversed (free slip);
+ *   - the operator set of Example 1a itself: the continuity equation
+ *     (eq. SPH_fluid_continuity, the divergence in the form of eq. diffop2
+ *     with V_j = m/rho_j), the linear equation of state p = c^2 (rho - rho0),
+ *     and the momentum equation with the artificial viscosity Pi_ij, each
+ *     equation finished for all particles before the next (Sec. 3.3).
  * Wall particles are ordinary particles held fixed (paper Sec. 5.3 builds
  * walls from fixed particles): they contribute density and pressure, keep
  * v = 0 and are not integrated.
@@ -65,14 +74,18 @@
 typedef struct {
     int32_t dim;         /* 1, 2 or 3 */
     int32_t n[3];        /* cells per axis (unused axes: 1) */
-    int32_t periodic[3]; /* 1 = periodic, 0 = cut-off */
+    int32_t periodic[3]; /* 1 = periodic faces */
+    int32_t mirror[3];   /* 1 = symmetric faces; neither flag = cut-off */
     double origin[3];
     double cs[3];
 } or_domain;
 
+/* alpha_av: coefficient of the artificial viscosity of Example 1a,
+ * Pi_ij = -alpha_av c0 h (v_ji . r_ji) / (rho_i |r_ji|^2) when approaching. */
 typedef struct {
     double h, mass, rho0, c0, gamma, nu, dt;
     double g[3];
+    double alpha_av;
 } or_params;
 
 /* ------------------------------------------------------------------------- */
@@ -209,15 +222,21 @@ static int or_cell_delta(const or_domain* D, int k, int64_t ci, int64_t cj)
  *   t_k  = fl32(off_i,k - delta_k * cs_k)      (delta*cs is exact)
  *   d_k  = fl32(off_j,k - t_k)                 (= r_j - r_i up to rounding)
  *   r2   = fmaf(d_z, d_z, fmaf(d_y, d_y, d_x * d_x))
- *   neighbour iff r2 < fl32(4 h^2) and j != i. */
-static int or_pred_f32(const or_domain* D, float R2, const int delta[3],
+ *   neighbour iff r2 < fl32(4 h^2) and j != i.
+ * The mirror image of j in a symmetric face of i's boundary cell (i and j
+ * both in that cell) takes sign_k = -1: its coordinate along k, measured in
+ * i's cell frame, is -off_j at the lower face and 2 cs - off_j at the upper
+ * face, so d_k = fl32(-off_j,k - t_k) with delta_k = 0 (lower) or 2 (upper).
+ * Negation is exact, so this is the image's r_j - r_i rounded once. */
+static int or_pred_f32(const or_domain* D, float R2, const int delta[3], const int sign[3],
                        const float* offi, const float* offj)
 {
     float d[3] = {0.0f, 0.0f, 0.0f};
     for (int k = 0; k < D->dim; ++k) {
         float cs = (float)D->cs[k];
         float t = offi[k] - (float)delta[k] * cs;
-        d[k] = offj[k] - t;
+        float oj = sign[k] < 0 ? -offj[k] : offj[k];
+        d[k] = oj - t;
     }
     float r2 = d[0] * d[0];
     if (D->dim >= 2) r2 = fmaf(d[1], d[1], r2);
@@ -295,11 +314,15 @@ static void or_cell_list_free(or_cell_list* L)
 /* For every particle i (or every i = which[s], s < n_eval, if which is not
  * NULL): count[s] = number of j satisfying the FP32 predicate.  If list !=
  * NULL, list[s*max_nbr + k] receives the neighbours' input indices (stencil
- * order, then index order), up to max_nbr of them.  Found through the cell
- * grid: only the 3^dim cells around i's cell. */
+ * order, then index order), up to max_nbr of them, and mirror[s*max_nbr + k]
+ * (if not NULL) the set of axes along which that neighbour is a mirror image
+ * (bit k for axis k).  Found through the cell grid: only the 3^dim cells
+ * around i's cell, where a cell beyond a symmetric face stands for the
+ * mirror image of the boundary cell itself. */
 int or_neighbours_f32(const or_domain* D, double h, int64_t n, const uint32_t* cell,
                       const float* ox, const float* oy, const float* oz, int64_t n_eval,
-                      const int64_t* which, int32_t* count, uint32_t* list, int32_t max_nbr)
+                      const int64_t* which, int32_t* count, uint32_t* list, uint8_t* mirror,
+                      int32_t max_nbr)
 {
     or_cell_list L;
     if (or_cell_list_build(D, n, cell, &L) != 0) return -1;
@@ -320,15 +343,26 @@ int or_neighbours_f32(const or_domain* D, double h, int64_t n, const uint32_t* c
                 for (int dx = 0; dx < span[0]; ++dx) {
                     int delta[3] = {span[0] == 3 ? dx - 1 : 0, span[1] == 3 ? dy - 1 : 0,
                                     span[2] == 3 ? dz - 1 : 0};
+                    int sign[3] = {1, 1, 1};
                     int64_t cj[3];
                     int ok = 1;
+                    uint8_t mask = 0;
                     for (int k = 0; k < 3; ++k) {
                         int64_t c = ci[k] + delta[k];
                         if (k < D->dim) {
-                            if (D->periodic[k])
+                            if (D->periodic[k]) {
                                 c = or_floor_mod(c, D->n[k]);
-                            else if (c < 0 || c >= D->n[k])
-                                ok = 0;
+                            } else if (c < 0 || c >= D->n[k]) {
+                                if (!D->mirror[k]) {
+                                    ok = 0;
+                                } else {
+                                    /* the image of i's own (boundary) cell */
+                                    c = ci[k];
+                                    sign[k] = -1;
+                                    delta[k] = delta[k] < 0 ? 0 : 2;
+                                    mask |= (uint8_t)(1u << k);
+                                }
+                            }
                         }
                         cj[k] = c;
                     }
@@ -337,11 +371,14 @@ int or_neighbours_f32(const or_domain* D, double h, int64_t n, const uint32_t* c
                     if (L.start[nc] == OR_EMPTY) continue;
                     for (uint32_t p = L.start[nc]; p < L.end[nc]; ++p) {
                         uint32_t j = L.perm[p];
-                        if ((int64_t)j == i) continue;
+                        if ((int64_t)j == i && mask == 0) continue;
                         float offj[3] = {0, 0, 0};
                         for (int k = 0; k < D->dim; ++k) offj[k] = off[k][j];
-                        if (or_pred_f32(D, R2, delta, offi, offj)) {
-                            if (list && cnt < max_nbr) list[s * (int64_t)max_nbr + cnt] = j;
+                        if (or_pred_f32(D, R2, delta, sign, offi, offj)) {
+                            if (list && cnt < max_nbr) {
+                                list[s * (int64_t)max_nbr + cnt] = j;
+                                if (mirror) mirror[s * (int64_t)max_nbr + cnt] = mask;
+                            }
                             ++cnt;
                         }
                     }
@@ -352,8 +389,11 @@ int or_neighbours_f32(const or_domain* D, double h, int64_t n, const uint32_t* c
     return 0;
 }
 
-/* The same counts by brute force over all pairs: used to pin the cell-grid
- * enumeration above. */
+/* The same counts by brute force over all pairs and all their mirror
+ * images: used to pin the cell-grid enumeration above.  Along a symmetric
+ * axis the reflection in the lower face maps cell c to cell -1 - c and the
+ * reflection in the upper face maps it to 2n - 1 - c; an image is a
+ * candidate when its cell is adjacent to i's cell. */
 void or_neighbours_f32_brute(const or_domain* D, double h, int64_t n, const uint32_t* cell,
                              const float* ox, const float* oy, const float* oz, int32_t* count)
 {
@@ -366,19 +406,37 @@ void or_neighbours_f32_brute(const or_domain* D, double h, int64_t n, const uint
         for (int k = 0; k < D->dim; ++k) offi[k] = off[k][i];
         int32_t cnt = 0;
         for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
             int64_t cj[3];
             or_cell_coords(D, cell[j], cj);
-            int delta[3] = {0, 0, 0};
-            int adjacent = 1;
-            for (int k = 0; k < D->dim; ++k) {
-                delta[k] = or_cell_delta(D, k, ci[k], cj[k]);
-                if (delta[k] == 2) adjacent = 0;
+            /* image choice per axis: 0 = j itself, 1 = lower face, 2 = upper face */
+            int n_img = 1;
+            for (int k = 0; k < D->dim; ++k) n_img *= D->mirror[k] ? 3 : 1;
+            for (int img = 0; img < n_img; ++img) {
+                int delta[3] = {0, 0, 0}, sign[3] = {1, 1, 1};
+                int adjacent = 1, mirrored = 0, rest = img;
+                for (int k = 0; k < D->dim; ++k) {
+                    int choice = 0;
+                    if (D->mirror[k]) {
+                        choice = rest % 3;
+                        rest /= 3;
+                    }
+                    if (choice == 0) {
+                        delta[k] = or_cell_delta(D, k, ci[k], cj[k]);
+                        if (delta[k] == 2) adjacent = 0;
+                    } else {
+                        int64_t c_img = choice == 1 ? -1 - cj[k] : 2 * (int64_t)D->n[k] - 1 - cj[k];
+                        int64_t dc = c_img - ci[k];
+                        if (dc < -1 || dc > 1) adjacent = 0;
+                        sign[k] = -1;
+                        delta[k] = choice == 1 ? 0 : 2;
+                        mirrored = 1;
+                    }
+                }
+                if (!adjacent || (j == i && !mirrored)) continue;
+                float offj[3] = {0, 0, 0};
+                for (int k = 0; k < D->dim; ++k) offj[k] = off[k][j];
+                cnt += or_pred_f32(D, R2, delta, sign, offi, offj);
             }
-            if (!adjacent) continue;
-            float offj[3] = {0, 0, 0};
-            for (int k = 0; k < D->dim; ++k) offj[k] = off[k][j];
-            cnt += or_pred_f32(D, R2, delta, offi, offj);
         }
         count[i] = cnt;
     }
@@ -441,9 +499,18 @@ static void or_rel(const or_domain* D, const double* xi, const double* xj, doubl
     }
 }
 
-/* Calls visit(ctx, i, j, r_ij, |r_ij|) for every j != i with |r_ij| < 2h.
- * Neighbours are enumerated from the 3^dim cells around i's cell. */
-typedef void (*or_visit_fn)(void* ctx, int64_t i, int64_t j, const double r[3], double rn);
+/* Calls visit(ctx, i, j, r_ij, |r_ij|, sgn) for every j != i with
+ * |r_ij| < 2h, and for every mirror image of a particle j (i itself
+ * included) in a symmetric face with |r_ij| < 2h.  For an image, r_ij is
+ * measured to the reflected position (2 o_k - x_j,k in the lower face,
+ * 2 (o_k + L_k) - x_j,k in the upper one) and sgn_k = -1 along each
+ * reflecting axis: the image's velocity is sgn * v_j (normal component
+ * reversed).  sgn is all ones for j itself.  Neighbours are enumerated from
+ * the 3^dim cells around i's cell; a cell beyond a symmetric face stands for
+ * the image of the boundary cell (only particles of that cell can have an
+ * image within 2h of a particle in it, since cells are at least 2h wide). */
+typedef void (*or_visit_fn)(void* ctx, int64_t i, int64_t j, const double r[3], double rn,
+                            const double sgn[3]);
 
 static void or_for_neighbours(const or_grid64* G, const double* x, int64_t i, or_visit_fn visit, void* ctx)
 {
@@ -458,14 +525,25 @@ static void or_for_neighbours(const or_grid64* G, const double* x, int64_t i, or
                 int delta[3] = {span[0] == 3 ? dx - 1 : 0, span[1] == 3 ? dy - 1 : 0,
                                 span[2] == 3 ? dz - 1 : 0};
                 int64_t cj[3];
-                int ok = 1;
+                int ok = 1, mirrored = 0;
+                /* face coordinate of the reflection along each axis (if any) */
+                double face[3] = {0.0, 0.0, 0.0};
+                double sgn[3] = {1.0, 1.0, 1.0};
                 for (int k = 0; k < 3; ++k) {
                     int64_t c = ci[k] + delta[k];
                     if (k < D->dim) {
-                        if (D->periodic[k])
+                        if (D->periodic[k]) {
                             c = or_floor_mod(c, D->n[k]);
-                        else if (c < 0 || c >= D->n[k])
-                            ok = 0;
+                        } else if (c < 0 || c >= D->n[k]) {
+                            if (!D->mirror[k]) {
+                                ok = 0;
+                            } else {
+                                c = ci[k];
+                                sgn[k] = -1.0;
+                                face[k] = delta[k] < 0 ? D->origin[k] : D->origin[k] + D->n[k] * D->cs[k];
+                                mirrored = 1;
+                            }
+                        }
                     }
                     cj[k] = c;
                 }
@@ -474,11 +552,14 @@ static void or_for_neighbours(const or_grid64* G, const double* x, int64_t i, or
                 if (G->L.start[nc] == OR_EMPTY) continue;
                 for (uint32_t p = G->L.start[nc]; p < G->L.end[nc]; ++p) {
                     int64_t j = G->L.perm[p];
-                    if (j == i) continue;
+                    if (j == i && !mirrored) continue;
+                    double xj[3];
+                    for (int k = 0; k < 3; ++k)
+                        xj[k] = sgn[k] < 0.0 ? 2.0 * face[k] - x[3 * j + k] : x[3 * j + k];
                     double r[3];
-                    or_rel(D, &x[3 * i], &x[3 * j], r);
+                    or_rel(D, &x[3 * i], xj, r);
                     double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-                    if (r2 < G->R2) visit(ctx, i, j, r, sqrt(r2));
+                    if (r2 < G->R2) visit(ctx, i, j, r, sqrt(r2), sgn);
                 }
             }
 }
@@ -548,9 +629,10 @@ typedef struct {
     int32_t cnt;
 } or_density_ctx;
 
-static void or_density_visit(void* c, int64_t i, int64_t j, const double r[3], double rn)
+static void or_density_visit(void* c, int64_t i, int64_t j, const double r[3], double rn,
+                             const double sgn[3])
 {
-    (void)i; (void)j; (void)r;
+    (void)i; (void)j; (void)r; (void)sgn;
     or_density_ctx* ctx = (or_density_ctx*)c;
     ctx->acc += ctx->P->mass * or_W(ctx->D->dim, ctx->P->h, rn);
     ctx->cnt += 1;
@@ -604,7 +686,8 @@ typedef struct {
     double acc[3];
 } or_force_ctx;
 
-static void or_force_visit(void* c, int64_t i, int64_t j, const double r[3], double rn)
+static void or_force_visit(void* c, int64_t i, int64_t j, const double r[3], double rn,
+                           const double sgn[3])
 {
     or_force_ctx* ctx = (or_force_ctx*)c;
     const or_params* P = ctx->P;
@@ -616,7 +699,7 @@ static void or_force_visit(void* c, int64_t i, int64_t j, const double r[3], dou
         /* symmetric pressure gradient: -m (s_i + s_j) grad_i W_ij */
         ctx->acc[k] -= P->mass * (si + sj) * F * r[k];
         /* Laplacian viscosity: m nu (1/rho_i + 1/rho_j) F_ij (v_i - v_j) */
-        ctx->acc[k] += P->mass * visc * F * (ctx->v[3 * i + k] - ctx->v[3 * j + k]);
+        ctx->acc[k] += P->mass * visc * F * (ctx->v[3 * i + k] - sgn[k] * ctx->v[3 * j + k]);
     }
 }
 
@@ -645,6 +728,121 @@ int or_forces(const or_domain* D, const or_params* P, int64_t n, const double* x
     if (or_grid64_build(&G, D, P->h, n, x) != 0) return -1;
     or_force_ctx ctx = {D, P, &G, x, v, rho, p, fixed, which, a, {0, 0, 0}};
     or_parallel(which ? n_eval : n, nthreads, or_force_range, &ctx);
+    or_grid64_free(&G);
+    return 0;
+}
+
+
+/* ------------------------------------------------------------------------- */
+/* Example 1a: continuity, linear equation of state, momentum with Pi_ij      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    const or_domain* D;
+    const or_params* P;
+    const or_grid64* G;
+    const double* x;
+    const double* v;
+    const double* rho;
+    const double* p;
+    const uint8_t* fixed;
+    const int64_t* which;
+    double* out;     /* drho (n) or a (n,3) */
+    double acc[3];
+} or_ex1a_ctx;
+
+/* One term of sum_j (v_j - v_i) . grad_i W_ij m / rho_j, with grad_i W_ij =
+ * F_ij r_ij and, for a mirror image, v_j reflected. */
+static void or_continuity_visit(void* c, int64_t i, int64_t j, const double r[3], double rn,
+                                const double sgn[3])
+{
+    or_ex1a_ctx* ctx = (or_ex1a_ctx*)c;
+    const or_params* P = ctx->P;
+    double F = or_F(ctx->D->dim, P->h, rn);
+    double dv_dot_grad = 0.0;
+    for (int k = 0; k < 3; ++k)
+        dv_dot_grad += (sgn[k] * ctx->v[3 * j + k] - ctx->v[3 * i + k]) * F * r[k];
+    ctx->acc[0] += dv_dot_grad * P->mass / ctx->rho[j];
+}
+
+static void or_continuity_range(void* c, int64_t begin, int64_t end)
+{
+    or_ex1a_ctx local = *(or_ex1a_ctx*)c;
+    for (int64_t s = begin; s < end; ++s) {
+        int64_t i = local.which ? local.which[s] : s;
+        local.acc[0] = 0.0;
+        or_for_neighbours(local.G, local.x, i, or_continuity_visit, &local);
+        local.out[s] = -local.rho[i] * local.acc[0];
+    }
+}
+
+/* Continuity equation of Example 1a (eq. SPH_fluid_continuity):
+ *   drho_i/dt = -rho_i sum_j (v_j - v_i) . grad_i W_ij m / rho_j
+ * for every particle (fixed ones included: their density evolves too).
+ * x, v are (n,3) row-major, rho (n); drho receives one value per evaluated
+ * particle. */
+int or_continuity(const or_domain* D, const or_params* P, int64_t n, const double* x,
+                  const double* v, const double* rho, int64_t n_eval, const int64_t* which,
+                  double* drho, int nthreads)
+{
+    or_grid64 G;
+    if (or_grid64_build(&G, D, P->h, n, x) != 0) return -1;
+    or_ex1a_ctx ctx = {D, P, &G, x, v, rho, NULL, NULL, which, drho, {0, 0, 0}};
+    or_parallel(which ? n_eval : n, nthreads, or_continuity_range, &ctx);
+    or_grid64_free(&G);
+    return 0;
+}
+
+/* Linear equation of state of Example 1a: p = c^2 (rho - rho0). */
+double or_linear_eos(const or_params* P, double rho)
+{
+    return P->c0 * P->c0 * (rho - P->rho0);
+}
+
+/* One term of the momentum equation of Example 1a:
+ *   -(p_i/rho_i^2 + p_j/rho_j^2 + Pi_ij) m grad_i W_ij, with
+ *   Pi_ij = -alpha_av c0 h (v_ji . r_ji) / (rho_i |r_ji|^2) if v_ji . r_ji < 0,
+ *   else 0; v_ji = v_j - v_i, r_ji = r_j - r_i (so v_ji . r_ji = v_ij . r_ij).
+ * A coincident pair (r = 0) has v_ji . r_ji = 0 and grad W = 0: no term. */
+static void or_momentum_visit(void* c, int64_t i, int64_t j, const double r[3], double rn,
+                              const double sgn[3])
+{
+    or_ex1a_ctx* ctx = (or_ex1a_ctx*)c;
+    const or_params* P = ctx->P;
+    double F = or_F(ctx->D->dim, P->h, rn);
+    double si = ctx->p[i] / (ctx->rho[i] * ctx->rho[i]);
+    double sj = ctx->p[j] / (ctx->rho[j] * ctx->rho[j]);
+    double vr = 0.0;
+    for (int k = 0; k < 3; ++k) vr += (ctx->v[3 * i + k] - sgn[k] * ctx->v[3 * j + k]) * r[k];
+    double Pi = vr < 0.0 ? -P->alpha_av * P->c0 * P->h * vr / (ctx->rho[i] * rn * rn) : 0.0;
+    for (int k = 0; k < 3; ++k) ctx->acc[k] -= (si + sj + Pi) * P->mass * F * r[k];
+}
+
+static void or_momentum_range(void* c, int64_t begin, int64_t end)
+{
+    or_ex1a_ctx local = *(or_ex1a_ctx*)c;
+    for (int64_t s = begin; s < end; ++s) {
+        int64_t i = local.which ? local.which[s] : s;
+        for (int k = 0; k < 3; ++k) local.acc[k] = 0.0;
+        or_for_neighbours(local.G, local.x, i, or_momentum_visit, &local);
+        int is_fixed = local.fixed ? local.fixed[i] : 0;
+        for (int k = 0; k < 3; ++k)
+            local.out[3 * s + k] = is_fixed ? 0.0 : local.acc[k] + (k < local.D->dim ? local.P->g[k] : 0.0);
+    }
+}
+
+/* Momentum equation of Example 1a (eq. SPH_fluid_momentum):
+ *   a_i = -sum_j (p_i/rho_i^2 + p_j/rho_j^2 + Pi_ij) m grad_i W_ij + g
+ * for every non-fixed particle (fixed particles get a = 0).  rho and p are
+ * inputs for all n particles; x, v, a are (n,3) row-major. */
+int or_momentum(const or_domain* D, const or_params* P, int64_t n, const double* x,
+                const double* v, const double* rho, const double* p, const uint8_t* fixed,
+                int64_t n_eval, const int64_t* which, double* a, int nthreads)
+{
+    or_grid64 G;
+    if (or_grid64_build(&G, D, P->h, n, x) != 0) return -1;
+    or_ex1a_ctx ctx = {D, P, &G, x, v, rho, p, fixed, which, a, {0, 0, 0}};
+    or_parallel(which ? n_eval : n, nthreads, or_momentum_range, &ctx);
     or_grid64_free(&G);
     return 0;
 }
@@ -718,6 +916,47 @@ int or_step(const or_domain* D, const or_params* P, int64_t n, double* x, double
     return rc;
 }
 
+
+/* Advances (x, v, rho) by n_steps steps of Example 1a, its equations in the
+ * paper's order, each finished for all particles before the next:
+ *   eq1 drho = continuity(x, v, rho);   eq2 rho <- rho + dt drho;
+ *   eq3 p = c^2 (rho - rho0);           eq4/eq5 a = momentum(x, v, rho, p) + g;
+ *   eq6 v <- v + dt a;                  eq7 x <- x + dt v (periodic shift).
+ * Fixed particles keep x and v; their density evolves like any other.
+ * drho, p, a (optional) receive the values of the last step. */
+int or_step_ex1a(const or_domain* D, const or_params* P, int64_t n, double* x, double* v,
+                 double* rho, const uint8_t* fixed, int32_t n_steps, double* drho_out,
+                 double* p_out, double* a_out, int nthreads)
+{
+    size_t N = (size_t)(n > 0 ? n : 1);
+    double* drho = (double*)malloc(sizeof(double) * N);
+    double* p = (double*)malloc(sizeof(double) * N);
+    double* a = (double*)malloc(sizeof(double) * 3 * N);
+    if (!drho || !p || !a) return -1;
+    int rc = 0;
+    for (int32_t s = 0; s < n_steps && rc == 0; ++s) {
+        rc = or_continuity(D, P, n, x, v, rho, 0, NULL, drho, nthreads);
+        if (rc != 0) break;
+        for (int64_t i = 0; i < n; ++i) {
+            rho[i] += P->dt * drho[i];
+            p[i] = or_linear_eos(P, rho[i]);
+        }
+        rc = or_momentum(D, P, n, x, v, rho, p, fixed, 0, NULL, a, nthreads);
+        if (rc != 0) break;
+        or_integrate_ctx ic = {D, P, x, v, a, fixed};
+        or_parallel(n, nthreads, or_integrate_range, &ic);
+    }
+    if (rc == 0 && n_steps > 0) {
+        if (drho_out) memcpy(drho_out, drho, sizeof(double) * (size_t)n);
+        if (p_out) memcpy(p_out, p, sizeof(double) * (size_t)n);
+        if (a_out) memcpy(a_out, a, sizeof(double) * 3 * (size_t)n);
+    }
+    free(drho);
+    free(p);
+    free(a);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Domain validation                                                          */
 /* ------------------------------------------------------------------------- */
@@ -732,6 +971,9 @@ int or_validate_domain(const or_domain* D, double h)
         if (D->n[k] < 1) return -1;
         if (D->cs[k] < 2.0 * h) return -2;
         if (D->periodic[k] && D->n[k] < 3) return -3;
+        /* both faces of a symmetric axis must be distinct cells, so that a
+         * boundary cell's images lie beyond one face only */
+        if (D->mirror[k] && (D->periodic[k] || D->n[k] < 2)) return -3;
     }
     for (int k = D->dim; k < 3; ++k)
         if (D->n[k] != 1) return -1;
@@ -785,8 +1027,10 @@ typedef struct {
     double acc_v[3], acc_x[3];
 } or_vjp_ctx;
 
-static void or_vjp_a_visit(void* c, int64_t i, int64_t j, const double r[3], double rn)
+static void or_vjp_a_visit(void* c, int64_t i, int64_t j, const double r[3], double rn,
+                           const double sgn[3])
 {
+    (void)sgn; /* or_step_vjp refuses domains with symmetric faces */
     or_vjp_ctx* ctx = (or_vjp_ctx*)c;
     const or_params* P = ctx->P;
     double F = or_F(ctx->D->dim, P->h, rn);
@@ -822,8 +1066,10 @@ static void or_vjp_a_range(void* c, int64_t begin, int64_t end)
     }
 }
 
-static void or_vjp_b_visit(void* c, int64_t i, int64_t j, const double r[3], double rn)
+static void or_vjp_b_visit(void* c, int64_t i, int64_t j, const double r[3], double rn,
+                           const double sgn[3])
 {
+    (void)sgn;
     or_vjp_ctx* ctx = (or_vjp_ctx*)c;
     const or_params* P = ctx->P;
     int dim = ctx->D->dim;
@@ -868,6 +1114,8 @@ int or_step_vjp(const or_domain* D, const or_params* P, int64_t n, const double*
                 const double* lam_v_next, double* lam_x, double* lam_v, double* dnu,
                 double* dc0, int nthreads)
 {
+    for (int k = 0; k < D->dim; ++k)
+        if (D->mirror[k]) return -4;  /* mirror images are outside this derivative */
     size_t N = (size_t)(n > 0 ? n : 1);
     double* rho = (double*)malloc(sizeof(double) * N);
     double* p = (double*)malloc(sizeof(double) * N);

@@ -12,7 +12,12 @@ Every function follows the paper (arXiv:1710.08259):
 * pressure gradient: eq. diffop1; viscosity: eq. diffop3 in Morris form;
 * time step: semi-implicit Euler of Example 1a (velocity, then position);
 * neighbour search: cell grid of Sec. 3.2.1 ("The computational domain");
-* periodic shifting of leaving particles: Sec. 3.2.1.
+* periodic shifting of leaving particles: Sec. 3.2.1;
+* symmetric (mirror, free-slip) faces: Sec. 3.2.1 boundary kinds, used by
+  the dam break of Example 1a;
+* Example 1a's own operator set: continuity (eq. SPH_fluid_continuity),
+  linear equation of state, momentum with the artificial viscosity Pi_ij
+  (eq. SPH_fluid_momentum), stepped in the order of its equations eq1-eq7.
 
 The one-step adjoint (:func:`step_vjp`) is not in the paper; it is the exact
 reverse-mode derivative of :func:`step` with one step, pinned against central
@@ -37,6 +42,7 @@ class _Domain(ctypes.Structure):
         ("dim", ctypes.c_int32),
         ("n", ctypes.c_int32 * 3),
         ("periodic", ctypes.c_int32 * 3),
+        ("mirror", ctypes.c_int32 * 3),
         ("origin", ctypes.c_double * 3),
         ("cs", ctypes.c_double * 3),
     ]
@@ -52,6 +58,7 @@ class _Params(ctypes.Structure):
         ("nu", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("g", ctypes.c_double * 3),
+        ("alpha_av", ctypes.c_double),
     ]
 
 
@@ -64,6 +71,9 @@ class Domain:
     cs: tuple
     origin: tuple = (0.0, 0.0, 0.0)
     periodic: tuple = (True, True, True)
+    # symmetric (mirror) faces; an axis that is neither periodic nor
+    # symmetric is cut-off
+    symmetric: tuple = (False, False, False)
 
     def length(self) -> np.ndarray:
         return np.array([self.n[k] * self.cs[k] for k in range(3)], dtype=np.float64)
@@ -77,6 +87,7 @@ class Domain:
         for k in range(3):
             d.n[k] = int(self.n[k])
             d.periodic[k] = 1 if self.periodic[k] else 0
+            d.mirror[k] = 1 if self.symmetric[k] else 0
             d.origin[k] = float(self.origin[k])
             d.cs[k] = float(self.cs[k])
         return d
@@ -92,6 +103,7 @@ class Params:
     nu: float = 1e-3
     dt: float = 1e-4
     g: tuple = (0.0, 0.0, 0.0)
+    alpha_av: float = 0.0   # artificial viscosity coefficient of Example 1a (0.1 there)
 
     def _c(self) -> _Params:
         p = _Params()
@@ -99,6 +111,7 @@ class Params:
         p.gamma, p.nu, p.dt = self.gamma, self.nu, self.dt
         for k in range(3):
             p.g[k] = float(self.g[k])
+        p.alpha_av = float(self.alpha_av)
         return p
 
 
@@ -131,7 +144,7 @@ def _load():
     lib.or_sort_keys.restype = ctypes.c_int
     lib.or_sort_keys.argtypes = [i64, vp, ctypes.c_uint32, vp, vp, vp, vp]
     lib.or_neighbours_f32.restype = ctypes.c_int
-    lib.or_neighbours_f32.argtypes = [P(_Domain), dbl, i64, vp, vp, vp, vp, i64, vp, vp, vp, i32]
+    lib.or_neighbours_f32.argtypes = [P(_Domain), dbl, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, i32]
     lib.or_neighbours_f32_brute.restype = None
     lib.or_neighbours_f32_brute.argtypes = [P(_Domain), dbl, i64, vp, vp, vp, vp, vp]
     lib.or_density.restype = ctypes.c_int
@@ -140,6 +153,16 @@ def _load():
     lib.or_forces.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, i64, vp, vp, ctypes.c_int]
     lib.or_step.restype = ctypes.c_int
     lib.or_step.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, i32, vp, vp, vp, ctypes.c_int]
+    lib.or_continuity.restype = ctypes.c_int
+    lib.or_continuity.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, i64, vp, vp, ctypes.c_int]
+    lib.or_linear_eos.restype = dbl
+    lib.or_linear_eos.argtypes = [P(_Params), dbl]
+    lib.or_momentum.restype = ctypes.c_int
+    lib.or_momentum.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, i64, vp, vp,
+                                ctypes.c_int]
+    lib.or_step_ex1a.restype = ctypes.c_int
+    lib.or_step_ex1a.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, i32, vp, vp, vp,
+                                 ctypes.c_int]
     lib.or_step_vjp.restype = ctypes.c_int
     lib.or_step_vjp.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, vp,
                                 P(dbl), P(dbl), ctypes.c_int]
@@ -216,9 +239,11 @@ def sort_keys(keys: np.ndarray, n_keys: int):
 
 
 def neighbours_f32(dom: Domain, h: float, cell: np.ndarray, off: np.ndarray,
-                   max_nbr: int = 0, brute: bool = False, which=None):
+                   max_nbr: int = 0, brute: bool = False, which=None, mirrors: bool = False):
     """FP32-predicate neighbour counts (and lists if max_nbr > 0), for all
-    particles or for the subset ``which``."""
+    particles or for the subset ``which``.  With ``mirrors`` the lists come
+    with a second array: per entry, the bit set of axes along which the
+    neighbour is a mirror image."""
     cell = np.ascontiguousarray(cell, dtype=np.uint32)
     n = cell.shape[0]
     cols = [np.ascontiguousarray(off[:, k], dtype=np.float32) for k in range(dom.dim)]
@@ -231,11 +256,14 @@ def neighbours_f32(dom: Domain, h: float, cell: np.ndarray, off: np.ndarray,
         _load().or_neighbours_f32_brute(ctypes.byref(dom._c()), h, n, _ptr(cell), *args, _ptr(count))
         return count
     lst = np.zeros((m, max_nbr), np.uint32) if max_nbr > 0 else None
+    mir = np.zeros((m, max_nbr), np.uint8) if max_nbr > 0 else None
     rc = _load().or_neighbours_f32(ctypes.byref(dom._c()), h, n, _ptr(cell), *args, m, _ptr(w),
-                                   _ptr(count), _ptr(lst), max_nbr)
+                                   _ptr(count), _ptr(lst), _ptr(mir), max_nbr)
     if rc != 0:
         raise MemoryError("or_neighbours_f32 failed")
-    return (count, lst) if max_nbr > 0 else count
+    if max_nbr == 0:
+        return count
+    return (count, lst, mir) if mirrors else (count, lst)
 
 
 # --------------------------------------------------------------------------
@@ -320,17 +348,25 @@ def _neighbourhood(dom: Domain, prm: Params, x3, which):
         for d in itertools.product(*[(-1, 0, 1) if k < dom.dim else (0,) for k in range(3)]):
             c = ci + np.array(d)
             ok = True
+            image = False
             for k in range(dom.dim):
                 if dom.periodic[k]:
                     c[k] %= dom.n[k]
                 elif c[k] < 0 or c[k] >= dom.n[k]:
-                    ok = False
+                    if dom.symmetric[k]:
+                        c[k] = ci[k]  # the boundary cell's mirror image
+                        image = True
+                    else:
+                        ok = False
             if not ok:
                 continue
             key = c[0] + dom.n[0] * (c[1] + dom.n[1] * c[2])
             lo = np.searchsorted(lin_sorted, key, "left")
             hi = np.searchsorted(lin_sorted, key, "right")
             js = order[lo:hi]
+            if image:  # a superset is enough here: keep the whole cell
+                sel.update(int(j) for j in js)
+                continue
             r = x3[js] - xs[s]
             for k in range(dom.dim):
                 if dom.periodic[k]:
@@ -357,6 +393,70 @@ def step(dom: Domain, prm: Params, x, v, fixed=None, n_steps=1, nthreads=None):
     return x3[:, :d], v3[:, :d], rho, p, a[:, :d]
 
 
+# --------------------------------------------------------------------------
+# Example 1a operator set
+# --------------------------------------------------------------------------
+
+def continuity(dom: Domain, prm: Params, x, v, rho, which=None, nthreads=None):
+    """drho/dt = -rho_i sum_j (v_j - v_i) . grad_i W_ij m / rho_j for all
+    particles (or the subset ``which``); rho is given for all particles."""
+    x3, v3 = _x3(x), _x3(v)
+    n = x3.shape[0]
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    w = None if which is None else np.ascontiguousarray(which, dtype=np.int64)
+    m = n if w is None else w.shape[0]
+    drho = np.zeros(m)
+    rc = _load().or_continuity(ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3),
+                               _ptr(v3), _ptr(rho), m, _ptr(w), _ptr(drho),
+                               nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_continuity failed")
+    return drho
+
+
+def linear_eos(prm: Params, rho: float) -> float:
+    """p = c^2 (rho - rho0) (Example 1a)."""
+    return _load().or_linear_eos(ctypes.byref(prm._c()), rho)
+
+
+def momentum(dom: Domain, prm: Params, x, v, rho, p, fixed=None, which=None, nthreads=None):
+    """Example 1a accelerations: pressure gradient plus artificial viscosity
+    plus g; rho and p are given for all particles."""
+    x3, v3 = _x3(x), _x3(v)
+    n = x3.shape[0]
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+    w = None if which is None else np.ascontiguousarray(which, dtype=np.int64)
+    m = n if w is None else w.shape[0]
+    a = np.zeros((m, 3))
+    rc = _load().or_momentum(ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3),
+                             _ptr(v3), _ptr(rho), _ptr(p), _ptr(fx), m, _ptr(w), _ptr(a),
+                             nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_momentum failed")
+    return a[:, : dom.dim]
+
+
+def step_ex1a(dom: Domain, prm: Params, x, v, rho, fixed=None, n_steps=1, nthreads=None):
+    """Advance (x, v, rho) by n_steps of Example 1a; returns
+    (x, v, rho, drho, p, a), the last three of the last step."""
+    x3, v3 = _x3(x), _x3(v)
+    n = x3.shape[0]
+    r = np.array(rho, dtype=np.float64, copy=True)
+    fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+    drho = np.zeros(n)
+    p = np.zeros(n)
+    a = np.zeros((n, 3))
+    rc = _load().or_step_ex1a(ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3),
+                              _ptr(v3), _ptr(r), _ptr(fx), int(n_steps), _ptr(drho), _ptr(p),
+                              _ptr(a), nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_step_ex1a failed")
+    d = dom.dim
+    return x3[:, :d], v3[:, :d], r, drho, p, a[:, :d]
+
+
 def step_vjp(dom: Domain, prm: Params, x, v, lam_x_next, lam_v_next, fixed=None, nthreads=None):
     """Reverse mode of one :func:`step`: returns (lam_x, lam_v, dL/dnu, dL/dc0)."""
     x3, v3 = _x3(x), _x3(v)
@@ -370,6 +470,8 @@ def step_vjp(dom: Domain, prm: Params, x, v, lam_x_next, lam_v_next, fixed=None,
     rc = _load().or_step_vjp(ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3), _ptr(v3),
                              _ptr(fx), _ptr(lx), _ptr(lv), _ptr(ox), _ptr(ov),
                              ctypes.byref(dnu), ctypes.byref(dc0), nthreads or default_threads())
+    if rc == -4:
+        raise ValueError("step_vjp: domains with symmetric faces are not supported")
     if rc != 0:
         raise MemoryError("or_step_vjp failed")
     d = dom.dim

@@ -22,11 +22,18 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field, replace
+from typing import Optional
 
 import numpy as np
 
 PERIODIC = 0
 CUTOFF = 1
+SYMMETRIC = 2
+
+# Models of the interaction step: density summation + Tait + Morris
+# viscosity, or Example 1a's continuity + linear EOS + artificial viscosity.
+SUMMATION = 0
+CONTINUITY = 1
 
 
 def _f32(x: float) -> float:
@@ -41,7 +48,7 @@ class Case:
     ncell: tuple          # cells per axis, (nx, ny, nz); unused axes 1
     cell_size: tuple      # FP32-representable edge per axis
     origin: tuple         # FP32-representable lower corner
-    boundary: tuple       # PERIODIC / CUTOFF per axis
+    boundary: tuple       # PERIODIC / CUTOFF / SYMMETRIC per axis
     h: float
     mass: float
     rho0: float
@@ -54,6 +61,9 @@ class Case:
     vel: np.ndarray       # (n, dim) float32
     n_fixed: int = 0
     name: str = ""
+    model: int = SUMMATION
+    alpha_av: float = 0.0                 # artificial viscosity coefficient (CONTINUITY)
+    rho: Optional[np.ndarray] = None      # (n,) float32 initial density (CONTINUITY)
 
     @property
     def n(self) -> int:
@@ -147,6 +157,36 @@ def dam_break_case(dx=0.005, h_over_dx=1.2, c0=30.0, nu=1e-6, rho0=1000.0, gamma
                 gamma=gamma, nu=nu, dt=cfl * h / c0, g=(0.0, 0.0, g),
                 pos=pos.astype(np.float32), vel=vel.astype(np.float32),
                 n_fixed=int(W.shape[0]), name=name)
+
+
+def ex1a_dam_break(scale: float = 1.0, name: str = "") -> Case:
+    """The 2-D dam break of Example 1a (its appendix configuration), with
+    the resolution refined by ``scale``: h = 0.25 / scale, dx = h / 1.1,
+    rho0 = 1000, c = 50 m/s, m = dx^2 rho0, g = (0, -9.81), alpha_av = 0.1,
+    dt = 1e-3 / scale (the paper's dt at scale 1, kept at the same CFL
+    number when refined).  Box: cells of edge 2h, round(7/h) x round(10/h) of
+    them (the listing's integer extents read as cell counts), symmetric
+    faces on both axes.  Fluid: the listing's 7 x 4 m grid of spacing dx,
+    sites at (k + 1/2) dx inside it (31 x 18 at scale 1), at rest,
+    rho = rho0.  The half-spacing keeps every particle off the faces: one on
+    a symmetric face coincides with its own mirror image, feels nothing from
+    it, and would fall through the floor in the first step."""
+    h = 0.25 / scale
+    dx = h / 1.1
+    cs = _f32(2.0 * h)
+    ncell = (int(round(7.0 / h)), int(round(10.0 / h)), 1)
+    nx = int(math.ceil(7.0 / dx - 0.5 - 1e-9))
+    ny = int(math.ceil(4.0 / dx - 0.5 - 1e-9))
+    ix, iy = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    pos = (np.stack([ix.ravel(order="F"), iy.ravel(order="F")], axis=1).astype(np.float64) + 0.5) * dx
+    rho0 = 1000.0
+    n = pos.shape[0]
+    return Case(dim=2, ncell=ncell, cell_size=(cs, cs, 1.0), origin=(0.0, 0.0, 0.0),
+                boundary=(SYMMETRIC, SYMMETRIC, CUTOFF), h=h, mass=dx * dx * rho0, rho0=rho0,
+                c0=50.0, gamma=1.0, nu=0.0, dt=1e-3 / scale, g=(0.0, -9.81, 0.0),
+                pos=pos.astype(np.float32), vel=np.zeros((n, 2), np.float32), n_fixed=0,
+                name=name or f"ex1a_dam_break_2d_{n}", model=CONTINUITY, alpha_av=0.1,
+                rho=np.full(n, rho0, np.float32))
 
 
 # ---------------------------------------------------------------------------

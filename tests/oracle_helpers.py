@@ -9,12 +9,13 @@ from paper_1710_08259_amd import workloads as WL
 def domain_of(case: WL.Case) -> O.Domain:
     return O.Domain(dim=case.dim, n=tuple(case.ncell), cs=tuple(case.cell_size),
                     origin=tuple(case.origin),
-                    periodic=tuple(b == WL.PERIODIC for b in case.boundary))
+                    periodic=tuple(b == WL.PERIODIC for b in case.boundary),
+                    symmetric=tuple(b == WL.SYMMETRIC for b in case.boundary))
 
 
 def params_of(case: WL.Case) -> O.Params:
     return O.Params(h=case.h, mass=case.mass, rho0=case.rho0, c0=case.c0, gamma=case.gamma,
-                    nu=case.nu, dt=case.dt, g=tuple(case.g))
+                    nu=case.nu, dt=case.dt, g=tuple(case.g), alpha_av=case.alpha_av)
 
 
 def x64(case: WL.Case) -> np.ndarray:
