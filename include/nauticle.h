@@ -18,7 +18,14 @@
  *   - the first-order semi-implicit Euler step [Example 1a, eq6 then eq7],
  *     with periodic shifting of particles that leave the box on any axis
  *     [Sec. 3.2.1];
- *   - the reverse-mode derivative of one step (not in the paper).
+ *   - Example 1a's own model as a second choice: the continuity equation
+ *     [eq. SPH_fluid_continuity], the linear equation of state
+ *     p = c^2 (rho - rho0) and the momentum equation with the artificial
+ *     viscosity Pi_ij [eq. SPH_fluid_momentum], stepped as eq1..eq7;
+ *   - periodic, cut-off and symmetric (mirror, free-slip) faces [Sec. 3.2.1,
+ *     boundary treatments];
+ *   - the reverse-mode derivative of one step of the summation model (not in
+ *     the paper).
  * Phases are separated like the paper's equations [Sec. 3.3: an equation is
  * finished for all particles before the next one starts]: each entry point
  * is a sequence of kernels on one stream.
@@ -76,7 +83,18 @@ typedef enum {
     NAUTICLE_ERR_NEIGHBOUR_OVERFLOW = -7  /* (nauticle_check) a particle had > max_nbr neighbours */
 } nauticle_status;
 
-enum { NAUTICLE_PERIODIC = 0, NAUTICLE_CUTOFF = 1 };
+/* Face treatments [Sec. 3.2.1].  Symmetric: a particle within 2h of the
+ * face interacts with the mirror images of the particles near it (itself
+ * included): positions reflected in the face, the normal velocity component
+ * reversed, scalar fields unchanged. */
+enum { NAUTICLE_PERIODIC = 0, NAUTICLE_CUTOFF = 1, NAUTICLE_SYMMETRIC = 2 };
+
+/* Models of the interaction step.
+ *   SUMMATION:  density summation, Tait equation of state, Morris viscosity
+ *               (nu);
+ *   CONTINUITY: Example 1a -- density evolved by the continuity equation,
+ *               p = c0^2 (rho - rho0), artificial viscosity (alpha_av). */
+enum { NAUTICLE_MODEL_SUMMATION = 0, NAUTICLE_MODEL_CONTINUITY = 1 };
 
 /* Sentinel of an empty cell in cell_start / cell_end. */
 #define NAUTICLE_EMPTY 0xFFFFFFFFu
@@ -84,17 +102,20 @@ enum { NAUTICLE_PERIODIC = 0, NAUTICLE_CUTOFF = 1 };
 /* Neighbour-list entry: bits 0..25 hold the neighbour's global sorted
  * position, bits 26+2k..27+2k hold (cell offset along axis k) + 1, the
  * offset being the neighbour's cell minus the particle's cell, in {-1,0,1},
- * after periodic folding. */
+ * after periodic folding -- or 3 when the entry is the neighbour's mirror
+ * image in a symmetric face along axis k (then the neighbour and the
+ * particle share the boundary cell next to that face). */
 #define NAUTICLE_NBR_INDEX_BITS 26
 
 /* The box [Sec. 3.2.1]: ncell[k] cells of edge cell_size[k] per axis, so the
  * length is L_k = ncell[k] * cell_size[k].  cell_size is used rounded to
  * FP32; it must be >= 2h (the influence radius).  Periodic axes need
- * ncell >= 3.  Axes k >= dim must have ncell[k] = 1. */
+ * ncell >= 3, symmetric axes ncell >= 2.  Axes k >= dim must have
+ * ncell[k] = 1. */
 typedef struct {
     int32_t dim;
     int32_t ncell[3];
-    int32_t boundary[3]; /* NAUTICLE_PERIODIC or NAUTICLE_CUTOFF */
+    int32_t boundary[3]; /* NAUTICLE_PERIODIC, NAUTICLE_CUTOFF or NAUTICLE_SYMMETRIC */
     double origin[3];
     double cell_size[3];
 } nauticle_domain;
@@ -102,10 +123,16 @@ typedef struct {
 /* Constants of one case.  h: smoothing length (support 2h); mass: particle
  * mass m; rho0: reference density; c0: sound speed; gamma: Tait exponent
  * (B = c0^2 rho0 / gamma); nu: kinematic viscosity; dt: time step;
- * g: body acceleration. */
+ * g: body acceleration; alpha_av: artificial viscosity coefficient
+ * (Pi_ij = -alpha_av c0 h w / (rho_i |r_ij|^2) for approaching pairs,
+ * 0.1 in Example 1a); model: NAUTICLE_MODEL_*, the same for every case of a
+ * table (SUMMATION uses gamma and nu, CONTINUITY alpha_av); reserved: 0. */
 typedef struct {
     double h, mass, rho0, c0, gamma, nu, dt;
     double g[3];
+    double alpha_av;
+    int32_t model;
+    int32_t reserved;
 } nauticle_sph_params;
 
 /* One independent problem.  Particles whose id (position within the case
@@ -121,12 +148,15 @@ typedef struct {
 
 /* Particle state, cell-relative layout (see Conventions).  off[k], vel[k]
  * for k >= dim may be NULL.  id[p] is the particle's index within its case
- * at binning time; it travels with the particle through every reordering. */
+ * at binning time; it travels with the particle through every reordering.
+ * rho: the evolved density of the CONTINUITY model (required there,
+ * reordered with the particles; ignored and may be NULL otherwise). */
 typedef struct {
     uint32_t* cell;
     float* off[3];
     float* vel[3];
     uint32_t* id;
+    float* rho;
 } nauticle_state;
 
 /* Neighbour structure, filled by nauticle_build_cells.
@@ -159,13 +189,15 @@ typedef struct {
     int32_t max_nbr;
 } nauticle_cells;
 
-/* Per-particle fields in sorted order.  s = p / rho^2, inv_rho = 1 / rho. */
+/* Per-particle fields in sorted order.  s = p / rho^2, inv_rho = 1 / rho.
+ * drho (optional, may be NULL): drho/dt of the continuity pass. */
 typedef struct {
     float* rho;
     float* p;
     float* s;
     float* inv_rho;
     float* acc[3];
+    float* drho;
 } nauticle_fields;
 
 /* Launch shape of the neighbour loops (search, density, forces, adjoint),
@@ -226,9 +258,16 @@ nauticle_status nauticle_unbin(const nauticle_case* cases, int32_t n_cases,
  * neighbours), d_k = fl32(off_j,k - fl32(off_i,k - delta_k cell_size_k)) and
  * r2 = fmaf(d_z, d_z, fmaf(d_y, d_y, d_x d_x)), j is a neighbour of i iff
  * j != i and r2 < fl32(4h^2).
+ * On a symmetric axis a stencil cell beyond the face stands for the mirror
+ * image of the particle's own boundary cell: for such an axis
+ * d_k = fl32(-off_j,k - fl32(off_i,k - delta_k cell_size_k)) with
+ * delta_k = 0 at the lower face and 2 at the upper one, and the particle's
+ * own image is a neighbour (the only case j = i).
  * Each list holds the neighbours row by row of the stencil (z offset
  * outer, y offset inner, each -1..1), and within a row in ascending sorted
- * position (the cell wrapped across a periodic x face after the others). */
+ * position (the cell wrapped across a periodic x face, or the image of the
+ * cell at a symmetric x face, after the others).  With the CONTINUITY
+ * model, in->rho is reordered into sorted->rho. */
 nauticle_status nauticle_build_cells(const nauticle_case* cases, int32_t n_cases,
                                      const nauticle_state* in, nauticle_state* sorted,
                                      nauticle_cells* cells, void* ws, size_t ws_bytes,
@@ -242,23 +281,44 @@ nauticle_status nauticle_sph_density(const nauticle_case* cases, int32_t n_cases
                                      nauticle_fields* fields, void* ws, size_t ws_bytes,
                                      hipStream_t stream);
 
+/* Continuity pass of the CONTINUITY model [Example 1a, eq1..eq3; eq.
+ * SPH_fluid_continuity, the divergence in the form of eq. diffop2]:
+ *   drho_i = -rho_i sum_j (v_j - v_i) . grad_i W_ij m / rho_j
+ * over the lists of nauticle_build_cells (images with reflected velocity),
+ * every neighbour value taken from `sorted` (the step's start); then
+ *   rho_i' = rho_i + dt drho_i,  p_i = c0^2 (rho_i' - rho0),
+ * written to fields->rho, p, s = p/rho'^2, inv_rho = 1/rho' (and drho if
+ * fields->drho is not NULL).  Fixed particles' velocity counts as 0; their
+ * density evolves like any other.  Requires sorted->rho and the CONTINUITY
+ * model. */
+nauticle_status nauticle_sph_continuity(const nauticle_case* cases, int32_t n_cases,
+                                        const nauticle_state* sorted, const nauticle_cells* cells,
+                                        nauticle_fields* fields, void* ws, size_t ws_bytes,
+                                        hipStream_t stream);
+
 /* Accelerations [eq. diffop1 with A = p; eq. diffop3, Morris form]:
  *   a_i = -sum_j m (s_i + s_j) F_ij r_ij
  *         + sum_j m nu (inv_rho_i + inv_rho_j) F_ij (v_i - v_j) + g,
  * r_ij = r_i - r_j, F(r) = -5 alpha_D (1 - r/2h)^3 / h^2 (so that
- * grad_i W_ij = F_ij r_ij).  Fixed particles get a = 0.  Reads rho..inv_rho
+ * grad_i W_ij = F_ij r_ij).  With the CONTINUITY model the viscous term is
+ * Example 1a's artificial viscosity instead [eq. SPH_fluid_momentum]:
+ *   -sum_j Pi_ij m F_ij r_ij,  Pi_ij = -alpha_av c0 h w_ij inv_rho_i / |r_ij|^2
+ * when w_ij = (v_i - v_j) . r_ij < 0, else 0.  For an image neighbour v_j is
+ * the reflected velocity.  Fixed particles get a = 0.  Reads rho..inv_rho
  * from `fields`, writes fields->acc.  If `next` is not NULL the step is
  * completed in the same kernel [Example 1a, eq6 then eq7]:
  * v' = v + dt a, off' = off + dt v' re-split into (cell, offset) as in
  * nauticle_bin, written to `next` in sorted order (id copied; fixed
- * particles copied unchanged).  `next` must not alias `sorted`. */
+ * particles copied unchanged; with the CONTINUITY model next->rho =
+ * fields->rho).  `next` must not alias `sorted`. */
 nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases,
                                     const nauticle_state* sorted, const nauticle_cells* cells,
                                     nauticle_fields* fields, nauticle_state* next, void* ws,
                                     size_t ws_bytes, hipStream_t stream);
 
 /* n_steps full steps in place: build_cells(state -> workspace copy),
- * density, forces with the fused integration back into `state`.  After
+ * density (SUMMATION) or continuity (CONTINUITY, state->rho evolved),
+ * forces with the fused integration back into `state`.  After
  * the call `state` holds the particles in the sorted order of the last
  * step; `cells` and `fields` hold that step's neighbour structure and
  * fields.  phase_events (optional, NULL or 5 * n_steps caller-created HIP
@@ -269,7 +329,9 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
                               int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
                               hipEvent_t* phase_events, void* ws, size_t ws_bytes, hipStream_t stream);
 
-/* Reverse mode of one step (the derivative the paper does not have).
+/* Reverse mode of one step of the SUMMATION model (the derivative the paper
+ * does not have); cases with a symmetric axis or the CONTINUITY model are
+ * rejected with NAUTICLE_ERR_INVALID_ARG.
  * Inputs are the step's forward quantities: `sorted` (the state the step's
  * forces pass read), `cells` (its neighbour lists and perm) and `fields`
  * (rho, p, s, inv_rho of that step).  lam_x_next / lam_v_next (device, FP32,

@@ -85,6 +85,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     std::memset(&P, 0, sizeof(P));
     P.n_cases = n_cases;
     const int dim0 = cases[0].dom.dim;
+    const int32_t model0 = cases[0].prm.model;
+    bool any_mirror = false;
     uint64_t n_total = 0, n_cells_total = 0, n_fluid_total = 0;
     int64_t worst_items = 0;
     double halo_need = 0.0;
@@ -97,8 +99,12 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         if (d.dim != dim0) return fail(NAUTICLE_ERR_DOMAIN, "case %d: all cases must share one dim", b);
         if (!finite_pos(q.h) || !finite_pos(q.mass) || !finite_pos(q.rho0) || !finite_pos(q.c0) ||
             !finite_pos(q.gamma) || !std::isfinite(q.nu) || q.nu < 0.0 || !std::isfinite(q.dt) || q.dt < 0.0 ||
-            !std::isfinite(q.g[0]) || !std::isfinite(q.g[1]) || !std::isfinite(q.g[2]))
+            !std::isfinite(q.g[0]) || !std::isfinite(q.g[1]) || !std::isfinite(q.g[2]) ||
+            !std::isfinite(q.alpha_av) || q.alpha_av < 0.0)
             return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: non-finite or non-positive parameter", b);
+        if (q.model != NAUTICLE_MODEL_SUMMATION && q.model != NAUTICLE_MODEL_CONTINUITY)
+            return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: unknown model %d", b, q.model);
+        if (q.model != model0) return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: all cases must share one model", b);
         uint64_t ncell = 1;
         for (int k = 0; k < 3; ++k) {
             if (k >= d.dim) {
@@ -106,7 +112,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
                 continue;
             }
             if (d.ncell[k] < 1) return fail(NAUTICLE_ERR_DOMAIN, "case %d: ncell[%d] < 1", b, k);
-            if (d.boundary[k] != NAUTICLE_PERIODIC && d.boundary[k] != NAUTICLE_CUTOFF)
+            if (d.boundary[k] != NAUTICLE_PERIODIC && d.boundary[k] != NAUTICLE_CUTOFF &&
+                d.boundary[k] != NAUTICLE_SYMMETRIC)
                 return fail(NAUTICLE_ERR_DOMAIN, "case %d: boundary[%d] unknown", b, k);
             if (!finite_pos(d.cell_size[k]) || !std::isfinite(d.origin[k]))
                 return fail(NAUTICLE_ERR_DOMAIN, "case %d: bad cell_size/origin on axis %d", b, k);
@@ -116,6 +123,9 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
                             b, k, cs32, 2.0 * q.h);
             if (d.boundary[k] == NAUTICLE_PERIODIC && d.ncell[k] < 3)
                 return fail(NAUTICLE_ERR_DOMAIN, "case %d: periodic axis %d needs >= 3 cells", b, k);
+            // a boundary cell's images must lie beyond one face only
+            if (d.boundary[k] == NAUTICLE_SYMMETRIC && d.ncell[k] < 2)
+                return fail(NAUTICLE_ERR_DOMAIN, "case %d: symmetric axis %d needs >= 2 cells", b, k);
             ncell *= static_cast<uint64_t>(d.ncell[k]);
         }
         if (c.n < 0 || c.n_fixed < 0 || c.n_fixed > c.n)
@@ -129,6 +139,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         for (int k = 0; k < 3; ++k) {
             C.nc[k] = d.ncell[k];
             C.periodic[k] = (k < d.dim && d.boundary[k] == NAUTICLE_PERIODIC) ? 1 : 0;
+            C.mirror[k] = (k < d.dim && d.boundary[k] == NAUTICLE_SYMMETRIC) ? 1 : 0;
+            any_mirror = any_mirror || C.mirror[k];
             C.cs[k] = static_cast<float>(k < d.dim ? d.cell_size[k] : 1.0);
             C.inv_cs[k] = static_cast<float>(1.0 / (k < d.dim ? d.cell_size[k] : 1.0));
             C.origin[k] = static_cast<float>(k < d.dim ? d.origin[k] : 0.0);
@@ -154,6 +166,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         C.c0 = static_cast<float>(q.c0);
         C.nu = static_cast<float>(q.nu);
         C.dt = static_cast<float>(q.dt);
+        C.c2 = static_cast<float>(q.c0 * q.c0);
+        C.av_coef = static_cast<float>(q.alpha_av * q.c0 * q.h * q.mass);
         C.item_first = static_cast<uint32_t>(D->items.size());
         for (int64_t first = 0; first < c.n; first += block) {
             Item it;
@@ -188,6 +202,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         if (n_cells_total >= (1ull << 31)) return fail(NAUTICLE_ERR_DOMAIN, "more than 2^31 cells in total");
     }
     P.dim_max = dim0;
+    P.model = model0;
+    P.mirror = any_mirror ? 1u : 0u;
     P.n_total = static_cast<uint32_t>(n_total);
     P.n_cells_total = static_cast<uint32_t>(n_cells_total);
     P.n_fluid_total = static_cast<uint32_t>(n_fluid_total);
@@ -232,7 +248,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     L.items = take(sizeof(Item) * n_items_max);
     L.queue = take(sizeof(uint32_t) * n_items_max);
     L.counters = take(sizeof(uint32_t) * kCounters);
-    for (int k = 0; k < 8; ++k) L.state[k] = take(4 * N);
+    for (int k = 0; k < 9; ++k) L.state[k] = take(4 * N);
     L.sort_keys = take(4 * N);
     L.sort_vals = take(4 * N);
     L.sort_hist = take(4 * 256 * n_tiles);
@@ -243,6 +259,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     L.b4 = take(16 * N);
     L.adj4 = take(16 * N);
     L.adj4b = take(16 * N);
+    L.vr4 = model0 == NAUTICLE_MODEL_CONTINUITY ? take(16 * N) : 0;
     L.partial = take(2 * sizeof(double) * n_items_max);
     L.inv_map = take(4 * N);
     L.total = off;
@@ -269,11 +286,13 @@ nauticle_status plan_for(const nauticle_case* cases, int32_t n_cases, void* ws, 
     return NAUTICLE_OK;
 }
 
-nauticle_status check_state(const Plan& P, const nauticle_state* st, bool need_vel, const char* name)
+nauticle_status check_state(const Plan& P, const nauticle_state* st, bool need_vel, const char* name,
+                            bool need_rho = false)
 {
     if (!st) return fail(NAUTICLE_ERR_INVALID_ARG, "%s is null", name);
     if (P.n_total == 0) return NAUTICLE_OK;
     if (!st->cell || !st->id) return fail(NAUTICLE_ERR_INVALID_ARG, "%s: cell/id null", name);
+    if (need_rho && !st->rho) return fail(NAUTICLE_ERR_INVALID_ARG, "%s: rho null (continuity model)", name);
     for (int k = 0; k < P.dim_max; ++k) {
         if (!st->off[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "%s: off[%d] null", name, k);
         if (need_vel && !st->vel[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "%s: vel[%d] null", name, k);
@@ -317,6 +336,15 @@ StateDev to_dev(const nauticle_state* s)
         d.off[k] = s->off[k];
         d.vel[k] = s->vel[k];
     }
+    d.rho = s->rho;
+    return d;
+}
+
+// The state as the plan's model reads it: rho only for the continuity model.
+StateDev to_dev_model(const Plan& P, const nauticle_state* s)
+{
+    StateDev d = to_dev(s);
+    if (P.model != NAUTICLE_MODEL_CONTINUITY) d.rho = nullptr;
     return d;
 }
 
@@ -328,6 +356,7 @@ FieldsDev to_dev(const nauticle_fields* f)
     d.s = f->s;
     d.inv_rho = f->inv_rho;
     for (int k = 0; k < 3; ++k) d.acc[k] = f->acc[k];
+    d.drho = f->drho;
     return d;
 }
 
@@ -340,6 +369,7 @@ StateDev scratch_state(const Plan& P, void* ws)
         d.vel[k] = at<float>(ws, P.L.state[4 + k]);
     }
     d.id = at<uint32_t>(ws, P.L.state[7]);
+    d.rho = P.model == NAUTICLE_MODEL_CONTINUITY ? at<float>(ws, P.L.state[8]) : nullptr;
     return d;
 }
 
@@ -430,12 +460,13 @@ nauticle_status nauticle_build_cells(const nauticle_case* cases, int32_t n_cases
     const Plan* P;
     nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
     if (st != NAUTICLE_OK) return st;
-    if ((st = check_state(*P, in, true, "in")) != NAUTICLE_OK) return st;
-    if ((st = check_state(*P, sorted, true, "sorted")) != NAUTICLE_OK) return st;
+    const bool cont = P->model == NAUTICLE_MODEL_CONTINUITY;
+    if ((st = check_state(*P, in, true, "in", cont)) != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, sorted, true, "sorted", cont)) != NAUTICLE_OK) return st;
     if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
-    if (P->n_total && (in->cell == sorted->cell || in->off[0] == sorted->off[0]))
+    if (P->n_total && (in->cell == sorted->cell || in->off[0] == sorted->off[0] || (cont && in->rho == sorted->rho)))
         return fail(NAUTICLE_ERR_INVALID_ARG, "sorted must not alias in");
-    hipError_t e = launch_build_cells(*P, ws, to_dev(in), to_dev(sorted), *cells, stream);
+    hipError_t e = launch_build_cells(*P, ws, to_dev_model(*P, in), to_dev_model(*P, sorted), *cells, stream);
     return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_build_cells");
 }
 
@@ -455,6 +486,28 @@ nauticle_status nauticle_sph_density(const nauticle_case* cases, int32_t n_cases
     return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_sph_density");
 }
 
+nauticle_status nauticle_sph_continuity(const nauticle_case* cases, int32_t n_cases, const nauticle_state* sorted,
+                                        const nauticle_cells* cells, nauticle_fields* fields, void* ws,
+                                        size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if (P->model != NAUTICLE_MODEL_CONTINUITY)
+        return fail(NAUTICLE_ERR_INVALID_ARG, "nauticle_sph_continuity needs the continuity model");
+    if ((st = check_state(*P, sorted, true, "sorted", true)) != NAUTICLE_OK) return st;
+    if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
+    if ((st = check_fields(*P, fields, false)) != NAUTICLE_OK) return st;
+    if (P->n_total && fields->rho == sorted->rho)
+        return fail(NAUTICLE_ERR_INVALID_ARG, "fields->rho must not alias sorted->rho");
+    const StateDev sd = to_dev(sorted);
+    hipError_t e = launch_cell_first(*P, ws, *cells, stream);
+    if (e == hipSuccess) e = launch_pack_positions(*P, ws, sd, stream);
+    if (e == hipSuccess) e = launch_pack_continuity(*P, ws, sd, stream);
+    if (e == hipSuccess) e = launch_continuity(*P, ws, sd, *cells, to_dev(fields), stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_sph_continuity");
+}
+
 nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases, const nauticle_state* sorted,
                                     const nauticle_cells* cells, nauticle_fields* fields, nauticle_state* next,
                                     void* ws, size_t ws_bytes, hipStream_t stream)
@@ -467,15 +520,16 @@ nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases,
     if ((st = check_fields(*P, fields, true)) != NAUTICLE_OK) return st;
     StateDev nd;
     if (next) {
-        if ((st = check_state(*P, next, true, "next")) != NAUTICLE_OK) return st;
+        const bool cont = P->model == NAUTICLE_MODEL_CONTINUITY;
+        if ((st = check_state(*P, next, true, "next", cont)) != NAUTICLE_OK) return st;
         if (P->n_total && (next->cell == sorted->cell || next->off[0] == sorted->off[0]))
             return fail(NAUTICLE_ERR_INVALID_ARG, "next must not alias sorted");
-        nd = to_dev(next);
+        nd = to_dev_model(*P, next);
     }
     hipError_t e = launch_cell_first(*P, ws, *cells, stream);
-    if (e == hipSuccess) e = launch_pack_fields(*P, ws, to_dev(sorted), to_dev(fields), stream);
+    if (e == hipSuccess) e = launch_pack_fields(*P, ws, to_dev_model(*P, sorted), to_dev(fields), stream);
     if (e == hipSuccess)
-        e = launch_forces(*P, ws, to_dev(sorted), *cells, to_dev(fields), next ? &nd : nullptr, stream);
+        e = launch_forces(*P, ws, to_dev_model(*P, sorted), *cells, to_dev(fields), next ? &nd : nullptr, stream);
     return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_sph_forces");
 }
 
@@ -487,10 +541,11 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
     nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
     if (st != NAUTICLE_OK) return st;
     if (n_steps < 0) return fail(NAUTICLE_ERR_INVALID_ARG, "n_steps < 0");
-    if ((st = check_state(*P, state, true, "state")) != NAUTICLE_OK) return st;
+    const bool cont = P->model == NAUTICLE_MODEL_CONTINUITY;
+    if ((st = check_state(*P, state, true, "state", cont)) != NAUTICLE_OK) return st;
     if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
     if ((st = check_fields(*P, fields, true)) != NAUTICLE_OK) return st;
-    const StateDev cur = to_dev(state);
+    const StateDev cur = to_dev_model(*P, state);
     const StateDev tmp = scratch_state(*P, ws);
     const FieldsDev f = to_dev(fields);
     // build_cells leaves packed positions for density, and density leaves
@@ -503,7 +558,12 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
         if (e == hipSuccess)
             e = launch_build_cells(*P, ws, cur, tmp, *cells, stream, phase_events ? phase_events[5 * s + 1] : nullptr);
         if (e == hipSuccess) e = mark(s, 2);
-        if (e == hipSuccess) e = launch_density(*P, ws, tmp, *cells, f, stream);
+        if (cont) {
+            if (e == hipSuccess) e = launch_pack_continuity(*P, ws, tmp, stream);
+            if (e == hipSuccess) e = launch_continuity(*P, ws, tmp, *cells, f, stream);
+        } else if (e == hipSuccess) {
+            e = launch_density(*P, ws, tmp, *cells, f, stream);
+        }
         if (e == hipSuccess) e = mark(s, 3);
         if (e == hipSuccess) e = launch_forces(*P, ws, tmp, *cells, f, &cur, stream);
         if (e == hipSuccess) e = mark(s, 4);
@@ -524,6 +584,8 @@ nauticle_status nauticle_sph_adjoint(const nauticle_case* cases, int32_t n_cases
     if ((st = check_state(*P, sorted, true, "sorted")) != NAUTICLE_OK) return st;
     if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
     if ((st = check_fields(*P, fields, false)) != NAUTICLE_OK) return st;
+    if (P->mirror || P->model != NAUTICLE_MODEL_SUMMATION)
+        return fail(NAUTICLE_ERR_INVALID_ARG, "adjoint: only the summation model without symmetric faces");
     if (!lam_x_next || !lam_v_next || !lam_x || !lam_v || !dnu || !dc0)
         return fail(NAUTICLE_ERR_INVALID_ARG, "adjoint: null argument");
     for (int k = 0; k < P->dim_max; ++k) {

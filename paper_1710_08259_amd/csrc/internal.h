@@ -43,6 +43,7 @@ struct CaseDev {
     int32_t dim;
     int32_t nc[3];
     int32_t periodic[3];
+    int32_t mirror[3];   // symmetric faces (a cell beyond one stands for the boundary cell's image)
     uint32_t cell_base;  // first global cell key of the case
     uint32_t n_cells;
     uint32_t offset;     // first global particle
@@ -62,7 +63,15 @@ struct CaseDev {
     float rho0, inv_rho0, B, gamma, c0;
     float nu, dt;
     float g[3];
+    float c2;            // c0^2 (linear equation of state)
+    float av_coef;       // alpha_av c0 h m (artificial viscosity, times 1/rho_i per particle)
 };
+
+// Offset code of a list entry along axis k (bits 26 + 2k, 27 + 2k): the
+// neighbour's cell minus the particle's cell plus one, or kMirrorCode for the
+// mirror image of a neighbour in a symmetric face of the particle's own
+// (boundary) cell.
+constexpr uint32_t kMirrorCode = 3u;
 
 // A tile of at most kBlock consecutive particles of one case.
 struct Item {
@@ -78,6 +87,7 @@ struct StateDev {
     float* off[3];
     float* vel[3];
     uint32_t* id;
+    float* rho;  // evolved density (continuity model), else null
 };
 
 struct FieldsDev {
@@ -86,6 +96,7 @@ struct FieldsDev {
     float* s;
     float* inv_rho;
     float* acc[3];
+    float* drho;  // optional: drho/dt of the continuity pass
 };
 
 // Byte offsets of everything the library keeps in the caller's workspace.
@@ -95,7 +106,7 @@ struct Layout {
     size_t items;
     size_t queue;        // item indices in decreasing estimated cost (persistent launches)
     size_t counters;     // one queue counter per neighbour-loop launch of a step
-    size_t state[8];     // scratch state for nauticle_step: cell, off[3], vel[3], id
+    size_t state[9];     // scratch state for nauticle_step: cell, off[3], vel[3], id, rho
     size_t sort_keys;    // ping-pong keys
     size_t sort_vals;    // ping-pong values
     size_t sort_hist;    // [bins][tiles]
@@ -106,6 +117,7 @@ struct Layout {
     size_t b4;           // float4: velocity (0 for fixed particles), 1 / rho
     size_t adj4;         // float4: adjoint A = dt (lam_v' + dt lam_x'), 0
     size_t adj4b;        // float4: A, rhobar (after adjoint pass A)
+    size_t vr4;          // float4: velocity (0 for fixed), 1 / rho of the step's start (continuity model)
     size_t partial;      // per-item FP64 partial sums (2 per item)
     size_t inv_map;      // id -> position map (N u32)
     size_t total;
@@ -119,6 +131,7 @@ struct Packed {
     float4* adj4;
     float4* adj4b;
     uint32_t* cell_first;
+    float4* vr4;
 };
 
 // Everything derived from a case table.
@@ -135,6 +148,8 @@ struct Plan {
     uint32_t persistent;     // neighbour loops as persistent grids
     uint32_t persistent_grid;
     uint32_t halo_cap;       // LDS records staged per work item (neighbour loops)
+    uint32_t mirror;         // some case has a symmetric axis: the image-aware kernels run
+    int32_t model;           // NAUTICLE_MODEL_*, shared by all cases
     Layout L;
     // host copies (for launches that need per-case sizes)
     const CaseDev* host_cases;
@@ -145,8 +160,9 @@ inline T* at(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<cha
 
 inline Packed packed(const Plan& P, void* ws)
 {
-    return Packed{at<float4>(ws, P.L.pos4), at<float4>(ws, P.L.a4), at<float4>(ws, P.L.b4),
-                  at<float4>(ws, P.L.adj4), at<float4>(ws, P.L.adj4b), at<uint32_t>(ws, P.L.cell_first)};
+    return Packed{at<float4>(ws, P.L.pos4),  at<float4>(ws, P.L.a4),    at<float4>(ws, P.L.b4),
+                  at<float4>(ws, P.L.adj4),  at<float4>(ws, P.L.adj4b), at<uint32_t>(ws, P.L.cell_first),
+                  P.L.vr4 ? at<float4>(ws, P.L.vr4) : nullptr};
 }
 
 // How a neighbour-loop kernel finds its work items.
@@ -332,7 +348,13 @@ hipError_t launch_pack_fields(const Plan& P, void* ws, StateDev sorted, FieldsDe
 // writes the fields plus a4/b4 for the force pass
 hipError_t launch_density(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                           FieldsDev f, hipStream_t s);
-// forces read a4/b4 (written by density or launch_pack_fields)
+// continuity reads pos4 and vr4 (launch_pack_continuity) and writes the
+// fields plus a4/b4 for the force pass
+hipError_t launch_pack_continuity(const Plan& P, void* ws, StateDev sorted, hipStream_t s);
+hipError_t launch_continuity(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
+                             FieldsDev f, hipStream_t s);
+// forces read a4/b4 (written by density, continuity or launch_pack_fields);
+// the viscous term follows the plan's model
 hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                          FieldsDev f, const StateDev* next, hipStream_t s);
 // adjoint.hip

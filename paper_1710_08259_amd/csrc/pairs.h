@@ -33,6 +33,45 @@ __device__ inline float3 pair_d(const float4& sh, float ojx, float ojy, float oj
     return make_float3(ojx - (oix - sh.x), ojy - (oiy - sh.y), ojz - (oiz - sh.z));
 }
 
+// ---- symmetric faces ------------------------------------------------------------
+// An entry with offset code kMirrorCode along axis k is the mirror image of
+// the neighbour in a symmetric face of the particle's own boundary cell.
+// Along k the particle moves by 0 cells (lower face) or 2 cells (upper
+// face), which its cell decides, and the neighbour's offset and velocity
+// change sign (the image's normal velocity is reversed: free slip).
+struct ImageFrame {
+    float shift[3];  // 0 or 2 cs per axis; read for image axes only
+};
+
+__device__ inline ImageFrame image_frame(const CaseDev& C, uint32_t cell)
+{
+    int32_t c[3];
+    cell_coords(C, cell, c);
+    ImageFrame M;
+    for (int k = 0; k < 3; ++k) M.shift[k] = c[k] == 0 ? 0.0f : 2.0f * C.cs[k];
+    return M;
+}
+
+// pair_d for an entry that may be an image: d_k = fl32(sg_k off_j,k - t_k),
+// t_k = fl32(off_i,k - shift_k), sg_k = -1 along image axes (negation is
+// exact, so this is the search predicate's arithmetic); sg receives the
+// signs for the neighbour's velocity.  Without image axes the values equal
+// pair_d's.
+__device__ inline float3 pair_d_img(const float4& sh, uint32_t code, const ImageFrame& M, float ojx, float ojy,
+                                    float ojz, float oix, float oiy, float oiz, float3* sg)
+{
+#pragma clang fp contract(off)
+    const bool ix = (code & 3u) == kMirrorCode;
+    const bool iy = ((code >> 2) & 3u) == kMirrorCode;
+    const bool iz = ((code >> 4) & 3u) == kMirrorCode;
+    const float sx = ix ? -1.0f : 1.0f, sy = iy ? -1.0f : 1.0f, sz = iz ? -1.0f : 1.0f;
+    const float tx = oix - (ix ? M.shift[0] : sh.x);
+    const float ty = oiy - (iy ? M.shift[1] : sh.y);
+    const float tz = oiz - (iz ? M.shift[2] : sh.z);
+    *sg = make_float3(sx, sy, sz);
+    return make_float3(__builtin_fmaf(sx, ojx, -tx), __builtin_fmaf(sy, ojy, -ty), __builtin_fmaf(sz, ojz, -tz));
+}
+
 __device__ inline float pair_r2(const float3& d, int dim)
 {
     float r2 = __builtin_fmaf(d.y, d.y, d.x * d.x);
@@ -170,15 +209,23 @@ __device__ inline float density_term(float r2, float inv_h)
 
 // Sum of the kernel terms of sorted particle i (offsets `me`) over its first
 // cnt list entries; gather(e, v) puts the neighbour's offsets in v[0].
+// kMirror: entries may be images (frame M).
 // (G pairs per pipeline stage: the order of the sum does not depend on it.)
-template <int DIM, uint32_t G = kDensityGroup, typename Gather>
-__device__ inline float density_sum(const CaseDev& C, const ShiftTable& tab, uint32_t i, const float4& me,
-                                    const uint32_t* __restrict__ nbr, uint32_t cnt, uint32_t n_total, Gather&& gather)
+template <int DIM, bool kMirror, uint32_t G = kDensityGroup, typename Gather>
+__device__ inline float density_sum(const CaseDev& C, const ShiftTable& tab, const ImageFrame& M, uint32_t i,
+                                    const float4& me, const uint32_t* __restrict__ nbr, uint32_t cnt, uint32_t n_total,
+                                    Gather&& gather)
 {
     const float inv_h = C.inv_h;
     float sum = 0.0f;
     walk_pairs<G, 1>(nbr, i, cnt, n_total, DIM, gather, [&](uint32_t, const float4* v, uint32_t code) {
-        const float3 d = pair_d(tab.v[code], v[0].x, v[0].y, v[0].z, me.x, me.y, me.z);
+        float3 d;
+        if constexpr (kMirror) {
+            float3 sg;
+            d = pair_d_img(tab.v[code], code, M, v[0].x, v[0].y, v[0].z, me.x, me.y, me.z, &sg);
+        } else {
+            d = pair_d(tab.v[code], v[0].x, v[0].y, v[0].z, me.x, me.y, me.z);
+        }
         sum = __fadd_rn(sum, density_term(pair_r2(d, DIM), inv_h));  // + 0 for padding pairs
     });
     return sum;

@@ -322,6 +322,7 @@ k_reorder(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uin
     const uint32_t cell = in.cell[q];
     out.cell[p] = cell;
     out.id[p] = in.id[q];
+    if (in.rho) out.rho[p] = in.rho[q];
     float o[3] = {0.0f, 0.0f, 0.0f};
     for (int k = 0; k < 3; ++k) {
         if (k >= C.dim) break;
@@ -421,6 +422,49 @@ __device__ inline uint32_t test_group(const float4* o, float cref, float mex, fl
     return bits;
 }
 
+// The same test for a piece of mirror images: along an axis with sign -1
+// the candidate's offset is negated, d = fl(-off_j - t) (negation is exact),
+// and a mirrored x piece (one boundary cell) takes cref = c_x - delta, delta
+// 0 at the lower face and 2 at the upper one.  With every sign +1 this is
+// test_group's arithmetic.
+template <int DIM>
+__device__ inline uint32_t test_group_img(const float4* o, float cref, float mex, float csx, float ty, float tz,
+                                          float R2, float sx, float sy, float sz)
+{
+#pragma clang fp contract(off)
+    uint32_t bits = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+        const float tx = __builtin_fmaf(cref - o[u].w, csx, mex);
+        const float ddx = __builtin_fmaf(sx, o[u].x, -tx);
+        const float ddy = __builtin_fmaf(sy, o[u].y, -ty);
+        float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
+        if constexpr (DIM == 3) {
+            const float ddz = __builtin_fmaf(sz, o[u].z, -tz);
+            r2 = __builtin_fmaf(ddz, ddz, r2);
+        }
+        bits |= r2 < R2 ? (1u << u) : 0u;
+    }
+    return bits;
+}
+
+// Hit mask of the candidates q0 .. q0 + m - 1 (m <= 64) of a mirrored piece,
+// read from `src` (a plain loop: such pieces are the few cells along a
+// symmetric face).
+template <int DIM>
+__device__ inline uint64_t scan_chunk_img(const float4* src, uint32_t m, float cref, float mex, float csx, float ty,
+                                          float tz, float R2, float sx, float sy, float sz)
+{
+    uint64_t hits = 0;
+    for (uint32_t b = 0; b < m; b += kUnroll) {
+        float4 o[kUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) o[u] = src[b + u];
+        hits |= static_cast<uint64_t>(test_group_img<DIM>(o, cref, mex, csx, ty, tz, R2, sx, sy, sz)) << b;
+    }
+    return hits;
+}
+
 // Hit mask of the candidates q0 .. q0 + m - 1 (m <= 64) read from `src`
 // (src[k] = candidate q0 + k; readable up to 2 kUnroll - 1 past m).  Two
 // groups per iteration in ping-pong registers: group A is tested while group
@@ -448,7 +492,12 @@ __device__ inline uint64_t scan_chunk(const float4* src, uint32_t m, float cref,
     return hits;
 }
 
-template <int DIM>
+// kMirror: the case may have symmetric faces.  A stencil cell beyond such a
+// face stands for the mirror image of the particle's own boundary cell: its
+// rows (y, z) or its piece (x) are the boundary cell's particles with the
+// offsets along that axis negated, entered with offset code kMirrorCode; the
+// particle's own image is a neighbour like any other.
+template <int DIM, bool kMirror>
 __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev st, const float4* __restrict__ pos4,
                                       const HaloRows& H, const float4* halo,
                                       const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
@@ -477,59 +526,95 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
     constexpr int kZ = DIM == 3 ? 1 : 0;
     for (int dz = -kZ; dz <= kZ; ++dz) {
         int32_t cz = c[2] + dz;
+        bool mz = false;  // this plane is the mirror image of the particle's own
         if constexpr (DIM == 3) {
-            if (C.periodic[2]) cz = cz < 0 ? cz + C.nc[2] : (cz >= C.nc[2] ? cz - C.nc[2] : cz);
-            else if (cz < 0 || cz >= C.nc[2]) continue;
+            if (C.periodic[2]) {
+                cz = cz < 0 ? cz + C.nc[2] : (cz >= C.nc[2] ? cz - C.nc[2] : cz);
+            } else if (cz < 0 || cz >= C.nc[2]) {
+                if (!kMirror || !C.mirror[2]) continue;
+                cz = c[2];
+                mz = true;
+            }
         }
-        const float tz = me.z - static_cast<float>(dz) * C.cs[2];
+        // the particle's shift: delta cells, or 0 / 2 cells against a lower /
+        // upper face for an image plane
+        const float tz = me.z - static_cast<float>(mz ? (dz < 0 ? 0 : 2) : dz) * C.cs[2];
         for (int dy = -1; dy <= 1; ++dy) {
             int32_t cy = c[1] + dy;
-            if (C.periodic[1]) cy = cy < 0 ? cy + C.nc[1] : (cy >= C.nc[1] ? cy - C.nc[1] : cy);
-            else if (cy < 0 || cy >= C.nc[1]) continue;
+            bool my = false;
+            if (C.periodic[1]) {
+                cy = cy < 0 ? cy + C.nc[1] : (cy >= C.nc[1] ? cy - C.nc[1] : cy);
+            } else if (cy < 0 || cy >= C.nc[1]) {
+                if (!kMirror || !C.mirror[1]) continue;
+                cy = c[1];
+                my = true;
+            }
             const uint32_t row = C.cell_base + static_cast<uint32_t>(nx) *
                                                    (static_cast<uint32_t>(cy) + static_cast<uint32_t>(C.nc[1]) * static_cast<uint32_t>(cz));
-            const float ty = me.y - static_cast<float>(dy) * C.cs[1];
-            // the row's x span [c-1, c+1] as up to two contiguous pieces of cells
+            const float ty = me.y - static_cast<float>(my ? (dy < 0 ? 0 : 2) : dy) * C.cs[1];
+            // the row's x span [c-1, c+1] as up to two contiguous pieces of
+            // cells; the second is the wrapped cell of a periodic x axis or
+            // the image of the boundary cell of a symmetric one
             int32_t lo0 = c[0] - 1, hi0 = c[0] + 1, lo1 = 0, hi1 = -1;
+            bool mx1 = false;    // piece 1 is an image piece
+            int32_t dimg = 0;    // its shift in cells: 0 (lower face) or 2 (upper)
             if (px) {
                 if (lo0 < 0) { lo1 = nx - 1; hi1 = nx - 1; lo0 = 0; }
                 if (hi0 >= nx) { lo1 = 0; hi1 = 0; hi0 = nx - 1; }
             } else {
-                if (lo0 < 0) lo0 = 0;
-                if (hi0 >= nx) hi0 = nx - 1;
+                const bool img = kMirror && C.mirror[0];
+                if (lo0 < 0) {
+                    lo0 = 0;
+                    if (img) { lo1 = 0; hi1 = 0; mx1 = true; dimg = 0; }
+                }
+                if (hi0 >= nx) {
+                    hi0 = nx - 1;
+                    if (img) { lo1 = nx - 1; hi1 = nx - 1; mx1 = true; dimg = 2; }
+                }
             }
-            const uint32_t code_yz = (static_cast<uint32_t>(dy + 1) << (NAUTICLE_NBR_INDEX_BITS + 2)) |
-                                     (static_cast<uint32_t>(dz + 1) << (NAUTICLE_NBR_INDEX_BITS + 4));
+            const uint32_t code_yz = ((my ? kMirrorCode : static_cast<uint32_t>(dy + 1)) << (NAUTICLE_NBR_INDEX_BITS + 2)) |
+                                     ((mz ? kMirrorCode : static_cast<uint32_t>(dz + 1)) << (NAUTICLE_NBR_INDEX_BITS + 4));
             for (int piece = 0; piece < 2; ++piece) {
                 const int32_t xa = piece == 0 ? lo0 : lo1;
                 const int32_t xb = piece == 0 ? hi0 : hi1;
                 if (xb < xa) continue;
+                const bool mx = piece == 1 && mx1;
                 const uint32_t q_begin = min(cell_first[row + static_cast<uint32_t>(xa)], n_total);
                 const uint32_t q_end = min(cell_first[row + static_cast<uint32_t>(xb) + 1], n_total);
                 // cell x offset of the piece's first cell, where its next cells
                 // start, and the particle's x in each of those cells' frames
+                // (an image piece is one cell: code kMirrorCode = dx0 + 1)
                 int32_t dx0 = xa - c[0];
-                if (dx0 > 1) dx0 -= nx;
+                if (mx) dx0 = static_cast<int32_t>(kMirrorCode) - 1;
+                else if (dx0 > 1) dx0 -= nx;
                 else if (dx0 < -1) dx0 += nx;
                 const uint32_t b1 = xa + 1 <= xb ? cell_first[row + static_cast<uint32_t>(xa) + 1] : q_end;
                 const uint32_t b2 = xa + 2 <= xb ? cell_first[row + static_cast<uint32_t>(xa) + 2] : q_end;
                 // candidate cell x index - cref = delta_x (the wrapped piece's
-                // single cell included)
-                const float cref = static_cast<float>(xa - dx0);
-                // the piece from LDS when it lies in the row's staged range
-                const uint32_t hr = halo_row<DIM>(dy, dz);
+                // single cell included); for an image piece, -(its shift)
+                const float cref = static_cast<float>(mx ? c[0] - dimg : xa - dx0);
+                const bool image = mx || my || mz;
+                // the piece from LDS when it lies in the staged range of the
+                // row that holds its cells
+                const uint32_t hr = halo_row<DIM>(my ? 0 : dy, mz ? 0 : dz);
                 const bool staged = q_begin >= H.lo[hr] && q_end <= H.hi[hr];
                 const int32_t hshift = H.shift[hr];
                 for (uint32_t q0 = q_begin; q0 < q_end; q0 += 64) {
                     const uint32_t m = min(q_end - q0, 64u);
-                    const uint64_t hits_all =
-                        staged ? scan_chunk<DIM>(halo + (static_cast<int32_t>(q0) + hshift), m, cref, me.x, csx, ty,
-                                                 tz, R2)
-                               : scan_chunk<DIM>(pos4 + q0, m, cref, me.x, csx, ty, tz, R2);
+                    const float4* src = staged ? halo + (static_cast<int32_t>(q0) + hshift) : pos4 + q0;
+                    uint64_t hits_all;
+                    if (kMirror && image)
+                        hits_all = scan_chunk_img<DIM>(src, m, cref, me.x, csx, ty, tz, R2, mx ? -1.0f : 1.0f,
+                                                       my ? -1.0f : 1.0f, mz ? -1.0f : 1.0f);
+                    else
+                        hits_all = staged ? scan_chunk<DIM>(halo + (static_cast<int32_t>(q0) + hshift), m, cref, me.x,
+                                                            csx, ty, tz, R2)
+                                          : scan_chunk<DIM>(pos4 + q0, m, cref, me.x, csx, ty, tz, R2);
                     uint64_t hits = hits_all;
                     // drop candidates past the piece and the particle itself
+                    // (its own image stays)
                     if (m < 64) hits &= (uint64_t{1} << m) - 1u;
-                    if (p - q0 < 64u) hits &= ~(uint64_t{1} << (p - q0));
+                    if (p - q0 < 64u && !(kMirror && image)) hits &= ~(uint64_t{1} << (p - q0));
                     // entry of candidate q0 + b: the index plus the piece's first-cell
                     // code (the fields do not overlap), plus one x step per cell
                     // boundary at or before it
@@ -568,7 +653,7 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
     if (cnt > max_nbr) set_error(err, kErrOverflow);
 }
 
-template <int DIM>
+template <int DIM, bool kMirror>
 __global__ void __launch_bounds__(kMaxBlock)
 k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
         const float4* __restrict__ pos4, const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
@@ -583,7 +668,8 @@ k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
         halo_plan<DIM>(C, it, st.cell, cell_first, n_total, halo_cap, &s_rows);
         halo_copy<DIM>(s_rows, pos4, s_halo);
         if (threadIdx.x < it.count)
-            nlist_particle<DIM>(C, it, st, pos4, s_rows, s_halo, cell_first, nbr, nbr_count, max_nbr, n_total, err);
+            nlist_particle<DIM, kMirror>(C, it, st, pos4, s_rows, s_halo, cell_first, nbr, nbr_count, max_nbr,
+                                         n_total, err);
         __syncthreads();  // the next item's staging overwrites the LDS
     });
 }
@@ -648,12 +734,10 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     const uint32_t mx = static_cast<uint32_t>(cells.max_nbr);
     const uint32_t cap = halo_records(P.halo_cap, 1, kHaloBytes);
     const size_t lds = sizeof(float4) * (cap + kHaloPad);
-    if (P.dim_max == 3)
-        k_nlist<3><<<grid_for(P), P.block, lds, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
-                                                     cells.nbr_count, mx, n, cap, err);
-    else
-        k_nlist<2><<<grid_for(P), P.block, lds, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
-                                                     cells.nbr_count, mx, n, cap, err);
+    auto kern = P.dim_max == 3 ? (P.mirror ? k_nlist<3, true> : k_nlist<3, false>)
+                               : (P.mirror ? k_nlist<2, true> : k_nlist<2, false>);
+    kern<<<grid_for(P), P.block, lds, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
+                                           cells.nbr_count, mx, n, cap, err);
     return hipGetLastError();
 }
 

@@ -28,12 +28,17 @@ ERR_HIP = -6
 ERR_NEIGHBOUR_OVERFLOW = -7
 PERIODIC = 0
 CUTOFF = 1
+SYMMETRIC = 2
+MODEL_SUMMATION = 0
+MODEL_CONTINUITY = 1
+MIRROR_CODE = 3
 EMPTY = 0xFFFFFFFF
 NBR_INDEX_BITS = 26
 
 ENTRY_POINTS = (
     "nauticle_cells_total", "nauticle_workspace_bytes", "nauticle_prepare", "nauticle_bin",
-    "nauticle_unbin", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_forces",
+    "nauticle_unbin", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_continuity",
+    "nauticle_sph_forces",
     "nauticle_step", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
     "nauticle_last_error",
 )
@@ -57,7 +62,8 @@ class CDomain(ctypes.Structure):
 class CParams(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("mass", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("c0", ctypes.c_double), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
-                ("dt", ctypes.c_double), ("g", ctypes.c_double * 3)]
+                ("dt", ctypes.c_double), ("g", ctypes.c_double * 3), ("alpha_av", ctypes.c_double),
+                ("model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CCase(ctypes.Structure):
@@ -67,7 +73,7 @@ class CCase(ctypes.Structure):
 
 class CState(ctypes.Structure):
     _fields_ = [("cell", ctypes.c_void_p), ("off", ctypes.c_void_p * 3), ("vel", ctypes.c_void_p * 3),
-                ("id", ctypes.c_void_p)]
+                ("id", ctypes.c_void_p), ("rho", ctypes.c_void_p)]
 
 
 class CCells(ctypes.Structure):
@@ -97,7 +103,7 @@ class Tuning:
 
 class CFields(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_void_p), ("p", ctypes.c_void_p), ("s", ctypes.c_void_p),
-                ("inv_rho", ctypes.c_void_p), ("acc", ctypes.c_void_p * 3)]
+                ("inv_rho", ctypes.c_void_p), ("acc", ctypes.c_void_p * 3), ("drho", ctypes.c_void_p)]
 
 
 _lib = None
@@ -129,6 +135,9 @@ def lib():
     L.nauticle_build_cells.argtypes = [P(CCase), i32, P(CState), P(CState), P(CCells), vp, ctypes.c_size_t, vp]
     L.nauticle_sph_density.restype = st
     L.nauticle_sph_density.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CFields), vp, ctypes.c_size_t, vp]
+    L.nauticle_sph_continuity.restype = st
+    L.nauticle_sph_continuity.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CFields), vp, ctypes.c_size_t,
+                                          vp]
     L.nauticle_sph_forces.restype = st
     L.nauticle_sph_forces.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CFields), P(CState), vp,
                                       ctypes.c_size_t, vp]
@@ -178,6 +187,7 @@ class State:
     off: list                   # dim x float32
     vel: list                   # dim x float32
     id: torch.Tensor            # int32
+    rho: Optional[torch.Tensor] = None  # float32, the continuity model's evolved density
 
     def c(self) -> CState:
         s = CState()
@@ -186,15 +196,18 @@ class State:
         for k in range(3):
             s.off[k] = self.off[k].data_ptr() if k < len(self.off) else None
             s.vel[k] = self.vel[k].data_ptr() if k < len(self.vel) else None
+        s.rho = self.rho.data_ptr() if self.rho is not None else None
         return s
 
     def clone(self) -> "State":
         return State(self.cell.clone(), [t.clone() for t in self.off], [t.clone() for t in self.vel],
-                     self.id.clone())
+                     self.id.clone(), None if self.rho is None else self.rho.clone())
 
     def copy_(self, other: "State") -> "State":
         self.cell.copy_(other.cell)
         self.id.copy_(other.id)
+        if self.rho is not None and other.rho is not None:
+            self.rho.copy_(other.rho)
         for a, b in zip(self.off, other.off):
             a.copy_(b)
         for a, b in zip(self.vel, other.vel):
@@ -233,6 +246,7 @@ class Fields:
     s: torch.Tensor
     inv_rho: torch.Tensor
     acc: list
+    drho: Optional[torch.Tensor] = None
 
     def c(self) -> CFields:
         f = CFields()
@@ -240,6 +254,7 @@ class Fields:
                                       self.inv_rho.data_ptr())
         for k in range(3):
             f.acc[k] = self.acc[k].data_ptr() if k < len(self.acc) else None
+        f.drho = self.drho.data_ptr() if self.drho is not None else None
         return f
 
 
@@ -260,6 +275,9 @@ def case_table(cases) -> "ctypes.Array":
         p.gamma, p.nu, p.dt = c.gamma, c.nu, c.dt
         for k in range(3):
             p.g[k] = float(c.g[k])
+        p.alpha_av = float(getattr(c, "alpha_av", 0.0))
+        p.model = int(getattr(c, "model", MODEL_SUMMATION))
+        p.reserved = 0
         arr[b].offset = offset
         arr[b].n = c.n
         arr[b].n_fixed = c.n_fixed
@@ -287,6 +305,7 @@ class Problem:
         self.tuning = tuning or Tuning()
         self.device = torch.device(device)
         self.dim = self.cases[0].dim
+        self.model = int(getattr(self.cases[0], "model", MODEL_SUMMATION))
         self.table = case_table(self.cases)
         self.n_cases = len(self.cases)
         self.n = int(sum(c.n for c in self.cases))
@@ -305,8 +324,7 @@ class Problem:
         self.cells = Cells(torch.empty(N, **i32), torch.empty(N, **i32),
                            torch.empty(max(self.n_cells, 1), **i32), torch.empty(max(self.n_cells, 1), **i32),
                            torch.empty(_list_shape(self.max_nbr, N), **i32), torch.empty(N, **i32), self.max_nbr)
-        self.fields = Fields(torch.empty(N, **f32), torch.empty(N, **f32), torch.empty(N, **f32),
-                             torch.empty(N, **f32), [torch.empty(N, **f32) for _ in range(self.dim)])
+        self.fields = self.new_fields()
         self.sorted = self.new_state()
 
     # -- helpers ----------------------------------------------------------------
@@ -317,8 +335,9 @@ class Problem:
         N = max(self.n, 1)
         i32 = dict(dtype=torch.int32, device=self.device)
         f32 = dict(dtype=torch.float32, device=self.device)
+        rho = torch.zeros(N, **f32) if self.model == MODEL_CONTINUITY else None
         return State(torch.zeros(N, **i32), [torch.zeros(N, **f32) for _ in range(self.dim)],
-                     [torch.zeros(N, **f32) for _ in range(self.dim)], torch.zeros(N, **i32))
+                     [torch.zeros(N, **f32) for _ in range(self.dim)], torch.zeros(N, **i32), rho)
 
     def _ws(self):
         return _p(self.ws), self.ws_bytes, self.stream()
@@ -336,13 +355,19 @@ class Problem:
         return st
 
     def state_from_cases(self) -> State:
-        """Bins the cases' own positions and velocities (walls get v = 0)."""
+        """Bins the cases' own positions and velocities (walls get v = 0);
+        with the continuity model also their densities (rho0 if none)."""
         pos = np.concatenate([c.pos for c in self.cases], axis=0)
         vel = np.concatenate([np.where(c.fixed_mask()[:, None], 0.0, c.vel).astype(np.float32)
                               for c in self.cases], axis=0)
         pos_t = [torch.from_numpy(np.ascontiguousarray(pos[:, k])).to(self.device) for k in range(self.dim)]
         vel_t = [torch.from_numpy(np.ascontiguousarray(vel[:, k])).to(self.device) for k in range(self.dim)]
-        return self.bin(pos_t, vel_t)
+        st = self.bin(pos_t, vel_t)
+        if st.rho is not None:
+            rho = np.concatenate([c.rho if getattr(c, "rho", None) is not None
+                                  else np.full(c.n, c.rho0, np.float32) for c in self.cases]).astype(np.float32)
+            st.rho[: self.n].copy_(torch.from_numpy(rho))
+        return st
 
     def unbin(self, st: State) -> list:
         pos = [torch.empty(max(self.n, 1), dtype=torch.float32, device=self.device) for _ in range(self.dim)]
@@ -364,6 +389,15 @@ class Problem:
         f = self.fields if fields is None else fields
         _check(lib().nauticle_sph_density(self.table, self.n_cases, ctypes.byref(s.c()), ctypes.byref(c.c()),
                                           ctypes.byref(f.c()), *self._ws()), "nauticle_sph_density")
+        return f
+
+    def continuity(self, sorted_: Optional[State] = None, cells: Optional[Cells] = None,
+                   fields: Optional[Fields] = None):
+        s = self.sorted if sorted_ is None else sorted_
+        c = self.cells if cells is None else cells
+        f = self.fields if fields is None else fields
+        _check(lib().nauticle_sph_continuity(self.table, self.n_cases, ctypes.byref(s.c()), ctypes.byref(c.c()),
+                                             ctypes.byref(f.c()), *self._ws()), "nauticle_sph_continuity")
         return f
 
     def forces(self, sorted_: Optional[State] = None, next_: Optional[State] = None,
@@ -424,8 +458,9 @@ class Problem:
     def new_fields(self) -> Fields:
         f32 = dict(dtype=torch.float32, device=self.device)
         N = max(self.n, 1)
+        drho = torch.empty(N, **f32) if self.model == MODEL_CONTINUITY else None
         return Fields(torch.empty(N, **f32), torch.empty(N, **f32), torch.empty(N, **f32), torch.empty(N, **f32),
-                      [torch.empty(N, **f32) for _ in range(self.dim)])
+                      [torch.empty(N, **f32) for _ in range(self.dim)], drho)
 
 
 def to_numpy_u32(t: torch.Tensor) -> np.ndarray:

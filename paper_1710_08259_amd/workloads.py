@@ -189,6 +189,37 @@ def ex1a_dam_break(scale: float = 1.0, name: str = "") -> Case:
                 rho=np.full(n, rho0, np.float32))
 
 
+def mirror_box_case(dim, boundary, seed, n=2000, ncell=(12, 10, 8), h=0.02, model=SUMMATION,
+                    v_sigma=0.5, rho_sigma=0.02, name="") -> Case:
+    """Random particles in a box with (some) symmetric faces, crowded near
+    the faces and corners: about a fifth of them within 2h of a face, a few
+    exactly on the lower x face.  Cells of edge 2.14h; velocities N(0,
+    v_sigma); with the continuity model, densities rho0 (1 + N(0, rho_sigma)).
+    Particle volume (0.8 h)^dim."""
+    rng = np.random.default_rng(seed)
+    nc = tuple(int(c) for c in ncell[:dim]) + (1,) * (3 - dim)
+    cs = tuple(_f32(2.0 * h * 1.07) for _ in range(dim)) + (1.0,) * (3 - dim)
+    L = np.array([nc[k] * cs[k] for k in range(3)])
+    x = rng.uniform(0, 1, (n, dim)) * L[:dim]
+    near = rng.random(n) < 0.35
+    for k in range(dim):
+        side = rng.random(n) < 0.5
+        d = rng.uniform(0, 2.0 * h, n)
+        pick = near & (rng.random(n) < 0.6)
+        x[pick & side, k] = d[pick & side]
+        x[pick & ~side, k] = L[k] - d[pick & ~side]
+    x[:3, 0] = 0.0
+    x = np.minimum(x, np.nextafter(L[:dim].astype(np.float32), np.float32(0)))
+    rho0 = 1000.0
+    rho = (rho0 * (1.0 + rho_sigma * rng.standard_normal(n))).astype(np.float32) if model == CONTINUITY else None
+    return Case(dim=dim, ncell=nc, cell_size=cs, origin=(0.0, 0.0, 0.0), boundary=tuple(boundary), h=h,
+                mass=rho0 * (0.8 * h) ** dim, rho0=rho0, c0=20.0, gamma=7.0 if model == SUMMATION else 1.0,
+                nu=1e-3 if model == SUMMATION else 0.0, dt=1e-4, g=(0.0, -9.81, 0.0),
+                pos=x.astype(np.float32), vel=rng.normal(0.0, v_sigma, (n, dim)).astype(np.float32),
+                n_fixed=0, name=name or f"mirror_box_{dim}d_{seed}", model=model,
+                alpha_av=0.1 if model == CONTINUITY else 0.0, rho=rho)
+
+
 # ---------------------------------------------------------------------------
 # the named workloads
 # ---------------------------------------------------------------------------

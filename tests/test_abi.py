@@ -111,3 +111,31 @@ def test_invalid_tuning_is_rejected_on_the_host(N):
     table = N.case_table([WL.periodic_2d_4096()])
     for bad in (N.Tuning(block=96), N.Tuning(persistent=2), N.Tuning(persistent=1, groups_per_cu=100)):
         assert N.lib().nauticle_prepare(table, 1, ctypes.byref(bad.c()), None, 0, None) == N.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda c: WL.scaled(c, ncell=(1, c.ncell[1], 1)), -2),            # symmetric axis < 2 cells
+    (lambda c: WL.scaled(c, model=7), -1),                            # unknown model
+    (lambda c: WL.scaled(c, alpha_av=-0.1), -1),                      # negative artificial viscosity
+    (lambda c: WL.scaled(c, alpha_av=float("inf")), -1),
+])
+def test_invalid_symmetric_and_continuity_cases_are_rejected(N, mutate, status):
+    base = WL.ex1a_dam_break()
+    assert _ws_bytes(N, [base])[0] == N.OK
+    st, _ = _ws_bytes(N, [mutate(base)])
+    assert st == status
+    assert len(N.lib().nauticle_last_error()) > 0
+
+
+def test_cases_of_one_table_share_one_model(N):
+    a = WL.ex1a_dam_break()
+    b = WL.scaled(a, model=WL.SUMMATION)
+    assert _ws_bytes(N, [a, a])[0] == N.OK
+    assert _ws_bytes(N, [a, b])[0] == N.ERR_INVALID_ARG
+
+
+def test_continuity_model_workspace_holds_the_extra_arrays(N):
+    a = WL.ex1a_dam_break()
+    b = WL.scaled(a, model=WL.SUMMATION)
+    # one float4 per particle more (the start-of-step velocity and density)
+    assert _ws_bytes(N, [a])[1] >= _ws_bytes(N, [b])[1] + 16 * a.n
