@@ -80,6 +80,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="only the main workload")
     ap.add_argument("--cpu-sample", default="128x128x64", help="oracle sample box (lattice sites per axis)")
+    ap.add_argument("--ex1a-only", action="store_true",
+                    help="only the Example 1a dam break (continuity model, symmetric faces)")
+    ap.add_argument("--ex1a-scale", type=float, default=87.0,
+                    help="resolution factor of the Example 1a dam break (87: 4.1M particles)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy run before timing (counter calibration runs)")
     return ap.parse_args()
@@ -264,6 +268,39 @@ def dam_break_extra(device, steps=10):
             "interactions_per_s": pairs / wall, "ms_per_step": wall * 1e3 / steps}
 
 
+def ex1a_extra(device, scale, steps=10, warmup=2):
+    """Example 1a's 2-D dam break (continuity, linear EOS, artificial
+    viscosity, symmetric faces), refined by `scale`, from rest; next to it
+    the FP64 oracle's step on the paper's own 558-particle column."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
+
+    case = WL.ex1a_dam_break(scale)
+    prob = N.Problem([case], device=device)
+    st = prob.state_from_cases()
+    wall, phase, pairs = timed_steps(prob, st, steps, warmup)
+    del prob, st
+    small = WL.ex1a_dam_break(1.0)
+    dom = O.Domain(dim=2, n=small.ncell, cs=small.cell_size, origin=small.origin, periodic=(False,) * 3,
+                   symmetric=(True, True, False))
+    prm = O.Params(h=small.h, mass=small.mass, rho0=small.rho0, c0=small.c0, gamma=small.gamma, nu=small.nu,
+                   dt=small.dt, g=small.g, alpha_av=small.alpha_av)
+    x = small.pos.astype(np.float64)
+    k_or = 20
+    t0 = time.perf_counter()
+    O.step_ex1a(dom, prm, x, np.zeros_like(x), small.rho.astype(np.float64), n_steps=k_or, nthreads=1)
+    t_or = (time.perf_counter() - t0) / k_or
+    return {"workload": case.name, "particles": case.n, "cells": list(case.ncell), "scale": scale,
+            "steps_per_s": steps / wall, "ms_per_step": round(wall * 1e3 / steps, 4),
+            "interactions_per_s": pairs / wall, "neighbours_per_particle": round(pairs / steps / case.n, 2),
+            "phases": {"sort_reorder_ms": round(phase[0], 4), "neighbour_lists_ms": round(phase[1], 4),
+                       "continuity_ms": round(phase[2], 4), "momentum_integrate_ms": round(phase[3], 4)},
+            "oracle_paper_case": {"particles": small.n, "ms_per_step": round(t_or * 1e3, 3), "cores": 1}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -276,6 +313,10 @@ def main():
     from paper_1710_08259_amd import workloads as WL
 
     device = "cuda:0"
+    if args.ex1a_only:
+        print(json.dumps({"extra": {"ex1a": ex1a_extra(device, args.ex1a_scale, args.steps, args.warmup)}}),
+              flush=True)
+        return
     if args.calibrate_copy:
         nb = args.calibrate_copy << 20
         a = torch.empty(nb // 4, dtype=torch.float32, device=device).fill_(1.0)
@@ -327,6 +368,8 @@ def main():
         line["extra"]["batched"] = batched_extra(device)
         torch.cuda.empty_cache()
         line["extra"]["dam_break"] = dam_break_extra(device)
+        torch.cuda.empty_cache()
+        line["extra"]["ex1a"] = ex1a_extra(device, args.ex1a_scale)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args, case)
     print(json.dumps(line), flush=True)

@@ -174,6 +174,8 @@ def ex1a_dam_break(scale: float = 1.0, name: str = "") -> Case:
     h = 0.25 / scale
     dx = h / 1.1
     cs = _f32(2.0 * h)
+    if cs < 2.0 * h:  # never below the support in FP32
+        cs = float(np.nextafter(np.float32(cs), np.float32(np.inf)))
     ncell = (int(round(7.0 / h)), int(round(10.0 / h)), 1)
     nx = int(math.ceil(7.0 / dx - 0.5 - 1e-9))
     ny = int(math.ceil(4.0 / dx - 0.5 - 1e-9))
