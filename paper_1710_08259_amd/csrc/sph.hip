@@ -15,7 +15,12 @@
 
 namespace nau {
 
-constexpr uint32_t kForceGroup = 8;
+// Pairs per pipeline stage of the pair passes: 8 in 3-D (~57 neighbours per
+// particle); 4 in 2-D, where lists are short (~12-25 entries) and the
+// smaller stages leave registers for more resident waves to hide the
+// walk's latency.  The order of every sum does not depend on it.
+constexpr uint32_t kGroup3 = 8;
+constexpr uint32_t kGroup2 = 4;
 
 // ----------------------------------------------------------------------------
 // density + equation of state (arithmetic in pairs.h)
@@ -26,7 +31,7 @@ constexpr uint32_t kForceGroup = 8;
 // Also packs (offsets, s) and (velocity, 1/rho) for the force pass; fixed
 // particles get velocity 0 there.
 
-template <bool kMirror>
+template <bool kMirror, uint32_t G>
 __device__ inline void density_particle(const CaseDev& C, const ShiftTable& tab, uint32_t i, StateDev st,
                                         const float4* __restrict__ pos4, const uint32_t* __restrict__ nbr,
                                         const uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total,
@@ -39,12 +44,12 @@ __device__ inline void density_particle(const CaseDev& C, const ShiftTable& tab,
     if constexpr (kMirror) M = image_frame(C, min(st.cell[i], C.n_cells - 1));
     const __amdgpu_buffer_rsrc_t rpos = float4_rsrc(pos4, n_total);
     auto gather = [&](uint32_t e, float4* v) { v[0] = gather4(rpos, e); };
-    const float sum = C.dim == 3 ? density_sum<3, kMirror>(C, tab, M, i, me, nbr, cnt, n_total, gather)
-                                 : density_sum<2, kMirror>(C, tab, M, i, me, nbr, cnt, n_total, gather);
+    const float sum = C.dim == 3 ? density_sum<3, kMirror, G>(C, tab, M, i, me, nbr, cnt, n_total, gather)
+                                 : density_sum<2, kMirror, G>(C, tab, M, i, me, nbr, cnt, n_total, gather);
     density_finish(C, i, sum, me, st, f, a4, b4, err);
 }
 
-template <bool kMirror>
+template <bool kMirror, uint32_t G>
 __global__ void __launch_bounds__(kMaxBlock)
 k_density(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
           const float4* __restrict__ pos4, const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count,
@@ -58,8 +63,8 @@ k_density(const CaseDev* __restrict__ cases, const Item* __restrict__ items, Ite
         const CaseDev& C = cases[it.case_id];
         fill_shift_table(C, &tab);
         if (threadIdx.x < it.count)
-            density_particle<kMirror>(C, tab, it.first + threadIdx.x, st, pos4, nbr, nbr_count, max_nbr, n_total, f,
-                                      a4, b4, err);
+            density_particle<kMirror, G>(C, tab, it.first + threadIdx.x, st, pos4, nbr, nbr_count, max_nbr, n_total,
+                                         f, a4, b4, err);
     });
 }
 
@@ -71,7 +76,8 @@ hipError_t launch_density(const Plan& P, void* ws, StateDev sorted, const nautic
     ItemQueue Q;
     hipError_t e = item_queue(P, ws, 1, s, &Q);
     if (e != hipSuccess) return e;
-    auto kern = P.mirror ? k_density<true> : k_density<false>;
+    auto kern = P.dim_max == 3 ? (P.mirror ? k_density<true, kGroup3> : k_density<false, kGroup3>)
+                               : (P.mirror ? k_density<true, kGroup2> : k_density<false, kGroup2>);
     kern<<<grid_for(P), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), Q, sorted, pk.pos4,
                                          cells.nbr, cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), P.n_total,
                                          f, pk.a4, pk.b4, at<uint32_t>(ws, P.L.err));
@@ -116,9 +122,7 @@ hipError_t launch_pack_continuity(const Plan& P, void* ws, StateDev sorted, hipS
     return hipGetLastError();
 }
 
-constexpr uint32_t kContinuityGroup = 8;
-
-template <bool kMirror>
+template <bool kMirror, uint32_t G>
 __device__ inline void continuity_particle(const CaseDev& C, const ShiftTable& tab, uint32_t i, StateDev st,
                                            const float4* __restrict__ pos4, const float4* __restrict__ vr4,
                                            const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count,
@@ -135,7 +139,7 @@ __device__ inline void continuity_particle(const CaseDev& C, const ShiftTable& t
     if constexpr (kMirror) M = image_frame(C, min(st.cell[i], C.n_cells - 1));
     float sum = 0.0f;
     const __amdgpu_buffer_rsrc_t rp = float4_rsrc(pos4, n_total), rv = float4_rsrc(vr4, n_total);
-    walk_pairs<kContinuityGroup, 2>(
+    walk_pairs<G, 2>(
         nbr, i, cnt, n_total, dim,
         [&](uint32_t e, float4* v) {
             v[0] = gather4(rp, e);
@@ -171,7 +175,7 @@ __device__ inline void continuity_particle(const CaseDev& C, const ShiftTable& t
     if (!isfinite(rn) || !isfinite(drho)) set_error(err, kErrNonFinite);
 }
 
-template <bool kMirror>
+template <bool kMirror, uint32_t G>
 __global__ void __launch_bounds__(kMaxBlock)
 k_continuity(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
              const float4* __restrict__ pos4, const float4* __restrict__ vr4, const uint32_t* __restrict__ nbr,
@@ -185,7 +189,7 @@ k_continuity(const CaseDev* __restrict__ cases, const Item* __restrict__ items, 
         const CaseDev& C = cases[it.case_id];
         fill_shift_table(C, &tab);
         if (threadIdx.x < it.count)
-            continuity_particle<kMirror>(C, tab, it.first + threadIdx.x, st, pos4, vr4, nbr, nbr_count, max_nbr,
+            continuity_particle<kMirror, G>(C, tab, it.first + threadIdx.x, st, pos4, vr4, nbr, nbr_count, max_nbr,
                                          n_total, f, a4, b4, err);
     });
 }
@@ -198,7 +202,8 @@ hipError_t launch_continuity(const Plan& P, void* ws, StateDev sorted, const nau
     ItemQueue Q;
     hipError_t e = item_queue(P, ws, 1, s, &Q);
     if (e != hipSuccess) return e;
-    auto kern = P.mirror ? k_continuity<true> : k_continuity<false>;
+    auto kern = P.dim_max == 3 ? (P.mirror ? k_continuity<true, kGroup3> : k_continuity<false, kGroup3>)
+                               : (P.mirror ? k_continuity<true, kGroup2> : k_continuity<false, kGroup2>);
     kern<<<grid_for(P), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), Q, sorted, pk.pos4,
                                          pk.vr4, cells.nbr, cells.nbr_count, static_cast<uint32_t>(cells.max_nbr),
                                          P.n_total, f, pk.a4, pk.b4, at<uint32_t>(ws, P.L.err));
@@ -249,7 +254,7 @@ hipError_t launch_pack_fields(const Plan& P, void* ws, StateDev sorted, FieldsDe
 //     pair has w = 0: no term (the select never multiplies 0 by 1/0).
 // For an image neighbour (kMirror) v_j is the reflected velocity.
 
-template <bool kIntegrate, int kModel, bool kMirror>
+template <bool kIntegrate, int kModel, bool kMirror, uint32_t G>
 __device__ inline void forces_particle(const CaseDev& C, const ShiftTable& tab, uint32_t i, StateDev st,
                                        const float4* __restrict__ a4, const float4* __restrict__ b4,
                                        const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count,
@@ -268,7 +273,7 @@ __device__ inline void forces_particle(const CaseDev& C, const ShiftTable& tab, 
     if constexpr (kMirror) M = image_frame(C, min(st.cell[i], C.n_cells - 1));
     float ax = 0.0f, ay = 0.0f, az = 0.0f;
     const __amdgpu_buffer_rsrc_t ra = float4_rsrc(a4, n_total), rb = float4_rsrc(b4, n_total);
-    walk_pairs<kForceGroup, 2>(
+    walk_pairs<G, 2>(
         nbr, i, cnt, n_total, dim,
         [&](uint32_t e, float4* v) {
             v[0] = gather4(ra, e);
@@ -345,7 +350,7 @@ __device__ inline void forces_particle(const CaseDev& C, const ShiftTable& tab, 
     }
 }
 
-template <bool kIntegrate, int kModel, bool kMirror>
+template <bool kIntegrate, int kModel, bool kMirror, uint32_t G>
 __global__ void __launch_bounds__(kMaxBlock)
 k_forces(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
          const float4* __restrict__ a4, const float4* __restrict__ b4, const uint32_t* __restrict__ nbr,
@@ -359,9 +364,23 @@ k_forces(const CaseDev* __restrict__ cases, const Item* __restrict__ items, Item
         const CaseDev& C = cases[it.case_id];
         fill_shift_table(C, &tab);
         if (threadIdx.x < it.count)
-            forces_particle<kIntegrate, kModel, kMirror>(C, tab, it.first + threadIdx.x, st, a4, b4, nbr, nbr_count,
+            forces_particle<kIntegrate, kModel, kMirror, G>(C, tab, it.first + threadIdx.x, st, a4, b4, nbr, nbr_count,
                                                          max_nbr, n_total, f, next, err);
     });
+}
+
+using Kern = decltype(&k_forces<true, NAUTICLE_MODEL_SUMMATION, false, kGroup3>);
+
+// The force kernel for a plan: [integrate][model][mirror] at group size G.
+template <uint32_t G>
+Kern forces_kernel(const Plan& P, bool integrate)
+{
+    static const Kern table[2][2][2] = {
+        {{k_forces<false, NAUTICLE_MODEL_SUMMATION, false, G>, k_forces<false, NAUTICLE_MODEL_SUMMATION, true, G>},
+         {k_forces<false, NAUTICLE_MODEL_CONTINUITY, false, G>, k_forces<false, NAUTICLE_MODEL_CONTINUITY, true, G>}},
+        {{k_forces<true, NAUTICLE_MODEL_SUMMATION, false, G>, k_forces<true, NAUTICLE_MODEL_SUMMATION, true, G>},
+         {k_forces<true, NAUTICLE_MODEL_CONTINUITY, false, G>, k_forces<true, NAUTICLE_MODEL_CONTINUITY, true, G>}}};
+    return table[integrate ? 1 : 0][P.model == NAUTICLE_MODEL_CONTINUITY ? 1 : 0][P.mirror ? 1 : 0];
 }
 
 hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
@@ -376,14 +395,8 @@ hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticl
     ItemQueue Q;
     hipError_t e = item_queue(P, ws, 2, s, &Q);
     if (e != hipSuccess) return e;
-    using Kern = decltype(&k_forces<true, NAUTICLE_MODEL_SUMMATION, false>);
-    // [integrate][model][mirror]
-    static const Kern table[2][2][2] = {
-        {{k_forces<false, NAUTICLE_MODEL_SUMMATION, false>, k_forces<false, NAUTICLE_MODEL_SUMMATION, true>},
-         {k_forces<false, NAUTICLE_MODEL_CONTINUITY, false>, k_forces<false, NAUTICLE_MODEL_CONTINUITY, true>}},
-        {{k_forces<true, NAUTICLE_MODEL_SUMMATION, false>, k_forces<true, NAUTICLE_MODEL_SUMMATION, true>},
-         {k_forces<true, NAUTICLE_MODEL_CONTINUITY, false>, k_forces<true, NAUTICLE_MODEL_CONTINUITY, true>}}};
-    const Kern kern = table[next ? 1 : 0][P.model == NAUTICLE_MODEL_CONTINUITY ? 1 : 0][P.mirror ? 1 : 0];
+    const Kern kern = P.dim_max == 3 ? forces_kernel<kGroup3>(P, next != nullptr)
+                                     : forces_kernel<kGroup2>(P, next != nullptr);
     const StateDev none{};
     kern<<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.a4, pk.b4, cells.nbr, cells.nbr_count, mx,
                                          P.n_total, f, next ? *next : none, err);
