@@ -48,7 +48,12 @@
  *     (eq. SPH_fluid_continuity, the divergence in the form of eq. diffop2
  *     with V_j = m/rho_j), the linear equation of state p = c^2 (rho - rho0),
  *     and the momentum equation with the artificial viscosity Pi_ij, each
- *     equation finished for all particles before the next (Sec. 3.3).
+ *     equation finished for all particles before the next (Sec. 3.3);
+ *   - two further interaction laws on the same neighbour loop, as the
+ *     paper's interaction interface allows (Sec. 6): the DEM contact law of
+ *     Example 2 (eq. DEM_force with the effective quantities of eq.
+ *     effective_quantities) and the social force model (eq.
+ *     social_force_model, with the pair term of its listing).
  * Wall particles are ordinary particles held fixed (paper Sec. 5.3 builds
  * walls from fixed particles): they contribute density and pressure, keep
  * v = 0 and are not integrated.
@@ -86,6 +91,9 @@ typedef struct {
     double h, mass, rho0, c0, gamma, nu, dt;
     double g[3];
     double alpha_av;
+    /* constants of the pair laws: DEM law[0] = c_f (Coulomb friction);
+     * social force law[0..3] = A, B, k, tau */
+    double law[4];
 } or_params;
 
 /* ------------------------------------------------------------------------- */
@@ -953,6 +961,191 @@ int or_step_ex1a(const or_domain* D, const or_params* P, int64_t n, double* x, d
     }
     free(drho);
     free(p);
+    free(a);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Pair laws on the same neighbour loop (Sec. 6, the interaction interface)   */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    const or_domain* D;
+    const or_params* P;
+    const or_grid64* G;
+    const double* x;
+    const double* v;
+    const double* R;      /* radius */
+    const double* m;      /* mass */
+    const double* q;      /* DEM: (1 - nu^2) / E;  social force: c (attraction) */
+    const uint8_t* fixed;
+    const int64_t* which;
+    double* a;
+    double acc[3];
+} or_law_ctx;
+
+/* DEM contact force on i from j (Example 2, eq. DEM_force), neglecting
+ * rotation.  n = (r_j - r_i) / |r_j - r_i| points from i to j; the overlap
+ * is delta = R_i + R_j - |r_j - r_i|; only touching pairs (delta > 0) act.
+ *   R' = R_i R_j / (R_i + R_j),  m' = m_i m_j / (m_i + m_j),
+ *   E' = E_i E_j / (E_j (1 - nu_i^2) + E_i (1 - nu_j^2)) = 1 / (q_i + q_j),
+ *   k = (4/3) sqrt(R') E',  c = sqrt(m' k) / 8,
+ *   f_n = k delta^(3/2) + c delta^(1/4) ddelta/dt,  ddelta/dt = (v_i - v_j) . n,
+ *   v_t = (v_j - v_i) - ((v_j - v_i) . n) n,  f_t = c_f |f_n| v_t / |v_t|.
+ * The normal force pushes i away from j: F_i = -f_n n + f_t.  For a mirror
+ * image, v_j is reflected.  r = -rel (rel = r_i - r_j as visited). */
+static void or_dem_visit(void* c, int64_t i, int64_t j, const double rel[3], double rn,
+                         const double sgn[3])
+{
+    or_law_ctx* ctx = (or_law_ctx*)c;
+    double delta = ctx->R[i] + ctx->R[j] - rn;
+    if (delta <= 0.0 || rn <= 0.0) return;
+    double n[3], vj[3], dv[3];
+    for (int k = 0; k < 3; ++k) {
+        n[k] = -rel[k] / rn;
+        vj[k] = sgn[k] * ctx->v[3 * j + k];
+        dv[k] = vj[k] - ctx->v[3 * i + k]; /* v_j - v_i */
+    }
+    double Rs = ctx->R[i] * ctx->R[j] / (ctx->R[i] + ctx->R[j]);
+    double ms = ctx->m[i] * ctx->m[j] / (ctx->m[i] + ctx->m[j]);
+    double Es = 1.0 / (ctx->q[i] + ctx->q[j]);
+    double kh = 4.0 / 3.0 * sqrt(Rs) * Es;
+    double ch = sqrt(ms * kh) / 8.0;
+    double dvn = dv[0] * n[0] + dv[1] * n[1] + dv[2] * n[2];
+    double rate = -dvn; /* ddelta/dt = (v_i - v_j) . n */
+    double fn = kh * pow(delta, 1.5) + ch * pow(delta, 0.25) * rate;
+    double vt[3], vtn = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        vt[k] = dv[k] - dvn * n[k];
+        vtn += vt[k] * vt[k];
+    }
+    vtn = sqrt(vtn);
+    for (int k = 0; k < 3; ++k) {
+        ctx->acc[k] += -fn * n[k];
+        if (vtn > 0.0) ctx->acc[k] += ctx->P->law[0] * fabs(fn) * vt[k] / vtn;
+    }
+}
+
+/* Social force pair term on i from j (eq. social_force_model with the pair
+ * function of its listing): with d = |r_j - r_i|, n = (r_j - r_i) / d,
+ * R_ij = R_i + R_j and c_ij = (c_i + c_j) / 2,
+ *   F_i -= [A exp((R_ij - d) / B) + k max(R_ij - d, 0) - c_ij] n
+ * for 0 < d < 2h (the interaction radius). */
+static void or_social_visit(void* c, int64_t i, int64_t j, const double rel[3], double rn,
+                            const double sgn[3])
+{
+    (void)sgn;
+    or_law_ctx* ctx = (or_law_ctx*)c;
+    if (rn <= 0.0) return;
+    const double* L = ctx->P->law;
+    double Rij = ctx->R[i] + ctx->R[j];
+    double cij = 0.5 * (ctx->q[i] + ctx->q[j]);
+    double body = Rij - rn > 0.0 ? L[2] * (Rij - rn) : 0.0;
+    double s = L[0] * exp((Rij - rn) / L[1]) + body - cij;
+    for (int k = 0; k < 3; ++k) ctx->acc[k] -= s * (-rel[k] / rn);
+}
+
+typedef struct {
+    or_law_ctx base;
+    int law;             /* 0 DEM, 1 social force */
+    const double* v0;    /* social force: desired speed */
+    const double* goal;  /* social force: (n,3) target position */
+} or_law_run;
+
+static void or_law_range(void* c, int64_t begin, int64_t end)
+{
+    or_law_run* run = (or_law_run*)c;
+    or_law_ctx local = run->base;
+    const or_params* P = local.P;
+    for (int64_t s = begin; s < end; ++s) {
+        int64_t i = local.which ? local.which[s] : s;
+        for (int k = 0; k < 3; ++k) local.acc[k] = 0.0;
+        or_for_neighbours(local.G, local.x, i, run->law == 0 ? or_dem_visit : or_social_visit, &local);
+        int is_fixed = local.fixed ? local.fixed[i] : 0;
+        double own[3] = {0.0, 0.0, 0.0};
+        if (run->law == 1) {
+            /* relaxation to the desired velocity v0 e0, e0 towards the goal */
+            double e[3] = {0.0, 0.0, 0.0}, en = 0.0;
+            for (int k = 0; k < local.D->dim; ++k) {
+                e[k] = run->goal[3 * i + k] - local.x[3 * i + k];
+                en += e[k] * e[k];
+            }
+            en = sqrt(en);
+            for (int k = 0; k < local.D->dim; ++k) {
+                double ek = en > 0.0 ? e[k] / en : 0.0;
+                own[k] = (run->v0[i] * ek - local.v[3 * i + k]) / P->law[3];
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            double ak = k < local.D->dim ? local.acc[k] / local.m[i] + own[k] + P->g[k] : 0.0;
+            local.a[3 * s + k] = is_fixed ? 0.0 : ak;
+        }
+    }
+}
+
+static int or_law(int law, const or_domain* D, const or_params* P, int64_t n, const double* x,
+                  const double* v, const double* R, const double* m, const double* q,
+                  const double* v0, const double* goal, const uint8_t* fixed, int64_t n_eval,
+                  const int64_t* which, double* a, int nthreads)
+{
+    double Rmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) Rmax = R[i] > Rmax ? R[i] : Rmax;
+    /* contacts reach R_i + R_j <= 2 Rmax; the law itself cuts the rest */
+    if (law == 0 && 2.0 * Rmax > 2.0 * P->h) return -5;
+    or_grid64 G;
+    if (or_grid64_build(&G, D, P->h, n, x) != 0) return -1;
+    or_law_run run;
+    memset(&run, 0, sizeof(run));
+    run.base.D = D; run.base.P = P; run.base.G = &G; run.base.x = x; run.base.v = v;
+    run.base.R = R; run.base.m = m; run.base.q = q; run.base.fixed = fixed; run.base.which = which;
+    run.base.a = a;
+    run.law = law; run.v0 = v0; run.goal = goal;
+    or_parallel(which ? n_eval : n, nthreads, or_law_range, &run);
+    or_grid64_free(&G);
+    return 0;
+}
+
+/* DEM accelerations a_i = (1/m_i) sum_j F_ij + g (Example 2, eq.
+ * spheres_ode_full without the tank); q_i = (1 - nu_i^2) / E_i; c_f =
+ * P->law[0].  Neighbours within 2h; radii must satisfy R_i <= h. */
+int or_dem(const or_domain* D, const or_params* P, int64_t n, const double* x, const double* v,
+           const double* R, const double* m, const double* q, const uint8_t* fixed, int64_t n_eval,
+           const int64_t* which, double* a, int nthreads)
+{
+    return or_law(0, D, P, n, x, v, R, m, q, NULL, NULL, fixed, n_eval, which, a, nthreads);
+}
+
+/* Social force accelerations (eq. social_force_model):
+ *   a_i = (v0_i e0_i - v_i) / tau - (1/m_i) sum_j [A exp((R_ij - d)/B)
+ *         + k max(R_ij - d, 0) - c_ij] n_ji + g,
+ * e0_i the unit vector from r_i to goal_i; A, B, k, tau = P->law[0..3];
+ * c = per-particle attraction. */
+int or_social(const or_domain* D, const or_params* P, int64_t n, const double* x, const double* v,
+              const double* R, const double* m, const double* c, const double* v0,
+              const double* goal, const uint8_t* fixed, int64_t n_eval, const int64_t* which,
+              double* a, int nthreads)
+{
+    return or_law(1, D, P, n, x, v, R, m, c, v0, goal, fixed, n_eval, which, a, nthreads);
+}
+
+/* n_steps semi-implicit Euler steps (eq6, eq7 of Example 1a's scheme) of
+ * a pair law: law 0 DEM, 1 social force.  a (optional) receives the last
+ * step's accelerations. */
+int or_step_law(int law, const or_domain* D, const or_params* P, int64_t n, double* x, double* v,
+                const double* R, const double* m, const double* q, const double* v0,
+                const double* goal, const uint8_t* fixed, int32_t n_steps, double* a_out,
+                int nthreads)
+{
+    double* a = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!a) return -1;
+    int rc = 0;
+    for (int32_t s = 0; s < n_steps && rc == 0; ++s) {
+        rc = or_law(law, D, P, n, x, v, R, m, q, v0, goal, fixed, 0, NULL, a, nthreads);
+        if (rc != 0) break;
+        or_integrate_ctx ic = {D, P, x, v, a, fixed};
+        or_parallel(n, nthreads, or_integrate_range, &ic);
+    }
+    if (rc == 0 && n_steps > 0 && a_out) memcpy(a_out, a, sizeof(double) * 3 * (size_t)n);
     free(a);
     return rc;
 }

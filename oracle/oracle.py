@@ -17,7 +17,10 @@ Every function follows the paper (arXiv:1710.08259):
   the dam break of Example 1a;
 * Example 1a's own operator set: continuity (eq. SPH_fluid_continuity),
   linear equation of state, momentum with the artificial viscosity Pi_ij
-  (eq. SPH_fluid_momentum), stepped in the order of its equations eq1-eq7.
+  (eq. SPH_fluid_momentum), stepped in the order of its equations eq1-eq7;
+* two further pair laws on the same neighbour loop (Sec. 6, the interaction
+  interface): the DEM contact law of Example 2 (eq. DEM_force) and the
+  social force model (eq. social_force_model).
 
 The one-step adjoint (:func:`step_vjp`) is not in the paper; it is the exact
 reverse-mode derivative of :func:`step` with one step, pinned against central
@@ -59,6 +62,7 @@ class _Params(ctypes.Structure):
         ("dt", ctypes.c_double),
         ("g", ctypes.c_double * 3),
         ("alpha_av", ctypes.c_double),
+        ("law", ctypes.c_double * 4),
     ]
 
 
@@ -104,6 +108,7 @@ class Params:
     dt: float = 1e-4
     g: tuple = (0.0, 0.0, 0.0)
     alpha_av: float = 0.0   # artificial viscosity coefficient of Example 1a (0.1 there)
+    law: tuple = (0.0, 0.0, 0.0, 0.0)  # DEM: (c_f,); social force: (A, B, k, tau)
 
     def _c(self) -> _Params:
         p = _Params()
@@ -112,6 +117,8 @@ class Params:
         for k in range(3):
             p.g[k] = float(self.g[k])
         p.alpha_av = float(self.alpha_av)
+        for k in range(4):
+            p.law[k] = float(self.law[k]) if k < len(self.law) else 0.0
         return p
 
 
@@ -163,6 +170,14 @@ def _load():
     lib.or_step_ex1a.restype = ctypes.c_int
     lib.or_step_ex1a.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, i32, vp, vp, vp,
                                  ctypes.c_int]
+    lib.or_dem.restype = ctypes.c_int
+    lib.or_dem.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, i64, vp, vp, ctypes.c_int]
+    lib.or_social.restype = ctypes.c_int
+    lib.or_social.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp,
+                              ctypes.c_int]
+    lib.or_step_law.restype = ctypes.c_int
+    lib.or_step_law.argtypes = [ctypes.c_int, P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, vp, vp,
+                                i32, vp, ctypes.c_int]
     lib.or_step_vjp.restype = ctypes.c_int
     lib.or_step_vjp.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, vp,
                                 P(dbl), P(dbl), ctypes.c_int]
@@ -455,6 +470,69 @@ def step_ex1a(dom: Domain, prm: Params, x, v, rho, fixed=None, n_steps=1, nthrea
         raise MemoryError("or_step_ex1a failed")
     d = dom.dim
     return x3[:, :d], v3[:, :d], r, drho, p, a[:, :d]
+
+
+# --------------------------------------------------------------------------
+# pair laws: DEM contact (Example 2) and social force (Sec. 6)
+# --------------------------------------------------------------------------
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _u8(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def dem(dom: Domain, prm: Params, x, v, R, m, q, fixed=None, which=None, nthreads=None):
+    """DEM accelerations; q = (1 - nu^2) / E per particle, c_f = prm.law[0]."""
+    x3, v3 = _x3(x), _x3(v)
+    n = x3.shape[0]
+    w = None if which is None else np.ascontiguousarray(which, dtype=np.int64)
+    mm = n if w is None else w.shape[0]
+    a = np.zeros((mm, 3))
+    rc = _load().or_dem(ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3), _ptr(v3),
+                        _ptr(_f64(R)), _ptr(_f64(m)), _ptr(_f64(q)), _ptr(_u8(fixed)), mm, _ptr(w),
+                        _ptr(a), nthreads or default_threads())
+    if rc == -5:
+        raise ValueError("dem: a radius exceeds h (contacts beyond the cell stencil)")
+    if rc != 0:
+        raise MemoryError("or_dem failed")
+    return a[:, : dom.dim]
+
+
+def social(dom: Domain, prm: Params, x, v, R, m, c, v0, goal, fixed=None, which=None, nthreads=None):
+    """Social force accelerations; A, B, k, tau = prm.law."""
+    x3, v3, g3 = _x3(x), _x3(v), _x3(goal)
+    n = x3.shape[0]
+    w = None if which is None else np.ascontiguousarray(which, dtype=np.int64)
+    mm = n if w is None else w.shape[0]
+    a = np.zeros((mm, 3))
+    rc = _load().or_social(ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3), _ptr(v3),
+                           _ptr(_f64(R)), _ptr(_f64(m)), _ptr(_f64(c)), _ptr(_f64(v0)), _ptr(g3),
+                           _ptr(_u8(fixed)), mm, _ptr(w), _ptr(a), nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_social failed")
+    return a[:, : dom.dim]
+
+
+def step_law(law: str, dom: Domain, prm: Params, x, v, R, m, q, v0=None, goal=None, fixed=None,
+             n_steps=1, nthreads=None):
+    """n_steps semi-implicit Euler steps of a pair law ("dem" or "social");
+    returns (x, v, a) with a of the last step."""
+    x3, v3 = _x3(x), _x3(v)
+    n = x3.shape[0]
+    a = np.zeros((n, 3))
+    lid = {"dem": 0, "social": 1}[law]
+    g3 = None if goal is None else _x3(goal)
+    rc = _load().or_step_law(lid, ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3), _ptr(v3),
+                             _ptr(_f64(R)), _ptr(_f64(m)), _ptr(_f64(q)),
+                             _ptr(None if v0 is None else _f64(v0)), _ptr(g3), _ptr(_u8(fixed)),
+                             int(n_steps), _ptr(a), nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_step_law failed")
+    d = dom.dim
+    return x3[:, :d], v3[:, :d], a[:, :d]
 
 
 def step_vjp(dom: Domain, prm: Params, x, v, lam_x_next, lam_v_next, fixed=None, nthreads=None):
