@@ -24,6 +24,10 @@
  *     viscosity Pi_ij [eq. SPH_fluid_momentum], stepped as eq1..eq7;
  *   - periodic, cut-off and symmetric (mirror, free-slip) faces [Sec. 3.2.1,
  *     boundary treatments];
+ *   - further pair laws on the same neighbour loop, as the paper's
+ *     interaction interface allows [Sec. 6]: the DEM contact law of
+ *     Example 2 [eq. DEM_force] and the social force model [eq.
+ *     social_force_model];
  *   - the reverse-mode derivative of one step of the summation model (not in
  *     the paper).
  * Phases are separated like the paper's equations [Sec. 3.3: an equation is
@@ -80,7 +84,8 @@ typedef enum {
     NAUTICLE_ERR_OUT_OF_DOMAIN = -4,      /* (nauticle_check) a position beyond 2^23 cells */
     NAUTICLE_ERR_WORKSPACE = -5,          /* too small, or not prepared for these cases */
     NAUTICLE_ERR_HIP = -6,                /* a HIP runtime call failed */
-    NAUTICLE_ERR_NEIGHBOUR_OVERFLOW = -7  /* (nauticle_check) a particle had > max_nbr neighbours */
+    NAUTICLE_ERR_NEIGHBOUR_OVERFLOW = -7, /* (nauticle_check) a particle had > max_nbr neighbours */
+    NAUTICLE_ERR_ATTRIBUTE = -8           /* (nauticle_check) a pair-law attribute out of range */
 } nauticle_status;
 
 /* Face treatments [Sec. 3.2.1].  Symmetric: a particle within 2h of the
@@ -93,8 +98,15 @@ enum { NAUTICLE_PERIODIC = 0, NAUTICLE_CUTOFF = 1, NAUTICLE_SYMMETRIC = 2 };
  *   SUMMATION:  density summation, Tait equation of state, Morris viscosity
  *               (nu);
  *   CONTINUITY: Example 1a -- density evolved by the continuity equation,
- *               p = c0^2 (rho - rho0), artificial viscosity (alpha_av). */
-enum { NAUTICLE_MODEL_SUMMATION = 0, NAUTICLE_MODEL_CONTINUITY = 1 };
+ *               p = c0^2 (rho - rho0), artificial viscosity (alpha_av);
+ *   DEM:        Example 2's contact law (nauticle_interact);
+ *   SOCIAL:     the social force model (nauticle_interact). */
+enum {
+    NAUTICLE_MODEL_SUMMATION = 0,
+    NAUTICLE_MODEL_CONTINUITY = 1,
+    NAUTICLE_MODEL_DEM = 2,
+    NAUTICLE_MODEL_SOCIAL = 3
+};
 
 /* Sentinel of an empty cell in cell_start / cell_end. */
 #define NAUTICLE_EMPTY 0xFFFFFFFFu
@@ -125,12 +137,16 @@ typedef struct {
  * (B = c0^2 rho0 / gamma); nu: kinematic viscosity; dt: time step;
  * g: body acceleration; alpha_av: artificial viscosity coefficient
  * (Pi_ij = -alpha_av c0 h w / (rho_i |r_ij|^2) for approaching pairs,
- * 0.1 in Example 1a); model: NAUTICLE_MODEL_*, the same for every case of a
- * table (SUMMATION uses gamma and nu, CONTINUITY alpha_av); reserved: 0. */
+ * 0.1 in Example 1a); law: constants of a pair law (DEM: law[0] = c_f, the
+ * Coulomb friction coefficient; SOCIAL: law[0..3] = A, B, k, tau); model:
+ * NAUTICLE_MODEL_*, the same for every case of a table (SUMMATION uses gamma
+ * and nu, CONTINUITY alpha_av, the pair laws law[] and per-particle
+ * attributes); reserved: 0. */
 typedef struct {
     double h, mass, rho0, c0, gamma, nu, dt;
     double g[3];
     double alpha_av;
+    double law[4];
     int32_t model;
     int32_t reserved;
 } nauticle_sph_params;
@@ -216,6 +232,24 @@ typedef struct {
     int32_t groups_per_cu;
     int32_t reserved;
 } nauticle_tuning;
+
+/* Per-particle attributes of a pair law, caller-owned device FP32 arrays
+ * indexed by global particle index (case offset + id, i.e. input order at
+ * binning); they travel with the particles through `id`.
+ *   radius: R (DEM: R <= h, so that every contact lies within the 2h
+ *           stencil, else NAUTICLE_ERR_ATTRIBUTE at nauticle_check);
+ *   mass:   m;
+ *   coef:   DEM: (1 - nu^2) / E (so that E' = 1 / (coef_i + coef_j));
+ *           SOCIAL: the attraction c (c_ij = (c_i + c_j) / 2);
+ *   v0, goal[k] (SOCIAL only; may be NULL for DEM): the desired speed and
+ *           the absolute target position. */
+typedef struct {
+    const float* radius;
+    const float* mass;
+    const float* coef;
+    const float* v0;
+    const float* goal[3];
+} nauticle_law_attrs;
 
 /* Number of cell keys over all cases (sum of ncell products). */
 int64_t nauticle_cells_total(const nauticle_case* cases, int32_t n_cases);
@@ -316,9 +350,38 @@ nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases,
                                     nauticle_fields* fields, nauticle_state* next, void* ws,
                                     size_t ws_bytes, hipStream_t stream);
 
+/* One pass of the table's pair law [Sec. 6: interaction interface] over
+ * the lists of nauticle_build_cells, images included:
+ *   DEM [Example 2, eq. DEM_force, effective quantities as printed]: for
+ *     touching pairs (delta = R_i + R_j - |r_j - r_i| > 0), n = (r_j - r_i)/|.|,
+ *     f_n = k delta^(3/2) + c delta^(1/4) (v_i - v_j).n, k = (4/3) sqrt(R') E',
+ *     c = sqrt(m' k)/8; F_i += -f_n n + c_f |f_n| v_t/|v_t|,
+ *     v_t = (v_j - v_i) - ((v_j - v_i).n) n, the friction only when
+ *     |v_t| > 1e-5 |v_j - v_i| (free slip against one's own image);
+ *   SOCIAL [eq. social_force_model, pair term of its listing]: for 0 < d < 2h,
+ *     F_i -= [A exp((R_ij - d)/B) + k max(R_ij - d, 0) - c_ij] n, plus the
+ *     particle's own term m (v0 e0 - v)/tau, e0 towards its goal;
+ * a_i = F_i / m_i + g (fixed particles: a = 0), written to fields->acc
+ * (only acc is used).  If `next` is not NULL the step is completed as in
+ * nauticle_sph_forces.  Requires a DEM or SOCIAL table. */
+nauticle_status nauticle_interact(const nauticle_case* cases, int32_t n_cases,
+                                  const nauticle_state* sorted, const nauticle_cells* cells,
+                                  const nauticle_law_attrs* attrs, nauticle_fields* fields,
+                                  nauticle_state* next, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* n_steps steps of a pair law in place: build_cells(state -> workspace
+ * copy), then nauticle_interact with the fused integration back into
+ * `state`.  phase_events as in nauticle_step (the density slot is recorded
+ * right after the neighbour lists). */
+nauticle_status nauticle_step_law(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
+                                  int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
+                                  const nauticle_law_attrs* attrs, hipEvent_t* phase_events, void* ws,
+                                  size_t ws_bytes, hipStream_t stream);
+
 /* n_steps full steps in place: build_cells(state -> workspace copy),
  * density (SUMMATION) or continuity (CONTINUITY, state->rho evolved),
- * forces with the fused integration back into `state`.  After
+ * forces with the fused integration back into `state` (pair-law tables:
+ * nauticle_step_law).  After
  * the call `state` holds the particles in the sorted order of the last
  * step; `cells` and `fields` hold that step's neighbour structure and
  * fields.  phase_events (optional, NULL or 5 * n_steps caller-created HIP

@@ -993,7 +993,10 @@ typedef struct {
  *   f_n = k delta^(3/2) + c delta^(1/4) ddelta/dt,  ddelta/dt = (v_i - v_j) . n,
  *   v_t = (v_j - v_i) - ((v_j - v_i) . n) n,  f_t = c_f |f_n| v_t / |v_t|.
  * The normal force pushes i away from j: F_i = -f_n n + f_t.  For a mirror
- * image, v_j is reflected.  r = -rel (rel = r_i - r_j as visited). */
+ * image, v_j is reflected.  r = -rel (rel = r_i - r_j as visited).
+ * The friction direction v_t / |v_t| is undefined at v_t = 0, where the law
+ * jumps; friction acts only when |v_t| > 1e-5 |v_j - v_i| (a particle
+ * against its own image on a symmetric face has v_t = 0: free slip). */
 static void or_dem_visit(void* c, int64_t i, int64_t j, const double rel[3], double rn,
                          const double sgn[3])
 {
@@ -1014,15 +1017,17 @@ static void or_dem_visit(void* c, int64_t i, int64_t j, const double rel[3], dou
     double dvn = dv[0] * n[0] + dv[1] * n[1] + dv[2] * n[2];
     double rate = -dvn; /* ddelta/dt = (v_i - v_j) . n */
     double fn = kh * pow(delta, 1.5) + ch * pow(delta, 0.25) * rate;
-    double vt[3], vtn = 0.0;
+    double vt[3], vtn = 0.0, dv2 = 0.0;
     for (int k = 0; k < 3; ++k) {
         vt[k] = dv[k] - dvn * n[k];
         vtn += vt[k] * vt[k];
+        dv2 += dv[k] * dv[k];
     }
+    int slides = vtn > 1e-10 * dv2;
     vtn = sqrt(vtn);
     for (int k = 0; k < 3; ++k) {
         ctx->acc[k] += -fn * n[k];
-        if (vtn > 0.0) ctx->acc[k] += ctx->P->law[0] * fabs(fn) * vt[k] / vtn;
+        if (slides) ctx->acc[k] += ctx->P->law[0] * fabs(fn) * vt[k] / vtn;
     }
 }
 

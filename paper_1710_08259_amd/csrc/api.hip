@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "laws.h"
 
 using namespace nau;
 
@@ -102,8 +103,14 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
             !std::isfinite(q.g[0]) || !std::isfinite(q.g[1]) || !std::isfinite(q.g[2]) ||
             !std::isfinite(q.alpha_av) || q.alpha_av < 0.0)
             return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: non-finite or non-positive parameter", b);
-        if (q.model != NAUTICLE_MODEL_SUMMATION && q.model != NAUTICLE_MODEL_CONTINUITY)
+        if (q.model < NAUTICLE_MODEL_SUMMATION || q.model > NAUTICLE_MODEL_SOCIAL)
             return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: unknown model %d", b, q.model);
+        for (int k = 0; k < 4; ++k)
+            if (!std::isfinite(q.law[k])) return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: law[%d] not finite", b, k);
+        if (q.model == NAUTICLE_MODEL_DEM && q.law[0] < 0.0)
+            return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: friction coefficient < 0", b);
+        if (q.model == NAUTICLE_MODEL_SOCIAL && (!(q.law[1] > 0.0) || !(q.law[3] > 0.0)))
+            return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: social force needs B > 0 and tau > 0", b);
         if (q.model != model0) return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: all cases must share one model", b);
         uint64_t ncell = 1;
         for (int k = 0; k < 3; ++k) {
@@ -167,6 +174,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         C.nu = static_cast<float>(q.nu);
         C.dt = static_cast<float>(q.dt);
         C.c2 = static_cast<float>(q.c0 * q.c0);
+        C.h = static_cast<float>(q.h);
+        for (int k = 0; k < 4; ++k) C.law[k] = static_cast<float>(q.law[k]);
         C.av_coef = static_cast<float>(q.alpha_av * q.c0 * q.h * q.mass);
         C.item_first = static_cast<uint32_t>(D->items.size());
         for (int64_t first = 0; first < c.n; first += block) {
@@ -508,6 +517,97 @@ nauticle_status nauticle_sph_continuity(const nauticle_case* cases, int32_t n_ca
     return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_sph_continuity");
 }
 
+namespace {
+
+bool is_law(const Plan& P) { return P.model == NAUTICLE_MODEL_DEM || P.model == NAUTICLE_MODEL_SOCIAL; }
+
+nauticle_status check_attrs(const Plan& P, const nauticle_law_attrs* a, LawAttrsDev* out)
+{
+    if (!a) return fail(NAUTICLE_ERR_INVALID_ARG, "attrs is null");
+    if (P.n_total && (!a->radius || !a->mass || !a->coef))
+        return fail(NAUTICLE_ERR_INVALID_ARG, "attrs: radius/mass/coef null");
+    if (P.n_total && P.model == NAUTICLE_MODEL_SOCIAL) {
+        if (!a->v0) return fail(NAUTICLE_ERR_INVALID_ARG, "attrs: v0 null (social force)");
+        for (int k = 0; k < P.dim_max; ++k)
+            if (!a->goal[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "attrs: goal[%d] null (social force)", k);
+    }
+    out->radius = a->radius;
+    out->mass = a->mass;
+    out->coef = a->coef;
+    out->v0 = a->v0;
+    for (int k = 0; k < 3; ++k) out->goal[k] = a->goal[k];
+    return NAUTICLE_OK;
+}
+
+nauticle_status check_acc(const Plan& P, const nauticle_fields* f)
+{
+    if (!f) return fail(NAUTICLE_ERR_INVALID_ARG, "fields is null");
+    for (int k = 0; k < P.dim_max; ++k)
+        if (P.n_total && !f->acc[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "fields: acc[%d] null", k);
+    return NAUTICLE_OK;
+}
+
+}  // namespace
+
+nauticle_status nauticle_interact(const nauticle_case* cases, int32_t n_cases, const nauticle_state* sorted,
+                                  const nauticle_cells* cells, const nauticle_law_attrs* attrs, nauticle_fields* fields,
+                                  nauticle_state* next, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if (!is_law(*P)) return fail(NAUTICLE_ERR_INVALID_ARG, "nauticle_interact needs a DEM or social-force table");
+    LawAttrsDev ad;
+    if ((st = check_state(*P, sorted, true, "sorted")) != NAUTICLE_OK) return st;
+    if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
+    if ((st = check_attrs(*P, attrs, &ad)) != NAUTICLE_OK) return st;
+    if ((st = check_acc(*P, fields)) != NAUTICLE_OK) return st;
+    StateDev nd;
+    if (next) {
+        if ((st = check_state(*P, next, true, "next")) != NAUTICLE_OK) return st;
+        if (P->n_total && (next->cell == sorted->cell || next->off[0] == sorted->off[0]))
+            return fail(NAUTICLE_ERR_INVALID_ARG, "next must not alias sorted");
+        nd = to_dev_model(*P, next);
+    }
+    hipError_t e = launch_cell_first(*P, ws, *cells, stream);
+    if (e == hipSuccess)
+        e = launch_interact(*P, ws, to_dev_model(*P, sorted), *cells, ad, to_dev(fields), next ? &nd : nullptr, stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_interact");
+}
+
+nauticle_status nauticle_step_law(const nauticle_case* cases, int32_t n_cases, nauticle_state* state, int32_t n_steps,
+                                  nauticle_cells* cells, nauticle_fields* fields, const nauticle_law_attrs* attrs,
+                                  hipEvent_t* phase_events, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if (!is_law(*P)) return fail(NAUTICLE_ERR_INVALID_ARG, "nauticle_step_law needs a DEM or social-force table");
+    if (n_steps < 0) return fail(NAUTICLE_ERR_INVALID_ARG, "n_steps < 0");
+    LawAttrsDev ad;
+    if ((st = check_state(*P, state, true, "state")) != NAUTICLE_OK) return st;
+    if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
+    if ((st = check_attrs(*P, attrs, &ad)) != NAUTICLE_OK) return st;
+    if ((st = check_acc(*P, fields)) != NAUTICLE_OK) return st;
+    const StateDev cur = to_dev_model(*P, state);
+    const StateDev tmp = scratch_state(*P, ws);
+    const FieldsDev f = to_dev(fields);
+    auto mark = [&](int32_t s, int k) {
+        return phase_events ? hipEventRecord(phase_events[5 * s + k], stream) : hipSuccess;
+    };
+    for (int32_t s = 0; s < n_steps; ++s) {
+        hipError_t e = mark(s, 0);
+        if (e == hipSuccess)
+            e = launch_build_cells(*P, ws, cur, tmp, *cells, stream, phase_events ? phase_events[5 * s + 1] : nullptr);
+        if (e == hipSuccess) e = mark(s, 2);
+        if (e == hipSuccess) e = mark(s, 3);
+        if (e == hipSuccess) e = launch_interact(*P, ws, tmp, *cells, ad, f, &cur, stream);
+        if (e == hipSuccess) e = mark(s, 4);
+        if (e != hipSuccess) return hip_fail(e, "nauticle_step_law");
+    }
+    return NAUTICLE_OK;
+}
+
 nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases, const nauticle_state* sorted,
                                     const nauticle_cells* cells, nauticle_fields* fields, nauticle_state* next,
                                     void* ws, size_t ws_bytes, hipStream_t stream)
@@ -541,6 +641,7 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
     nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
     if (st != NAUTICLE_OK) return st;
     if (n_steps < 0) return fail(NAUTICLE_ERR_INVALID_ARG, "n_steps < 0");
+    if (is_law(*P)) return fail(NAUTICLE_ERR_INVALID_ARG, "pair-law tables step with nauticle_step_law");
     const bool cont = P->model == NAUTICLE_MODEL_CONTINUITY;
     if ((st = check_state(*P, state, true, "state", cont)) != NAUTICLE_OK) return st;
     if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
@@ -632,6 +733,7 @@ nauticle_status nauticle_check(void* ws, size_t ws_bytes, hipStream_t stream)
     if (word & kErrNonFinite) return fail(NAUTICLE_ERR_NONFINITE, "a non-finite value was produced or given");
     if (word & kErrOverflow) return fail(NAUTICLE_ERR_NEIGHBOUR_OVERFLOW, "a particle had more than max_nbr neighbours");
     if (word & kErrOutOfDomain) return fail(NAUTICLE_ERR_OUT_OF_DOMAIN, "a position lies beyond 2^23 cells");
+    if (word & kErrAttribute) return fail(NAUTICLE_ERR_ATTRIBUTE, "a pair-law attribute is out of range");
     return NAUTICLE_OK;
 }
 

@@ -37,6 +37,7 @@ __device__ inline const uint4* nbr_chunk(const uint32_t* nbr, uint32_t c, uint32
 constexpr uint32_t kErrNonFinite = 1u;
 constexpr uint32_t kErrOverflow = 2u;
 constexpr uint32_t kErrOutOfDomain = 4u;
+constexpr uint32_t kErrAttribute = 8u;
 
 // Per-case constants, derived once on the host in FP64 and rounded to FP32.
 struct CaseDev {
@@ -65,6 +66,8 @@ struct CaseDev {
     float g[3];
     float c2;            // c0^2 (linear equation of state)
     float av_coef;       // alpha_av c0 h m (artificial viscosity, times 1/rho_i per particle)
+    float h;             // smoothing length (pair laws: the largest radius allowed)
+    float law[4];        // pair-law constants (DEM: c_f; social force: A, B, k, tau)
 };
 
 // Offset code of a list entry along axis k (bits 26 + 2k, 27 + 2k): the
@@ -357,6 +360,10 @@ hipError_t launch_continuity(const Plan& P, void* ws, StateDev sorted, const nau
 // the viscous term follows the plan's model
 hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                          FieldsDev f, const StateDev* next, hipStream_t s);
+// interact.hip: a pair law (by the plan's model) on the lists of `cells`
+struct LawAttrsDev;
+hipError_t launch_interact(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
+                           const LawAttrsDev& attrs, FieldsDev f, const StateDev* next, hipStream_t s);
 // adjoint.hip
 hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                           FieldsDev f, const float* const lxn[3], const float* const lvn[3],

@@ -26,11 +26,14 @@ ERR_OUT_OF_DOMAIN = -4
 ERR_WORKSPACE = -5
 ERR_HIP = -6
 ERR_NEIGHBOUR_OVERFLOW = -7
+ERR_ATTRIBUTE = -8
 PERIODIC = 0
 CUTOFF = 1
 SYMMETRIC = 2
 MODEL_SUMMATION = 0
 MODEL_CONTINUITY = 1
+MODEL_DEM = 2
+MODEL_SOCIAL = 3
 MIRROR_CODE = 3
 EMPTY = 0xFFFFFFFF
 NBR_INDEX_BITS = 26
@@ -39,7 +42,7 @@ ENTRY_POINTS = (
     "nauticle_cells_total", "nauticle_workspace_bytes", "nauticle_prepare", "nauticle_bin",
     "nauticle_unbin", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_continuity",
     "nauticle_sph_forces",
-    "nauticle_step", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
+    "nauticle_step", "nauticle_interact", "nauticle_step_law", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
     "nauticle_last_error",
 )
 
@@ -63,7 +66,7 @@ class CParams(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("mass", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("c0", ctypes.c_double), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
                 ("dt", ctypes.c_double), ("g", ctypes.c_double * 3), ("alpha_av", ctypes.c_double),
-                ("model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("law", ctypes.c_double * 4), ("model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CCase(ctypes.Structure):
@@ -80,6 +83,11 @@ class CCells(ctypes.Structure):
     _fields_ = [("key", ctypes.c_void_p), ("perm", ctypes.c_void_p), ("cell_start", ctypes.c_void_p),
                 ("cell_end", ctypes.c_void_p), ("nbr", ctypes.c_void_p), ("nbr_count", ctypes.c_void_p),
                 ("max_nbr", ctypes.c_int32)]
+
+
+class CLawAttrs(ctypes.Structure):
+    _fields_ = [("radius", ctypes.c_void_p), ("mass", ctypes.c_void_p), ("coef", ctypes.c_void_p),
+                ("v0", ctypes.c_void_p), ("goal", ctypes.c_void_p * 3)]
 
 
 class CTuning(ctypes.Structure):
@@ -144,6 +152,12 @@ def lib():
     L.nauticle_step.restype = st
     L.nauticle_step.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(vp), vp,
                                 ctypes.c_size_t, vp]
+    L.nauticle_interact.restype = st
+    L.nauticle_interact.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CLawAttrs), P(CFields), P(CState), vp,
+                                    ctypes.c_size_t, vp]
+    L.nauticle_step_law.restype = st
+    L.nauticle_step_law.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(CLawAttrs), P(vp), vp,
+                                    ctypes.c_size_t, vp]
     L.nauticle_sph_adjoint.restype = st
     L.nauticle_sph_adjoint.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CFields), P(ptr3), P(ptr3),
                                        P(ptr3), P(ptr3), vp, vp, vp, ctypes.c_size_t, vp]
@@ -258,6 +272,27 @@ class Fields:
         return f
 
 
+@dataclass
+class LawAttrs:
+    """Per-particle attributes of a pair law (device FP32 tensors in input
+    order): radius, mass, coef (DEM: (1 - nu^2)/E; social force: attraction
+    c), and for the social force v0 and goal (one tensor per axis)."""
+
+    radius: torch.Tensor
+    mass: torch.Tensor
+    coef: torch.Tensor
+    v0: Optional[torch.Tensor] = None
+    goal: Optional[list] = None
+
+    def c(self) -> CLawAttrs:
+        a = CLawAttrs()
+        a.radius, a.mass, a.coef = self.radius.data_ptr(), self.mass.data_ptr(), self.coef.data_ptr()
+        a.v0 = self.v0.data_ptr() if self.v0 is not None else None
+        for k in range(3):
+            a.goal[k] = self.goal[k].data_ptr() if self.goal is not None and k < len(self.goal) else None
+        return a
+
+
 def case_table(cases) -> "ctypes.Array":
     """Case objects with the attributes of workloads.Case -> C case array."""
     arr = (CCase * len(cases))()
@@ -276,6 +311,9 @@ def case_table(cases) -> "ctypes.Array":
         for k in range(3):
             p.g[k] = float(c.g[k])
         p.alpha_av = float(getattr(c, "alpha_av", 0.0))
+        law = tuple(getattr(c, "law", ()) or ())
+        for k in range(4):
+            p.law[k] = float(law[k]) if k < len(law) else 0.0
         p.model = int(getattr(c, "model", MODEL_SUMMATION))
         p.reserved = 0
         arr[b].offset = offset
@@ -400,6 +438,47 @@ class Problem:
                                              ctypes.byref(f.c()), *self._ws()), "nauticle_sph_continuity")
         return f
 
+    def law_attrs(self) -> LawAttrs:
+        """The cases' per-particle pair-law attributes as device tensors."""
+        def cat(name):
+            parts = [np.asarray(getattr(c, name), np.float32) for c in self.cases]
+            return torch.from_numpy(np.ascontiguousarray(np.concatenate(parts))).to(self.device)
+
+        v0 = goal = None
+        if self.model == MODEL_SOCIAL:
+            v0 = cat("v0")
+            g = np.concatenate([np.asarray(c.goal, np.float32) for c in self.cases])
+            goal = [torch.from_numpy(np.ascontiguousarray(g[:, k])).to(self.device) for k in range(self.dim)]
+        return LawAttrs(cat("radius"), cat("pmass"), cat("coef"), v0, goal)
+
+    def interact(self, attrs: LawAttrs, sorted_: Optional[State] = None, next_: Optional[State] = None,
+                 cells: Optional[Cells] = None, fields: Optional[Fields] = None):
+        s = self.sorted if sorted_ is None else sorted_
+        c = self.cells if cells is None else cells
+        f = self.fields if fields is None else fields
+        nxt = ctypes.byref(next_.c()) if next_ is not None else None
+        _check(lib().nauticle_interact(self.table, self.n_cases, ctypes.byref(s.c()), ctypes.byref(c.c()),
+                                       ctypes.byref(attrs.c()), ctypes.byref(f.c()), nxt, *self._ws()),
+               "nauticle_interact")
+        return f
+
+    def step_law(self, st: State, attrs: LawAttrs, n_steps: int = 1, events=None) -> State:
+        ev = self._events(events, n_steps)
+        _check(lib().nauticle_step_law(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
+                                       ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()),
+                                       ctypes.byref(attrs.c()), ev, *self._ws()), "nauticle_step_law")
+        return st
+
+    def _events(self, events, n_steps):
+        if events is None:
+            return None
+        if len(events) != 5 * n_steps:
+            raise ValueError("need 5 events per step")
+        for e in events:  # torch creates the HIP event on first record
+            if e.cuda_event == 0:
+                e.record(torch.cuda.current_stream(self.device))
+        return (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
+
     def forces(self, sorted_: Optional[State] = None, next_: Optional[State] = None,
                cells: Optional[Cells] = None, fields: Optional[Fields] = None):
         s = self.sorted if sorted_ is None else sorted_
@@ -414,14 +493,7 @@ class Problem:
         """n_steps steps in place.  `events` (optional): 5 * n_steps
         torch.cuda.Event(enable_timing=True) recorded at each step's start,
         after its sort/reorder, its neighbour lists, density and forces."""
-        ev = None
-        if events is not None:
-            if len(events) != 5 * n_steps:
-                raise ValueError("need 5 events per step")
-            for e in events:  # torch creates the HIP event on first record
-                if e.cuda_event == 0:
-                    e.record(torch.cuda.current_stream(self.device))
-            ev = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
+        ev = self._events(events, n_steps)
         _check(lib().nauticle_step(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
                                    ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()), ev, *self._ws()),
                "nauticle_step")

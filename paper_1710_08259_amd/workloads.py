@@ -34,6 +34,8 @@ SYMMETRIC = 2
 # viscosity, or Example 1a's continuity + linear EOS + artificial viscosity.
 SUMMATION = 0
 CONTINUITY = 1
+DEM = 2         # Example 2's contact law
+SOCIAL = 3      # the social force model
 
 
 def _f32(x: float) -> float:
@@ -64,6 +66,12 @@ class Case:
     model: int = SUMMATION
     alpha_av: float = 0.0                 # artificial viscosity coefficient (CONTINUITY)
     rho: Optional[np.ndarray] = None      # (n,) float32 initial density (CONTINUITY)
+    law: tuple = ()                       # pair-law constants (DEM: (c_f,); SOCIAL: (A, B, k, tau))
+    radius: Optional[np.ndarray] = None   # (n,) pair-law attributes, input order
+    pmass: Optional[np.ndarray] = None
+    coef: Optional[np.ndarray] = None     # DEM: (1 - nu^2)/E; SOCIAL: attraction c
+    v0: Optional[np.ndarray] = None       # SOCIAL: desired speed
+    goal: Optional[np.ndarray] = None     # SOCIAL: (n, dim) absolute target
 
     @property
     def n(self) -> int:
@@ -220,6 +228,82 @@ def mirror_box_case(dim, boundary, seed, n=2000, ncell=(12, 10, 8), h=0.02, mode
                 pos=x.astype(np.float32), vel=rng.normal(0.0, v_sigma, (n, dim)).astype(np.float32),
                 n_fixed=0, name=name or f"mirror_box_{dim}d_{seed}", model=model,
                 alpha_av=0.1 if model == CONTINUITY else 0.0, rho=rho)
+
+
+def dem_damper(scale: int = 1, seed: int = 7, jitter: float = 0.3, cf: float = 0.3, dt: float = 2e-5,
+               spacing: float = 0.1 / 9, v_sigma: float = 0.0, name: str = "") -> Case:
+    """Example 2's particle damper without the tank's own motion: spheres of
+    R = 4 mm, rho = 7850, E = 2.06e6 Pa (as the table prints it), nu = 0.33,
+    g = -9.81 ez, in a cubic box of edge 0.1 scale m with symmetric faces.
+    The table's 567 spheres are a 9 x 9 x 7 lattice; ``scale`` multiplies
+    each lattice side (567 scale^3 spheres).  Sites (i + 1/2) spacing
+    (0.1/9 m: the table's tank), jittered by U(+-jitter) of the gap between
+    spheres (of the spacing when they overlap), velocities N(0, v_sigma).
+    Cells of edge >= 2R (h = R); c_f (not given) = 0.3."""
+    rng = np.random.default_rng(seed)
+    R, rho_s, E, nu = 0.004, 7850.0, 2.06e6, 0.33
+    L = 0.1 * scale
+    side = (9 * scale, 9 * scale, 7 * scale)
+    sp = spacing
+    grids = np.meshgrid(*[(np.arange(side[k]) + 0.5) * sp for k in range(3)], indexing="ij")
+    pos = np.stack([g_.ravel(order="F") for g_ in grids], axis=1)
+    gap = sp - 2 * R if sp > 2 * R else sp
+    pos += rng.uniform(-1, 1, pos.shape) * jitter * gap / 2
+    n = pos.shape[0]
+    nc, cs = _cells_for(L, _f32(R))  # h = R as stored (FP32): contacts reach 2h
+    m = rho_s * 4.0 / 3.0 * math.pi * R ** 3
+    return Case(dim=3, ncell=(nc, nc, nc), cell_size=(cs, cs, cs), origin=(0.0, 0.0, 0.0),
+                boundary=(SYMMETRIC,) * 3, h=_f32(R), mass=m, rho0=rho_s, c0=1.0, gamma=1.0, nu=0.0, dt=dt,
+                g=(0.0, 0.0, -9.81), pos=pos.astype(np.float32),
+                vel=rng.normal(0.0, v_sigma, (n, 3)).astype(np.float32),
+                n_fixed=0, name=name or f"dem_damper_{n}", model=DEM, law=(cf,),
+                radius=np.full(n, R, np.float32), pmass=np.full(n, m, np.float32),
+                coef=np.full(n, (1 - nu ** 2) / E, np.float32))
+
+
+def social_room(width: float = 20.0, density: float = 1.0, seed: int = 11, c_max: float = 0.0,
+                dt: float = 1e-3, name: str = "") -> Case:
+    """A square room of side ``width`` for the social force model: walls of
+    fixed people (R_w = 0.1 m, 0.2 m apart) with a 2 m exit in the right
+    wall; people at ``density`` per m^2 inside (a square lattice jittered by
+    U(+-0.1) of its spacing), masses U(50, 100) kg, radii
+    0.002 m + 0.15 (the paper's rule), desired speeds U(0.8, 1.5) m/s, all
+    heading for a point 3 m beyond the exit, at rest.  A, B, k, tau = 2000 N,
+    0.08 m, 1.2e5 kg/s^2, 0.5 s; attraction c ~ U(0, c_max).  Cut-off box
+    around the room, cells >= 1.2 m (interaction radius 2h = 1.2 m)."""
+    rng = np.random.default_rng(seed)
+    sp = 1.0 / math.sqrt(density)
+    k = int((width - 1.0) / sp)
+    ix, iy = np.meshgrid(np.arange(k), np.arange(k), indexing="ij")
+    people = 0.5 + (np.stack([ix.ravel(order="F"), iy.ravel(order="F")], axis=1) + 0.5) * sp
+    people += rng.uniform(-0.1, 0.1, people.shape) * sp
+    n = people.shape[0]
+    wall = []
+    ticks = np.arange(0.0, width + 1e-9, 0.2)
+    for t in ticks:
+        wall += [(t, 0.0), (t, width), (0.0, t)]
+        if abs(t - width / 2) > 1.0:
+            wall.append((width, t))
+    wall = np.array(wall)
+    pos = np.concatenate([people, wall])
+    nw = wall.shape[0]
+    mass = np.concatenate([rng.uniform(50, 100, n), np.full(nw, 80.0)])
+    radius = np.concatenate([0.002 * mass[:n] + 0.15, np.full(nw, 0.1)])
+    h = 0.6
+    lo = np.array([-2.0, -2.0])
+    hi = np.array([width + 5.0, width + 2.0])
+    ncell, cs = [1, 1, 1], [1.0, 1.0, 1.0]
+    for k in range(2):
+        ncell[k], cs[k] = _cells_for(hi[k] - lo[k], h)
+    goal = np.tile([width + 3.0, width / 2], (n + nw, 1))
+    return Case(dim=2, ncell=tuple(ncell), cell_size=tuple(cs), origin=(float(lo[0]), float(lo[1]), 0.0),
+                boundary=(CUTOFF,) * 3, h=h, mass=80.0, rho0=1.0, c0=1.0, gamma=1.0, nu=0.0, dt=dt,
+                g=(0.0, 0.0, 0.0), pos=pos.astype(np.float32), vel=np.zeros((n + nw, 2), np.float32),
+                n_fixed=nw, name=name or f"social_room_{n}", model=SOCIAL, law=(2000.0, 0.08, 1.2e5, 0.5),
+                radius=radius.astype(np.float32), pmass=mass.astype(np.float32),
+                coef=rng.uniform(0, c_max, n + nw).astype(np.float32),
+                v0=np.concatenate([rng.uniform(0.8, 1.5, n), np.zeros(nw)]).astype(np.float32),
+                goal=goal.astype(np.float32))
 
 
 # ---------------------------------------------------------------------------

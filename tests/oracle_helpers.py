@@ -15,7 +15,8 @@ def domain_of(case: WL.Case) -> O.Domain:
 
 def params_of(case: WL.Case) -> O.Params:
     return O.Params(h=case.h, mass=case.mass, rho0=case.rho0, c0=case.c0, gamma=case.gamma,
-                    nu=case.nu, dt=case.dt, g=tuple(case.g), alpha_av=case.alpha_av)
+                    nu=case.nu, dt=case.dt, g=tuple(case.g), alpha_av=case.alpha_av,
+                    law=tuple(case.law) + (0.0,) * (4 - len(case.law)))
 
 
 def x64(case: WL.Case) -> np.ndarray:

@@ -139,3 +139,13 @@ def test_continuity_model_workspace_holds_the_extra_arrays(N):
     b = WL.scaled(a, model=WL.SUMMATION)
     # one float4 per particle more (the start-of-step velocity and density)
     assert _ws_bytes(N, [a])[1] >= _ws_bytes(N, [b])[1] + 16 * a.n
+
+
+def test_pair_law_tables_are_validated(N):
+    dem = WL.dem_damper()
+    assert _ws_bytes(N, [dem])[0] == N.OK
+    assert _ws_bytes(N, [WL.scaled(dem, law=(-0.1,))])[0] == N.ERR_INVALID_ARG   # negative friction
+    soc = WL.social_room(width=6.0)
+    assert _ws_bytes(N, [soc])[0] == N.OK
+    assert _ws_bytes(N, [WL.scaled(soc, law=(2000.0, 0.0, 1.2e5, 0.5))])[0] == N.ERR_INVALID_ARG  # B = 0
+    assert _ws_bytes(N, [WL.scaled(soc, law=(2000.0, 0.08, 1.2e5, float("nan")))])[0] == N.ERR_INVALID_ARG

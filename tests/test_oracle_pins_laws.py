@@ -205,3 +205,18 @@ def test_social_pair_terms_cancel_and_walls_stay():
     fixed[:20] = 1
     a = O.social(dom, prm, x, v, R, m, c, v0, goal, fixed=fixed)
     assert np.all(a[:20] == 0.0)
+
+
+def test_dem_sphere_sliding_on_a_symmetric_floor_feels_no_friction():
+    """A sphere pressed into the floor and sliding along it meets its own
+    image, whose velocity differs only in the normal component: v_t = 0, so
+    the symmetric face is frictionless (free slip), whatever c_f."""
+    dom = _dem_box(n_cells=(6, 6, 6), cs=0.01)
+    R = 0.004
+    m = 7850 * 4 / 3 * np.pi * R ** 3
+    q = (1 - NU ** 2) / E_STEEL_PAPER
+    prm = O.Params(h=0.005, mass=m, g=(0.0, 0.0, 0.0), law=(0.8,))
+    x = np.array([[0.031, 0.027, R - 2e-4]])
+    v = np.array([[0.7, -0.3, -0.2]])
+    a = O.dem(dom, prm, x, v, [R], [m], [q])
+    assert a[0, 0] == 0.0 and a[0, 1] == 0.0 and a[0, 2] > 0
