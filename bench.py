@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--cpu-sample", default="128x128x64", help="oracle sample box (lattice sites per axis)")
     ap.add_argument("--ex1a-only", action="store_true",
                     help="only the Example 1a dam break (continuity model, symmetric faces)")
+    ap.add_argument("--law-only", choices=("dem", "social"), default=None,
+                    help="only one pair-law workload (DEM damper or social force room)")
     ap.add_argument("--ex1a-scale", type=float, default=87.0,
                     help="resolution factor of the Example 1a dam break (87: 4.1M particles)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -107,8 +109,9 @@ def candidates_per_step(prob, case):
     return float((grid * s).sum().item())
 
 
-def timed_steps(prob, st, steps, warmup):
-    """Runs warmup + steps full steps; returns (wall s, per-phase ms [4], pairs)."""
+def timed_steps(prob, st, steps, warmup, step=None):
+    """Runs warmup + steps full steps; returns (wall s, per-phase ms [4], pairs).
+    `step(st, events)` runs one step (default: nauticle_step)."""
     import numpy as np
     import torch
 
@@ -120,7 +123,10 @@ def timed_steps(prob, st, steps, warmup):
     pairs = torch.zeros((), dtype=torch.int64, device=prob.device)
 
     def body(k):
-        prob.step(st, 1, events=evs[5 * k: 5 * k + 5])
+        if step is None:
+            prob.step(st, 1, events=evs[5 * k: 5 * k + 5])
+        else:
+            step(st, evs[5 * k: 5 * k + 5])
         pairs.add_(prob.cells.nbr_count[:n].sum(dtype=torch.int64))
 
     for k in range(warmup):  # the timed body itself, so every kernel module is loaded
@@ -301,6 +307,47 @@ def ex1a_extra(device, scale, steps=10, warmup=2):
             "oracle_paper_case": {"particles": small.n, "ms_per_step": round(t_or * 1e3, 3), "cores": 1}}
 
 
+def law_extra(device, which, steps=10, warmup=2):
+    """A pair law at scale: Example 2's DEM damper with 19^3 times the
+    table's 567 spheres (3,889,053, symmetric faces) packed at 0.99 of their
+    diameter (every sphere touching its lattice neighbours, a compressed
+    bed), or the social force room of side 800 m (654,394 people, fixed
+    walls); next to it the FP64 oracle's step on the paper-size case (the
+    567 spheres packed the same way / a 20 m room)."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
+
+    packed = dict(spacing=2 * 0.004 * 0.99, jitter=0.05)
+    case = WL.dem_damper(19, **packed) if which == "dem" else WL.social_room(width=800.0)
+    prob = N.Problem([case], device=device, max_nbr=32 if which == "dem" else 64)
+    st = prob.state_from_cases()
+    attrs = prob.law_attrs()
+    wall, phase, pairs = timed_steps(prob, st, steps, warmup,
+                                     step=lambda s_, ev: prob.step_law(s_, attrs, 1, events=ev))
+    del prob, st
+    small = WL.dem_damper(1, **packed) if which == "dem" else WL.social_room(width=20.0)
+    dom = O.Domain(dim=small.dim, n=small.ncell, cs=small.cell_size, origin=small.origin,
+                   periodic=tuple(b == WL.PERIODIC for b in small.boundary),
+                   symmetric=tuple(b == WL.SYMMETRIC for b in small.boundary))
+    prm = O.Params(h=small.h, mass=small.mass, rho0=small.rho0, c0=small.c0, gamma=small.gamma, nu=small.nu,
+                   dt=small.dt, g=small.g, law=tuple(small.law) + (0.0,) * (4 - len(small.law)))
+    k_or = 20
+    t0 = time.perf_counter()
+    O.step_law(which, dom, prm, small.pos.astype(np.float64), small.vel.astype(np.float64), small.radius,
+               small.pmass, small.coef, v0=small.v0, goal=small.goal, fixed=small.fixed_mask(), n_steps=k_or,
+               nthreads=1)
+    t_or = (time.perf_counter() - t0) / k_or
+    return {"workload": case.name, "particles": case.n, "fixed": case.n_fixed, "cells": list(case.ncell),
+            "steps_per_s": steps / wall, "ms_per_step": round(wall * 1e3 / steps, 4),
+            "pairs_within_2h_per_s": pairs / wall, "pairs_per_particle": round(pairs / steps / case.n, 2),
+            "phases": {"sort_reorder_ms": round(phase[0], 4), "neighbour_lists_ms": round(phase[1], 4),
+                       "pair_law_integrate_ms": round(phase[3], 4)},
+            "oracle_paper_case": {"particles": small.n, "ms_per_step": round(t_or * 1e3, 3), "cores": 1}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -313,6 +360,10 @@ def main():
     from paper_1710_08259_amd import workloads as WL
 
     device = "cuda:0"
+    if args.law_only:
+        print(json.dumps({"extra": {args.law_only: law_extra(device, args.law_only, args.steps, args.warmup)}}),
+              flush=True)
+        return
     if args.ex1a_only:
         print(json.dumps({"extra": {"ex1a": ex1a_extra(device, args.ex1a_scale, args.steps, args.warmup)}}),
               flush=True)
@@ -370,6 +421,10 @@ def main():
         line["extra"]["dam_break"] = dam_break_extra(device)
         torch.cuda.empty_cache()
         line["extra"]["ex1a"] = ex1a_extra(device, args.ex1a_scale)
+        torch.cuda.empty_cache()
+        line["extra"]["dem"] = law_extra(device, "dem")
+        torch.cuda.empty_cache()
+        line["extra"]["social"] = law_extra(device, "social")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args, case)
     print(json.dumps(line), flush=True)

@@ -187,16 +187,17 @@ hipError_t launch_law(const Plan& P, void* ws, StateDev sorted, const nauticle_c
     return hipGetLastError();
 }
 
+// Contact and crowd lists are short (a handful of entries in 2-D and 3-D
+// alike): groups of 4 pairs per pipeline stage, for four resident waves per
+// SIMD instead of two.
+constexpr uint32_t kLawGroup = 4;
+
 hipError_t launch_interact(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                            const LawAttrsDev& attrs, FieldsDev f, const StateDev* next, hipStream_t s)
 {
     if (P.n_items == 0) return hipSuccess;
-    const bool d3 = P.dim_max == 3;
-    if (P.model == NAUTICLE_MODEL_DEM)
-        return d3 ? launch_law<DemLaw, 8>(P, ws, sorted, cells, attrs, f, next, s)
-                  : launch_law<DemLaw, 4>(P, ws, sorted, cells, attrs, f, next, s);
-    return d3 ? launch_law<SocialLaw, 8>(P, ws, sorted, cells, attrs, f, next, s)
-              : launch_law<SocialLaw, 4>(P, ws, sorted, cells, attrs, f, next, s);
+    if (P.model == NAUTICLE_MODEL_DEM) return launch_law<DemLaw, kLawGroup>(P, ws, sorted, cells, attrs, f, next, s);
+    return launch_law<SocialLaw, kLawGroup>(P, ws, sorted, cells, attrs, f, next, s);
 }
 
 }  // namespace nau
