@@ -53,7 +53,9 @@
  *     paper's interaction interface allows (Sec. 6): the DEM contact law of
  *     Example 2 (eq. DEM_force with the effective quantities of eq.
  *     effective_quantities) and the social force model (eq.
- *     social_force_model, with the pair term of its listing).
+ *     social_force_model, with the pair term of its listing);
+ *   - Example 1b: the Cahn-Hilliard equation on a surface with the
+ *     Laplacian of eq. diffop3 (sph_L0) and its adaptive time step.
  * Wall particles are ordinary particles held fixed (paper Sec. 5.3 builds
  * walls from fixed particles): they contribute density and pressure, keep
  * v = 0 and are not integrated.
@@ -1152,6 +1154,105 @@ int or_step_law(int law, const or_domain* D, const or_params* P, int64_t n, doub
     }
     if (rc == 0 && n_steps > 0 && a_out) memcpy(a_out, a, sizeof(double) * 3 * (size_t)n);
     free(a);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Example 1b: Cahn-Hilliard with the SPH Laplacian (sph_L0)                  */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    const or_domain* D;
+    const or_params* P;
+    const or_grid64* G;
+    const double* x;
+    const double* A;
+    const int64_t* which;
+    double* out;
+    int kdim;   /* dimension the kernel is normalised in */
+    double acc;
+} or_lap_ctx;
+
+/* One term of eq. diffop3 as Example 1b discretises it:
+ *   2 (A_j - A_i) (r_j - r_i) . grad_i W_ij / |r_j - r_i|^2 V_j
+ *   = 2 (A_i - A_j) F_ij V_j      (grad_i W_ij = F_ij (r_i - r_j)),
+ * V_j = m / rho0. */
+static void or_lap_visit(void* c, int64_t i, int64_t j, const double r[3], double rn,
+                         const double sgn[3])
+{
+    (void)r; (void)sgn;
+    or_lap_ctx* ctx = (or_lap_ctx*)c;
+    double F = or_F(ctx->kdim, ctx->P->h, rn);
+    ctx->acc += 2.0 * (ctx->A[i] - ctx->A[j]) * F * ctx->P->mass / ctx->P->rho0;
+}
+
+static void or_lap_range(void* c, int64_t begin, int64_t end)
+{
+    or_lap_ctx local = *(or_lap_ctx*)c;
+    for (int64_t s = begin; s < end; ++s) {
+        int64_t i = local.which ? local.which[s] : s;
+        local.acc = 0.0;
+        or_for_neighbours(local.G, local.x, i, or_lap_visit, &local);
+        local.out[s] = local.acc;
+    }
+}
+
+/* SPH Laplacian of the scalar field A (sph_L0: eq. diffop3 with V = m/rho0),
+ * kernel normalised in kdim dimensions (Example 1b: 2, on a surface in 3-D
+ * space). */
+int or_laplacian(const or_domain* D, const or_params* P, int kdim, int64_t n, const double* x,
+                 const double* A, int64_t n_eval, const int64_t* which, double* out, int nthreads)
+{
+    or_grid64 G;
+    if (or_grid64_build(&G, D, P->h, n, x) != 0) return -1;
+    or_lap_ctx ctx = {D, P, &G, x, A, which, out, kdim, 0.0};
+    or_parallel(which ? n_eval : n, nthreads, or_lap_range, &ctx);
+    or_grid64_free(&G);
+    return 0;
+}
+
+/* n_steps of Example 1b's equations in their listed order, the particles
+ * fixed (so the neighbours are found once):
+ *   eq1 time += dt;  eq2 mu = c^3 - c - gamma L0(c);  eq3 cdot = D L0(mu);
+ *   eq4 c += dt cdot;  eq5 dt = fac min(1 / max_i |cdot_i|, dt_g),
+ * dt_g = gamma / (2h)^2; D, gamma, fac = P->law[0..2]; kernel in kdim
+ * dimensions.  c is updated in place; clock = {time, dt} in/out; mu and
+ * cdot (optional) receive the last step's fields. */
+int or_ch_steps(const or_domain* D, const or_params* P, int kdim, int64_t n, const double* x,
+                double* c, double* clock, int32_t n_steps, double* mu_out, double* cdot_out,
+                int nthreads)
+{
+    size_t N = (size_t)(n > 0 ? n : 1);
+    double* mu = (double*)malloc(sizeof(double) * N);
+    double* lc = (double*)malloc(sizeof(double) * N);
+    double* cdot = (double*)malloc(sizeof(double) * N);
+    if (!mu || !lc || !cdot) return -1;
+    double Dc = P->law[0], gamma = P->law[1], fac = P->law[2];
+    double dt_g = gamma / (4.0 * P->h * P->h);
+    int rc = 0;
+    for (int32_t s = 0; s < n_steps && rc == 0; ++s) {
+        clock[0] += clock[1];
+        rc = or_laplacian(D, P, kdim, n, x, c, 0, NULL, lc, nthreads);
+        if (rc != 0) break;
+        for (int64_t i = 0; i < n; ++i) mu[i] = c[i] * c[i] * c[i] - c[i] - gamma * lc[i];
+        rc = or_laplacian(D, P, kdim, n, x, mu, 0, NULL, cdot, nthreads);
+        if (rc != 0) break;
+        double mx = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            cdot[i] *= Dc;
+            c[i] += clock[1] * cdot[i];
+            if (fabs(cdot[i]) > mx) mx = fabs(cdot[i]);
+        }
+        double lim = mx > 0.0 ? 1.0 / mx : dt_g;
+        clock[1] = fac * (lim < dt_g ? lim : dt_g);
+    }
+    if (rc == 0 && n_steps > 0) {
+        if (mu_out) memcpy(mu_out, mu, sizeof(double) * (size_t)n);
+        if (cdot_out) memcpy(cdot_out, cdot, sizeof(double) * (size_t)n);
+    }
+    free(mu);
+    free(lc);
+    free(cdot);
     return rc;
 }
 

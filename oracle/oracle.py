@@ -20,7 +20,9 @@ Every function follows the paper (arXiv:1710.08259):
   (eq. SPH_fluid_momentum), stepped in the order of its equations eq1-eq7;
 * two further pair laws on the same neighbour loop (Sec. 6, the interaction
   interface): the DEM contact law of Example 2 (eq. DEM_force) and the
-  social force model (eq. social_force_model).
+  social force model (eq. social_force_model);
+* Example 1b: Cahn-Hilliard with the SPH Laplacian sph_L0 (eq. diffop3 as
+  Example 1b discretises it) and its adaptive time step.
 
 The one-step adjoint (:func:`step_vjp`) is not in the paper; it is the exact
 reverse-mode derivative of :func:`step` with one step, pinned against central
@@ -178,6 +180,11 @@ def _load():
     lib.or_step_law.restype = ctypes.c_int
     lib.or_step_law.argtypes = [ctypes.c_int, P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, vp, vp,
                                 i32, vp, ctypes.c_int]
+    lib.or_laplacian.restype = ctypes.c_int
+    lib.or_laplacian.argtypes = [P(_Domain), P(_Params), ctypes.c_int, i64, vp, vp, i64, vp, vp, ctypes.c_int]
+    lib.or_ch_steps.restype = ctypes.c_int
+    lib.or_ch_steps.argtypes = [P(_Domain), P(_Params), ctypes.c_int, i64, vp, vp, vp, i32, vp, vp,
+                                ctypes.c_int]
     lib.or_step_vjp.restype = ctypes.c_int
     lib.or_step_vjp.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, vp,
                                 P(dbl), P(dbl), ctypes.c_int]
@@ -533,6 +540,41 @@ def step_law(law: str, dom: Domain, prm: Params, x, v, R, m, q, v0=None, goal=No
         raise MemoryError("or_step_law failed")
     d = dom.dim
     return x3[:, :d], v3[:, :d], a[:, :d]
+
+
+# --------------------------------------------------------------------------
+# Example 1b: Cahn-Hilliard with sph_L0
+# --------------------------------------------------------------------------
+
+def laplacian(dom: Domain, prm: Params, x, A, kdim=None, which=None, nthreads=None):
+    """sph_L0: L(A)_i = 2 sum_j (A_i - A_j) F_ij m/rho0, kernel normalised in
+    kdim dimensions (default: the domain's)."""
+    x3 = _x3(x)
+    n = x3.shape[0]
+    w = None if which is None else np.ascontiguousarray(which, dtype=np.int64)
+    m = n if w is None else w.shape[0]
+    out = np.zeros(m)
+    rc = _load().or_laplacian(ctypes.byref(dom._c()), ctypes.byref(prm._c()), int(kdim or dom.dim), n,
+                              _ptr(x3), _ptr(_f64(A)), m, _ptr(w), _ptr(out), nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_laplacian failed")
+    return out
+
+
+def ch_steps(dom: Domain, prm: Params, x, c, time, dt, n_steps, kdim=2, nthreads=None):
+    """n_steps of Example 1b (eq1-eq5); returns (c, time, dt, mu, cdot), the
+    last two of the last step.  D, gamma, fac = prm.law[0..2]."""
+    x3 = _x3(x)
+    n = x3.shape[0]
+    cc = np.array(c, dtype=np.float64, copy=True)
+    clock = np.array([time, dt], dtype=np.float64)
+    mu = np.zeros(n)
+    cdot = np.zeros(n)
+    rc = _load().or_ch_steps(ctypes.byref(dom._c()), ctypes.byref(prm._c()), int(kdim), n, _ptr(x3), _ptr(cc),
+                             _ptr(clock), int(n_steps), _ptr(mu), _ptr(cdot), nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_ch_steps failed")
+    return cc, float(clock[0]), float(clock[1]), mu, cdot
 
 
 def step_vjp(dom: Domain, prm: Params, x, v, lam_x_next, lam_v_next, fixed=None, nthreads=None):

@@ -36,6 +36,7 @@ SUMMATION = 0
 CONTINUITY = 1
 DEM = 2         # Example 2's contact law
 SOCIAL = 3      # the social force model
+CAHN_HILLIARD = 4  # Example 1b
 
 
 def _f32(x: float) -> float:
@@ -69,7 +70,7 @@ class Case:
     law: tuple = ()                       # pair-law constants (DEM: (c_f,); SOCIAL: (A, B, k, tau))
     radius: Optional[np.ndarray] = None   # (n,) pair-law attributes, input order
     pmass: Optional[np.ndarray] = None
-    coef: Optional[np.ndarray] = None     # DEM: (1 - nu^2)/E; SOCIAL: attraction c
+    coef: Optional[np.ndarray] = None     # DEM: (1 - nu^2)/E; SOCIAL: attraction c; CAHN_HILLIARD: c
     v0: Optional[np.ndarray] = None       # SOCIAL: desired speed
     goal: Optional[np.ndarray] = None     # SOCIAL: (n, dim) absolute target
 
@@ -304,6 +305,37 @@ def social_room(width: float = 20.0, density: float = 1.0, seed: int = 11, c_max
                 coef=rng.uniform(0, c_max, n + nw).astype(np.float32),
                 v0=np.concatenate([rng.uniform(0.8, 1.5, n), np.zeros(nw)]).astype(np.float32),
                 goal=goal.astype(np.float32))
+
+
+def ch_sphere(dx: float = 0.07, radius: float = 2.0, seed: int = 13, name: str = "") -> Case:
+    """Example 1b: the Cahn-Hilliard equation on a sphere.  The paper reads
+    its points from a file it does not include; here a Fibonacci lattice of
+    round(4 pi R^2 / dx^2) points on a sphere of radius ``radius`` (2 m: inside
+    the listing's box of +-15 cells of 2h) stands in for it.  dx = 0.07,
+    h = 1.05 dx, m = dx^2 rho0, rho0 = 1000, D = 0.003, gamma = (2h/3)^2,
+    dt = 0.003 to start, then 0.1 min(1/max|cdot|, gamma/(2h)^2);
+    c ~ U(-1, 1).  Cells of 2h, +-15 of them (scaled with h) per axis,
+    periodic (the listing's boundary 0)."""
+    rng = np.random.default_rng(seed)
+    n = int(round(4.0 * math.pi * radius * radius / dx ** 2))
+    k = np.arange(n) + 0.5
+    phi = np.arccos(1.0 - 2.0 * k / n)
+    th = math.pi * (1.0 + 5.0 ** 0.5) * k
+    pos = np.stack([radius * np.cos(th) * np.sin(phi), radius * np.sin(th) * np.sin(phi),
+                    radius * np.cos(phi)], axis=1)
+    h = 1.05 * dx
+    cs = _f32(2.0 * h)
+    if cs < 2.0 * h:
+        cs = float(np.nextafter(np.float32(cs), np.float32(np.inf)))
+    half = int(math.ceil(1.1 * radius / cs))
+    nc = 2 * max(half, 15)
+    o = _f32(-nc / 2 * cs)
+    gamma = (2.0 * h / 3.0) ** 2
+    return Case(dim=3, ncell=(nc, nc, nc), cell_size=(cs, cs, cs), origin=(o, o, o), boundary=(PERIODIC,) * 3,
+                h=h, mass=dx * dx * 1000.0, rho0=1000.0, c0=1.0, gamma=1.0, nu=0.0, dt=0.003,
+                g=(0.0, 0.0, 0.0), pos=pos.astype(np.float32), vel=np.zeros((n, 3), np.float32), n_fixed=0,
+                name=name or f"ch_sphere_{n}", model=CAHN_HILLIARD, law=(0.003, gamma, 0.1),
+                coef=rng.uniform(-1.0, 1.0, n).astype(np.float32))
 
 
 # ---------------------------------------------------------------------------
