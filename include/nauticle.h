@@ -100,12 +100,15 @@ enum { NAUTICLE_PERIODIC = 0, NAUTICLE_CUTOFF = 1, NAUTICLE_SYMMETRIC = 2 };
  *   CONTINUITY: Example 1a -- density evolved by the continuity equation,
  *               p = c0^2 (rho - rho0), artificial viscosity (alpha_av);
  *   DEM:        Example 2's contact law (nauticle_interact);
- *   SOCIAL:     the social force model (nauticle_interact). */
+ *   SOCIAL:     the social force model (nauticle_interact);
+ *   CAHN_HILLIARD: Example 1b on fixed particles (nauticle_ch_steps); its
+ *               kernel is normalised in 2-D (a surface in 3-D space). */
 enum {
     NAUTICLE_MODEL_SUMMATION = 0,
     NAUTICLE_MODEL_CONTINUITY = 1,
     NAUTICLE_MODEL_DEM = 2,
-    NAUTICLE_MODEL_SOCIAL = 3
+    NAUTICLE_MODEL_SOCIAL = 3,
+    NAUTICLE_MODEL_CAHN_HILLIARD = 4
 };
 
 /* Sentinel of an empty cell in cell_start / cell_end. */
@@ -138,7 +141,8 @@ typedef struct {
  * g: body acceleration; alpha_av: artificial viscosity coefficient
  * (Pi_ij = -alpha_av c0 h w / (rho_i |r_ij|^2) for approaching pairs,
  * 0.1 in Example 1a); law: constants of a pair law (DEM: law[0] = c_f, the
- * Coulomb friction coefficient; SOCIAL: law[0..3] = A, B, k, tau); model:
+ * Coulomb friction coefficient; SOCIAL: law[0..3] = A, B, k, tau;
+ * CAHN_HILLIARD: law[0..2] = D, gamma, the time-step factor 0.1); model:
  * NAUTICLE_MODEL_*, the same for every case of a table (SUMMATION uses gamma
  * and nu, CONTINUITY alpha_av, the pair laws law[] and per-particle
  * attributes); reserved: 0. */
@@ -376,6 +380,23 @@ nauticle_status nauticle_interact(const nauticle_case* cases, int32_t n_cases,
 nauticle_status nauticle_step_law(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
                                   int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
                                   const nauticle_law_attrs* attrs, hipEvent_t* phase_events, void* ws,
+                                  size_t ws_bytes, hipStream_t stream);
+
+/* n_steps of Example 1b [eq. cahnhilliard_sph_discretized; its listing's
+ * eq1-eq5] on particles that do not move, so `sorted` and `cells` come
+ * from one nauticle_build_cells and are reused (the paper runs the search
+ * only when the layout changes [Sec. 4]).  Per step, in order:
+ *   time += dt;  mu = c^3 - c - gamma L(c);  cdot = D L(mu);  c += dt cdot;
+ *   dt = fac min(1 / max_i |cdot_i|, gamma / (2h)^2),
+ * L(A)_i = 2 (m/rho0) sum_j (A_i - A_j) F_ij [eq. diffop3 as the example
+ * discretises it], F with the kernel normalised in 2-D.  c (sorted order,
+ * FP32) is updated in place; mu, cdot (optional) receive the last step's
+ * fields; clock (device FP64, {time, dt} per case) is read and advanced on
+ * the device, so no step waits for the host.  Requires a CAHN_HILLIARD
+ * table. */
+nauticle_status nauticle_ch_steps(const nauticle_case* cases, int32_t n_cases,
+                                  const nauticle_state* sorted, const nauticle_cells* cells, float* c,
+                                  float* mu, float* cdot, double* clock, int32_t n_steps, void* ws,
                                   size_t ws_bytes, hipStream_t stream);
 
 /* n_steps full steps in place: build_cells(state -> workspace copy),

@@ -103,7 +103,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
             !std::isfinite(q.g[0]) || !std::isfinite(q.g[1]) || !std::isfinite(q.g[2]) ||
             !std::isfinite(q.alpha_av) || q.alpha_av < 0.0)
             return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: non-finite or non-positive parameter", b);
-        if (q.model < NAUTICLE_MODEL_SUMMATION || q.model > NAUTICLE_MODEL_SOCIAL)
+        if (q.model < NAUTICLE_MODEL_SUMMATION || q.model > NAUTICLE_MODEL_CAHN_HILLIARD)
             return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: unknown model %d", b, q.model);
         for (int k = 0; k < 4; ++k)
             if (!std::isfinite(q.law[k])) return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: law[%d] not finite", b, k);
@@ -111,6 +111,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
             return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: friction coefficient < 0", b);
         if (q.model == NAUTICLE_MODEL_SOCIAL && (!(q.law[1] > 0.0) || !(q.law[3] > 0.0)))
             return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: social force needs B > 0 and tau > 0", b);
+        if (q.model == NAUTICLE_MODEL_CAHN_HILLIARD && (q.law[0] < 0.0 || q.law[1] < 0.0 || !(q.law[2] > 0.0)))
+            return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: Cahn-Hilliard needs D >= 0, gamma >= 0, factor > 0", b);
         if (q.model != model0) return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: all cases must share one model", b);
         uint64_t ncell = 1;
         for (int k = 0; k < 3; ++k) {
@@ -158,8 +160,10 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         C.offset = static_cast<uint32_t>(n_total);
         C.n = static_cast<uint32_t>(c.n);
         C.n_fluid = static_cast<uint32_t>(c.n - c.n_fixed);
-        const double alpha = d.dim == 2 ? 7.0 / (4.0 * M_PI * q.h * q.h)
-                                        : 21.0 / (16.0 * M_PI * q.h * q.h * q.h);
+        // the kernel's dimension: the domain's, or 2 for Example 1b's surface
+        const int kdim = q.model == NAUTICLE_MODEL_CAHN_HILLIARD ? 2 : d.dim;
+        const double alpha = kdim == 2 ? 7.0 / (4.0 * M_PI * q.h * q.h)
+                                       : 21.0 / (16.0 * M_PI * q.h * q.h * q.h);
         C.R2 = static_cast<float>(4.0 * q.h * q.h);
         C.inv_h = static_cast<float>(1.0 / q.h);
         C.m = static_cast<float>(q.mass);
@@ -176,6 +180,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         C.c2 = static_cast<float>(q.c0 * q.c0);
         C.h = static_cast<float>(q.h);
         for (int k = 0; k < 4; ++k) C.law[k] = static_cast<float>(q.law[k]);
+        if (q.model == NAUTICLE_MODEL_CAHN_HILLIARD)  // the gradient limit of dt, gamma / (2h)^2
+            C.law[3] = static_cast<float>(q.law[1] / (4.0 * q.h * q.h));
         C.av_coef = static_cast<float>(q.alpha_av * q.c0 * q.h * q.mass);
         C.item_first = static_cast<uint32_t>(D->items.size());
         for (int64_t first = 0; first < c.n; first += block) {
@@ -269,6 +275,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     L.adj4 = take(16 * N);
     L.adj4b = take(16 * N);
     L.vr4 = model0 == NAUTICLE_MODEL_CONTINUITY ? take(16 * N) : 0;
+    L.chmax = take(sizeof(uint32_t) * static_cast<size_t>(n_cases));
     L.partial = take(2 * sizeof(double) * n_items_max);
     L.inv_map = take(4 * N);
     L.total = off;
@@ -608,6 +615,26 @@ nauticle_status nauticle_step_law(const nauticle_case* cases, int32_t n_cases, n
     return NAUTICLE_OK;
 }
 
+nauticle_status nauticle_ch_steps(const nauticle_case* cases, int32_t n_cases, const nauticle_state* sorted,
+                                  const nauticle_cells* cells, float* c, float* mu, float* cdot, double* clock,
+                                  int32_t n_steps, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if (P->model != NAUTICLE_MODEL_CAHN_HILLIARD)
+        return fail(NAUTICLE_ERR_INVALID_ARG, "nauticle_ch_steps needs a Cahn-Hilliard table");
+    if (n_steps < 0) return fail(NAUTICLE_ERR_INVALID_ARG, "n_steps < 0");
+    if ((st = check_state(*P, sorted, false, "sorted")) != NAUTICLE_OK) return st;
+    if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
+    if (!clock) return fail(NAUTICLE_ERR_INVALID_ARG, "clock is null");
+    if (P->n_total && !c) return fail(NAUTICLE_ERR_INVALID_ARG, "c is null");
+    if (P->n_total && (c == mu || c == cdot || (mu && mu == cdot)))
+        return fail(NAUTICLE_ERR_INVALID_ARG, "c, mu and cdot must be distinct");
+    hipError_t e = launch_ch_steps(*P, ws, to_dev_model(*P, sorted), *cells, c, mu, cdot, clock, n_steps, stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_ch_steps");
+}
+
 nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases, const nauticle_state* sorted,
                                     const nauticle_cells* cells, nauticle_fields* fields, nauticle_state* next,
                                     void* ws, size_t ws_bytes, hipStream_t stream)
@@ -642,6 +669,8 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
     if (st != NAUTICLE_OK) return st;
     if (n_steps < 0) return fail(NAUTICLE_ERR_INVALID_ARG, "n_steps < 0");
     if (is_law(*P)) return fail(NAUTICLE_ERR_INVALID_ARG, "pair-law tables step with nauticle_step_law");
+    if (P->model == NAUTICLE_MODEL_CAHN_HILLIARD)
+        return fail(NAUTICLE_ERR_INVALID_ARG, "Cahn-Hilliard tables step with nauticle_ch_steps");
     const bool cont = P->model == NAUTICLE_MODEL_CONTINUITY;
     if ((st = check_state(*P, state, true, "state", cont)) != NAUTICLE_OK) return st;
     if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;

@@ -121,6 +121,7 @@ struct Layout {
     size_t adj4;         // float4: adjoint A = dt (lam_v' + dt lam_x'), 0
     size_t adj4b;        // float4: A, rhobar (after adjoint pass A)
     size_t vr4;          // float4: velocity (0 for fixed), 1 / rho of the step's start (continuity model)
+    size_t chmax;        // per-case max |cdot| as float bits (Cahn-Hilliard)
     size_t partial;      // per-item FP64 partial sums (2 per item)
     size_t inv_map;      // id -> position map (N u32)
     size_t total;
@@ -364,6 +365,9 @@ hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticl
 struct LawAttrsDev;
 hipError_t launch_interact(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                            const LawAttrsDev& attrs, FieldsDev f, const StateDev* next, hipStream_t s);
+// ch.hip: n_steps of Example 1b on fixed particles (lists of `cells`)
+hipError_t launch_ch_steps(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells, float* c,
+                           float* mu, float* cdot, double* clock, int32_t n_steps, hipStream_t s);
 // adjoint.hip
 hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
                           FieldsDev f, const float* const lxn[3], const float* const lvn[3],

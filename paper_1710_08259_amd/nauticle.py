@@ -34,6 +34,7 @@ MODEL_SUMMATION = 0
 MODEL_CONTINUITY = 1
 MODEL_DEM = 2
 MODEL_SOCIAL = 3
+MODEL_CAHN_HILLIARD = 4
 MIRROR_CODE = 3
 EMPTY = 0xFFFFFFFF
 NBR_INDEX_BITS = 26
@@ -42,7 +43,7 @@ ENTRY_POINTS = (
     "nauticle_cells_total", "nauticle_workspace_bytes", "nauticle_prepare", "nauticle_bin",
     "nauticle_unbin", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_continuity",
     "nauticle_sph_forces",
-    "nauticle_step", "nauticle_interact", "nauticle_step_law", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
+    "nauticle_step", "nauticle_interact", "nauticle_step_law", "nauticle_ch_steps", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
     "nauticle_last_error",
 )
 
@@ -158,6 +159,9 @@ def lib():
     L.nauticle_step_law.restype = st
     L.nauticle_step_law.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(CLawAttrs), P(vp), vp,
                                     ctypes.c_size_t, vp]
+    L.nauticle_ch_steps.restype = st
+    L.nauticle_ch_steps.argtypes = [P(CCase), i32, P(CState), P(CCells), vp, vp, vp, vp, i32, vp, ctypes.c_size_t,
+                                    vp]
     L.nauticle_sph_adjoint.restype = st
     L.nauticle_sph_adjoint.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CFields), P(ptr3), P(ptr3),
                                        P(ptr3), P(ptr3), vp, vp, vp, ctypes.c_size_t, vp]
@@ -468,6 +472,16 @@ class Problem:
                                        ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()),
                                        ctypes.byref(attrs.c()), ev, *self._ws()), "nauticle_step_law")
         return st
+
+    def ch_steps(self, c: torch.Tensor, clock: torch.Tensor, n_steps: int = 1, mu: Optional[torch.Tensor] = None,
+                 cdot: Optional[torch.Tensor] = None, sorted_: Optional[State] = None, cells: Optional[Cells] = None):
+        """Example 1b steps on the lists of the last build_cells: c (FP32,
+        sorted order) in place; clock (FP64 device, {time, dt} per case)."""
+        s = self.sorted if sorted_ is None else sorted_
+        cl = self.cells if cells is None else cells
+        _check(lib().nauticle_ch_steps(self.table, self.n_cases, ctypes.byref(s.c()), ctypes.byref(cl.c()), _p(c),
+                                       _p(mu), _p(cdot), _p(clock), int(n_steps), *self._ws()), "nauticle_ch_steps")
+        return c
 
     def _events(self, events, n_steps):
         if events is None:
