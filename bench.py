@@ -82,6 +82,7 @@ def parse():
     ap.add_argument("--cpu-sample", default="128x128x64", help="oracle sample box (lattice sites per axis)")
     ap.add_argument("--ex1a-only", action="store_true",
                     help="only the Example 1a dam break (continuity model, symmetric faces)")
+    ap.add_argument("--ch-only", action="store_true", help="only the Example 1b Cahn-Hilliard sphere")
     ap.add_argument("--law-only", choices=("dem", "social"), default=None,
                     help="only one pair-law workload (DEM damper or social force room)")
     ap.add_argument("--ex1a-scale", type=float, default=87.0,
@@ -348,6 +349,56 @@ def law_extra(device, which, steps=10, warmup=2):
             "oracle_paper_case": {"particles": small.n, "ms_per_step": round(t_or * 1e3, 3), "cores": 1}}
 
 
+def ch_extra(device, dx=0.005, steps=20, warmup=3):
+    """Example 1b refined: the Cahn-Hilliard equation on a Fibonacci sphere
+    of radius 2 m at dx = 0.005 (2,010,619 points; the paper's dx = 0.07
+    gives 10,258), lists built once (fixed particles), steps timed with the
+    device-side adaptive dt; next to it the FP64 oracle's step at the
+    paper's dx."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as O
+    from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
+
+    case = WL.ch_sphere(dx=dx)
+    prob = N.Problem([case], device=device, max_nbr=32)
+    st = prob.state_from_cases()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.build_cells(st)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    perm = prob.cells.perm[: case.n].long()
+    c = torch.from_numpy(case.coef).to(device)[perm].contiguous()
+    clock = torch.tensor([0.0, case.dt], dtype=torch.float64, device=device)
+    prob.ch_steps(c, clock, warmup)
+    torch.cuda.synchronize()
+    pairs = int(prob.cells.nbr_count[: case.n].sum(dtype=torch.int64).item())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    prob.ch_steps(c, clock, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    prob.check()
+    ms = e0.elapsed_time(e1) / steps
+    t_sim, dt_now = clock.cpu().tolist()
+    small = WL.ch_sphere()
+    dom = O.Domain(dim=3, n=small.ncell, cs=small.cell_size, origin=small.origin, periodic=(True,) * 3)
+    prm = O.Params(h=small.h, mass=small.mass, rho0=small.rho0, law=tuple(small.law) + (0.0,))
+    k_or = 5
+    t0 = time.perf_counter()
+    O.ch_steps(dom, prm, small.pos.astype(np.float64), small.coef.astype(np.float64), 0.0, small.dt, k_or,
+               nthreads=1)
+    t_or = (time.perf_counter() - t0) / k_or
+    return {"workload": case.name, "particles": case.n, "cells": list(case.ncell), "dx": dx,
+            "ms_per_step": round(ms, 4), "steps_per_s": 1e3 / ms, "pairs_per_particle": round(pairs / case.n, 2),
+            "laplacian_pairs_per_s": 2 * pairs / (ms * 1e-3), "lists_built_once_ms": round(t_build * 1e3, 2),
+            "sim_time": t_sim, "dt": dt_now,
+            "oracle_paper_case": {"particles": small.n, "ms_per_step": round(t_or * 1e3, 3), "cores": 1}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -360,6 +411,9 @@ def main():
     from paper_1710_08259_amd import workloads as WL
 
     device = "cuda:0"
+    if args.ch_only:
+        print(json.dumps({"extra": {"ch": ch_extra(device)}}), flush=True)
+        return
     if args.law_only:
         print(json.dumps({"extra": {args.law_only: law_extra(device, args.law_only, args.steps, args.warmup)}}),
               flush=True)
@@ -425,6 +479,8 @@ def main():
         line["extra"]["dem"] = law_extra(device, "dem")
         torch.cuda.empty_cache()
         line["extra"]["social"] = law_extra(device, "social")
+        torch.cuda.empty_cache()
+        line["extra"]["ch"] = ch_extra(device)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args, case)
     print(json.dumps(line), flush=True)

@@ -275,7 +275,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     L.adj4 = take(16 * N);
     L.adj4b = take(16 * N);
     L.vr4 = model0 == NAUTICLE_MODEL_CONTINUITY ? take(16 * N) : 0;
-    L.chmax = take(sizeof(uint32_t) * static_cast<size_t>(n_cases));
+    L.chmax = take(sizeof(float) * n_items_max);
     L.partial = take(2 * sizeof(double) * n_items_max);
     L.inv_map = take(4 * N);
     L.total = off;

@@ -4,8 +4,9 @@
 //
 // Per step (the example's eq1-eq5 in order):
 //   k_ch_mu:    mu_i = c_i^3 - c_i - gamma L(c)_i,
-//   k_ch_cdot:  cdot_i = D L(mu)_i,  c_i += dt cdot_i,  max |cdot| per case,
-//   k_ch_clock: time += dt;  dt = fac min(1 / max|cdot|, gamma / (2h)^2),
+//   k_ch_cdot:  cdot_i = D L(mu)_i,  c_i += dt cdot_i,  max |cdot| per item,
+//   k_ch_clock: max over the case's items; time += dt;
+//               dt = fac min(1 / max|cdot|, gamma / (2h)^2),
 // with L(A)_i = 2 V sum_j (A_i - A_j) F_ij (eq. diffop3 as the example
 // discretises it; V = m / rho0; F with the kernel normalised in 2-D).  The
 // particles never move, so the neighbour lists are built once by the caller
@@ -17,13 +18,8 @@
 
 namespace nau {
 
-constexpr uint32_t kChGroup = 8;
-
-__global__ void k_ch_zero(uint32_t* __restrict__ a, uint32_t n)
-{
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = 0u;
-}
+// ~12 neighbours per particle on the surface: groups of 4 pairs per stage
+constexpr uint32_t kChGroup = 4;
 
 // (offsets, c) of every sorted particle.
 __global__ void __launch_bounds__(kMaxBlock)
@@ -99,11 +95,12 @@ __global__ void __launch_bounds__(kMaxBlock)
 k_ch_cdot(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
           float4* __restrict__ rc, const float4* __restrict__ rm, const uint32_t* __restrict__ nbr,
           const uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total, float* __restrict__ c_out,
-          float* __restrict__ cdot_out, const double* __restrict__ clock, uint32_t* __restrict__ maxbits,
+          float* __restrict__ cdot_out, const double* __restrict__ clock, float* __restrict__ item_max,
           uint32_t* err)
 {
     __shared__ ShiftTable tab;
     __shared__ uint32_t s_pos;
+    __shared__ float s_max[kMaxBlock / 64];
     for_each_item(Q, &s_pos, [&](uint32_t ix) {
         const Item it = items[ix];
         const CaseDev& C = cases[it.case_id];
@@ -124,27 +121,41 @@ k_ch_cdot(const CaseDev* __restrict__ cases, const Item* __restrict__ items, Ite
             a = fabsf(cd);
             if (!isfinite(cn)) set_error(err, kErrNonFinite);
         }
-        // the wave's maximum, then one atomic per wave (|cdot| >= 0, so the
-        // float bits order like the values)
+        // the item's maximum: within each wave, then across the waves in
+        // LDS; one plain store per item (no atomics on a shared address)
         for (int off = 32; off > 0; off >>= 1) a = fmaxf(a, __shfl_xor(a, off));
-        if ((threadIdx.x & 63u) == 0u && a > 0.0f) atomicMax(&maxbits[it.case_id], __float_as_uint(a));
+        if ((threadIdx.x & 63u) == 0u) s_max[threadIdx.x >> 6] = a;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = 0.0f;
+            for (uint32_t w = 0; w < blockDim.x / 64; ++w) m = fmaxf(m, s_max[w]);
+            item_max[ix] = m;
+        }
+        __syncthreads();  // s_max is reused by the next item
     });
 }
 
-// eq1 and eq5 for every case: time += dt; dt = fac min(1 / max|cdot|, dt_g);
-// clears the maximum for the next step.
-__global__ void k_ch_clock(const CaseDev* __restrict__ cases, uint32_t n_cases, double* __restrict__ clock,
-                           uint32_t* __restrict__ maxbits)
+// eq1 and eq5, one workgroup per case: the maximum of |cdot| over the
+// case's items, then time += dt; dt = fac min(1 / max|cdot|, dt_g).
+__global__ void __launch_bounds__(kBlock)
+k_ch_clock(const CaseDev* __restrict__ cases, double* __restrict__ clock, const float* __restrict__ item_max)
 {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n_cases) return;
+    __shared__ float s_max[kBlock / 64];
+    const uint32_t b = blockIdx.x;
     const CaseDev& C = cases[b];
-    const double dt_g = static_cast<double>(C.law[3]);
-    const double mx = static_cast<double>(__uint_as_float(maxbits[b]));
-    const double lim = mx > 0.0 ? 1.0 / mx : dt_g;
-    clock[2 * b] += clock[2 * b + 1];
-    clock[2 * b + 1] = static_cast<double>(C.law[2]) * (lim < dt_g ? lim : dt_g);
-    maxbits[b] = 0u;
+    float m = 0.0f;
+    for (uint32_t k = threadIdx.x; k < C.item_count; k += blockDim.x) m = fmaxf(m, item_max[C.item_first + k]);
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63u) == 0u) s_max[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float mx = 0.0f;
+        for (uint32_t w = 0; w < blockDim.x / 64; ++w) mx = fmaxf(mx, s_max[w]);
+        const double dt_g = static_cast<double>(C.law[3]);
+        const double lim = mx > 0.0f ? 1.0 / static_cast<double>(mx) : dt_g;
+        clock[2 * b] += clock[2 * b + 1];
+        clock[2 * b + 1] = static_cast<double>(C.law[2]) * (lim < dt_g ? lim : dt_g);
+    }
 }
 
 hipError_t launch_ch_steps(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells, float* c,
@@ -155,10 +166,8 @@ hipError_t launch_ch_steps(const Plan& P, void* ws, StateDev sorted, const nauti
     const CaseDev* cases = at<CaseDev>(ws, P.L.cases);
     const Item* items = at<Item>(ws, P.L.items);
     uint32_t* err = at<uint32_t>(ws, P.L.err);
-    uint32_t* maxbits = at<uint32_t>(ws, P.L.chmax);
+    float* item_max = at<float>(ws, P.L.chmax);
     const uint32_t mx = static_cast<uint32_t>(cells.max_nbr);
-    // a kernel, not a memset: safe under graph capture
-    k_ch_zero<<<(P.n_cases + kBlock - 1) / kBlock, kBlock, 0, s>>>(maxbits, static_cast<uint32_t>(P.n_cases));
     k_ch_pack<<<xcd_grid(P.n_items), P.block, 0, s>>>(cases, items, P.n_items, sorted, c, pk.a4);
     hipError_t e = hipGetLastError();
     auto kmu = P.mirror ? k_ch_mu<true, kChGroup> : k_ch_mu<false, kChGroup>;
@@ -170,8 +179,8 @@ hipError_t launch_ch_steps(const Plan& P, void* ws, StateDev sorted, const nauti
                                             P.n_total, mu, err);
         if ((e = item_queue(P, ws, 7, s, &Q)) != hipSuccess) break;
         kcd<<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.a4, pk.b4, cells.nbr, cells.nbr_count, mx,
-                                            P.n_total, c, cdot, clock, maxbits, err);
-        k_ch_clock<<<(P.n_cases + 63) / 64, 64, 0, s>>>(cases, static_cast<uint32_t>(P.n_cases), clock, maxbits);
+                                            P.n_total, c, cdot, clock, item_max, err);
+        k_ch_clock<<<P.n_cases, kBlock, 0, s>>>(cases, clock, item_max);
         e = hipGetLastError();
     }
     return e;

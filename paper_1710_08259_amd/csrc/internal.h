@@ -121,7 +121,7 @@ struct Layout {
     size_t adj4;         // float4: adjoint A = dt (lam_v' + dt lam_x'), 0
     size_t adj4b;        // float4: A, rhobar (after adjoint pass A)
     size_t vr4;          // float4: velocity (0 for fixed), 1 / rho of the step's start (continuity model)
-    size_t chmax;        // per-case max |cdot| as float bits (Cahn-Hilliard)
+    size_t chmax;        // per-item max |cdot| (Cahn-Hilliard)
     size_t partial;      // per-item FP64 partial sums (2 per item)
     size_t inv_map;      // id -> position map (N u32)
     size_t total;
