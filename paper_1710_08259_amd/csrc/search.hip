@@ -397,36 +397,11 @@ hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipSt
 constexpr uint32_t kUnroll = 4;
 static_assert(2 * kUnroll <= kPosPad && 64 % (2 * kUnroll) == 0, "candidate groups must tile the 64-bit mask");
 
-// Bit u set iff candidate u of the group passes the distance test (FP32,
-// the frame shift applied to the particle).  The candidate's cell x index
-// (o.w) against the piece's reference gives delta_x in {-1, 0, 1}, so
-// tx = fl(me.x - delta_x cs) is one fused multiply-add of an exact product.
-template <int DIM>
-__device__ inline uint32_t test_group(const float4* o, float cref, float mex, float csx, float ty, float tz,
-                                      float R2)
-{
-#pragma clang fp contract(off)
-    uint32_t bits = 0;
-#pragma unroll
-    for (uint32_t u = 0; u < kUnroll; ++u) {
-        const float tx = __builtin_fmaf(cref - o[u].w, csx, mex);
-        const float ddx = o[u].x - tx;
-        const float ddy = o[u].y - ty;
-        float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
-        if constexpr (DIM == 3) {
-            const float ddz = o[u].z - tz;
-            r2 = __builtin_fmaf(ddz, ddz, r2);
-        }
-        bits |= r2 < R2 ? (1u << u) : 0u;
-    }
-    return bits;
-}
-
 // The same test for a piece of mirror images: along an axis with sign -1
 // the candidate's offset is negated, d = fl(-off_j - t) (negation is exact),
 // and a mirrored x piece (one boundary cell) takes cref = c_x - delta, delta
 // 0 at the lower face and 2 at the upper one.  With every sign +1 this is
-// test_group's arithmetic.
+// shift_group's arithmetic.
 template <int DIM>
 __device__ inline uint32_t test_group_img(const float4* o, float cref, float mex, float csx, float ty, float tz,
                                           float R2, float sx, float sy, float sz)
@@ -465,31 +440,74 @@ __device__ inline uint64_t scan_chunk_img(const float4* src, uint32_t m, float c
     return hits;
 }
 
-// Hit mask of the candidates q0 .. q0 + m - 1 (m <= 64) read from `src`
-// (src[k] = candidate q0 + k; readable up to 2 kUnroll - 1 past m).  Two
-// groups per iteration in ping-pong registers: group A is tested while group
-// B loads, then B while the next A loads.
+// The distance test of one candidate group, shifted into a running mask:
+// each candidate's bit enters at bit 0 and the earlier ones move up, so
+// after n candidates candidate k sits at bit n - 1 - k.  The bit is the
+// sign of fl(r2 - R2), which is r2 < R2 exactly: both are finite and
+// non-negative, near R2 the difference is exact, elsewhere it is far from
+// zero.  One subtraction and one funnel shift per candidate, instead of a
+// compare, a select and the merging of group masks.  The candidate's cell x
+// index (o.w) against the piece's reference gives delta_x in {-1, 0, 1}, so
+// tx = fl(me.x - delta_x cs) is one fused multiply-add of an exact product.
 template <int DIM>
-__device__ inline uint64_t scan_chunk(const float4* src, uint32_t m, float cref, float mex, float csx, float ty,
-                                      float tz, float R2)
+__device__ inline uint32_t shift_group(const float4* o, float cref, float mex, float csx, float ty, float tz, float R2,
+                                       uint32_t acc)
 {
-    uint64_t hits = 0;
+#pragma clang fp contract(off)
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+        const float tx = __builtin_fmaf(cref - o[u].w, csx, mex);
+        const float ddx = o[u].x - tx;
+        const float ddy = o[u].y - ty;
+        float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
+        if constexpr (DIM == 3) {
+            const float ddz = o[u].z - tz;
+            r2 = __builtin_fmaf(ddz, ddz, r2);
+        }
+        acc = __builtin_amdgcn_alignbit(acc, __builtin_bit_cast(uint32_t, r2 - R2), 31u);
+    }
+    return acc;
+}
+
+// Hit mask (bit k = candidate k) of the candidates src[0 .. m-1], 1 <= m <=
+// 32 (readable up to 2 kUnroll - 1 past m).  Two groups per iteration in
+// ping-pong registers: group A is tested while group B loads, then B while
+// the next A loads.  The loop tests b = 8 ceil(m/8) candidates; the shifted
+// mask is reversed and aligned at the end.
+template <int DIM>
+__device__ inline uint32_t scan32(const float4* src, uint32_t m, float cref, float mex, float csx, float ty, float tz,
+                                  float R2)
+{
+    uint32_t acc = 0;
     float4 oa[kUnroll], ob[kUnroll];
 #pragma unroll
     for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[u];
-    for (uint32_t b = 0; b < m; b += 2 * kUnroll) {
+    uint32_t b = 0;
+    for (; b < m; b += 2 * kUnroll) {
 #pragma unroll
         for (uint32_t u = 0; u < kUnroll; ++u) ob[u] = src[b + kUnroll + u];
         __builtin_amdgcn_sched_barrier(0);
-        hits |= static_cast<uint64_t>(test_group<DIM>(oa, cref, mex, csx, ty, tz, R2)) << b;
+        acc = shift_group<DIM>(oa, cref, mex, csx, ty, tz, R2, acc);
         // the next A group, or this one again past the end (stays readable)
         const uint32_t na = b + 2 * kUnroll < m ? b + 2 * kUnroll : b;
 #pragma unroll
         for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[na + u];
         __builtin_amdgcn_sched_barrier(0);
-        hits |= static_cast<uint64_t>(test_group<DIM>(ob, cref, mex, csx, ty, tz, R2)) << (b + kUnroll);
+        acc = shift_group<DIM>(ob, cref, mex, csx, ty, tz, R2, acc);
     }
-    return hits;
+    return __builtin_bitreverse32(acc) >> (32u - b);  // 8 <= b <= 32
+}
+
+// Hit mask of the candidates q0 .. q0 + m - 1 (m <= 64) read from `src`
+// (src[k] = candidate q0 + k; readable up to 2 kUnroll - 1 past m), as two
+// halves of 32.
+template <int DIM>
+__device__ inline uint64_t scan_chunk(const float4* src, uint32_t m, float cref, float mex, float csx, float ty,
+                                      float tz, float R2)
+{
+    const uint32_t lo = scan32<DIM>(src, m < 32u ? m : 32u, cref, mex, csx, ty, tz, R2);
+    const uint32_t hi = m > 32u ? scan32<DIM>(src + 32, m - 32u, cref, mex, csx, ty, tz, R2) : 0u;
+    return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
 }
 
 // kMirror: the case may have symmetric faces.  A stencil cell beyond such a
