@@ -47,6 +47,11 @@ NLIST_TRAFFIC_SOURCE_SHA256 = "4b02198fe733fb93"
 # way (by the sources of the kernels they were taken on).
 NLIST_VALU_ISSUE_FRAC = 0.946
 FORCE_L1_ACCESS_RATE = 1.06   # accesses per CU per clock; the vector L1 serves about one
+# HBM bytes per density / force launch (FETCH_SIZE x2 + WRITE_SIZE, same
+# runs and guard as the L1 rate), and the force pass's VALU issue fraction.
+DENSITY_TRAFFIC_BYTES = 2.703e9 + 0.403e9
+FORCE_TRAFFIC_BYTES = 3.019e9 + 0.369e9
+FORCE_VALU_ISSUE_FRAC = 0.468
 FORCE_SOURCES_SHA256 = "2a9abd70431d93be"
 
 
@@ -70,6 +75,39 @@ def nlist_issue_frac():
 
 def force_l1_rate():
     return FORCE_L1_ACCESS_RATE if _digest("sph.hip", "pairs.h", "internal.h") == FORCE_SOURCES_SHA256 else None
+
+
+def _force_guard(v):
+    return v if _digest("sph.hip", "pairs.h", "internal.h") == FORCE_SOURCES_SHA256 else None
+
+
+# Algorithmic HBM bytes per particle and step (3-D FP32 SoA): density reads
+# offsets (12) and writes rho, p, s, 1/rho (16); the force pass with the
+# integration reads offsets, velocity, s, 1/rho (32) and writes the new
+# cell, offsets, velocity (28) plus a (12); keys, three sort passes, cell
+# ranges and the reorder move about 128.
+DENSITY_ALGO_BYTES = 28
+FORCE_ALGO_BYTES = 72
+SORT_REORDER_ALGO_BYTES = 128
+
+
+def hbm_fractions(n, phase_ms):
+    """Measured (counter) and algorithmic HBM rates of the step's phases
+    against the 8 TB/s peak."""
+    def rate(nbytes, ms):
+        if nbytes is None:
+            return None
+        tbps = nbytes / (ms * 1e-3) / 1e12
+        return {"bytes": nbytes, "TB_per_s": round(tbps, 3), "frac": round(tbps * 1e3 / PEAK_HBM_GBS, 4)}
+
+    return {
+        "density": {"measured": rate(_force_guard(DENSITY_TRAFFIC_BYTES), phase_ms[2]),
+                    "algorithmic": rate(DENSITY_ALGO_BYTES * n, phase_ms[2])},
+        "force_pass": {"measured": rate(_force_guard(FORCE_TRAFFIC_BYTES), phase_ms[3]),
+                       "algorithmic": rate(FORCE_ALGO_BYTES * n, phase_ms[3]),
+                       "valu_issue_frac": _force_guard(FORCE_VALU_ISSUE_FRAC)},
+        "sort_cells_reorder": {"algorithmic": rate(SORT_REORDER_ALGO_BYTES * n, phase_ms[0])},
+    }
 
 
 def parse():
@@ -147,6 +185,28 @@ def timed_steps(prob, st, steps, warmup, step=None):
         e = evs[5 * k: 5 * k + 5]
         phase += [e[i].elapsed_time(e[i + 1]) for i in range(4)]
     return wall, phase / steps, int(pairs.item())
+
+
+def cpu_single_thread(case):
+    """The oracle on one thread: one FP64 step of a 64^3 box of the same
+    lattice recipe (about 3 s)."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_1710_08259_amd import workloads as WL
+
+    sample = WL.lattice_case(3, (64, 64, 64), 0.01, 1.2, 0.05, 0.05, seed=3, c0=case.c0, nu=case.nu, dt=case.dt)
+    dom = O.Domain(dim=3, n=sample.ncell, cs=sample.cell_size, origin=sample.origin)
+    prm = O.Params(h=sample.h, mass=sample.mass, rho0=sample.rho0, c0=sample.c0, gamma=sample.gamma,
+                   nu=sample.nu, dt=sample.dt, g=sample.g)
+    x = sample.pos.astype(np.float64)
+    v = sample.vel.astype(np.float64)
+    _, _, counts = O.density(dom, prm, x, counts=True, nthreads=1)
+    t0 = time.perf_counter()
+    O.step(dom, prm, x, v, n_steps=1, nthreads=1)
+    dt = time.perf_counter() - t0
+    return {"value": int(counts.sum()) / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
+            "steps_per_s": 1.0 / dt, "sample": f"one FP64 step of a 64^3 box ({sample.n} particles), {dt:.2f} s"}
 
 
 def cpu_baseline(args, case):
@@ -463,7 +523,8 @@ def main():
             "bound": "alu", "kernel": "k_forces<true> (force pass with fused integration)",
             "achieved": round(force_tflops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": round(force_tflops / PEAK_FP32_TFLOPS, 4), "ms": round(phase_ms[3], 4),
-            "l1_accesses_per_cu_clock": force_l1_rate()}},
+            "l1_accesses_per_cu_clock": force_l1_rate()},
+            "hbm": hbm_fractions(case.n, phase_ms)},
     }
     del prob, st
     torch.cuda.empty_cache()
@@ -483,6 +544,7 @@ def main():
         line["extra"]["ch"] = ch_extra(device)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args, case)
+        line["extra"]["cpu_single_thread"] = cpu_single_thread(case)
     print(json.dumps(line), flush=True)
 
 
