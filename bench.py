@@ -123,6 +123,9 @@ def parse():
     ap.add_argument("--ch-only", action="store_true", help="only the Example 1b Cahn-Hilliard sphere")
     ap.add_argument("--law-only", choices=("dem", "social"), default=None,
                     help="only one pair-law workload (DEM damper or social force room)")
+    ap.add_argument("--verlet-only", action="store_true",
+                    help="only the main lattice with neighbour lists reused between builds")
+    ap.add_argument("--skin-frac", type=float, default=0.1, help="Verlet skin in units of 2h")
     ap.add_argument("--ex1a-scale", type=float, default=87.0,
                     help="resolution factor of the Example 1a dam break (87: 4.1M particles)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -368,6 +371,55 @@ def ex1a_extra(device, scale, steps=10, warmup=2):
             "oracle_paper_case": {"particles": small.n, "ms_per_step": round(t_or * 1e3, 3), "cores": 1}}
 
 
+def verlet_extra(device, skin_frac=0.1, steps=100, warmup=5, pairs_2h_per_step=None, plain_ms=None):
+    """The main workload's lattice stepped with neighbour lists reused
+    between builds: lists reaching 2h + skin (skin = skin_frac 2h, cells
+    resized to fit), a build only before a step at whose start a particle
+    has moved about skin / 2 since the last one.  Reports the builds, the
+    mean step and its phases over the build and the reuse steps."""
+    import numpy as np
+    import torch
+
+    from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
+
+    base = WL.periodic_3d_8m()
+    skin = skin_frac * 2.0 * base.h
+    case = WL.lattice_case(3, (256, 256, 128), 0.01, 1.2, 0.05, 0.05, seed=3, c0=10.0, nu=1e-3, dt=1e-4,
+                           skin=skin, name=f"periodic_3d_8388608_skin{skin_frac:g}")
+    prob = N.Problem([case], device=device)
+    st = prob.state_from_cases()
+    prob.step_verlet(st, warmup)  # loads every kernel module
+    torch.cuda.synchronize()
+    prob.check()
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(5 * steps)]
+    for e in evs:
+        e.record(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    builds = prob.step_verlet(st, steps, events=evs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prob.check()
+    per = np.array([[evs[5 * k + i].elapsed_time(evs[5 * k + i + 1]) for i in range(4)] for k in range(steps)])
+    built = per[:, 0] + per[:, 1] > 0.02
+    entries = float(prob.cells.nbr_count[: case.n].sum(dtype=torch.int64).item())
+    out = {"workload": case.name, "particles": case.n, "cells": list(case.ncell), "skin": skin,
+           "skin_over_2h": skin_frac, "steps": steps, "builds": builds,
+           "ms_per_step": round(wall * 1e3 / steps, 4), "steps_per_s": steps / wall,
+           "list_entries_per_particle": round(entries / case.n, 2),
+           "reuse_step_ms": {"density": round(float(per[~built, 2].mean()), 4),
+                             "forces_drift": round(float(per[~built, 3].mean()), 4)} if (~built).any() else None,
+           "build_step_ms": {"sort_reorder": round(float(per[built, 0].mean()), 4),
+                             "neighbour_lists": round(float(per[built, 1].mean()), 4)} if built.any() else None}
+    if pairs_2h_per_step:
+        out["interactions_per_s"] = pairs_2h_per_step * steps / wall
+    if plain_ms:
+        out["speedup_vs_build_every_step"] = round(plain_ms / (wall * 1e3 / steps), 3)
+    return out
+
+
 def law_extra(device, which, steps=10, warmup=2):
     """A pair law at scale: Example 2's DEM damper with 19^3 times the
     table's 567 spheres (3,889,053, symmetric faces) packed at 0.99 of their
@@ -482,6 +534,10 @@ def main():
         print(json.dumps({"extra": {"ex1a": ex1a_extra(device, args.ex1a_scale, args.steps, args.warmup)}}),
               flush=True)
         return
+    if args.verlet_only:
+        print(json.dumps({"extra": {"verlet": verlet_extra(device, args.skin_frac, max(args.steps, 20))}}),
+              flush=True)
+        return
     if args.calibrate_copy:
         nb = args.calibrate_copy << 20
         a = torch.empty(nb // 4, dtype=torch.float32, device=device).fill_(1.0)
@@ -542,6 +598,9 @@ def main():
         line["extra"]["social"] = law_extra(device, "social")
         torch.cuda.empty_cache()
         line["extra"]["ch"] = ch_extra(device)
+        torch.cuda.empty_cache()
+        line["extra"]["verlet"] = verlet_extra(device, args.skin_frac, pairs_2h_per_step=pairs_per_step,
+                                               plain_ms=wall * 1e3 / args.steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args, case)
         line["extra"]["cpu_single_thread"] = cpu_single_thread(case)

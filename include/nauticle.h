@@ -9,6 +9,9 @@
  *     radius 2h, found through the cell grid of the domain [Sec. 3.2.1, "The
  *     computational domain": an axis-aligned box of cuboid cells no smaller
  *     than the influence radius; pairs farther than one cell apart ignored];
+ *     optionally the lists reach a skin beyond 2h and are reused while no
+ *     particle has moved far enough to enter the support unlisted (the
+ *     paper reruns the search only when the layout changes [Sec. 4]);
  *   - interaction sums over those neighbours [Sec. 2.1, eq.
  *     interaction_formula]: SPH density summation with the Wendland kernel
  *     [Example 1a, kernel equation; SPH sampling expression with A = rho],
@@ -124,7 +127,8 @@ enum {
 
 /* The box [Sec. 3.2.1]: ncell[k] cells of edge cell_size[k] per axis, so the
  * length is L_k = ncell[k] * cell_size[k].  cell_size is used rounded to
- * FP32; it must be >= 2h (the influence radius).  Periodic axes need
+ * FP32; it must be >= 2h + skin (the influence radius plus the case's
+ * neighbour-list skin, 0 unless set).  Periodic axes need
  * ncell >= 3, symmetric axes ncell >= 2.  Axes k >= dim must have
  * ncell[k] = 1. */
 typedef struct {
@@ -145,12 +149,19 @@ typedef struct {
  * CAHN_HILLIARD: law[0..2] = D, gamma, the time-step factor 0.1); model:
  * NAUTICLE_MODEL_*, the same for every case of a table (SUMMATION uses gamma
  * and nu, CONTINUITY alpha_av, the pair laws law[] and per-particle
- * attributes); reserved: 0. */
+ * attributes); skin: >= 0, the neighbour lists' reach beyond the support:
+ * every build (nauticle_build_cells, nauticle_step, ...) lists the pairs
+ * closer than 2h + skin (FP32 predicate r^2 < fl32((2h + skin)^2), with
+ * (2h + skin)^2 evaluated in FP64), so that nauticle_step_verlet can reuse
+ * them; every pass's terms vanish beyond 2h, so results do not depend on
+ * it (the SOCIAL model, whose force is not compactly supported, requires
+ * skin = 0); reserved: 0. */
 typedef struct {
     double h, mass, rho0, c0, gamma, nu, dt;
     double g[3];
     double alpha_av;
     double law[4];
+    double skin;
     int32_t model;
     int32_t reserved;
 } nauticle_sph_params;
@@ -412,6 +423,38 @@ nauticle_status nauticle_ch_steps(const nauticle_case* cases, int32_t n_cases,
 nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
                               int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
                               hipEvent_t* phase_events, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* n_steps steps of the SUMMATION or CONTINUITY model, as nauticle_step
+ * computes them, with the neighbour lists reused between builds (a Verlet
+ * list).  The lists reach 2h + skin (the table's skin); a build (sort,
+ * reorder, lists) runs at the first step and then only before a step at
+ * whose start some particle has moved more than
+ *   lim = max(skin / 2 - 2^-18 max_k cell_size_k, 0)
+ * from where it was at the last build, or has left the box across a face
+ * of a non-periodic axis (the build's re-split shifts it periodically, as
+ * nauticle_step does in the step it leaves), so every pair closer than 2h is
+ * listed at every step (two particles each within lim of their build-time
+ * positions close a gap of at most 2 lim < skin; the 2^-18 cell_size margin
+ * covers the FP32 rounding of the predicate and of the displacement).
+ * Between builds a particle keeps its build-time cell and its offset drifts
+ * (off = off + dt v may leave [0, cell_size) by up to lim), which the pair
+ * arithmetic (offsets and cell differences) takes exactly; each build, and
+ * the end of the call, re-split the positions into (cell, offset in
+ * [0, cell_size)).  With skin = 0 every step in which a particle moves
+ * rebuilds, and the result equals nauticle_step's bit for bit.
+ * The decision is made on the host: after each step the library copies one
+ * device word back and waits for `stream` (one host-device round trip per
+ * step).  After the call `state` holds the particles, re-split, in the
+ * sorted order of the last build; `fields` hold the last step's fields and
+ * `cells` the last build's lists (their cell offsets refer to the
+ * build-time cells, not to `state`'s).  n_builds (optional host pointer)
+ * receives the number of builds.  phase_events as in nauticle_step (in a
+ * step without a build, slots 1 and 2 are recorded right after slot 0).
+ * Tables of other models are rejected with NAUTICLE_ERR_INVALID_ARG. */
+nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
+                                     int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
+                                     int32_t* n_builds, hipEvent_t* phase_events, void* ws, size_t ws_bytes,
+                                     hipStream_t stream);
 
 /* Reverse mode of one step of the SUMMATION model (the derivative the paper
  * does not have); cases with a symmetric axis or the CONTINUITY model are

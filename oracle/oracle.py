@@ -22,7 +22,10 @@ Every function follows the paper (arXiv:1710.08259):
   interface): the DEM contact law of Example 2 (eq. DEM_force) and the
   social force model (eq. social_force_model);
 * Example 1b: Cahn-Hilliard with the SPH Laplacian sph_L0 (eq. diffop3 as
-  Example 1b discretises it) and its adaptive time step.
+  Example 1b discretises it) and its adaptive time step;
+* neighbour lists reused between builds (Sec. 4: the search reruns only when
+  the layout has changed), with a skin beyond 2h and the displacement rule
+  that keeps every pair inside the support listed (:func:`verlet_steps`).
 
 The one-step adjoint (:func:`step_vjp`) is not in the paper; it is the exact
 reverse-mode derivative of :func:`step` with one step, pinned against central
@@ -31,6 +34,7 @@ finite differences of :func:`step` in the tests.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass, field
 
@@ -656,3 +660,81 @@ def rollout_grad(dom: Domain, prm: Params, x0, v0, target, n_steps, checkpoint_e
             dnu += a
             dc0 += b
     return loss, lam_v, dnu, dc0
+
+
+# --------------------------------------------------------------------------
+# neighbour lists reused between builds (a Verlet list)
+# --------------------------------------------------------------------------
+
+def pair_keys(dom: Domain, x, radius: float) -> np.ndarray:
+    """Every pair closer than ``radius`` (FP64, minimum image on periodic
+    axes), as sorted keys (i n + j) 27 + image: image = sum_k 3^k c_k with
+    c_k = 0 for j itself, 1 or 2 for j's reflection in the lower or upper
+    symmetric face along axis k (a particle's own reflection included)."""
+    x = np.asarray(x, dtype=np.float64)
+    n, d = x.shape[0], dom.dim
+    L = dom.length()
+    lo = np.array(dom.origin[:3], dtype=np.float64)
+    choices = [(0, 1, 2) if dom.symmetric[k] else (0,) for k in range(d)]
+    out = []
+    for combo in np.array(np.meshgrid(*choices, indexing="ij")).reshape(d, -1).T:
+        xj = x.copy()
+        code = 0
+        for k in range(d):
+            if combo[k] == 1:
+                xj[:, k] = 2.0 * lo[k] - x[:, k]
+            elif combo[k] == 2:
+                xj[:, k] = 2.0 * (lo[k] + L[k]) - x[:, k]
+            code += int(combo[k]) * 3 ** k
+        for i0 in range(0, n, 256):
+            diff = xj[None, :, :] - x[i0:i0 + 256, None, :]
+            for k in range(d):
+                if dom.periodic[k]:
+                    diff[:, :, k] -= L[k] * np.rint(diff[:, :, k] / L[k])
+            ii, jj = np.nonzero((diff * diff).sum(axis=2) < radius * radius)
+            if code == 0:
+                keep = ii + i0 != jj
+                ii, jj = ii[keep], jj[keep]
+            out.append(((ii + i0).astype(np.int64) * n + jj) * 27 + code)
+    return np.unique(np.concatenate(out)) if out else np.zeros(0, np.int64)
+
+
+def verlet_steps(dom: Domain, prm: Params, x, v, skin: float, n_steps: int, fixed=None, rho=None,
+                 limit_fraction: float = 0.5, nthreads=None):
+    """n_steps of :func:`step` (or of :func:`step_ex1a` when ``rho`` is
+    given) with a Verlet neighbour list kept beside them: the pairs closer
+    than 2h + skin at the last build, rebuilt before a step at whose start
+    some particle lies farther than
+
+        lim = max(limit_fraction * skin - 2^-18 max_k cs_k, 0)
+
+    from its build-time position.  Before every step it checks that each
+    pair closer than 2h is in the list, and raises AssertionError if not:
+    with limit_fraction = 1/2 two particles close a gap of at most 2 lim <
+    skin between builds, so the check holds.  The steps themselves do not
+    use the list (pairs beyond 2h add exact zeros), so x and v are those of
+    the plain rollout.  A particle shifted across a face of a non-periodic
+    axis has moved about a box length, which forces a build.  Returns
+    (x, v, rho, builds, build_steps)."""
+    d = dom.dim
+    x = np.asarray(x, dtype=np.float64)[:, :d].copy()
+    v = np.asarray(v, dtype=np.float64)[:, :d].copy()
+    r = None if rho is None else np.array(rho, dtype=np.float64, copy=True)
+    cs_max = max(float(dom.cs[k]) for k in range(d))
+    lim = max(limit_fraction * skin - math.ldexp(cs_max, -18), 0.0)
+    listed = None
+    x_build = None
+    build_steps = []
+    for s in range(n_steps):
+        if listed is None or (min_image(dom, x - x_build) ** 2).sum(axis=1).max() > lim * lim:
+            listed = pair_keys(dom, x, 2.0 * prm.h + skin)
+            x_build = x.copy()
+            build_steps.append(s)
+        missing = np.setdiff1d(pair_keys(dom, x, 2.0 * prm.h), listed, assume_unique=True)
+        if missing.size:
+            raise AssertionError(f"step {s}: {missing.size} pairs closer than 2h are not in the list")
+        if r is None:
+            x, v, _, _, _ = step(dom, prm, x, v, fixed=fixed, n_steps=1, nthreads=nthreads)
+        else:
+            x, v, r, _, _, _ = step_ex1a(dom, prm, x, v, r, fixed=fixed, n_steps=1, nthreads=nthreads)
+    return x, v, r, len(build_steps), build_steps

@@ -101,8 +101,10 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         if (!finite_pos(q.h) || !finite_pos(q.mass) || !finite_pos(q.rho0) || !finite_pos(q.c0) ||
             !finite_pos(q.gamma) || !std::isfinite(q.nu) || q.nu < 0.0 || !std::isfinite(q.dt) || q.dt < 0.0 ||
             !std::isfinite(q.g[0]) || !std::isfinite(q.g[1]) || !std::isfinite(q.g[2]) ||
-            !std::isfinite(q.alpha_av) || q.alpha_av < 0.0)
+            !std::isfinite(q.alpha_av) || q.alpha_av < 0.0 || !std::isfinite(q.skin) || q.skin < 0.0)
             return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: non-finite or non-positive parameter", b);
+        if (q.model == NAUTICLE_MODEL_SOCIAL && q.skin != 0.0)
+            return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: the social force needs skin = 0", b);
         if (q.model < NAUTICLE_MODEL_SUMMATION || q.model > NAUTICLE_MODEL_CAHN_HILLIARD)
             return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: unknown model %d", b, q.model);
         for (int k = 0; k < 4; ++k)
@@ -114,6 +116,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         if (q.model == NAUTICLE_MODEL_CAHN_HILLIARD && (q.law[0] < 0.0 || q.law[1] < 0.0 || !(q.law[2] > 0.0)))
             return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: Cahn-Hilliard needs D >= 0, gamma >= 0, factor > 0", b);
         if (q.model != model0) return fail(NAUTICLE_ERR_INVALID_ARG, "case %d: all cases must share one model", b);
+        // the lists' reach: the support plus the skin
+        const double reach = 2.0 * q.h + q.skin;
         uint64_t ncell = 1;
         for (int k = 0; k < 3; ++k) {
             if (k >= d.dim) {
@@ -127,9 +131,9 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
             if (!finite_pos(d.cell_size[k]) || !std::isfinite(d.origin[k]))
                 return fail(NAUTICLE_ERR_DOMAIN, "case %d: bad cell_size/origin on axis %d", b, k);
             const double cs32 = static_cast<double>(static_cast<float>(d.cell_size[k]));
-            if (cs32 < 2.0 * q.h)
-                return fail(NAUTICLE_ERR_DOMAIN, "case %d: cell_size[%d] = %.9g below the support 2h = %.9g",
-                            b, k, cs32, 2.0 * q.h);
+            if (cs32 < reach)
+                return fail(NAUTICLE_ERR_DOMAIN, "case %d: cell_size[%d] = %.9g below 2h + skin = %.9g", b, k,
+                            cs32, reach);
             if (d.boundary[k] == NAUTICLE_PERIODIC && d.ncell[k] < 3)
                 return fail(NAUTICLE_ERR_DOMAIN, "case %d: periodic axis %d needs >= 3 cells", b, k);
             // a boundary cell's images must lie beyond one face only
@@ -164,7 +168,16 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         const int kdim = q.model == NAUTICLE_MODEL_CAHN_HILLIARD ? 2 : d.dim;
         const double alpha = kdim == 2 ? 7.0 / (4.0 * M_PI * q.h * q.h)
                                        : 21.0 / (16.0 * M_PI * q.h * q.h * q.h);
-        C.R2 = static_cast<float>(4.0 * q.h * q.h);
+        C.R2 = static_cast<float>(reach * reach);
+        {
+            // a build is due once a particle has moved lim from its build-time
+            // position; the margin covers the FP32 rounding of the predicate
+            // and of the displacement
+            double cs_max = 0.0;
+            for (int k = 0; k < d.dim; ++k) cs_max = std::max(cs_max, static_cast<double>(C.cs[k]));
+            const double lim = std::max(0.5 * q.skin - std::ldexp(cs_max, -18), 0.0);
+            C.verlet_lim2 = static_cast<float>(lim * lim);
+        }
         C.inv_h = static_cast<float>(1.0 / q.h);
         C.m = static_cast<float>(q.mass);
         C.m_alpha = static_cast<float>(q.mass * alpha);
@@ -196,7 +209,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
         // expected neighbours per particle at the case's mean number density
         double volume = 1.0;
         for (int k = 0; k < d.dim; ++k) volume *= d.ncell[k] * d.cell_size[k];
-        const double ball = d.dim == 2 ? M_PI * 4.0 * q.h * q.h : 4.0 / 3.0 * M_PI * 8.0 * q.h * q.h * q.h;
+        const double ball = d.dim == 2 ? M_PI * reach * reach : 4.0 / 3.0 * M_PI * reach * reach * reach;
         nbr_per_particle.push_back(static_cast<double>(c.n) / volume * ball);
         // LDS records for an item's neighbourhood at the reference density
         // (particle volume m / rho0): 3^(dim-1) rows of the item's cells plus
@@ -278,6 +291,9 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     L.chmax = take(sizeof(float) * n_items_max);
     L.partial = take(2 * sizeof(double) * n_items_max);
     L.inv_map = take(4 * N);
+    const bool sph = model0 == NAUTICLE_MODEL_SUMMATION || model0 == NAUTICLE_MODEL_CONTINUITY;
+    for (int k = 0; k < 3; ++k) L.off0[k] = sph && k < dim0 ? take(4 * N) : 0;
+    L.vflag = take(2 * sizeof(uint32_t));
     L.total = off;
     return NAUTICLE_OK;
 }
@@ -699,6 +715,70 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
         if (e == hipSuccess) e = mark(s, 4);
         if (e != hipSuccess) return hip_fail(e, "nauticle_step");
     }
+    return NAUTICLE_OK;
+}
+
+nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
+                                     int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
+                                     int32_t* n_builds, hipEvent_t* phase_events, void* ws, size_t ws_bytes,
+                                     hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if (n_steps < 0) return fail(NAUTICLE_ERR_INVALID_ARG, "n_steps < 0");
+    if (P->model != NAUTICLE_MODEL_SUMMATION && P->model != NAUTICLE_MODEL_CONTINUITY)
+        return fail(NAUTICLE_ERR_INVALID_ARG, "nauticle_step_verlet needs a SUMMATION or CONTINUITY table");
+    const bool cont = P->model == NAUTICLE_MODEL_CONTINUITY;
+    if ((st = check_state(*P, state, true, "state", cont)) != NAUTICLE_OK) return st;
+    if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
+    if ((st = check_fields(*P, fields, true)) != NAUTICLE_OK) return st;
+    if (n_builds) *n_builds = 0;
+    const StateDev cur = to_dev_model(*P, state);
+    const StateDev tmp = scratch_state(*P, ws);
+    const FieldsDev f = to_dev(fields);
+    const uint32_t* flag = at<uint32_t>(ws, P->L.vflag);
+    auto mark = [&](int32_t s, int k) {
+        return phase_events ? hipEventRecord(phase_events[5 * s + k], stream) : hipSuccess;
+    };
+    int32_t builds = 0;
+    bool build = true;
+    hipError_t e = n_steps > 0 ? launch_verlet_clear(*P, ws, stream) : hipSuccess;
+    // the live state is the workspace copy `tmp` (sorted order of the last
+    // build, offsets drifting); `state` receives it re-split before each
+    // build and at the end
+    for (int32_t s = 0; s < n_steps && e == hipSuccess; ++s) {
+        e = mark(s, 0);
+        if (build) {
+            if (e == hipSuccess && builds > 0) e = launch_resplit(*P, ws, tmp, cur, stream);
+            if (e == hipSuccess)
+                e = launch_build_cells(*P, ws, cur, tmp, *cells, stream, phase_events ? phase_events[5 * s + 1] : nullptr);
+            ++builds;
+        } else if (e == hipSuccess) {
+            e = mark(s, 1);
+        }
+        if (e == hipSuccess) e = mark(s, 2);
+        if (cont) {
+            if (e == hipSuccess) e = launch_pack_continuity(*P, ws, tmp, stream);
+            if (e == hipSuccess) e = launch_continuity(*P, ws, tmp, *cells, f, stream);
+        } else if (e == hipSuccess) {
+            e = launch_density(*P, ws, tmp, *cells, f, stream);
+        }
+        if (e == hipSuccess) e = mark(s, 3);
+        if (e == hipSuccess) e = launch_forces(*P, ws, tmp, *cells, f, nullptr, stream);
+        if (e == hipSuccess) e = launch_verlet_drift(*P, ws, tmp, f, build, s & 1, stream);
+        if (e == hipSuccess) e = mark(s, 4);
+        if (e == hipSuccess && s + 1 < n_steps) {
+            // is a build due before the next step?
+            uint32_t word = 0;
+            e = hipMemcpyAsync(&word, flag + (s & 1), sizeof(word), hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            build = word != 0u;
+        }
+    }
+    if (e == hipSuccess && n_steps > 0) e = launch_resplit(*P, ws, tmp, cur, stream);
+    if (e != hipSuccess) return hip_fail(e, "nauticle_step_verlet");
+    if (n_builds) *n_builds = builds;
     return NAUTICLE_OK;
 }
 

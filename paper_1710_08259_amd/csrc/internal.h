@@ -55,7 +55,7 @@ struct CaseDev {
     float cs[3];         // fl32(cell_size)
     float inv_cs[3];     // fl32(1 / cell_size)
     float origin[3];     // fl32(origin)
-    float R2;            // fl32(4 h^2)
+    float R2;            // fl32((2h + skin)^2): the neighbour lists' reach
     float inv_h;
     float m;             // particle mass
     float m_alpha;       // m * alpha_D (self density, and W's scale)
@@ -68,6 +68,7 @@ struct CaseDev {
     float av_coef;       // alpha_av c0 h m (artificial viscosity, times 1/rho_i per particle)
     float h;             // smoothing length (pair laws: the largest radius allowed)
     float law[4];        // pair-law constants (DEM: c_f; social force: A, B, k, tau)
+    float verlet_lim2;   // fl32(lim^2): a displacement beyond lim since the last build forces one
 };
 
 // Offset code of a list entry along axis k (bits 26 + 2k, 27 + 2k): the
@@ -124,6 +125,8 @@ struct Layout {
     size_t chmax;        // per-item max |cdot| (Cahn-Hilliard)
     size_t partial;      // per-item FP64 partial sums (2 per item)
     size_t inv_map;      // id -> position map (N u32)
+    size_t off0[3];      // offsets at the last build (Verlet steps; N f32 per axis)
+    size_t vflag;        // two rebuild words (Verlet steps; one per step parity)
     size_t total;
 };
 
@@ -375,6 +378,17 @@ hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nautic
                           hipStream_t s);
 hipError_t launch_position_loss(const Plan& P, void* ws, StateDev a, StateDev b, double* loss,
                                 float* const grad[3], hipStream_t s);
+// verlet.hip: steps between neighbour builds.  drift completes a step in
+// place on the sorted state (velocity, then offset without re-splitting;
+// pos4 for the next pair pass; the continuity model's density), records the
+// build-time offsets on the first step after a build, and sets rebuild word
+// `parity` if some particle has moved beyond its case's lim (clearing the
+// other word for the next step).  resplit copies `src` into `dst` with the
+// positions re-split into (cell, offset in [0, cs)).
+hipError_t launch_verlet_clear(const Plan& P, void* ws, hipStream_t s);
+hipError_t launch_verlet_drift(const Plan& P, void* ws, StateDev st, FieldsDev f, bool first, int parity,
+                               hipStream_t s);
+hipError_t launch_resplit(const Plan& P, void* ws, StateDev src, StateDev dst, hipStream_t s);
 
 // ---- device helpers -----------------------------------------------------------
 

@@ -43,7 +43,7 @@ ENTRY_POINTS = (
     "nauticle_cells_total", "nauticle_workspace_bytes", "nauticle_prepare", "nauticle_bin",
     "nauticle_unbin", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_continuity",
     "nauticle_sph_forces",
-    "nauticle_step", "nauticle_interact", "nauticle_step_law", "nauticle_ch_steps", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
+    "nauticle_step", "nauticle_step_verlet", "nauticle_interact", "nauticle_step_law", "nauticle_ch_steps", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
     "nauticle_last_error",
 )
 
@@ -67,7 +67,8 @@ class CParams(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("mass", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("c0", ctypes.c_double), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
                 ("dt", ctypes.c_double), ("g", ctypes.c_double * 3), ("alpha_av", ctypes.c_double),
-                ("law", ctypes.c_double * 4), ("model", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("law", ctypes.c_double * 4), ("skin", ctypes.c_double), ("model", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class CCase(ctypes.Structure):
@@ -153,6 +154,9 @@ def lib():
     L.nauticle_step.restype = st
     L.nauticle_step.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(vp), vp,
                                 ctypes.c_size_t, vp]
+    L.nauticle_step_verlet.restype = st
+    L.nauticle_step_verlet.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(i32), P(vp), vp,
+                                       ctypes.c_size_t, vp]
     L.nauticle_interact.restype = st
     L.nauticle_interact.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CLawAttrs), P(CFields), P(CState), vp,
                                     ctypes.c_size_t, vp]
@@ -318,6 +322,7 @@ def case_table(cases) -> "ctypes.Array":
         law = tuple(getattr(c, "law", ()) or ())
         for k in range(4):
             p.law[k] = float(law[k]) if k < len(law) else 0.0
+        p.skin = float(getattr(c, "skin", 0.0))
         p.model = int(getattr(c, "model", MODEL_SUMMATION))
         p.reserved = 0
         arr[b].offset = offset
@@ -512,6 +517,17 @@ class Problem:
                                    ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()), ev, *self._ws()),
                "nauticle_step")
         return st
+
+    def step_verlet(self, st: State, n_steps: int = 1, events=None) -> int:
+        """n_steps steps in place with the neighbour lists reused while no
+        particle has moved beyond the table's skin allows; returns the
+        number of neighbour builds.  `events` as in step()."""
+        ev = self._events(events, n_steps)
+        builds = ctypes.c_int32(0)
+        _check(lib().nauticle_step_verlet(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
+                                          ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()),
+                                          ctypes.byref(builds), ev, *self._ws()), "nauticle_step_verlet")
+        return int(builds.value)
 
     def adjoint(self, sorted_: State, cells: Cells, fields: Fields, lam_x_next, lam_v_next, lam_x, lam_v,
                 dnu: torch.Tensor, dc0: torch.Tensor):

@@ -73,6 +73,7 @@ class Case:
     coef: Optional[np.ndarray] = None     # DEM: (1 - nu^2)/E; SOCIAL: attraction c; CAHN_HILLIARD: c
     v0: Optional[np.ndarray] = None       # SOCIAL: desired speed
     goal: Optional[np.ndarray] = None     # SOCIAL: (n, dim) absolute target
+    skin: float = 0.0                     # neighbour-list reach beyond 2h (Verlet steps)
 
     @property
     def n(self) -> int:
@@ -92,29 +93,31 @@ class Case:
         return m
 
 
-def _cells_for(length: float, h: float) -> tuple[int, float]:
-    n = int(math.floor(length / (2.0 * h)))
+def _cells_for(length: float, h: float, skin: float = 0.0) -> tuple[int, float]:
+    reach = 2.0 * h + skin
+    n = int(math.floor(length / reach))
     n = max(n, 1)
     cs = _f32(length / n)
-    if cs < 2.0 * h:  # FP32 rounding went below the support: one cell fewer
+    if cs < reach:  # FP32 rounding went below the support: one cell fewer
         n -= 1
         cs = _f32(length / n)
     return n, cs
 
 
 def lattice_case(dim, n_side, dx, h_over_dx, jitter, v_sigma, seed, *, c0=10.0, nu=1e-3,
-                 dt=1e-4, rho0=1000.0, gamma=7.0, g=(0.0, 0.0, 0.0), name="") -> Case:
+                 dt=1e-4, rho0=1000.0, gamma=7.0, g=(0.0, 0.0, 0.0), skin=0.0, name="") -> Case:
     """Periodic box filled with a jittered square/cubic lattice.
 
     ``n_side`` lattice sites per axis at nominal spacing ``dx``; ``jitter``
     is the half-width of the uniform per-component perturbation in units of
-    dx; velocities are N(0, v_sigma) per component."""
+    dx; velocities are N(0, v_sigma) per component.  ``skin``: the
+    neighbour-list skin (cells no smaller than 2h + skin)."""
     rng = np.random.default_rng(seed)
     n_side = tuple(int(s) for s in n_side) + (1,) * (3 - dim)
     h = h_over_dx * dx
     ncell, cs, spacing = [1, 1, 1], [1.0, 1.0, 1.0], [dx, dx, dx]
     for k in range(dim):
-        n, c = _cells_for(n_side[k] * dx, h)
+        n, c = _cells_for(n_side[k] * dx, h, skin)
         ncell[k], cs[k] = n, c
         spacing[k] = n * c / n_side[k]
     grids = np.meshgrid(*[(np.arange(n_side[k]) + 0.5) * spacing[k] for k in range(dim)],
@@ -129,7 +132,7 @@ def lattice_case(dim, n_side, dx, h_over_dx, jitter, v_sigma, seed, *, c0=10.0, 
     return Case(dim=dim, ncell=tuple(ncell), cell_size=tuple(cs), origin=(0.0, 0.0, 0.0),
                 boundary=(PERIODIC,) * 3, h=h, mass=mass, rho0=rho0, c0=c0, gamma=gamma,
                 nu=nu, dt=dt, g=tuple(g), pos=pos.astype(np.float32),
-                vel=vel.astype(np.float32), n_fixed=0, name=name)
+                vel=vel.astype(np.float32), n_fixed=0, name=name, skin=float(skin))
 
 
 def dam_break_case(dx=0.005, h_over_dx=1.2, c0=30.0, nu=1e-6, rho0=1000.0, gamma=7.0,

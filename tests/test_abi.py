@@ -149,3 +149,25 @@ def test_pair_law_tables_are_validated(N):
     assert _ws_bytes(N, [soc])[0] == N.OK
     assert _ws_bytes(N, [WL.scaled(soc, law=(2000.0, 0.0, 1.2e5, 0.5))])[0] == N.ERR_INVALID_ARG  # B = 0
     assert _ws_bytes(N, [WL.scaled(soc, law=(2000.0, 0.08, 1.2e5, float("nan")))])[0] == N.ERR_INVALID_ARG
+
+
+def test_skin_tables_are_validated(N):
+    """A skin needs cells of at least 2h + skin, must be finite and >= 0,
+    and is refused by the social force (not compactly supported)."""
+    base = WL.periodic_2d_4096()                       # h = 0.013, cells of 0.02667
+    gap = float(np.float32(base.cell_size[0])) - 2.0 * base.h
+    assert _ws_bytes(N, [WL.scaled(base, skin=0.99 * gap)])[0] == N.OK
+    assert _ws_bytes(N, [WL.scaled(base, skin=1.01 * gap)])[0] == N.ERR_DOMAIN
+    assert _ws_bytes(N, [WL.scaled(base, skin=-1e-4)])[0] == N.ERR_INVALID_ARG
+    assert _ws_bytes(N, [WL.scaled(base, skin=float("nan"))])[0] == N.ERR_INVALID_ARG
+    assert _ws_bytes(N, [WL.lattice_case(2, (64, 64), 0.01, 1.3, 0.01, 0.1, seed=1, skin=0.005)])[0] == N.OK
+    soc = WL.social_room(width=6.0)
+    assert _ws_bytes(N, [WL.scaled(soc, skin=1e-3)])[0] == N.ERR_INVALID_ARG
+
+
+def test_skin_does_not_change_the_workspace(N):
+    """Every summation or continuity table keeps room for the build-time
+    offsets of the Verlet steps; the skin itself only changes the lists."""
+    a = WL.periodic_2d_4096()
+    gap = float(np.float32(a.cell_size[0])) - 2.0 * a.h
+    assert _ws_bytes(N, [WL.scaled(a, skin=0.5 * gap)])[1] == _ws_bytes(N, [a])[1]

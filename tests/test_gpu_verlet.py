@@ -1,0 +1,146 @@
+"""Parity of nauticle_step_verlet (neighbour lists reused between builds,
+reaching a skin beyond 2h) with the FP64 oracle, through the C-ABI.
+
+- Lists of a table with a skin: counts and sets bit-exact against the
+  oracle's FP32 predicate at the reach 2h + skin.
+- Skin 0: every step of a moving system builds, and the result is
+  nauticle_step's, bit for bit (state and fields).
+- Rollouts with a skin: positions and velocities within 5e-4 (as the plain
+  rollouts) of the oracle's rollout, which checks at every step that the
+  list holds every pair inside 2h; the number of builds within one of the
+  oracle's (FP32 and FP64 displacements may cross the limit one step
+  apart), and well below one per step."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1710_08259_amd import workloads as WL
+from tests.gpu_common import case_absolute_from_state, f32, nauticle, norms, stack, u32
+from tests.oracle_helpers import domain_of, params_of
+
+pytestmark = pytest.mark.gpu
+
+TOL_ROLLOUT = 5e-4
+SYM, CUT, PER = WL.SYMMETRIC, WL.CUTOFF, WL.PERIODIC
+
+
+def _skinned(c, frac=0.9):
+    """The case with the largest skin its cells allow, times frac."""
+    cs = min(float(np.float32(c.cell_size[k])) for k in range(c.dim))
+    return WL.scaled(c, skin=(cs - 2.0 * c.h) * frac)
+
+
+CASES = {
+    "lattice_2d": WL.lattice_case(2, (48, 48), 0.01, 1.3, 0.05, 0.5, seed=21, c0=10.0, skin=0.004),
+    "lattice_3d": WL.lattice_case(3, (16, 16, 16), 0.01, 1.2, 0.05, 0.5, seed=22, c0=10.0, skin=0.003),
+    "mirror_2d_continuity": _skinned(WL.mirror_box_case(2, (SYM, SYM, CUT), 14, n=700, model=WL.CONTINUITY)),
+    "mirror_3d": _skinned(WL.mirror_box_case(3, (SYM, PER, SYM), 13, n=3000)),
+}
+MAX_NBR = {"lattice_2d": 64, "lattice_3d": 128, "mirror_2d_continuity": 256, "mirror_3d": 256}
+ROLLOUT = {"lattice_2d": 60, "lattice_3d": 40, "mirror_2d_continuity": 30}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_lists_reach_the_skin_bit_exactly(name):
+    N = nauticle()
+    case = CASES[name]
+    prob = N.Problem([case], max_nbr=MAX_NBR[name])
+    st = prob.state_from_cases()
+    prob.build_cells(st)
+    torch.cuda.synchronize()
+    prob.check()
+    n = case.n
+    cell_in, off_in = u32(st.cell)[:n], stack(st.off, n)
+    perm = u32(prob.cells.perm)[:n]
+    # reach 2h + skin = 2 (h + skin / 2): the oracle's predicate at h + skin / 2
+    cnt_ref, lst_ref, mir_ref = O.neighbours_f32(domain_of(case), case.h + case.skin / 2, cell_in, off_in,
+                                                 max_nbr=MAX_NBR[name], mirrors=True)
+    cnt_2h = O.neighbours_f32(domain_of(case), case.h, cell_in, off_in)
+    cnt = u32(prob.cells.nbr_count)[:n]
+    np.testing.assert_array_equal(cnt, cnt_ref[perm])
+    assert cnt_ref.sum() > cnt_2h.sum()  # the skin adds pairs
+    ent = u32(prob.cells.entries())[:, :n]
+    j = ent & ((1 << 26) - 1)
+    code = [((ent >> (26 + 2 * k)) & 3).astype(np.int64) for k in range(3)]
+    for p in range(n):
+        k = cnt[p]
+        mask = np.zeros(k, np.int64)
+        for a in range(case.dim):
+            mask |= (code[a][:k, p] == N.MIRROR_CODE).astype(np.int64) << a
+        got = sorted(zip(perm[j[:k, p]].tolist(), mask.tolist()))
+        want = sorted(zip(lst_ref[perm[p], :k].tolist(), mir_ref[perm[p], :k].astype(np.int64).tolist()))
+        assert got == want, p
+
+
+def _state_arrays(st, n, rho):
+    out = [u32(st.cell)[:n], u32(st.id)[:n], stack(st.off, n).view(np.uint32), stack(st.vel, n).view(np.uint32)]
+    if rho:
+        out.append(f32(st.rho)[:n].view(np.uint32))
+    return out
+
+
+@pytest.mark.parametrize("name", ["lattice_2d", "mirror_2d_continuity"])
+def test_skin_zero_equals_plain_steps_bitwise(name):
+    N = nauticle()
+    case = WL.scaled(CASES[name], skin=0.0)
+    steps = 8
+    plain = N.Problem([case], max_nbr=MAX_NBR[name])
+    st_p = plain.state_from_cases()
+    plain.step(st_p, steps)
+    verlet = N.Problem([case], max_nbr=MAX_NBR[name])
+    st_v = verlet.state_from_cases()
+    builds = verlet.step_verlet(st_v, steps)
+    torch.cuda.synchronize()
+    plain.check()
+    verlet.check()
+    assert builds == steps
+    n = case.n
+    cont = case.model == WL.CONTINUITY
+    for a, b in zip(_state_arrays(st_p, n, cont), _state_arrays(st_v, n, cont)):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip([plain.fields.rho] + list(plain.fields.acc), [verlet.fields.rho] + list(verlet.fields.acc)):
+        np.testing.assert_array_equal(f32(a)[:n].view(np.uint32), f32(b)[:n].view(np.uint32))
+
+
+@pytest.mark.parametrize("name", list(ROLLOUT))
+def test_verlet_rollout_matches_oracle(name):
+    N = nauticle()
+    case = CASES[name]
+    steps = ROLLOUT[name]
+    prob = N.Problem([case], max_nbr=MAX_NBR[name])
+    st = prob.state_from_cases()
+    builds = prob.step_verlet(st, steps)
+    torch.cuda.synchronize()
+    prob.check()
+    n, dim = case.n, case.dim
+    ids = u32(st.id)[:n]
+    x_g = np.empty((n, dim))
+    v_g = np.empty((n, dim))
+    x_g[ids] = case_absolute_from_state(case, u32(st.cell)[:n], stack(st.off, n))
+    v_g[ids] = stack(st.vel, n)
+    cont = case.model == WL.CONTINUITY
+    dom, prm = domain_of(case), params_of(case)
+    x, v, r, builds_ref, when = O.verlet_steps(dom, prm, case.pos, case.vel, case.skin, steps,
+                                               fixed=case.fixed_mask(), rho=case.rho if cont else None)
+    err_x = np.abs(O.min_image(dom, x_g - x)).max() / norms(case)["x"]
+    err_v = np.abs(v_g - v).max() / np.abs(v).max()
+    print(f"{name} {steps} steps: builds {builds} (oracle {builds_ref} at {when}), err x {err_x:.2e} v {err_v:.2e}")
+    assert err_x < TOL_ROLLOUT and err_v < TOL_ROLLOUT
+    if cont:
+        r_g = np.empty(n)
+        r_g[ids] = f32(st.rho)[:n]
+        assert np.abs(r_g - r).max() / case.rho0 < TOL_ROLLOUT
+    assert abs(builds - builds_ref) <= 1
+    assert 1 < builds < steps // 2
+
+
+def test_verlet_refuses_other_models():
+    N = nauticle()
+    dem = WL.dem_damper(spacing=2 * 0.004 * 0.985, jitter=0.05, seed=3)
+    prob = N.Problem([dem], max_nbr=64)
+    st = prob.state_from_cases()
+    with pytest.raises(N.NauticleError) as e:
+        prob.step_verlet(st, 2)
+    assert e.value.status == N.ERR_INVALID_ARG
+    torch.cuda.synchronize()
