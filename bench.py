@@ -408,6 +408,7 @@ def verlet_extra(device, skin_frac=0.1, steps=100, warmup=5, pairs_2h_per_step=N
     out = {"workload": case.name, "particles": case.n, "cells": list(case.ncell), "skin": skin,
            "skin_over_2h": skin_frac, "steps": steps, "builds": builds,
            "ms_per_step": round(wall * 1e3 / steps, 4), "steps_per_s": steps / wall,
+           "gpu_ms_per_step": round(float(per.sum(axis=1).mean()), 4),
            "list_entries_per_particle": round(entries / case.n, 2),
            "reuse_step_ms": {"density": round(float(per[~built, 2].mean()), 4),
                              "forces_drift": round(float(per[~built, 3].mean()), 4)} if (~built).any() else None,
