@@ -425,8 +425,9 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
                               hipEvent_t* phase_events, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* n_steps steps of the SUMMATION or CONTINUITY model, as nauticle_step
- * computes them, with the neighbour lists reused between builds (a Verlet
- * list).  The lists reach 2h + skin (the table's skin); a build (sort,
+ * computes them, or of the DEM contact law, as nauticle_step_law computes
+ * them (attrs as there; NULL for the SPH models), with the neighbour lists
+ * reused between builds (a Verlet list).  The lists reach 2h + skin (the table's skin); a build (sort,
  * reorder, lists) runs at the first step and then only before a step at
  * whose start some particle has moved more than
  *   lim = max(skin / 2 - 2^-18 max_k cell_size_k, 0)
@@ -449,12 +450,14 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
  * `cells` the last build's lists (their cell offsets refer to the
  * build-time cells, not to `state`'s).  n_builds (optional host pointer)
  * receives the number of builds.  phase_events as in nauticle_step (in a
- * step without a build, slots 1 and 2 are recorded right after slot 0).
- * Tables of other models are rejected with NAUTICLE_ERR_INVALID_ARG. */
+ * step without a build, slots 1 and 2 are recorded right after slot 0; for
+ * DEM, slots 2 and 3 enclose nothing and slot 4 follows the contact pass
+ * and the update).  Tables of other models are rejected with
+ * NAUTICLE_ERR_INVALID_ARG. */
 nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
                                      int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
-                                     int32_t* n_builds, hipEvent_t* phase_events, void* ws, size_t ws_bytes,
-                                     hipStream_t stream);
+                                     const nauticle_law_attrs* attrs, int32_t* n_builds,
+                                     hipEvent_t* phase_events, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Reverse mode of one step of the SUMMATION model (the derivative the paper
  * does not have); cases with a symmetric axis or the CONTINUITY model are

@@ -700,16 +700,18 @@ def pair_keys(dom: Domain, x, radius: float) -> np.ndarray:
 
 
 def verlet_steps(dom: Domain, prm: Params, x, v, skin: float, n_steps: int, fixed=None, rho=None,
-                 limit_fraction: float = 0.5, nthreads=None):
+                 limit_fraction: float = 0.5, nthreads=None, step_fn=None, check: bool = True):
     """n_steps of :func:`step` (or of :func:`step_ex1a` when ``rho`` is
-    given) with a Verlet neighbour list kept beside them: the pairs closer
+    given, or of ``step_fn(x, v) -> (x, v)``, e.g. one step of a pair law)
+    with a Verlet neighbour list kept beside them: the pairs closer
     than 2h + skin at the last build, rebuilt before a step at whose start
     some particle lies farther than
 
         lim = max(limit_fraction * skin - 2^-18 max_k cs_k, 0)
 
-    from its build-time position.  Before every step it checks that each
-    pair closer than 2h is in the list, and raises AssertionError if not:
+    from its build-time position.  Before every step (unless ``check`` is
+    false: then only the build schedule is kept) it checks that each pair
+    closer than 2h is in the list, and raises AssertionError if not:
     with limit_fraction = 1/2 two particles close a gap of at most 2 lim <
     skin between builds, so the check holds.  The steps themselves do not
     use the list (pairs beyond 2h add exact zeros), so x and v are those of
@@ -726,14 +728,17 @@ def verlet_steps(dom: Domain, prm: Params, x, v, skin: float, n_steps: int, fixe
     x_build = None
     build_steps = []
     for s in range(n_steps):
-        if listed is None or (min_image(dom, x - x_build) ** 2).sum(axis=1).max() > lim * lim:
-            listed = pair_keys(dom, x, 2.0 * prm.h + skin)
+        if x_build is None or (min_image(dom, x - x_build) ** 2).sum(axis=1).max() > lim * lim:
+            listed = pair_keys(dom, x, 2.0 * prm.h + skin) if check else None
             x_build = x.copy()
             build_steps.append(s)
-        missing = np.setdiff1d(pair_keys(dom, x, 2.0 * prm.h), listed, assume_unique=True)
-        if missing.size:
-            raise AssertionError(f"step {s}: {missing.size} pairs closer than 2h are not in the list")
-        if r is None:
+        if check:
+            missing = np.setdiff1d(pair_keys(dom, x, 2.0 * prm.h), listed, assume_unique=True)
+            if missing.size:
+                raise AssertionError(f"step {s}: {missing.size} pairs closer than 2h are not in the list")
+        if step_fn is not None:
+            x, v = step_fn(x, v)
+        elif r is None:
             x, v, _, _, _ = step(dom, prm, x, v, fixed=fixed, n_steps=1, nthreads=nthreads)
         else:
             x, v, r, _, _, _ = step_ex1a(dom, prm, x, v, r, fixed=fixed, n_steps=1, nthreads=nthreads)

@@ -291,8 +291,9 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     L.chmax = take(sizeof(float) * n_items_max);
     L.partial = take(2 * sizeof(double) * n_items_max);
     L.inv_map = take(4 * N);
-    const bool sph = model0 == NAUTICLE_MODEL_SUMMATION || model0 == NAUTICLE_MODEL_CONTINUITY;
-    for (int k = 0; k < 3; ++k) L.off0[k] = sph && k < dim0 ? take(4 * N) : 0;
+    const bool moving = model0 == NAUTICLE_MODEL_SUMMATION || model0 == NAUTICLE_MODEL_CONTINUITY ||
+                        model0 == NAUTICLE_MODEL_DEM;
+    for (int k = 0; k < 3; ++k) L.off0[k] = moving && k < dim0 ? take(4 * N) : 0;
     L.vflag = take(2 * sizeof(uint32_t));
     L.total = off;
     return NAUTICLE_OK;
@@ -720,19 +721,22 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
 
 nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
                                      int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
-                                     int32_t* n_builds, hipEvent_t* phase_events, void* ws, size_t ws_bytes,
-                                     hipStream_t stream)
+                                     const nauticle_law_attrs* attrs, int32_t* n_builds, hipEvent_t* phase_events,
+                                     void* ws, size_t ws_bytes, hipStream_t stream)
 {
     const Plan* P;
     nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
     if (st != NAUTICLE_OK) return st;
     if (n_steps < 0) return fail(NAUTICLE_ERR_INVALID_ARG, "n_steps < 0");
-    if (P->model != NAUTICLE_MODEL_SUMMATION && P->model != NAUTICLE_MODEL_CONTINUITY)
-        return fail(NAUTICLE_ERR_INVALID_ARG, "nauticle_step_verlet needs a SUMMATION or CONTINUITY table");
+    const bool dem = P->model == NAUTICLE_MODEL_DEM;
+    if (P->model != NAUTICLE_MODEL_SUMMATION && P->model != NAUTICLE_MODEL_CONTINUITY && !dem)
+        return fail(NAUTICLE_ERR_INVALID_ARG, "nauticle_step_verlet needs a SUMMATION, CONTINUITY or DEM table");
     const bool cont = P->model == NAUTICLE_MODEL_CONTINUITY;
+    LawAttrsDev ad{};
     if ((st = check_state(*P, state, true, "state", cont)) != NAUTICLE_OK) return st;
     if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
-    if ((st = check_fields(*P, fields, true)) != NAUTICLE_OK) return st;
+    if ((st = dem ? check_acc(*P, fields) : check_fields(*P, fields, true)) != NAUTICLE_OK) return st;
+    if (dem && (st = check_attrs(*P, attrs, &ad)) != NAUTICLE_OK) return st;
     if (n_builds) *n_builds = 0;
     const StateDev cur = to_dev_model(*P, state);
     const StateDev tmp = scratch_state(*P, ws);
@@ -758,14 +762,19 @@ nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases
             e = mark(s, 1);
         }
         if (e == hipSuccess) e = mark(s, 2);
-        if (cont) {
-            if (e == hipSuccess) e = launch_pack_continuity(*P, ws, tmp, stream);
-            if (e == hipSuccess) e = launch_continuity(*P, ws, tmp, *cells, f, stream);
-        } else if (e == hipSuccess) {
-            e = launch_density(*P, ws, tmp, *cells, f, stream);
+        if (dem) {
+            if (e == hipSuccess) e = mark(s, 3);
+            if (e == hipSuccess) e = launch_interact(*P, ws, tmp, *cells, ad, f, nullptr, stream);
+        } else {
+            if (cont) {
+                if (e == hipSuccess) e = launch_pack_continuity(*P, ws, tmp, stream);
+                if (e == hipSuccess) e = launch_continuity(*P, ws, tmp, *cells, f, stream);
+            } else if (e == hipSuccess) {
+                e = launch_density(*P, ws, tmp, *cells, f, stream);
+            }
+            if (e == hipSuccess) e = mark(s, 3);
+            if (e == hipSuccess) e = launch_forces(*P, ws, tmp, *cells, f, nullptr, stream);
         }
-        if (e == hipSuccess) e = mark(s, 3);
-        if (e == hipSuccess) e = launch_forces(*P, ws, tmp, *cells, f, nullptr, stream);
         if (e == hipSuccess) e = launch_verlet_drift(*P, ws, tmp, f, build, s & 1, stream);
         if (e == hipSuccess) e = mark(s, 4);
         if (e == hipSuccess && s + 1 < n_steps) {

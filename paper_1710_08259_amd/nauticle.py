@@ -155,8 +155,8 @@ def lib():
     L.nauticle_step.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(vp), vp,
                                 ctypes.c_size_t, vp]
     L.nauticle_step_verlet.restype = st
-    L.nauticle_step_verlet.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(i32), P(vp), vp,
-                                       ctypes.c_size_t, vp]
+    L.nauticle_step_verlet.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(CLawAttrs), P(i32),
+                                       P(vp), vp, ctypes.c_size_t, vp]
     L.nauticle_interact.restype = st
     L.nauticle_interact.argtypes = [P(CCase), i32, P(CState), P(CCells), P(CLawAttrs), P(CFields), P(CState), vp,
                                     ctypes.c_size_t, vp]
@@ -518,14 +518,16 @@ class Problem:
                "nauticle_step")
         return st
 
-    def step_verlet(self, st: State, n_steps: int = 1, events=None) -> int:
+    def step_verlet(self, st: State, n_steps: int = 1, attrs: Optional["LawAttrs"] = None, events=None) -> int:
         """n_steps steps in place with the neighbour lists reused while no
         particle has moved beyond the table's skin allows; returns the
-        number of neighbour builds.  `events` as in step()."""
+        number of neighbour builds.  `attrs`: the DEM attributes (DEM
+        tables only).  `events` as in step()."""
         ev = self._events(events, n_steps)
         builds = ctypes.c_int32(0)
+        a = ctypes.byref(attrs.c()) if attrs is not None else None
         _check(lib().nauticle_step_verlet(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
-                                          ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()),
+                                          ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()), a,
                                           ctypes.byref(builds), ev, *self._ws()), "nauticle_step_verlet")
         return int(builds.value)
 

@@ -235,7 +235,7 @@ def mirror_box_case(dim, boundary, seed, n=2000, ncell=(12, 10, 8), h=0.02, mode
 
 
 def dem_damper(scale: int = 1, seed: int = 7, jitter: float = 0.3, cf: float = 0.3, dt: float = 2e-5,
-               spacing: float = 0.1 / 9, v_sigma: float = 0.0, name: str = "") -> Case:
+               spacing: float = 0.1 / 9, v_sigma: float = 0.0, skin: float = 0.0, name: str = "") -> Case:
     """Example 2's particle damper without the tank's own motion: spheres of
     R = 4 mm, rho = 7850, E = 2.06e6 Pa (as the table prints it), nu = 0.33,
     g = -9.81 ez, in a cubic box of edge 0.1 scale m with symmetric faces.
@@ -243,7 +243,7 @@ def dem_damper(scale: int = 1, seed: int = 7, jitter: float = 0.3, cf: float = 0
     each lattice side (567 scale^3 spheres).  Sites (i + 1/2) spacing
     (0.1/9 m: the table's tank), jittered by U(+-jitter) of the gap between
     spheres (of the spacing when they overlap), velocities N(0, v_sigma).
-    Cells of edge >= 2R (h = R); c_f (not given) = 0.3."""
+    Cells of edge >= 2R + skin (h = R); c_f (not given) = 0.3."""
     rng = np.random.default_rng(seed)
     R, rho_s, E, nu = 0.004, 7850.0, 2.06e6, 0.33
     L = 0.1 * scale
@@ -254,7 +254,7 @@ def dem_damper(scale: int = 1, seed: int = 7, jitter: float = 0.3, cf: float = 0
     gap = sp - 2 * R if sp > 2 * R else sp
     pos += rng.uniform(-1, 1, pos.shape) * jitter * gap / 2
     n = pos.shape[0]
-    nc, cs = _cells_for(L, _f32(R))  # h = R as stored (FP32): contacts reach 2h
+    nc, cs = _cells_for(L, _f32(R), skin)  # h = R as stored (FP32): contacts reach 2h
     m = rho_s * 4.0 / 3.0 * math.pi * R ** 3
     return Case(dim=3, ncell=(nc, nc, nc), cell_size=(cs, cs, cs), origin=(0.0, 0.0, 0.0),
                 boundary=(SYMMETRIC,) * 3, h=_f32(R), mass=m, rho0=rho_s, c0=1.0, gamma=1.0, nu=0.0, dt=dt,
@@ -262,7 +262,7 @@ def dem_damper(scale: int = 1, seed: int = 7, jitter: float = 0.3, cf: float = 0
                 vel=rng.normal(0.0, v_sigma, (n, 3)).astype(np.float32),
                 n_fixed=0, name=name or f"dem_damper_{n}", model=DEM, law=(cf,),
                 radius=np.full(n, R, np.float32), pmass=np.full(n, m, np.float32),
-                coef=np.full(n, (1 - nu ** 2) / E, np.float32))
+                coef=np.full(n, (1 - nu ** 2) / E, np.float32), skin=float(skin))
 
 
 def social_room(width: float = 20.0, density: float = 1.0, seed: int = 11, c_max: float = 0.0,

@@ -9,7 +9,11 @@ reaching a skin beyond 2h) with the FP64 oracle, through the C-ABI.
   rollouts) of the oracle's rollout, which checks at every step that the
   list holds every pair inside 2h; the number of builds within one of the
   oracle's (FP32 and FP64 displacements may cross the limit one step
-  apart), and well below one per step."""
+  apart), and well below one per step.
+- The DEM contact law under the same lists: skin 0 equals nauticle_step_law
+  bit for bit; a 150-step rollout of moving spheres without friction within
+  5e-4 of the oracle's, builds within two of its schedule (23 builds, each
+  of which may fall a step apart)."""
 import numpy as np
 import pytest
 import torch
@@ -135,12 +139,72 @@ def test_verlet_rollout_matches_oracle(name):
     assert 1 < builds < steps // 2
 
 
-def test_verlet_refuses_other_models():
+def test_verlet_refuses_other_models_and_missing_attributes():
     N = nauticle()
-    dem = WL.dem_damper(spacing=2 * 0.004 * 0.985, jitter=0.05, seed=3)
-    prob = N.Problem([dem], max_nbr=64)
+    soc = WL.social_room(width=6.0)
+    prob = N.Problem([soc], max_nbr=64)
     st = prob.state_from_cases()
     with pytest.raises(N.NauticleError) as e:
-        prob.step_verlet(st, 2)
+        prob.step_verlet(st, 2, attrs=prob.law_attrs())
+    assert e.value.status == N.ERR_INVALID_ARG
+    dem = N.Problem([WL.dem_damper(spacing=2 * 0.004 * 0.985, jitter=0.05, seed=3)], max_nbr=64)
+    st = dem.state_from_cases()
+    with pytest.raises(N.NauticleError) as e:
+        dem.step_verlet(st, 2)  # DEM needs its attributes
     assert e.value.status == N.ERR_INVALID_ARG
     torch.cuda.synchronize()
+
+
+def _dem_case(skin):
+    # moving spheres (so that builds recur) without friction, whose direction
+    # is ill-conditioned in FP32 (see the pair-law rollouts)
+    return WL.dem_damper(spacing=2 * 0.004 * 0.985, jitter=0.05, v_sigma=1.0, seed=3, cf=0.0, skin=skin)
+
+
+def test_dem_skin_zero_equals_step_law_bitwise():
+    N = nauticle()
+    case = _dem_case(0.0)
+    steps = 6
+    a = N.Problem([case], max_nbr=64)
+    st_a = a.state_from_cases()
+    a.step_law(st_a, a.law_attrs(), steps)
+    b = N.Problem([case], max_nbr=64)
+    st_b = b.state_from_cases()
+    builds = b.step_verlet(st_b, steps, attrs=b.law_attrs())
+    torch.cuda.synchronize()
+    a.check()
+    b.check()
+    assert builds == steps
+    for x, y in zip(_state_arrays(st_a, case.n, False), _state_arrays(st_b, case.n, False)):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_dem_verlet_rollout_matches_oracle():
+    N = nauticle()
+    case = _dem_case(0.0008)
+    steps = 150
+    prob = N.Problem([case], max_nbr=64)
+    st = prob.state_from_cases()
+    builds = prob.step_verlet(st, steps, attrs=prob.law_attrs())
+    torch.cuda.synchronize()
+    prob.check()
+    n = case.n
+    ids = u32(st.id)[:n]
+    x_g = np.empty((n, 3))
+    v_g = np.empty((n, 3))
+    x_g[ids] = case_absolute_from_state(case, u32(st.cell)[:n], stack(st.off, n))
+    v_g[ids] = stack(st.vel, n)
+    dom, prm = domain_of(case), params_of(case)
+    x0, v0 = case.pos.astype(np.float64), case.vel.astype(np.float64)
+
+    def one(x, v):
+        x1, v1, _ = O.step_law("dem", dom, prm, x, v, case.radius, case.pmass, case.coef,
+                               fixed=case.fixed_mask(), n_steps=1)
+        return x1, v1
+
+    x, v, _, builds_ref, when = O.verlet_steps(dom, prm, x0, v0, case.skin, steps, step_fn=one, check=False)
+    err_x = np.abs(x_g - x).max() / 0.1
+    err_v = np.abs(v_g - v).max() / np.abs(v).max()
+    print(f"dem {steps} steps: builds {builds} (oracle {builds_ref}), err x {err_x:.2e} v {err_v:.2e}")
+    assert err_x < TOL_ROLLOUT and err_v < TOL_ROLLOUT
+    assert abs(builds - builds_ref) <= 2 and 1 < builds < steps // 2

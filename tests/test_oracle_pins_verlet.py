@@ -120,3 +120,23 @@ def test_skin_zero_builds_every_step_of_a_moving_system():
     dom, prm = domain_of(c), params_of(c)
     _, _, _, builds, when = O.verlet_steps(dom, prm, c.pos, c.vel, 0.0, 6)
     assert builds == 6 and when == list(range(6))
+
+
+def test_a_pair_law_steps_through_the_same_schedule():
+    """Any stepper can run under the list: one DEM contact step at a time
+    gives the plain DEM rollout, with the list complete at every step."""
+    c = WL.dem_damper(spacing=2 * 0.004 * 0.985, jitter=0.05, v_sigma=1.0, seed=3, cf=0.0, skin=0.0008)
+    dom, prm = domain_of(c), params_of(c)
+    x0, v0 = c.pos.astype(np.float64), c.vel.astype(np.float64)
+    fixed = c.fixed_mask()
+
+    def one(x, v):
+        x1, v1, _ = O.step_law("dem", dom, prm, x, v, c.radius, c.pmass, c.coef, fixed=fixed, n_steps=1)
+        return x1, v1
+
+    steps = 30
+    x, v, _, builds, _ = O.verlet_steps(dom, prm, x0, v0, c.skin, steps, step_fn=one)
+    x2, v2, _ = O.step_law("dem", dom, prm, x0, v0, c.radius, c.pmass, c.coef, fixed=fixed, n_steps=steps)
+    np.testing.assert_array_equal(x, x2)
+    np.testing.assert_array_equal(v, v2)
+    assert 1 < builds < steps
