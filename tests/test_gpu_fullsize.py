@@ -11,7 +11,8 @@ any size.
   (velocities against max |v'| or dt times the acceleration scale, the
   larger: from rest v' is dt a).
 - 3-D dam break, 1,595,308 particles (571,308 fixed): the same one-step
-  checks on a sample drawn from the fluid and the walls.
+  checks on a sample drawn from the fluid and the walls, and the 500th
+  step's fields on the state the GPU reached after 499 steps.
 - The 8.4M lattice recipe with cells for a skin of 0.1 2h, stepped 20 times
   with Verlet lists against 20 plain steps on the same table: positions and
   velocities of every particle within the rollout bar 5e-4 (the plain path
@@ -152,3 +153,49 @@ def test_verlet_steps_at_8388608_track_the_plain_steps():
     print(f"8.4M, {steps} steps: Verlet builds {builds}, err x {err_x:.2e} v {err_v:.2e}", flush=True)
     assert builds < steps
     assert err_x < TOL_ROLLOUT and err_v < TOL_ROLLOUT
+
+
+def test_dam_break_step_500_on_the_evolved_state_sampled():
+    """After 499 steps the column has collapsed into an irregular layout.
+    The 500th step's fields, for a sample, against the oracle evaluated on
+    the GPU's own state at that time (read back exactly: cell-relative FP32
+    is exact in FP64)."""
+    N = nauticle()
+    case = WL.dam_break_3d()
+    prob = N.Problem([case])
+    st = prob.state_from_cases()
+    prob.step(st, 499)
+    torch.cuda.synchronize()
+    prob.check()
+    n = case.n
+    ids = u32(st.id)[:n].copy()
+    x = np.empty((n, 3))
+    v = np.empty((n, 3))
+    x[ids] = case_absolute_from_state(case, u32(st.cell)[:n], stack(st.off, n))
+    v[ids] = stack(st.vel, n)
+    fixed = case.fixed_mask()
+    x0 = x64(case)
+    assert np.abs(x[fixed] - x0[fixed]).max() < 1e-6 and np.all(v[fixed] == 0.0)  # walls stay
+    assert np.abs(x[~fixed] - x0[~fixed]).max() > 0.05  # the column has moved
+    prob.step(st, 1)
+    torch.cuda.synchronize()
+    prob.check()
+    perm = u32(prob.cells.perm)[:n]
+    sorted_ids = ids[perm]  # particle id at each sorted position of step 500
+    where = np.empty(n, np.int64)
+    where[sorted_ids] = np.arange(n)
+    rng = np.random.default_rng(103)
+    fs = np.sort(rng.choice(np.flatnonzero(~fixed), 2048, replace=False))
+    dom, prm = domain_of(case), params_of(case)
+    rho_r, p_r = O.density(dom, prm, x, which=fs)
+    a_r = O.forces_at(dom, prm, x, v, fs, fixed=fixed)
+    rho_g = f32(prob.fields.rho)[:n][where[fs]]
+    p_g = f32(prob.fields.p)[:n][where[fs]]
+    a_g = stack(prob.fields.acc, n)[where[fs]]
+    S = norms(case, rho_r, p_r, a_r)
+    err = dict(rho=np.abs(rho_g - rho_r).max() / S["rho"], p=np.abs(p_g - p_r).max() / S["p"],
+               a=np.abs(a_g - a_r).max() / S["a"])
+    print(f"dam break, step 500 on the evolved state: " + ", ".join(f"err {k} {e:.2e}" for k, e in err.items())
+          + f"; max |v| {np.abs(v).max():.3f} m/s", flush=True)
+    for k, e in err.items():
+        assert e < TOL_STEP, k
