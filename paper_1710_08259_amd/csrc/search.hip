@@ -286,21 +286,58 @@ k_cell_ranges(const uint32_t* __restrict__ keys, uint32_t n, uint32_t* __restric
 }
 
 // cell_first[c] = first sorted position whose key is >= c, for every key c in
-// [0, n_cells] (binary search in the sorted keys).  Unlike cell_start it is
-// defined for empty cells too, so [cell_first[a], cell_first[b + 1]) is the
-// sorted range of the cells a..b.
+// [0, n_cells].  Unlike cell_start it is defined for empty cells too, so
+// [cell_first[a], cell_first[b + 1]) is the sorted range of the cells a..b.
+// For a non-empty cell it is cell_start[c]; for an empty one, the start of
+// the next non-empty cell (starts grow with the key), i.e. the minimum of
+// cell_start over c' >= c, with the empty marker 0xFFFFFFFF above every
+// start.  A workgroup takes kCellsPerGroup cells: a suffix minimum over its
+// cells (per thread, then across the threads in LDS), and past its last cell
+// the first position whose key is beyond it (one binary search), or n.
+constexpr uint32_t kCellsPerThread = 4;
+constexpr uint32_t kCellsPerGroup = kCellsPerThread * kBlock;
+
 __global__ void __launch_bounds__(kBlock)
-k_cell_first(const uint32_t* __restrict__ keys, uint32_t n, uint32_t n_cells, uint32_t* __restrict__ first)
+k_cell_first(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ start, uint32_t n, uint32_t n_cells,
+             uint32_t* __restrict__ first)
 {
-    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c > n_cells) return;
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = lo + (hi - lo) / 2;
-        if (keys[mid] < c) lo = mid + 1;
-        else hi = mid;
+    __shared__ uint32_t s_min[kBlock];
+    __shared__ uint32_t s_after;
+    const uint32_t c0 = blockIdx.x * kCellsPerGroup;
+    if (threadIdx.x == 0) {  // first position whose key is >= the cell after this group's
+        const uint32_t c_next = c0 + kCellsPerGroup;
+        uint32_t lo = 0, hi = n;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (keys[mid] < c_next) lo = mid + 1;
+            else hi = mid;
+        }
+        s_after = lo;
     }
-    first[c] = lo;
+    const uint32_t cb = c0 + threadIdx.x * kCellsPerThread;
+    uint32_t v[kCellsPerThread];
+#pragma unroll
+    for (uint32_t i = 0; i < kCellsPerThread; ++i) {
+        const uint32_t c = cb + i;
+        v[i] = c < n_cells ? start[c] : (c == n_cells ? n : 0xFFFFFFFFu);
+    }
+#pragma unroll
+    for (int i = static_cast<int>(kCellsPerThread) - 2; i >= 0; --i) v[i] = min(v[i], v[i + 1]);
+    // suffix minimum across the threads: s_min[t] = min over threads t' >= t
+    s_min[threadIdx.x] = v[0];
+    __syncthreads();
+    for (uint32_t d = 1; d < kBlock; d <<= 1) {
+        const uint32_t o = threadIdx.x + d < kBlock ? s_min[threadIdx.x + d] : 0xFFFFFFFFu;
+        __syncthreads();
+        s_min[threadIdx.x] = min(s_min[threadIdx.x], o);
+        __syncthreads();
+    }
+    const uint32_t later = min(threadIdx.x + 1 < kBlock ? s_min[threadIdx.x + 1] : 0xFFFFFFFFu, s_after);
+#pragma unroll
+    for (uint32_t i = 0; i < kCellsPerThread; ++i) {
+        const uint32_t c = cb + i;
+        if (c <= n_cells) first[c] = min(v[i], later);
+    }
 }
 
 // Gathers the state into sorted order and packs each particle's offsets into
@@ -364,7 +401,9 @@ hipError_t launch_cell_first(const Plan& P, void* ws, const nauticle_cells& cell
 {
     if (P.n_total == 0) return hipSuccess;
     const uint32_t nc = P.n_cells_total;
-    k_cell_first<<<(nc + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(cells.key, P.n_total, nc, packed(P, ws).cell_first);
+    k_cell_first<<<(nc + 1 + kCellsPerGroup - 1) / kCellsPerGroup, kBlock, 0, s>>>(cells.key, cells.cell_start,
+                                                                                  P.n_total, nc,
+                                                                                  packed(P, ws).cell_first);
     return hipGetLastError();
 }
 
@@ -743,7 +782,8 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     // now ka == cells.key, va == cells.perm
     const int nb = static_cast<int>((n + kBlock - 1) / kBlock);
     k_cell_ranges<<<nb, kBlock, 0, s>>>(cells.key, n, cells.cell_start, cells.cell_end);
-    k_cell_first<<<(nc + 1 + kBlock - 1) / kBlock, kBlock, 0, s>>>(cells.key, n, nc, pk.cell_first);
+    k_cell_first<<<(nc + 1 + kCellsPerGroup - 1) / kCellsPerGroup, kBlock, 0, s>>>(cells.key, cells.cell_start, n,
+                                                                                  nc, pk.cell_first);
     k_reorder<<<grid, P.block, 0, s>>>(cases, items, P.n_items, cells.perm, n, in, sorted, pk.pos4);
     ItemQueue Q;
     hipError_t e = item_queue(P, ws, 0, s, &Q);
