@@ -10,6 +10,9 @@ reaching a skin beyond 2h) with the FP64 oracle, through the C-ABI.
   list holds every pair inside 2h; the number of builds within one of the
   oracle's (FP32 and FP64 displacements may cross the limit one step
   apart), and well below one per step.
+- Several cases in one table, each with its own skin: every case matches
+  its own oracle rollout; the table builds as often as its most demanding
+  case (within one).
 - The DEM contact law under the same lists: skin 0 equals nauticle_step_law
   bit for bit; a 150-step rollout of moving spheres without friction within
   5e-4 of the oracle's, builds within two of its schedule (23 builds, each
@@ -208,3 +211,40 @@ def test_dem_verlet_rollout_matches_oracle():
     print(f"dem {steps} steps: builds {builds} (oracle {builds_ref}), err x {err_x:.2e} v {err_v:.2e}")
     assert err_x < TOL_ROLLOUT and err_v < TOL_ROLLOUT
     assert abs(builds - builds_ref) <= 2 and 1 < builds < steps // 2
+
+
+def test_batched_cases_with_their_own_skins():
+    """Three cases of one table, each with its own skin (and cells): a build
+    is due when any case's particle passes its own limit, and every case
+    still matches its own oracle rollout."""
+    N = nauticle()
+    cases = [WL.lattice_case(2, (24 + 6 * b, 20 + 4 * b), 0.01, 1.3, 0.05, 0.5, seed=40 + b, c0=10.0,
+                             skin=s, name=f"skin_case_{b}")
+             for b, s in enumerate((0.002, 0.004, 0.003))]
+    steps = 40
+    prob = N.Problem(cases, max_nbr=64)
+    st = prob.state_from_cases()
+    builds = prob.step_verlet(st, steps)
+    torch.cuda.synchronize()
+    prob.check()
+    ids = u32(st.id)
+    first = 0
+    refs = []
+    for c in cases:
+        # the sorted state keeps each case's particles in its own range
+        sl = slice(first, first + c.n)
+        x_g = np.empty((c.n, 2))
+        v_g = np.empty((c.n, 2))
+        x_g[ids[sl]] = case_absolute_from_state(c, u32(st.cell)[sl], stack(st.off, first + c.n)[first:])
+        v_g[ids[sl]] = stack(st.vel, first + c.n)[first:]
+        dom, prm = domain_of(c), params_of(c)
+        x, v, _, b_ref, _ = O.verlet_steps(dom, prm, c.pos, c.vel, c.skin, steps)
+        err_x = np.abs(O.min_image(dom, x_g - x)).max() / norms(c)["x"]
+        err_v = np.abs(v_g - v).max() / np.abs(v).max()
+        print(f"{c.name}: err x {err_x:.2e} v {err_v:.2e}, oracle builds {b_ref}")
+        assert err_x < TOL_ROLLOUT and err_v < TOL_ROLLOUT
+        refs.append(b_ref)
+        first += c.n
+    print(f"table builds {builds}, per-case oracle builds {refs}")
+    # the table builds at least as often as its most demanding case, and still skips builds
+    assert max(refs) - 1 <= builds < steps
