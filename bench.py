@@ -20,6 +20,7 @@ same case: the "vs plain" figure), the 256-case batched workload and the
 import argparse
 import json
 import os
+import tempfile
 import sys
 import time
 
@@ -32,7 +33,7 @@ sys.path.insert(0, ROOT)
 SEARCH_FLOP_PER_CANDIDATE = 9
 FORCE_FLOP_PER_PAIR = 40
 PEAK_FP32_TFLOPS = 157.3            # published MI355X FP32 vector peak (packed FP32)
-PEAK_FP32_TFLOPS_UNPACKED = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz: packed FP32 is disabled in this build
+PEAK_FP32_TFLOPS_UNPACKED = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz: the kernels are compiled without packed FP32
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per k_nlist launch from the FETCH_SIZE / WRITE_SIZE counter runs
 # summarised in profiles/neighbour_kernels_periodic_3d_8388608_traffic.md
@@ -319,8 +320,8 @@ def batched_extra(device, steps=10):
     cases = WL.batched_2d()
     cands = (N.Tuning(), N.Tuning(block=128, persistent=1, groups_per_cu=4),
              N.Tuning(block=256, persistent=1, groups_per_cu=4), N.Tuning(block=128))
-    best, timings = autotune.tune(cases, steps=2, candidates=cands,
-                                  cache_path=os.path.join(ROOT, "gpurun_out", "tuning.json"), force=True)
+    cache = os.environ.get("NAUTICLE_TUNING_CACHE", os.path.join(tempfile.gettempdir(), "nauticle_tuning.json"))
+    best, timings = autotune.tune(cases, steps=2, candidates=cands, cache_path=cache, force=True)
     prob = N.Problem(cases, device=device, tuning=best)
     st = prob.state_from_cases()
     wall, phase, pairs = timed_steps(prob, st, steps, 2)

@@ -255,7 +255,7 @@ def test_lattice_density_converges_to_rho0():
     assert errs[-1] < 1e-3 and errs[-1] < errs[0]
 
 
-def test_survey_lattice_values():
+def test_lattice_sum_regression_values():
     """Regression values of the exact lattice sums (2-D h = 1.3 dx, 3-D
     h = 1.2 dx and 1.05 dx) and of the gradient moments."""
     assert _lattice_moments(2, 1.3)[0] == pytest.approx(1.01047315, abs=1e-8)
