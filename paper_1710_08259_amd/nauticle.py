@@ -398,7 +398,7 @@ class Problem:
                                   *self._ws()), "nauticle_bin")
         if vel is not None:
             for k in range(self.dim):
-                st.vel[k].copy_(vel[k])
+                st.vel[k][: self.n].copy_(vel[k][: self.n])
         return st
 
     def state_from_cases(self) -> State:

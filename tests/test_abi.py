@@ -171,3 +171,24 @@ def test_skin_does_not_change_the_workspace(N):
     a = WL.periodic_2d_4096()
     gap = float(np.float32(a.cell_size[0])) - 2.0 * a.h
     assert _ws_bytes(N, [WL.scaled(a, skin=0.5 * gap)])[1] == _ws_bytes(N, [a])[1]
+
+
+def test_particle_count_limit_of_the_list_index(N):
+    """A list entry holds the neighbour's index in 26 bits: 2^26 - 1
+    particles are accepted, 2^26 are rejected on the host.  (Case stand-ins:
+    only the count matters here.)"""
+    base = WL.periodic_2d_4096()
+
+    class Counted:
+        def __init__(self, n):
+            self.__dict__.update(base.__dict__)
+            self._n = n
+
+        @property
+        def n(self):
+            return self._n
+
+    limit = (1 << 26) - 1
+    assert _ws_bytes(N, [Counted(limit)])[0] == N.OK
+    assert _ws_bytes(N, [Counted(limit + 1)])[0] == N.ERR_INVALID_ARG
+    assert "2^26" in N.lib().nauticle_last_error().decode()

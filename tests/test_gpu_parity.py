@@ -371,3 +371,45 @@ def test_adjoint_one_step_matches_oracle_vjp():
     ec0 = abs(dc0.item() - oc0) / abs(oc0)
     print(f"adjoint: x {ex:.2e} v {ev:.2e} nu {enu:.2e} c0 {ec0:.2e}")
     assert ex < 1e-4 and ev < 1e-5 and enu < 1e-4 and ec0 < 1e-4
+
+
+def test_empty_and_single_particle_cases_in_one_table():
+    """Empty cases and a one-particle case beside an ordinary one: the
+    ordinary case steps bit for bit as it does alone; the lone particle has
+    no neighbour (its density is its own kernel value) and follows the
+    oracle; a table holding only an empty case steps as a no-op."""
+    N = nauticle()
+    base = WL.lattice_case(2, (16, 12), 0.01, 1.3, 0.05, 0.2, seed=61, c0=10.0, name="base")
+    empty = WL.scaled(base, pos=base.pos[:0], vel=base.vel[:0], name="empty")
+    single = WL.scaled(base, pos=base.pos[5:6], vel=base.vel[5:6], g=(0.3, -1.0, 0.0), name="single")
+    steps = 3
+    prob = N.Problem([empty, single, base, empty])
+    st = prob.state_from_cases()
+    prob.step(st, steps)
+    torch.cuda.synchronize()
+    prob.check()
+    solo = N.Problem([base])
+    st_s = solo.state_from_cases()
+    solo.step(st_s, steps)
+    torch.cuda.synchronize()
+    solo.check()
+    n = base.n
+    sl = slice(1, 1 + n)  # the base case's global range: after the empty case and the single particle
+    np.testing.assert_array_equal(u32(st.cell)[sl], u32(st_s.cell)[:n])
+    np.testing.assert_array_equal(u32(st.id)[sl], u32(st_s.id)[:n])
+    for k in range(2):
+        np.testing.assert_array_equal(f32(st.off[k])[sl].view(np.uint32), f32(st_s.off[k])[:n].view(np.uint32))
+        np.testing.assert_array_equal(f32(st.vel[k])[sl].view(np.uint32), f32(st_s.vel[k])[:n].view(np.uint32))
+    # the lone particle
+    dom, prm = domain_of(single), params_of(single)
+    x, v, rho, _, _ = O.step(dom, prm, x64(single), v64(single), n_steps=steps)
+    x_g = case_absolute_from_state(single, u32(st.cell)[0:1], stack(st.off, 1))
+    assert np.abs(x_g - x).max() < 1e-7 and np.abs(stack(st.vel, 1) - v).max() < 1e-6
+    assert u32(prob.cells.nbr_count)[0] == 0
+    assert f32(prob.fields.rho)[0] == pytest.approx(rho[0], rel=1e-6)
+    # nothing but an empty case
+    none = N.Problem([empty])
+    st0 = none.state_from_cases()
+    none.step(st0, 2)
+    torch.cuda.synchronize()
+    none.check()
