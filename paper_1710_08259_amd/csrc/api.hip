@@ -763,8 +763,11 @@ nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases
         }
         if (e == hipSuccess) e = mark(s, 2);
         if (dem) {
+            // the records are packed at a build; between builds the drift keeps them current
             if (e == hipSuccess) e = mark(s, 3);
-            if (e == hipSuccess) e = launch_interact(*P, ws, tmp, *cells, ad, f, nullptr, stream);
+            if (e == hipSuccess)
+                e = build ? launch_interact(*P, ws, tmp, *cells, ad, f, nullptr, stream)
+                          : launch_interact_on_records(*P, ws, tmp, *cells, ad, f, stream);
         } else {
             if (cont) {
                 if (e == hipSuccess) e = launch_pack_continuity(*P, ws, tmp, stream);

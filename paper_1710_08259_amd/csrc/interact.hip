@@ -160,9 +160,10 @@ k_interact(const CaseDev* __restrict__ cases, const Item* __restrict__ items, It
     });
 }
 
+// pack: write the records first (else they are in place already).
 template <class Law, uint32_t G>
 hipError_t launch_law(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells, LawAttrsDev at_,
-                      FieldsDev f, const StateDev* next, hipStream_t s)
+                      FieldsDev f, const StateDev* next, bool pack, hipStream_t s)
 {
     const Packed pk = packed(P, ws);
     float4* r0 = pk.a4;
@@ -171,9 +172,13 @@ hipError_t launch_law(const Plan& P, void* ws, StateDev sorted, const nauticle_c
     const CaseDev* cases = at<CaseDev>(ws, P.L.cases);
     const Item* items = at<Item>(ws, P.L.items);
     uint32_t* err = at<uint32_t>(ws, P.L.err);
-    k_pack_law<Law><<<xcd_grid(P.n_items), P.block, 0, s>>>(cases, items, P.n_items, sorted, at_, r0, r1, r2, err);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (pack) {
+        k_pack_law<Law><<<xcd_grid(P.n_items), P.block, 0, s>>>(cases, items, P.n_items, sorted, at_, r0, r1, r2,
+                                                                err);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     ItemQueue Q;
     e = item_queue(P, ws, 5, s, &Q);
     if (e != hipSuccess) return e;
@@ -196,8 +201,16 @@ hipError_t launch_interact(const Plan& P, void* ws, StateDev sorted, const nauti
                            const LawAttrsDev& attrs, FieldsDev f, const StateDev* next, hipStream_t s)
 {
     if (P.n_items == 0) return hipSuccess;
-    if (P.model == NAUTICLE_MODEL_DEM) return launch_law<DemLaw, kLawGroup>(P, ws, sorted, cells, attrs, f, next, s);
-    return launch_law<SocialLaw, kLawGroup>(P, ws, sorted, cells, attrs, f, next, s);
+    if (P.model == NAUTICLE_MODEL_DEM)
+        return launch_law<DemLaw, kLawGroup>(P, ws, sorted, cells, attrs, f, next, true, s);
+    return launch_law<SocialLaw, kLawGroup>(P, ws, sorted, cells, attrs, f, next, true, s);
+}
+
+hipError_t launch_interact_on_records(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
+                                      const LawAttrsDev& attrs, FieldsDev f, hipStream_t s)
+{
+    if (P.n_items == 0 || P.model != NAUTICLE_MODEL_DEM) return hipSuccess;
+    return launch_law<DemLaw, kLawGroup>(P, ws, sorted, cells, attrs, f, nullptr, false, s);
 }
 
 }  // namespace nau

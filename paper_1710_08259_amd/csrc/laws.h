@@ -105,4 +105,11 @@ struct SocialLaw {
     }
 };
 
+// The DEM contact pass (accelerations only) on records that are in place
+// already: packed by an earlier launch_interact on the same sorted order and
+// refreshed since by the Verlet drift (steps between neighbour builds: the
+// radii, masses and material constants of a sorted position do not change).
+hipError_t launch_interact_on_records(const Plan& P, void* ws, StateDev sorted, const nauticle_cells& cells,
+                                      const LawAttrsDev& attrs, FieldsDev f, hipStream_t s);
+
 }  // namespace nau

@@ -25,20 +25,23 @@ __global__ void k_verlet_clear(uint32_t* __restrict__ flag)
 // The semi-implicit Euler update of sorted particle i in place, offsets not
 // re-split: v' = v + dt a, off' = off + dt v' (fixed particles: v' = 0, off
 // kept), the same FP32 operations as the fused update of the force pass.
-// Also refreshes pos4 (offsets, cell x index: what the density and
-// continuity passes gather) and, in the continuity model, the evolved
-// density.  `first`: the state is the one the lists were built from, so its
+// Also refreshes what the next pair pass gathers: pos4 (offsets, cell x
+// index) for the density and continuity passes, or, for the DEM contact law
+// (kLaw), the motion parts of its records (offsets, radius) and (velocity,
+// mass), whose other parts stay valid between builds; and, in the
+// continuity model, the evolved density.  `first`: the state is the one the lists were built from, so its
 // offsets become the build-time offsets off0.  A particle with
 // |off' - off0|^2 > lim^2, or one that left the box across a face of a
 // non-periodic axis (which the fused step shifts periodically at once, and
 // the next build's re-split does the same), raises the step's rebuild word
 // (one store per wave at most, and none once the word is set); workgroup 0
 // clears the other word, which the next step raises.
-template <int kModel>
+template <int kModel, bool kLaw>
 __global__ void __launch_bounds__(kMaxBlock)
 k_verlet_drift(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
                FieldsDev f, float* __restrict__ off0x, float* __restrict__ off0y, float* __restrict__ off0z,
-               float4* __restrict__ pos4, uint32_t first, uint32_t* flag_set, uint32_t* flag_clear, uint32_t* err)
+               float4* __restrict__ pos4, float4* __restrict__ rec_b, uint32_t first, uint32_t* flag_set,
+               uint32_t* flag_clear, uint32_t* err)
 {
     const uint32_t ix = xcd_item(n_items);
     if (ix >= n_items) return;
@@ -54,6 +57,7 @@ k_verlet_drift(const CaseDev* __restrict__ cases, const Item* __restrict__ items
         cell_coords(C, cell, cc);
         float* const o0[3] = {off0x, off0y, off0z};
         float o[3] = {0.0f, 0.0f, 0.0f};
+        float vo[3] = {0.0f, 0.0f, 0.0f};
         float d2 = 0.0f;
         bool finite = true, left = false;
         for (int c = 0; c < 3; ++c) {
@@ -66,12 +70,18 @@ k_verlet_drift(const CaseDev* __restrict__ cases, const Item* __restrict__ items
             st.vel[c][i] = vn;
             st.off[c][i] = on;
             o[c] = on;
+            vo[c] = vn;
             const float d = on - ob;
             d2 = fmaf(d, d, d2);
             finite &= isfinite(on);
             if (!C.periodic[c]) left |= (cc[c] == 0 && on < 0.0f) || (cc[c] == C.nc[c] - 1 && on >= C.cs[c]);
         }
-        pos4[i] = make_float4(o[0], o[1], o[2], static_cast<float>(cc[0]));
+        if constexpr (kLaw) {  // pos4 is the law's (offsets, radius), rec_b its (velocity, mass)
+            pos4[i] = make_float4(o[0], o[1], o[2], pos4[i].w);
+            rec_b[i] = make_float4(vo[0], vo[1], vo[2], rec_b[i].w);
+        } else {
+            pos4[i] = make_float4(o[0], o[1], o[2], static_cast<float>(cc[0]));
+        }
         if constexpr (kModel == NAUTICLE_MODEL_CONTINUITY) st.rho[i] = f.rho[i];
         if (!finite) set_error(err, kErrNonFinite);
         exceed = left || d2 > C.verlet_lim2;
@@ -129,12 +139,16 @@ hipError_t launch_verlet_drift(const Plan& P, void* ws, StateDev st, FieldsDev f
 {
     if (P.n_items == 0) return hipSuccess;
     uint32_t* flag = at<uint32_t>(ws, P.L.vflag);
-    auto kern = P.model == NAUTICLE_MODEL_CONTINUITY ? k_verlet_drift<NAUTICLE_MODEL_CONTINUITY>
-                                                     : k_verlet_drift<NAUTICLE_MODEL_SUMMATION>;
+    // the DEM contact pass gathers its records (a4 = (offsets, R), b4 = (v, m)), the SPH passes pos4
+    const bool law = P.model == NAUTICLE_MODEL_DEM;
+    const Packed pk = packed(P, ws);
+    auto kern = law ? k_verlet_drift<NAUTICLE_MODEL_SUMMATION, true>
+                    : (P.model == NAUTICLE_MODEL_CONTINUITY ? k_verlet_drift<NAUTICLE_MODEL_CONTINUITY, false>
+                                                            : k_verlet_drift<NAUTICLE_MODEL_SUMMATION, false>);
     kern<<<xcd_grid(P.n_items), P.block, 0, s>>>(
         at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), P.n_items, st, f, at<float>(ws, P.L.off0[0]),
-        at<float>(ws, P.L.off0[1]), at<float>(ws, P.L.off0[2]), packed(P, ws).pos4, first ? 1u : 0u,
-        flag + (parity & 1), flag + ((parity + 1) & 1), at<uint32_t>(ws, P.L.err));
+        at<float>(ws, P.L.off0[1]), at<float>(ws, P.L.off0[2]), law ? pk.a4 : pk.pos4, law ? pk.b4 : nullptr,
+        first ? 1u : 0u, flag + (parity & 1), flag + ((parity + 1) & 1), at<uint32_t>(ws, P.L.err));
     return hipGetLastError();
 }
 
