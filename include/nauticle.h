@@ -444,8 +444,12 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
  * [0, cell_size)).  With skin = 0 every step in which a particle moves
  * rebuilds, and the result equals nauticle_step's bit for bit.
  * The decision is made on the host: after each step the library copies one
- * device word back and waits for `stream` (one host-device round trip per
- * step).  After the call `state` holds the particles, re-split, in the
+ * device word back (into a 4-byte pinned host word it allocates once per
+ * host thread) and waits for that copy.  Without phase events it first
+ * queues the next step's first pass (density, continuity or the contact
+ * pass: they write only fields), so the device keeps working during the
+ * round trip; when a build turns out to be due, that pass is redone after
+ * the build.  After the call `state` holds the particles, re-split, in the
  * sorted order of the last build; `fields` hold the last step's fields and
  * `cells` the last build's lists (their cell offsets refer to the
  * build-time cells, not to `state`'s).  n_builds (optional host pointer)

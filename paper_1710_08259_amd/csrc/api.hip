@@ -738,6 +738,20 @@ nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases
     if ((st = dem ? check_acc(*P, fields) : check_fields(*P, fields, true)) != NAUTICLE_OK) return st;
     if (dem && (st = check_attrs(*P, attrs, &ad)) != NAUTICLE_OK) return st;
     if (n_builds) *n_builds = 0;
+    if (n_steps == 0) return NAUTICLE_OK;
+    // the rebuild word comes back through a pinned host word (one per host
+    // thread, kept until the process ends), so the copy does not block
+    thread_local uint32_t* t_word = nullptr;
+    if (!t_word) {
+        hipError_t a = hipHostMalloc(reinterpret_cast<void**>(&t_word), sizeof(uint32_t), hipHostMallocDefault);
+        if (a != hipSuccess) {
+            t_word = nullptr;
+            return hip_fail(a, "nauticle_step_verlet: pinned host word");
+        }
+    }
+    hipEvent_t copied;
+    hipError_t e = hipEventCreateWithFlags(&copied, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "nauticle_step_verlet: event");
     const StateDev cur = to_dev_model(*P, state);
     const StateDev tmp = scratch_state(*P, ws);
     const FieldsDev f = to_dev(fields);
@@ -745,9 +759,28 @@ nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases
     auto mark = [&](int32_t s, int k) {
         return phase_events ? hipEventRecord(phase_events[5 * s + k], stream) : hipSuccess;
     };
+    // the step's first pass: density or continuity (SPH), the contact pass (DEM; its records are
+    // packed at a build, and between builds the drift keeps them current)
+    auto first_pass = [&](bool after_build) -> hipError_t {
+        if (dem)
+            return after_build ? launch_interact(*P, ws, tmp, *cells, ad, f, nullptr, stream)
+                               : launch_interact_on_records(*P, ws, tmp, *cells, ad, f, stream);
+        if (cont) {
+            hipError_t r = launch_pack_continuity(*P, ws, tmp, stream);
+            return r == hipSuccess ? launch_continuity(*P, ws, tmp, *cells, f, stream) : r;
+        }
+        return launch_density(*P, ws, tmp, *cells, f, stream);
+    };
+    // Without phase events, the next step's first pass is queued before the
+    // host waits for the rebuild word, so the device does not idle during the
+    // round trip.  It reads the state and writes only fields and packed
+    // records, so when a build turns out to be due its work is redone after
+    // the build.
+    const bool ahead_ok = phase_events == nullptr;
+    bool ahead = false;  // this step's first pass was queued at the end of the previous one
     int32_t builds = 0;
     bool build = true;
-    hipError_t e = n_steps > 0 ? launch_verlet_clear(*P, ws, stream) : hipSuccess;
+    e = launch_verlet_clear(*P, ws, stream);
     // the live state is the workspace copy `tmp` (sorted order of the last
     // build, offsets drifting); `state` receives it re-split before each
     // build and at the end
@@ -763,32 +796,29 @@ nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases
         }
         if (e == hipSuccess) e = mark(s, 2);
         if (dem) {
-            // the records are packed at a build; between builds the drift keeps them current
             if (e == hipSuccess) e = mark(s, 3);
-            if (e == hipSuccess)
-                e = build ? launch_interact(*P, ws, tmp, *cells, ad, f, nullptr, stream)
-                          : launch_interact_on_records(*P, ws, tmp, *cells, ad, f, stream);
+            if (e == hipSuccess && !ahead) e = first_pass(build);
         } else {
-            if (cont) {
-                if (e == hipSuccess) e = launch_pack_continuity(*P, ws, tmp, stream);
-                if (e == hipSuccess) e = launch_continuity(*P, ws, tmp, *cells, f, stream);
-            } else if (e == hipSuccess) {
-                e = launch_density(*P, ws, tmp, *cells, f, stream);
-            }
+            if (e == hipSuccess && !ahead) e = first_pass(build);
             if (e == hipSuccess) e = mark(s, 3);
             if (e == hipSuccess) e = launch_forces(*P, ws, tmp, *cells, f, nullptr, stream);
         }
         if (e == hipSuccess) e = launch_verlet_drift(*P, ws, tmp, f, build, s & 1, stream);
         if (e == hipSuccess) e = mark(s, 4);
+        ahead = false;
         if (e == hipSuccess && s + 1 < n_steps) {
             // is a build due before the next step?
-            uint32_t word = 0;
-            e = hipMemcpyAsync(&word, flag + (s & 1), sizeof(word), hipMemcpyDeviceToHost, stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(stream);
-            build = word != 0u;
+            e = hipMemcpyAsync(t_word, flag + (s & 1), sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipEventRecord(copied, stream);
+            if (e == hipSuccess && ahead_ok) e = first_pass(false);
+            if (e == hipSuccess) e = hipEventSynchronize(copied);
+            build = *t_word != 0u;
+            ahead = ahead_ok && !build;
         }
     }
-    if (e == hipSuccess && n_steps > 0) e = launch_resplit(*P, ws, tmp, cur, stream);
+    if (e == hipSuccess) e = launch_resplit(*P, ws, tmp, cur, stream);
+    const hipError_t d = hipEventDestroy(copied);
+    if (e == hipSuccess) e = d;
     if (e != hipSuccess) return hip_fail(e, "nauticle_step_verlet");
     if (n_builds) *n_builds = builds;
     return NAUTICLE_OK;
