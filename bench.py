@@ -128,6 +128,8 @@ def parse():
     ap.add_argument("--verlet-only", action="store_true",
                     help="only the main lattice with neighbour lists reused between builds")
     ap.add_argument("--skin-frac", type=float, default=0.1, help="Verlet skin in units of 2h")
+    ap.add_argument("--law-tuning", default=None,
+                    help="block/persistent/groups_per_cu for the pair-law workloads instead of the autotuner's pick")
     ap.add_argument("--ex1a-scale", type=float, default=87.0,
                     help="resolution factor of the Example 1a dam break (87: 4.1M particles)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -446,7 +448,8 @@ def dem_verlet_extra(device, skin_frac=0.1, steps=100, warmup=5, plain_ms=None):
     skin = skin_frac * 2.0 * 0.004
     case = WL.dem_damper(19, spacing=2 * 0.004 * 0.99, jitter=0.05, skin=skin,
                          name=f"dem_damper_3889053_skin{skin_frac:g}")
-    prob = N.Problem([case], device=device, max_nbr=32)
+    best, _ = law_tuning(case, 32, device, force=False)
+    prob = N.Problem([case], device=device, max_nbr=32, tuning=best)
     st = prob.state_from_cases()
     attrs = prob.law_attrs()
     prob.step_verlet(st, warmup, attrs=attrs)
@@ -458,11 +461,31 @@ def dem_verlet_extra(device, skin_frac=0.1, steps=100, warmup=5, plain_ms=None):
     wall = time.perf_counter() - t0
     prob.check()
     out = {"workload": case.name, "particles": case.n, "cells": list(case.ncell), "skin": skin,
-           "skin_over_2h": skin_frac, "steps": steps, "builds": builds,
+           "skin_over_2h": skin_frac, "tuning": best.__dict__, "steps": steps, "builds": builds,
            "ms_per_step": round(wall * 1e3 / steps, 4), "steps_per_s": steps / wall}
     if plain_ms:
         out["speedup_vs_build_every_step"] = round(plain_ms / (wall * 1e3 / steps), 3)
     return out
+
+
+LAW_TUNING = None  # a fixed launch shape for the pair-law workloads (--law-tuning), else the autotuner's
+
+
+def law_tuning(case, max_nbr, device, force):
+    """The autotuner's launch shape for a pair-law case (measured now when
+    `force`, else from its cache when there), and the timings it measured;
+    or the shape fixed on the command line."""
+    from paper_1710_08259_amd import autotune
+    from paper_1710_08259_amd import nauticle as N
+
+    if LAW_TUNING is not None:
+        return LAW_TUNING, {}
+
+    cands = (N.Tuning(), N.Tuning(block=128), N.Tuning(block=64), N.Tuning(block=128, persistent=1, groups_per_cu=4))
+    cache = os.environ.get("NAUTICLE_TUNING_CACHE", os.path.join(tempfile.gettempdir(), "nauticle_tuning.json"))
+    best, timings = autotune.tune([case], steps=3, candidates=cands, cache_path=cache, device=device, force=force,
+                                  max_nbr=max_nbr)
+    return best, timings or {}
 
 
 def law_extra(device, which, steps=10, warmup=2):
@@ -470,8 +493,9 @@ def law_extra(device, which, steps=10, warmup=2):
     table's 567 spheres (3,889,053, symmetric faces) packed at 0.99 of their
     diameter (every sphere touching its lattice neighbours, a compressed
     bed), or the social force room of side 800 m (654,394 people, fixed
-    walls); next to it the FP64 oracle's step on the paper-size case (the
-    567 spheres packed the same way / a 20 m room)."""
+    walls), in the launch shape the autotuner picks for it; next to it the
+    FP64 oracle's step on the paper-size case (the 567 spheres packed the
+    same way / a 20 m room)."""
     import numpy as np
 
     from oracle import oracle as O
@@ -480,7 +504,9 @@ def law_extra(device, which, steps=10, warmup=2):
 
     packed = dict(spacing=2 * 0.004 * 0.99, jitter=0.05)
     case = WL.dem_damper(19, **packed) if which == "dem" else WL.social_room(width=800.0)
-    prob = N.Problem([case], device=device, max_nbr=32 if which == "dem" else 64)
+    max_nbr = 32 if which == "dem" else 64
+    best, timings = law_tuning(case, max_nbr, device, force=True)
+    prob = N.Problem([case], device=device, max_nbr=max_nbr, tuning=best)
     st = prob.state_from_cases()
     attrs = prob.law_attrs()
     wall, phase, pairs = timed_steps(prob, st, steps, warmup,
@@ -499,6 +525,9 @@ def law_extra(device, which, steps=10, warmup=2):
                nthreads=1)
     t_or = (time.perf_counter() - t0) / k_or
     return {"workload": case.name, "particles": case.n, "fixed": case.n_fixed, "cells": list(case.ncell),
+            "tuning": best.__dict__,
+            "tuning_ms_per_step": {f"{t.block}/{t.persistent}/{t.groups_per_cu}": round(v, 4)
+                                   for t, v in timings.items()},
             "steps_per_s": steps / wall, "ms_per_step": round(wall * 1e3 / steps, 4),
             "pairs_within_2h_per_s": pairs / wall, "pairs_per_particle": round(pairs / steps / case.n, 2),
             "phases": {"sort_reorder_ms": round(phase[0], 4), "neighbour_lists_ms": round(phase[1], 4),
@@ -568,6 +597,10 @@ def main():
     from paper_1710_08259_amd import workloads as WL
 
     device = "cuda:0"
+    if args.law_tuning:
+        global LAW_TUNING
+        b, p, g = (int(v) for v in args.law_tuning.split("/"))
+        LAW_TUNING = N.Tuning(block=b, persistent=p, groups_per_cu=g)
     if args.ch_only:
         print(json.dumps({"extra": {"ch": ch_extra(device)}}), flush=True)
         return

@@ -3,11 +3,13 @@
 For a set of cases it times a short run of full steps under every candidate
 tuning (particles per work item / threads per workgroup, grid vs persistent
 launch, persistent workgroups per compute unit) with HIP events on the
-library's stream, and keeps the fastest.  Results are cached as JSON per
-workload bucket: dimension, log2 of particles per cell, log2 of the total
-particle count and log2 of the number of cases.  The tuning changes only how
-work is distributed, never the arithmetic: every candidate gives bitwise the
-same results.
+library's stream, and keeps the fastest.  Full steps are nauticle_step for
+the SPH models and nauticle_step_law for the pair laws (with the cases' own
+attributes).  Results are cached as JSON per workload bucket: model,
+dimension, log2 of particles per cell, log2 of the total particle count and
+log2 of the number of cases.  The tuning changes only how work is
+distributed, never the arithmetic: every candidate gives bitwise the same
+results.
 """
 from __future__ import annotations
 
@@ -29,7 +31,8 @@ def bucket(cases) -> str:
     n = sum(c.n for c in cases)
     cells = sum(c.n_cells for c in cases)
     ppc = max(n / max(cells, 1), 1e-3)
-    return (f"d{cases[0].dim}-ppc{round(math.log2(ppc))}-n{round(math.log2(max(n, 1)))}"
+    model = int(getattr(cases[0], "model", N.MODEL_SUMMATION))
+    return (f"m{model}-d{cases[0].dim}-ppc{round(math.log2(ppc))}-n{round(math.log2(max(n, 1)))}"
             f"-c{round(math.log2(len(cases)))}")
 
 
@@ -48,20 +51,31 @@ def _load(path):
         return {}
 
 
-def time_tuning(cases, tuning: N.Tuning, steps: int = 3, warmup: int = 1, device="cuda:0") -> float:
+def time_tuning(cases, tuning: N.Tuning, steps: int = 3, warmup: int = 1, device="cuda:0",
+                max_nbr: Optional[int] = None) -> float:
     """Mean GPU milliseconds per full step under `tuning`."""
-    prob = N.Problem(cases, device=device, tuning=tuning)
+    prob = N.Problem(cases, device=device, tuning=tuning, max_nbr=max_nbr)
     st = prob.state_from_cases()
-    prob.step(st, warmup)
+    if prob.model in (N.MODEL_DEM, N.MODEL_SOCIAL):
+        attrs = prob.law_attrs()
+
+        def run(n, events=None):
+            prob.step_law(st, attrs, n, events=events)
+    elif prob.model in (N.MODEL_SUMMATION, N.MODEL_CONTINUITY):
+        def run(n, events=None):
+            prob.step(st, n, events=events)
+    else:
+        raise ValueError("the autotuner times stepping models (SPH and the pair laws)")
+    run(warmup)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5 * steps)]
-    prob.step(st, steps, events=ev)
+    run(steps, events=ev)
     torch.cuda.synchronize()
     prob.check()
     return sum(ev[5 * k].elapsed_time(ev[5 * k + 4]) for k in range(steps)) / steps
 
 
 def tune(cases, steps: int = 3, candidates=CANDIDATES, cache_path: Optional[str] = None, device="cuda:0",
-         force: bool = False):
+         force: bool = False, max_nbr: Optional[int] = None):
     """Best tuning for `cases` (from the cache unless `force`), and the table
     of timings {tuning: ms per step} when it was measured now."""
     path = cache_path or default_cache_path()
@@ -71,7 +85,7 @@ def tune(cases, steps: int = 3, candidates=CANDIDATES, cache_path: Optional[str]
         return N.Tuning(**cache[key]["tuning"]), None
     timings = {}
     for cand in candidates:
-        timings[cand] = time_tuning(cases, cand, steps=steps, device=device)
+        timings[cand] = time_tuning(cases, cand, steps=steps, device=device, max_nbr=max_nbr)
     best = min(timings, key=timings.get)
     cache[key] = {"tuning": {"block": best.block, "persistent": best.persistent,
                              "groups_per_cu": best.groups_per_cu},

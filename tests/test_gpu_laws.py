@@ -176,3 +176,27 @@ def test_pair_law_entry_points_refuse_other_tables():
         dem.step(s2, 1)  # pair-law tables step with step_law
     assert e.value.status == N.ERR_INVALID_ARG
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_pair_law_steps_are_identical_under_every_tuning(name, tmp_path):
+    """The launch shape distributes the work and never changes a value; the
+    autotuner times pair-law tables with their own steps and caches a pick."""
+    from paper_1710_08259_amd import autotune
+
+    N = nauticle()
+    case = CASES[name]
+    runs = []
+    for t in (N.Tuning(), N.Tuning(block=64), N.Tuning(block=128, persistent=1, groups_per_cu=4)):
+        prob = N.Problem([case], max_nbr=64, tuning=t)
+        st = prob.state_from_cases()
+        prob.step_law(st, prob.law_attrs(), 5)
+        torch.cuda.synchronize()
+        prob.check()
+        runs.append([u32(st.cell)[: case.n], stack(st.off, case.n).view(np.uint32), stack(st.vel, case.n).view(np.uint32)])
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            np.testing.assert_array_equal(a, b)
+    best, timings = autotune.tune([case], steps=2, candidates=(N.Tuning(), N.Tuning(block=64)),
+                                  cache_path=str(tmp_path / "t.json"), max_nbr=64)
+    assert best in timings and autotune.bucket([case]).startswith(f"m{case.model}-")
