@@ -347,16 +347,22 @@ def dam_break_extra(device, steps=10):
 
 def ex1a_extra(device, scale, steps=10, warmup=2):
     """Example 1a's 2-D dam break (continuity, linear EOS, artificial
-    viscosity, symmetric faces), refined by `scale`, from rest; next to it
-    the FP64 oracle's step on the paper's own 558-particle column."""
+    viscosity, symmetric faces), refined by `scale`, from rest, in the launch
+    shape the autotuner picks; next to it the FP64 oracle's step on the
+    paper's own 558-particle column."""
     import numpy as np
 
     from oracle import oracle as O
     from paper_1710_08259_amd import nauticle as N
     from paper_1710_08259_amd import workloads as WL
 
+    from paper_1710_08259_amd import autotune
+
     case = WL.ex1a_dam_break(scale)
-    prob = N.Problem([case], device=device)
+    cache = os.environ.get("NAUTICLE_TUNING_CACHE", os.path.join(tempfile.gettempdir(), "nauticle_tuning.json"))
+    best, timings = autotune.tune([case], steps=3, candidates=(N.Tuning(), N.Tuning(block=128), N.Tuning(block=64)),
+                                  cache_path=cache, device=device, force=True)
+    prob = N.Problem([case], device=device, tuning=best)
     st = prob.state_from_cases()
     wall, phase, pairs = timed_steps(prob, st, steps, warmup)
     del prob, st
@@ -371,6 +377,9 @@ def ex1a_extra(device, scale, steps=10, warmup=2):
     O.step_ex1a(dom, prm, x, np.zeros_like(x), small.rho.astype(np.float64), n_steps=k_or, nthreads=1)
     t_or = (time.perf_counter() - t0) / k_or
     return {"workload": case.name, "particles": case.n, "cells": list(case.ncell), "scale": scale,
+            "tuning": best.__dict__,
+            "tuning_ms_per_step": {f"{t.block}/{t.persistent}/{t.groups_per_cu}": round(v, 4)
+                                   for t, v in (timings or {}).items()},
             "steps_per_s": steps / wall, "ms_per_step": round(wall * 1e3 / steps, 4),
             "interactions_per_s": pairs / wall, "neighbours_per_particle": round(pairs / steps / case.n, 2),
             "phases": {"sort_reorder_ms": round(phase[0], 4), "neighbour_lists_ms": round(phase[1], 4),
