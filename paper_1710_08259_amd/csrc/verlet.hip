@@ -8,10 +8,10 @@
 // build-time one.  The paper reruns the search only when the layout has
 // changed (Sec. 4); a skin lets the layout change a little without a new
 // search.  A particle that moved more than its case's lim (just under
-// skin / 2) from its build-time position makes the next step rebuild, which
-// first re-splits every offset into (cell, offset in [0, cs)) with the
-// binning rule's own arithmetic (split_offset), exactly as the fused step
-// does every step.
+// skin / 2) from its build-time position, or left the box across a face of a
+// non-periodic axis, makes the next step rebuild, which first re-splits
+// every offset into (cell, offset in [0, cs)) with the binning rule's own
+// arithmetic (split_offset), exactly as the fused step does every step.
 #include "internal.h"
 
 namespace nau {
@@ -25,17 +25,19 @@ __global__ void k_verlet_clear(uint32_t* __restrict__ flag)
 // The semi-implicit Euler update of sorted particle i in place, offsets not
 // re-split: v' = v + dt a, off' = off + dt v' (fixed particles: v' = 0, off
 // kept), the same FP32 operations as the fused update of the force pass.
-// Also refreshes what the next pair pass gathers: pos4 (offsets, cell x
-// index) for the density and continuity passes, or, for the DEM contact law
-// (kLaw), the motion parts of its records (offsets, radius) and (velocity,
-// mass), whose other parts stay valid between builds; and, in the
-// continuity model, the evolved density.  `first`: the state is the one the lists were built from, so its
-// offsets become the build-time offsets off0.  A particle with
-// |off' - off0|^2 > lim^2, or one that left the box across a face of a
-// non-periodic axis (which the fused step shifts periodically at once, and
-// the next build's re-split does the same), raises the step's rebuild word
-// (one store per wave at most, and none once the word is set); workgroup 0
-// clears the other word, which the next step raises.
+// It also refreshes what the next pair pass gathers:
+// - pos4 (offsets, cell x index) for the density and continuity passes;
+// - for the DEM contact law (kLaw), the motion parts of its records
+//   (offsets, radius) and (velocity, mass), whose other parts stay valid
+//   between builds;
+// - in the continuity model, the evolved density.
+// `first`: the state is the one the lists were built from, so its offsets
+// become the build-time offsets off0.  A particle with |off' - off0|^2 >
+// lim^2, or one that left the box across a face of a non-periodic axis
+// (which the fused step shifts periodically at once, and the next build's
+// re-split does the same), raises the step's rebuild word (one store per
+// wave at most, and none once the word is set); workgroup 0 clears the
+// other word, which the next step raises.
 template <int kModel, bool kLaw>
 __global__ void __launch_bounds__(kMaxBlock)
 k_verlet_drift(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
