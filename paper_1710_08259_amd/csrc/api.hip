@@ -13,6 +13,7 @@
 
 #include "internal.h"
 #include "laws.h"
+#include "sort.h"
 
 using namespace nau;
 
@@ -263,7 +264,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     // workspace layout
     Layout& L = P.L;
     const size_t N = std::max<size_t>(n_total, 1);
-    const size_t n_tiles = (N + 4095) / 4096;
+    const size_t n_tiles = (N + kSortTile - 1) / kSortTile;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -279,8 +280,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     for (int k = 0; k < 9; ++k) L.state[k] = take(4 * N);
     L.sort_keys = take(4 * N);
     L.sort_vals = take(4 * N);
-    L.sort_hist = take(4 * 256 * n_tiles);
-    L.sort_totals = take(4 * 256);
+    L.sort_hist = take(4 * kSortBins * n_tiles);
+    L.sort_totals = take(4 * kSortBins);
     L.cell_first = take(4 * (static_cast<size_t>(n_cells_total) + 1));
     L.pos4 = take(16 * (N + kPosPad));
     L.a4 = take(16 * N);

@@ -1,5 +1,6 @@
-// Neighbour search on gfx950: binning, cell keys, stable LSD radix sort,
-// cell start/end table, reorder, and the per-particle neighbour lists.
+// Neighbour search on gfx950: binning, cell keys, their stable sort (in
+// sort.hip), cell start/end table, reorder, and the per-particle neighbour
+// lists.
 //
 // The cell grid follows the paper's domain (Sec. 3.2.1): cuboid cells no
 // smaller than the influence radius, so every neighbour of a particle lies in
@@ -7,7 +8,7 @@
 // x fastest, offset by the case's first key, so one global sort orders every
 // case of a batch at once and a row of cells along x is contiguous in sorted
 // order.
-#include "internal.h"
+#include "sort.h"
 
 namespace nau {
 
@@ -106,162 +107,6 @@ k_make_keys(const CaseDev* __restrict__ cases, const Item* __restrict__ items, u
     if (c >= C.n_cells) c = C.n_cells - 1;
     keys[i] = C.cell_base + c;
     vals[i] = i;
-}
-
-// ----------------------------------------------------------------------------
-// stable LSD radix sort of (key, value) pairs
-// ----------------------------------------------------------------------------
-// Per pass (digit of `bits` <= 8 bits at `shift`):
-//   1. k_rs_hist:    per tile of kTile keys, digit histogram -> hist[d][tile]
-//   2. k_rs_scan:    per digit, exclusive scan over tiles; digit totals
-//   3. k_rs_scatter: per tile, in input order, each key's rank among equal
-//                    digits (wave ballots for lanes of one wave, LDS counters
-//                    across waves and iterations) -> stable scatter.
-
-constexpr int kBins = 256;
-constexpr int kItems = 16;
-constexpr int kTile = kBlock * kItems;
-
-__device__ inline uint32_t wave_lane() { return __lane_id(); }
-
-// Inclusive scan across a wave64 with shuffles.
-__device__ inline uint32_t wave_inclusive_scan(uint32_t v)
-{
-    const uint32_t lane = wave_lane();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, kWave);
-        if (lane >= static_cast<uint32_t>(d)) v += o;
-    }
-    return v;
-}
-
-// Exclusive scan over the 256 threads of a block; returns the block total in
-// *total.  `tmp` must hold kBlock / kWave words.  Contains barriers.
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp, uint32_t* total)
-{
-    const uint32_t lane = wave_lane();
-    const uint32_t wave = threadIdx.x / kWave;
-    uint32_t inc = wave_inclusive_scan(v);
-    if (lane == kWave - 1) tmp[wave] = inc;
-    __syncthreads();
-    uint32_t before = 0, all = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) {
-        uint32_t t = tmp[w];
-        if (static_cast<uint32_t>(w) < wave) before += t;
-        all += t;
-    }
-    __syncthreads();
-    *total = all;
-    return before + inc - v;
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_rs_hist(const uint32_t* __restrict__ keys, uint32_t n, int shift, uint32_t mask,
-          uint32_t* __restrict__ hist, uint32_t n_tiles)
-{
-    __shared__ uint32_t h[kBins];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t base = blockIdx.x * kTile;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-        uint32_t idx = base + k * kBlock + threadIdx.x;
-        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
-    }
-    __syncthreads();
-    hist[threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_rs_scan(uint32_t* __restrict__ hist, uint32_t n_tiles, uint32_t* __restrict__ totals)
-{
-    __shared__ uint32_t tmp[kBlock / kWave];
-    uint32_t* row = hist + static_cast<size_t>(blockIdx.x) * n_tiles;
-    uint32_t running = 0;
-    constexpr int kPer = 4;
-    for (uint32_t base = 0; base < n_tiles; base += kBlock * kPer) {
-        uint32_t v[kPer];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            uint32_t idx = base + threadIdx.x * kPer + k;
-            v[k] = idx < n_tiles ? row[idx] : 0u;
-            sum += v[k];
-        }
-        uint32_t total;
-        uint32_t ex = block_exclusive_scan(sum, tmp, &total);
-        uint32_t acc = running + ex;
-#pragma unroll
-        for (int k = 0; k < kPer; ++k) {
-            uint32_t idx = base + threadIdx.x * kPer + k;
-            if (idx < n_tiles) row[idx] = acc;
-            acc += v[k];
-        }
-        running += total;
-    }
-    if (threadIdx.x == 0) totals[blockIdx.x] = running;
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_rs_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in, uint32_t n,
-             int shift, uint32_t mask, int bits, const uint32_t* __restrict__ hist,
-             const uint32_t* __restrict__ totals, uint32_t n_tiles, uint32_t* __restrict__ keys_out,
-             uint32_t* __restrict__ vals_out)
-{
-    __shared__ uint32_t digit_base[kBins];
-    __shared__ uint32_t wave_cnt[kBlock / kWave][kBins];
-    __shared__ uint32_t tmp[kBlock / kWave];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = wave_lane();
-    const uint32_t wave = tid / kWave;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-
-    // global start of each digit for this tile
-    uint32_t total;
-    uint32_t ex = block_exclusive_scan(totals[tid], tmp, &total);
-    digit_base[tid] = ex + hist[tid * n_tiles + blockIdx.x];
-#pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) wave_cnt[w][tid] = 0;
-    __syncthreads();
-
-    const uint32_t base = blockIdx.x * kTile;
-    for (int k = 0; k < kItems; ++k) {
-        const uint32_t idx = base + k * kBlock + tid;
-        const bool valid = idx < n;
-        const uint32_t key = valid ? keys_in[idx] : 0u;
-        const uint32_t val = valid ? vals_in[idx] : 0u;
-        const uint32_t d = (key >> shift) & mask;
-        // lanes of this wave holding the same digit
-        uint64_t peers = __ballot(valid);
-        for (int b = 0; b < bits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        const uint32_t rank = __popcll(peers & lt_mask);
-        if (valid && rank == 0) wave_cnt[wave][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = digit_base[d] + rank;
-            for (uint32_t w = 0; w < wave; ++w) pos += wave_cnt[w][d];
-            if (pos < n) {  // always true for a consistent histogram; guards memory
-                keys_out[pos] = key;
-                vals_out[pos] = val;
-            }
-        }
-        __syncthreads();
-        // advance each digit's base past this iteration's keys
-        uint32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < kBlock / kWave; ++w) {
-            add += wave_cnt[w][tid];
-            wave_cnt[w][tid] = 0;
-        }
-        digit_base[tid] += add;
-        __syncthreads();
-    }
 }
 
 // ----------------------------------------------------------------------------
@@ -751,42 +596,28 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     }
     if (n == 0) return hipGetLastError();
 
-    // radix sort: passes of <= 8 bits, balanced
-    const int bits = P.key_bits;
-    const int passes = (bits + 7) / 8;
-    const int per = (bits + passes - 1) / passes;
-    // ping-pong so that the last pass lands in cells.key / cells.perm
-    uint32_t* ka = at<uint32_t>(ws, P.L.sort_keys);
-    uint32_t* va = at<uint32_t>(ws, P.L.sort_vals);
-    uint32_t* kb = cells.key;
-    uint32_t* vb = cells.perm;
-    if (passes % 2 == 0) {
-        uint32_t* t = ka; ka = kb; kb = t;
-        t = va; va = vb; vb = t;
-    }
+    // stable radix sort of (key, index); started in the buffer pair that makes
+    // the last pass land in cells.key / cells.perm
+    uint32_t* const ws_keys = at<uint32_t>(ws, P.L.sort_keys);
+    uint32_t* const ws_vals = at<uint32_t>(ws, P.L.sort_vals);
+    const bool even = radix_passes(P.key_bits) % 2 == 0;
+    uint32_t* const keys[2] = {even ? cells.key : ws_keys, even ? ws_keys : cells.key};
+    uint32_t* const vals[2] = {even ? cells.perm : ws_vals, even ? ws_vals : cells.perm};
     const uint32_t grid = xcd_grid(P.n_items);
-    k_make_keys<<<grid, P.block, 0, s>>>(cases, items, P.n_items, in.cell, ka, va);
-    const uint32_t n_tiles = (n + kTile - 1) / kTile;
-    uint32_t* hist = at<uint32_t>(ws, P.L.sort_hist);
-    uint32_t* totals = at<uint32_t>(ws, P.L.sort_totals);
-    for (int pass = 0; pass < passes; ++pass) {
-        const int shift = pass * per;
-        const int b = (bits - shift) < per ? (bits - shift) : per;
-        const uint32_t mask = (1u << b) - 1u;
-        k_rs_hist<<<n_tiles, kBlock, 0, s>>>(ka, n, shift, mask, hist, n_tiles);
-        k_rs_scan<<<kBins, kBlock, 0, s>>>(hist, n_tiles, totals);
-        k_rs_scatter<<<n_tiles, kBlock, 0, s>>>(ka, va, n, shift, mask, b, hist, totals, n_tiles, kb, vb);
-        uint32_t* t = ka; ka = kb; kb = t;
-        t = va; va = vb; vb = t;
-    }
-    // now ka == cells.key, va == cells.perm
+    k_make_keys<<<grid, P.block, 0, s>>>(cases, items, P.n_items, in.cell, keys[0], vals[0]);
+    // fewer particles than cells: consecutive keys mostly differ, and the
+    // sort's scatter orders each tile in LDS before storing it
+    const bool sparse = n < nc;
+    hipError_t e = launch_radix_sort(keys, vals, n, P.key_bits, sparse, at<uint32_t>(ws, P.L.sort_hist),
+                                     at<uint32_t>(ws, P.L.sort_totals), s);
+    if (e != hipSuccess) return e;
     const int nb = static_cast<int>((n + kBlock - 1) / kBlock);
     k_cell_ranges<<<nb, kBlock, 0, s>>>(cells.key, n, cells.cell_start, cells.cell_end);
     k_cell_first<<<(nc + 1 + kCellsPerGroup - 1) / kCellsPerGroup, kBlock, 0, s>>>(cells.key, cells.cell_start, n,
                                                                                   nc, pk.cell_first);
     k_reorder<<<grid, P.block, 0, s>>>(cases, items, P.n_items, cells.perm, n, in, sorted, pk.pos4);
     ItemQueue Q;
-    hipError_t e = item_queue(P, ws, 0, s, &Q);
+    e = item_queue(P, ws, 0, s, &Q);
     if (e == hipSuccess && mid) e = hipEventRecord(mid, s);
     if (e != hipSuccess) return e;
     const uint32_t mx = static_cast<uint32_t>(cells.max_nbr);
