@@ -38,8 +38,24 @@ def _clustered():
     return WL.scaled(base, pos=np.mod(pts, L).astype(np.float32))
 
 
+def _sparse(dim, n_side, seed):
+    """Fewer particles than cells: uniform random points in a periodic box
+    whose cells of 2h hold ~0.2-0.5 particles each, over several sort tiles
+    with a partial last one."""
+    base = WL.lattice_case(dim, n_side, 0.01, 0.3, 0.0, 0.05, seed=seed, name=f"sparse_{dim}d")
+    rng = np.random.default_rng(seed)
+    L = base.length()[:dim]
+    pts = np.zeros((base.n, 3))
+    pts[:, :dim] = rng.uniform(0, 1, (base.n, dim)) * L
+    return WL.scaled(base, pos=pts[:, :dim].astype(np.float32))
+
+
 CASES = small_cases()
 NAMES = list(CASES)
+# tables with fewer particles than cells, whose sort orders each tile in LDS
+# before storing it: 3-D, 20,384 particles in 46 x 46 x 43 cells (17 key
+# bits, 3 passes); 2-D, 18,000 in 250 x 200 cells (16 key bits, 2 passes)
+SPARSE = {"sparse_3d": _sparse(3, (28, 28, 26), 43), "sparse_2d": _sparse(2, (150, 120), 44)}
 # the clustered layout has up to ~380 neighbours per particle
 MAX_NBR = {"clustered_3d": 512}
 
@@ -82,7 +98,18 @@ def test_bin_is_bit_exact(name):
 @pytest.mark.parametrize("name", NAMES)
 def test_build_cells_is_bit_exact(name):
     N = nauticle()
-    case = CASES[name]
+    _check_build_cells(N, CASES[name])
+
+
+@pytest.mark.parametrize("name", list(SPARSE))
+def test_sparse_build_cells_is_bit_exact(name):
+    N = nauticle()
+    case = SPARSE[name]
+    assert case.n < case.n_cells and case.n % 4096 != 0 and case.n > 4 * 4096
+    _check_build_cells(N, case)
+
+
+def _check_build_cells(N, case):
     prob, st = run_search(N, case)
     n = case.n
     cell_in = u32(st.cell)[:n]
