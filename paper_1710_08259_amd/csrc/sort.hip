@@ -115,11 +115,13 @@ k_rs_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ 
              const uint32_t* __restrict__ totals, uint32_t n_tiles, uint32_t* __restrict__ keys_out,
              uint32_t* __restrict__ vals_out)
 {
+    // the staging arrays are used by the ordered variant only
     constexpr uint32_t kStage = kOrdered ? kSortTile : 1u;
+    constexpr uint32_t kStageBins = kOrdered ? kSortBins : 1u;
     __shared__ uint32_t s_key[kStage];  // the tile ordered by digit, stably
     __shared__ uint32_t s_val[kStage];
-    __shared__ uint32_t out_base[kSortBins];    // where the tile's digit-d keys go in the output
-    __shared__ uint32_t tile_start[kSortBins];  // where they start in the tile's order
+    __shared__ uint32_t out_base[kStageBins];    // where the tile's digit-d keys go in the output
+    __shared__ uint32_t tile_start[kStageBins];  // where they start in the tile's order
     __shared__ uint32_t next[kSortBins];        // the next free place of digit d (tile order, or output)
     __shared__ uint32_t wave_cnt[kBlock / kWave][kSortBins];
     __shared__ uint32_t tmp[kBlock / kWave];
