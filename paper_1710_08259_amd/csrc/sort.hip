@@ -148,13 +148,24 @@ k_rs_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ 
     for (int w = 0; w < kBlock / kWave; ++w) wave_cnt[w][tid] = 0;
     __syncthreads();
 
-    // each key's place among the tile's keys of its digit, in input order
+    // the tile's keys and values, all loads in flight at once (the ranking
+    // loop below has barriers, across which loads would not be moved)
     const uint32_t base = tile * kSortTile;
+    uint32_t keys[kItems], vals[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint32_t idx = base + k * kBlock + tid;
+        keys[k] = idx < n ? keys_in[idx] : 0u;
+        vals[k] = idx < n ? vals_in[idx] : 0u;
+    }
+
+    // each key's place among the tile's keys of its digit, in input order
+#pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const uint32_t idx = base + k * kBlock + tid;
         const bool valid = idx < n;
-        const uint32_t key = valid ? keys_in[idx] : 0u;
-        const uint32_t val = valid ? vals_in[idx] : 0u;
+        const uint32_t key = keys[k];
+        const uint32_t val = vals[k];
         const uint32_t d = (key >> shift) & mask;
         // lanes of this wave holding the same digit
         uint64_t peers = __ballot(valid);
