@@ -189,30 +189,69 @@ k_cell_first(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ sta
 // one float4 for the neighbour search and the density pass; w holds the x
 // index of the particle's cell (exact in FP32), from which the search forms
 // its cell frame shift.
+// Two items per workgroup, one particle of each per thread: the reads of
+// both permutation entries, and then all the gathers, are in flight
+// together.  Each particle costs two dependent trips to memory, so twice the
+// particles per thread keep twice the bytes in flight.
+constexpr uint32_t kReorderItems = 2;
+
 __global__ void __launch_bounds__(kMaxBlock)
 k_reorder(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
           const uint32_t* __restrict__ perm, uint32_t n, StateDev in, StateDev out, float4* __restrict__ pos4)
 {
-    const uint32_t ix = xcd_item(n_items);
-    if (ix >= n_items) return;
-    const Item it = items[ix];
-    if (threadIdx.x >= it.count) return;
-    const CaseDev& C = cases[it.case_id];
-    const uint32_t p = it.first + threadIdx.x;
-    uint32_t q = perm[p];
-    if (q >= n) q = p;  // never for a permutation; guards memory
-    const uint32_t cell = in.cell[q];
-    out.cell[p] = cell;
-    out.id[p] = in.id[q];
-    if (in.rho) out.rho[p] = in.rho[q];
-    float o[3] = {0.0f, 0.0f, 0.0f};
-    for (int k = 0; k < 3; ++k) {
-        if (k >= C.dim) break;
-        o[k] = in.off[k][q];
-        out.off[k][p] = o[k];
-        out.vel[k][p] = in.vel[k][q];
+    const uint32_t n_groups = (n_items + kReorderItems - 1) / kReorderItems;
+    const uint32_t gx = xcd_item(n_groups);
+    if (gx >= n_groups) return;
+    bool live[kReorderItems];
+    uint32_t p[kReorderItems], q[kReorderItems], ncx[kReorderItems];
+    int dim[kReorderItems];
+#pragma unroll
+    for (uint32_t h = 0; h < kReorderItems; ++h) {
+        const uint32_t ix = gx * kReorderItems + h;
+        live[h] = false;
+        p[h] = 0;
+        ncx[h] = 1;
+        dim[h] = 0;
+        if (ix < n_items) {
+            const Item it = items[ix];
+            const CaseDev& C = cases[it.case_id];
+            live[h] = threadIdx.x < it.count;
+            p[h] = it.first + threadIdx.x;
+            ncx[h] = static_cast<uint32_t>(C.nc[0]);
+            dim[h] = C.dim;
+        }
     }
-    pos4[p] = make_float4(o[0], o[1], o[2], static_cast<float>(cell % static_cast<uint32_t>(C.nc[0])));
+#pragma unroll
+    for (uint32_t h = 0; h < kReorderItems; ++h) {
+        q[h] = live[h] ? perm[p[h]] : 0u;
+        if (q[h] >= n) q[h] = p[h] < n ? p[h] : 0u;  // never for a permutation; guards memory
+    }
+    uint32_t cell[kReorderItems], id[kReorderItems];
+    float rho[kReorderItems], o[kReorderItems][3], v[kReorderItems][3];
+#pragma unroll
+    for (uint32_t h = 0; h < kReorderItems; ++h) {
+        if (!live[h]) continue;
+        cell[h] = in.cell[q[h]];
+        id[h] = in.id[q[h]];
+        rho[h] = in.rho ? in.rho[q[h]] : 0.0f;
+        for (int k = 0; k < 3; ++k) {
+            o[h][k] = k < dim[h] ? in.off[k][q[h]] : 0.0f;
+            v[h][k] = k < dim[h] ? in.vel[k][q[h]] : 0.0f;
+        }
+    }
+#pragma unroll
+    for (uint32_t h = 0; h < kReorderItems; ++h) {
+        if (!live[h]) continue;
+        out.cell[p[h]] = cell[h];
+        out.id[p[h]] = id[h];
+        if (in.rho) out.rho[p[h]] = rho[h];
+        for (int k = 0; k < 3; ++k) {
+            if (k >= dim[h]) break;
+            out.off[k][p[h]] = o[h][k];
+            out.vel[k][p[h]] = v[h][k];
+        }
+        pos4[p[h]] = make_float4(o[h][0], o[h][1], o[h][2], static_cast<float>(cell[h] % ncx[h]));
+    }
 }
 
 __global__ void __launch_bounds__(kMaxBlock)
@@ -615,7 +654,8 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     k_cell_ranges<<<nb, kBlock, 0, s>>>(cells.key, n, cells.cell_start, cells.cell_end);
     k_cell_first<<<(nc + 1 + kCellsPerGroup - 1) / kCellsPerGroup, kBlock, 0, s>>>(cells.key, cells.cell_start, n,
                                                                                   nc, pk.cell_first);
-    k_reorder<<<grid, P.block, 0, s>>>(cases, items, P.n_items, cells.perm, n, in, sorted, pk.pos4);
+    const uint32_t reorder_groups = (P.n_items + kReorderItems - 1) / kReorderItems;
+    k_reorder<<<xcd_grid(reorder_groups), P.block, 0, s>>>(cases, items, P.n_items, cells.perm, n, in, sorted, pk.pos4);
     ItemQueue Q;
     e = item_queue(P, ws, 0, s, &Q);
     if (e == hipSuccess && mid) e = hipEventRecord(mid, s);
