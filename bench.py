@@ -39,20 +39,20 @@ PEAK_HBM_GBS = 8000.0
 # summarised in profiles/neighbour_kernels_periodic_3d_8388608_traffic.md
 # (scaled by a plain 1 GiB copy); valid only for the search source the
 # counters were taken on, reported as null otherwise.
-NLIST_TRAFFIC_BYTES = 3.393e9
-NLIST_TRAFFIC_SOURCE_SHA256 = "4f2d2a13526381dc"
+NLIST_TRAFFIC_BYTES = 3.394e9
+NLIST_TRAFFIC_SOURCE_SHA256 = "53792ec679911904"
 
 
 # Issue-slot and vector-L1 figures from the counter runs summarised in
 # profiles/neighbour_kernels_periodic_3d_8388608_issue.md, guarded the same
 # way (by the sources of the kernels they were taken on).
-NLIST_VALU_ISSUE_FRAC = 0.944
-FORCE_L1_ACCESS_RATE = 1.04   # accesses per CU per clock; the vector L1 serves about one
+NLIST_VALU_ISSUE_FRAC = 0.946
+FORCE_L1_ACCESS_RATE = 1.08   # accesses per CU per clock; the vector L1 serves about one
 # HBM bytes per density / force launch (FETCH_SIZE x2 + WRITE_SIZE, same
 # runs and guard as the L1 rate), and the force pass's VALU issue fraction.
-DENSITY_TRAFFIC_BYTES = 2.705e9 + 0.403e9
+DENSITY_TRAFFIC_BYTES = 2.702e9 + 0.403e9
 FORCE_TRAFFIC_BYTES = 3.019e9 + 0.369e9
-FORCE_VALU_ISSUE_FRAC = 0.465
+FORCE_VALU_ISSUE_FRAC = 0.474
 FORCE_SOURCES_SHA256 = "f8cafb7c444e8c70"
 
 

@@ -119,6 +119,32 @@ __global__ void k_fill_u32(uint32_t* __restrict__ a, uint32_t n, uint32_t v)
     if (i < n) a[i] = v;
 }
 
+// The same fill, four words per thread with 16-byte stores (a 16-byte aligned).
+constexpr uint32_t kFillWords = 4;
+
+__global__ void k_fill_u32x4(uint32_t* __restrict__ a, uint32_t n, uint32_t v)
+{
+    const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) * kFillWords;
+    if (i + kFillWords <= n) {
+        *reinterpret_cast<uint4*>(a + i) = make_uint4(v, v, v, v);
+    } else {
+        for (uint32_t k = i; k < n; ++k) a[k] = v;
+    }
+}
+
+// Fills a[0 .. n) with v on s: 16-byte stores where a is 16-byte aligned.
+hipError_t fill_u32(uint32_t* a, uint32_t n, uint32_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (reinterpret_cast<uintptr_t>(a) % 16u == 0) {
+        const uint32_t threads = (n + kFillWords - 1) / kFillWords;
+        k_fill_u32x4<<<(threads + kBlock - 1) / kBlock, kBlock, 0, s>>>(a, n, v);
+    } else {
+        k_fill_u32<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(a, n, v);
+    }
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_cell_ranges(const uint32_t* __restrict__ keys, uint32_t n, uint32_t* __restrict__ start,
               uint32_t* __restrict__ end)
@@ -142,6 +168,7 @@ k_cell_ranges(const uint32_t* __restrict__ keys, uint32_t n, uint32_t* __restric
 constexpr uint32_t kCellsPerThread = 4;
 constexpr uint32_t kCellsPerGroup = kCellsPerThread * kBlock;
 
+template <bool kVec>  // start is 16-byte aligned
 __global__ void __launch_bounds__(kBlock)
 k_cell_first(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ start, uint32_t n, uint32_t n_cells,
              uint32_t* __restrict__ first)
@@ -161,10 +188,18 @@ k_cell_first(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ sta
     }
     const uint32_t cb = c0 + threadIdx.x * kCellsPerThread;
     uint32_t v[kCellsPerThread];
+    if (kVec && cb + kCellsPerThread <= n_cells) {  // one 16-byte load
+        const uint4 w = *reinterpret_cast<const uint4*>(start + cb);
+        v[0] = w.x;
+        v[1] = w.y;
+        v[2] = w.z;
+        v[3] = w.w;
+    } else {
 #pragma unroll
-    for (uint32_t i = 0; i < kCellsPerThread; ++i) {
-        const uint32_t c = cb + i;
-        v[i] = c < n_cells ? start[c] : (c == n_cells ? n : 0xFFFFFFFFu);
+        for (uint32_t i = 0; i < kCellsPerThread; ++i) {
+            const uint32_t c = cb + i;
+            v[i] = c < n_cells ? start[c] : (c == n_cells ? n : 0xFFFFFFFFu);
+        }
     }
 #pragma unroll
     for (int i = static_cast<int>(kCellsPerThread) - 2; i >= 0; --i) v[i] = min(v[i], v[i + 1]);
@@ -285,9 +320,10 @@ hipError_t launch_cell_first(const Plan& P, void* ws, const nauticle_cells& cell
 {
     if (P.n_total == 0) return hipSuccess;
     const uint32_t nc = P.n_cells_total;
-    k_cell_first<<<(nc + 1 + kCellsPerGroup - 1) / kCellsPerGroup, kBlock, 0, s>>>(cells.key, cells.cell_start,
-                                                                                  P.n_total, nc,
-                                                                                  packed(P, ws).cell_first);
+    auto cell_first = reinterpret_cast<uintptr_t>(cells.cell_start) % 16u == 0 ? k_cell_first<true>
+                                                                               : k_cell_first<false>;
+    cell_first<<<(nc + 1 + kCellsPerGroup - 1) / kCellsPerGroup, kBlock, 0, s>>>(cells.key, cells.cell_start,
+                                                                                P.n_total, nc, packed(P, ws).cell_first);
     return hipGetLastError();
 }
 
@@ -628,10 +664,10 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     const Item* items = at<Item>(ws, P.L.items);
     uint32_t* err = at<uint32_t>(ws, P.L.err);
     const Packed pk = packed(P, ws);
-    const int fill_blocks = static_cast<int>((nc + kBlock - 1) / kBlock);
     if (nc > 0) {
-        k_fill_u32<<<fill_blocks, kBlock, 0, s>>>(cells.cell_start, nc, NAUTICLE_EMPTY);
-        k_fill_u32<<<fill_blocks, kBlock, 0, s>>>(cells.cell_end, nc, NAUTICLE_EMPTY);
+        hipError_t fe = fill_u32(cells.cell_start, nc, NAUTICLE_EMPTY, s);
+        if (fe == hipSuccess) fe = fill_u32(cells.cell_end, nc, NAUTICLE_EMPTY, s);
+        if (fe != hipSuccess) return fe;
     }
     if (n == 0) return hipGetLastError();
 
@@ -652,8 +688,10 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     if (e != hipSuccess) return e;
     const int nb = static_cast<int>((n + kBlock - 1) / kBlock);
     k_cell_ranges<<<nb, kBlock, 0, s>>>(cells.key, n, cells.cell_start, cells.cell_end);
-    k_cell_first<<<(nc + 1 + kCellsPerGroup - 1) / kCellsPerGroup, kBlock, 0, s>>>(cells.key, cells.cell_start, n,
-                                                                                  nc, pk.cell_first);
+    auto cell_first = reinterpret_cast<uintptr_t>(cells.cell_start) % 16u == 0 ? k_cell_first<true>
+                                                                               : k_cell_first<false>;
+    cell_first<<<(nc + 1 + kCellsPerGroup - 1) / kCellsPerGroup, kBlock, 0, s>>>(cells.key, cells.cell_start, n, nc,
+                                                                                pk.cell_first);
     const uint32_t reorder_groups = (P.n_items + kReorderItems - 1) / kReorderItems;
     k_reorder<<<xcd_grid(reorder_groups), P.block, 0, s>>>(cases, items, P.n_items, cells.perm, n, in, sorted, pk.pos4);
     ItemQueue Q;
