@@ -109,6 +109,34 @@ def test_sparse_build_cells_is_bit_exact(name):
     _check_build_cells(N, case)
 
 
+@pytest.mark.parametrize("name", ["sparse_3d", "periodic_3d_ragged"])
+def test_cell_table_in_unaligned_arrays(name):
+    """Cell-start and cell-end arrays that are not 16-byte aligned take the
+    word-by-word fill and cell_first kernels: keys, permutation, cell table
+    and lists equal those of the aligned arrays, bit for bit."""
+    N = nauticle()
+    case = SPARSE.get(name) or CASES[name]
+    prob_a, st_a = run_search(N, case)
+    prob_u = N.Problem([case], max_nbr=prob_a.max_nbr)
+    nc = case.n_cells
+    start = torch.empty(nc + 1, dtype=torch.int32, device="cuda")[1:]
+    end = torch.empty(nc + 1, dtype=torch.int32, device="cuda")[1:]
+    assert start.data_ptr() % 16 != 0 and end.data_ptr() % 16 != 0
+    prob_u.cells.cell_start, prob_u.cells.cell_end = start, end
+    st_u = prob_u.state_from_cases()
+    prob_u.build_cells(st_u)
+    torch.cuda.synchronize()
+    prob_u.check()
+    n = case.n
+    for field in ("key", "perm", "nbr_count"):
+        np.testing.assert_array_equal(u32(getattr(prob_u.cells, field))[:n], u32(getattr(prob_a.cells, field))[:n])
+    for field in ("cell_start", "cell_end"):
+        np.testing.assert_array_equal(u32(getattr(prob_u.cells, field))[:nc], u32(getattr(prob_a.cells, field))[:nc])
+    cnt = u32(prob_a.cells.nbr_count)[:n]
+    live = np.arange(prob_a.max_nbr)[:, None] < cnt[None, :]
+    np.testing.assert_array_equal(u32(prob_u.cells.entries())[:, :n][live], u32(prob_a.cells.entries())[:, :n][live])
+
+
 def _check_build_cells(N, case):
     prob, st = run_search(N, case)
     n = case.n
