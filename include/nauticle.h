@@ -304,12 +304,13 @@ nauticle_status nauticle_unbin(const nauticle_case* cases, int32_t n_cases,
  * (sorted must not alias in), then every particle's neighbour list under
  * the FP32 predicate: with delta = j's cell minus i's cell (in {-1,0,1}^dim
  * after periodic folding; no folding on cut-off axes; other pairs are never
- * neighbours), d_k = fl32(off_j,k - fl32(off_i,k - delta_k cell_size_k)) and
+ * neighbours), d_k = fl32(fl32(off_j,k - off_i,k) + delta_k cell_size_k) and
  * r2 = fmaf(d_z, d_z, fmaf(d_y, d_y, d_x d_x)), j is a neighbour of i iff
- * j != i and r2 < fl32(4h^2).
+ * j != i and r2 < fl32(4h^2).  The pair taken the other way round gives
+ * exactly -d, so j is in i's list if and only if i is in j's.
  * On a symmetric axis a stencil cell beyond the face stands for the mirror
  * image of the particle's own boundary cell: for such an axis
- * d_k = fl32(-off_j,k - fl32(off_i,k - delta_k cell_size_k)) with
+ * d_k = fl32(fl32(-off_j,k - off_i,k) + delta_k cell_size_k) with
  * delta_k = 0 at the lower face and 2 at the upper one, and the particle's
  * own image is a neighbour (the only case j = i).
  * Each list holds the neighbours row by row of the stencil (z offset

@@ -227,26 +227,29 @@ static int or_cell_delta(const or_domain* D, int k, int64_t ci, int64_t cj)
 }
 
 /* FP32 neighbour predicate between particle i and j whose cells differ by
- * delta (j's cell minus i's, each component in {-1,0,1}): i's offset is
- * moved into j's cell frame, then
- *   t_k  = fl32(off_i,k - delta_k * cs_k)      (delta*cs is exact)
- *   d_k  = fl32(off_j,k - t_k)                 (= r_j - r_i up to rounding)
+ * delta (j's cell minus i's, each component in {-1,0,1}):
+ *   d_k  = fl32(fl32(off_j,k - off_i,k) + delta_k * cs_k)   (delta*cs is exact)
  *   r2   = fmaf(d_z, d_z, fmaf(d_y, d_y, d_x * d_x))
  *   neighbour iff r2 < fl32(4 h^2) and j != i.
+ * The offsets are subtracted first, in the frame of neither cell, and the
+ * cell shift is added after.  Rounding is symmetric about zero, so the pair
+ * taken the other way round gives exactly -d: the relation is symmetric, i
+ * lists j if and only if j lists i, as the exact relation |r_ij| < 2h is.
  * The mirror image of j in a symmetric face of i's boundary cell (i and j
  * both in that cell) takes sign_k = -1: its coordinate along k, measured in
  * i's cell frame, is -off_j at the lower face and 2 cs - off_j at the upper
- * face, so d_k = fl32(-off_j,k - t_k) with delta_k = 0 (lower) or 2 (upper).
- * Negation is exact, so this is the image's r_j - r_i rounded once. */
+ * face, so d_k = fl32(fl32(-off_j,k - off_i,k) + delta_k cs_k) with delta_k
+ * = 0 (lower) or 2 (upper).  Negation is exact, and j's image seen from i
+ * is as far as i's image seen from j, so image pairs are symmetric too. */
 static int or_pred_f32(const or_domain* D, float R2, const int delta[3], const int sign[3],
                        const float* offi, const float* offj)
 {
     float d[3] = {0.0f, 0.0f, 0.0f};
     for (int k = 0; k < D->dim; ++k) {
         float cs = (float)D->cs[k];
-        float t = offi[k] - (float)delta[k] * cs;
         float oj = sign[k] < 0 ? -offj[k] : offj[k];
-        d[k] = oj - t;
+        float diff = oj - offi[k];
+        d[k] = diff + (float)delta[k] * cs;
     }
     float r2 = d[0] * d[0];
     if (D->dim >= 2) r2 = fmaf(d[1], d[1], r2);
@@ -984,6 +987,10 @@ typedef struct {
     const int64_t* which;
     double* a;
     double acc[3];
+    /* conditioning of the particle's sum (test diagnostics, not physics):
+     * sum of |F_ij|, and over touching contacts the smallest overlap
+     * delta / (R_i + R_j) and the smallest |v_t| / |v_j - v_i| (DEM) */
+    double fabs_sum, min_overlap, min_slip;
 } or_law_ctx;
 
 /* DEM contact force on i from j (Example 2, eq. DEM_force), neglecting
@@ -997,8 +1004,10 @@ typedef struct {
  * The normal force pushes i away from j: F_i = -f_n n + f_t.  For a mirror
  * image, v_j is reflected.  r = -rel (rel = r_i - r_j as visited).
  * The friction direction v_t / |v_t| is undefined at v_t = 0, where the law
- * jumps; friction acts only when |v_t| > 1e-5 |v_j - v_i| (a particle
- * against its own image on a symmetric face has v_t = 0: free slip). */
+ * jumps: there the friction term is taken as 0, and it acts wherever
+ * v_t != 0.  (A particle against its own image in one symmetric face has
+ * v_t = 0 exactly: n and v_j - v_i both lie along the face normal, and the
+ * other components of both are exact zeros.  Free slip.) */
 static void or_dem_visit(void* c, int64_t i, int64_t j, const double rel[3], double rn,
                          const double sgn[3])
 {
@@ -1019,18 +1028,23 @@ static void or_dem_visit(void* c, int64_t i, int64_t j, const double rel[3], dou
     double dvn = dv[0] * n[0] + dv[1] * n[1] + dv[2] * n[2];
     double rate = -dvn; /* ddelta/dt = (v_i - v_j) . n */
     double fn = kh * pow(delta, 1.5) + ch * pow(delta, 0.25) * rate;
-    double vt[3], vtn = 0.0, dv2 = 0.0;
+    double vt[3], vtn = 0.0;
     for (int k = 0; k < 3; ++k) {
         vt[k] = dv[k] - dvn * n[k];
         vtn += vt[k] * vt[k];
-        dv2 += dv[k] * dv[k];
     }
-    int slides = vtn > 1e-10 * dv2;
+    int slides = vtn > 0.0;
     vtn = sqrt(vtn);
+    double ft = slides ? ctx->P->law[0] * fabs(fn) : 0.0;
     for (int k = 0; k < 3; ++k) {
         ctx->acc[k] += -fn * n[k];
-        if (slides) ctx->acc[k] += ctx->P->law[0] * fabs(fn) * vt[k] / vtn;
+        if (slides) ctx->acc[k] += ft * vt[k] / vtn;
     }
+    ctx->fabs_sum += sqrt(fn * fn + ft * ft);
+    double ov = delta / (ctx->R[i] + ctx->R[j]);
+    if (ov < ctx->min_overlap) ctx->min_overlap = ov;
+    double dvn2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
+    if (slides && dvn2 > 0.0 && vtn / sqrt(dvn2) < ctx->min_slip) ctx->min_slip = vtn / sqrt(dvn2);
 }
 
 /* Social force pair term on i from j (eq. social_force_model with the pair
@@ -1050,6 +1064,7 @@ static void or_social_visit(void* c, int64_t i, int64_t j, const double rel[3], 
     double body = Rij - rn > 0.0 ? L[2] * (Rij - rn) : 0.0;
     double s = L[0] * exp((Rij - rn) / L[1]) + body - cij;
     for (int k = 0; k < 3; ++k) ctx->acc[k] -= s * (-rel[k] / rn);
+    ctx->fabs_sum += fabs(s);
 }
 
 typedef struct {
@@ -1057,6 +1072,7 @@ typedef struct {
     int law;             /* 0 DEM, 1 social force */
     const double* v0;    /* social force: desired speed */
     const double* goal;  /* social force: (n,3) target position */
+    double* diag;        /* optional (n_eval, 3): see or_law_diag */
 } or_law_run;
 
 static void or_law_range(void* c, int64_t begin, int64_t end)
@@ -1067,6 +1083,9 @@ static void or_law_range(void* c, int64_t begin, int64_t end)
     for (int64_t s = begin; s < end; ++s) {
         int64_t i = local.which ? local.which[s] : s;
         for (int k = 0; k < 3; ++k) local.acc[k] = 0.0;
+        local.fabs_sum = 0.0;
+        local.min_overlap = INFINITY;
+        local.min_slip = INFINITY;
         or_for_neighbours(local.G, local.x, i, run->law == 0 ? or_dem_visit : or_social_visit, &local);
         int is_fixed = local.fixed ? local.fixed[i] : 0;
         double own[3] = {0.0, 0.0, 0.0};
@@ -1087,13 +1106,20 @@ static void or_law_range(void* c, int64_t begin, int64_t end)
             double ak = k < local.D->dim ? local.acc[k] / local.m[i] + own[k] + P->g[k] : 0.0;
             local.a[3 * s + k] = is_fixed ? 0.0 : ak;
         }
+        if (run->diag) {
+            double on = sqrt(own[0] * own[0] + own[1] * own[1] + own[2] * own[2]);
+            double gn = sqrt(P->g[0] * P->g[0] + P->g[1] * P->g[1] + P->g[2] * P->g[2]);
+            run->diag[3 * s + 0] = local.fabs_sum / local.m[i] + on + gn;
+            run->diag[3 * s + 1] = local.min_overlap;
+            run->diag[3 * s + 2] = local.min_slip;
+        }
     }
 }
 
-static int or_law(int law, const or_domain* D, const or_params* P, int64_t n, const double* x,
-                  const double* v, const double* R, const double* m, const double* q,
-                  const double* v0, const double* goal, const uint8_t* fixed, int64_t n_eval,
-                  const int64_t* which, double* a, int nthreads)
+static int or_law_d(int law, const or_domain* D, const or_params* P, int64_t n, const double* x,
+                    const double* v, const double* R, const double* m, const double* q,
+                    const double* v0, const double* goal, const uint8_t* fixed, int64_t n_eval,
+                    const int64_t* which, double* a, double* diag, int nthreads)
 {
     double Rmax = 0.0;
     for (int64_t i = 0; i < n; ++i) Rmax = R[i] > Rmax ? R[i] : Rmax;
@@ -1106,10 +1132,33 @@ static int or_law(int law, const or_domain* D, const or_params* P, int64_t n, co
     run.base.D = D; run.base.P = P; run.base.G = &G; run.base.x = x; run.base.v = v;
     run.base.R = R; run.base.m = m; run.base.q = q; run.base.fixed = fixed; run.base.which = which;
     run.base.a = a;
-    run.law = law; run.v0 = v0; run.goal = goal;
+    run.law = law; run.v0 = v0; run.goal = goal; run.diag = diag;
     or_parallel(which ? n_eval : n, nthreads, or_law_range, &run);
     or_grid64_free(&G);
     return 0;
+}
+
+static int or_law(int law, const or_domain* D, const or_params* P, int64_t n, const double* x,
+                  const double* v, const double* R, const double* m, const double* q,
+                  const double* v0, const double* goal, const uint8_t* fixed, int64_t n_eval,
+                  const int64_t* which, double* a, int nthreads)
+{
+    return or_law_d(law, D, P, n, x, v, R, m, q, v0, goal, fixed, n_eval, which, a, NULL, nthreads);
+}
+
+/* The accelerations of a pair law (0 DEM, 1 social force) together with,
+ * per evaluated particle, how well its sum is conditioned (a test
+ * diagnostic, no part of the method): diag[3s] = sum_j |F_ij| / m_i + |own
+ * term| + |g| (the size of the terms the acceleration is a sum of),
+ * diag[3s+1] = min over touching contacts of delta / (R_i + R_j), diag[3s+2]
+ * = min over sliding contacts of |v_t| / |v_j - v_i| (both +inf without
+ * such contacts; DEM only). */
+int or_law_diag(int law, const or_domain* D, const or_params* P, int64_t n, const double* x,
+                const double* v, const double* R, const double* m, const double* q,
+                const double* v0, const double* goal, const uint8_t* fixed, int64_t n_eval,
+                const int64_t* which, double* a, double* diag, int nthreads)
+{
+    return or_law_d(law, D, P, n, x, v, R, m, q, v0, goal, fixed, n_eval, which, a, diag, nthreads);
 }
 
 /* DEM accelerations a_i = (1/m_i) sum_j F_ij + g (Example 2, eq.

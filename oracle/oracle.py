@@ -34,7 +34,6 @@ finite differences of :func:`step` in the tests.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from dataclasses import dataclass, field
 
@@ -181,6 +180,9 @@ def _load():
     lib.or_social.restype = ctypes.c_int
     lib.or_social.argtypes = [P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp, vp,
                               ctypes.c_int]
+    lib.or_law_diag.restype = ctypes.c_int
+    lib.or_law_diag.argtypes = [ctypes.c_int, P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, vp, vp, i64,
+                                vp, vp, vp, ctypes.c_int]
     lib.or_step_law.restype = ctypes.c_int
     lib.or_step_law.argtypes = [ctypes.c_int, P(_Domain), P(_Params), i64, vp, vp, vp, vp, vp, vp, vp, vp,
                                 i32, vp, ctypes.c_int]
@@ -495,6 +497,27 @@ def _u8(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.uint8)
 
 
+def law_diag(law: str, dom: Domain, prm: Params, x, v, R, m, q, v0=None, goal=None, fixed=None, nthreads=None):
+    """Accelerations of a pair law ("dem" or "social") and, per particle,
+    how well its sum is conditioned (a test diagnostic): columns (sum_j
+    |F_ij| / m_i + |own term| + |g|, the smallest overlap delta / (R_i +
+    R_j) of its contacts, the smallest |v_t| / |v_j - v_i| of its sliding
+    contacts; inf where there are none)."""
+    x3, v3 = _x3(x), _x3(v)
+    n = x3.shape[0]
+    a = np.zeros((n, 3))
+    diag = np.zeros((n, 3))
+    lid = {"dem": 0, "social": 1}[law]
+    g3 = None if goal is None else _x3(goal)
+    rc = _load().or_law_diag(lid, ctypes.byref(dom._c()), ctypes.byref(prm._c()), n, _ptr(x3), _ptr(v3),
+                             _ptr(_f64(R)), _ptr(_f64(m)), _ptr(_f64(q)),
+                             _ptr(None if v0 is None else _f64(v0)), _ptr(g3), _ptr(_u8(fixed)), n, None,
+                             _ptr(a), _ptr(diag), nthreads or default_threads())
+    if rc != 0:
+        raise MemoryError("or_law_diag failed")
+    return a[:, : dom.dim], diag
+
+
 def dem(dom: Domain, prm: Params, x, v, R, m, q, fixed=None, which=None, nthreads=None):
     """DEM accelerations; q = (1 - nu^2) / E per particle, c_f = prm.law[0]."""
     x3, v3 = _x3(x), _x3(v)
@@ -707,13 +730,14 @@ def verlet_steps(dom: Domain, prm: Params, x, v, skin: float, n_steps: int, fixe
     than 2h + skin at the last build, rebuilt before a step at whose start
     some particle lies farther than
 
-        lim = max(limit_fraction * skin - 2^-18 max_k cs_k, 0)
+        lim = limit_fraction * skin
 
     from its build-time position.  Before every step (unless ``check`` is
     false: then only the build schedule is kept) it checks that each pair
     closer than 2h is in the list, and raises AssertionError if not:
-    with limit_fraction = 1/2 two particles close a gap of at most 2 lim <
-    skin between builds, so the check holds.  The steps themselves do not
+    with limit_fraction = 1/2 two particles close a gap of at most 2 lim =
+    skin between builds, and a pair left out of the list was at least 2h +
+    skin apart, so the check holds.  The steps themselves do not
     use the list (pairs beyond 2h add exact zeros), so x and v are those of
     the plain rollout.  A particle shifted across a face of a non-periodic
     axis has moved about a box length, which forces a build.  Returns
@@ -722,8 +746,7 @@ def verlet_steps(dom: Domain, prm: Params, x, v, skin: float, n_steps: int, fixe
     x = np.asarray(x, dtype=np.float64)[:, :d].copy()
     v = np.asarray(v, dtype=np.float64)[:, :d].copy()
     r = None if rho is None else np.array(rho, dtype=np.float64, copy=True)
-    cs_max = max(float(dom.cs[k]) for k in range(d))
-    lim = max(limit_fraction * skin - math.ldexp(cs_max, -18), 0.0)
+    lim = limit_fraction * skin
     listed = None
     x_build = None
     build_steps = []

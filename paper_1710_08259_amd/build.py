@@ -24,19 +24,45 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def _flags():
+    return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]
+
+
 def build(verbose: bool = False) -> str:
+    """Compiles every source to an object (in parallel; no device code
+    crosses a source file, so no relocatable device code is needed), then
+    links the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+
+    def compile_one(src):
+        obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
+        res = subprocess.run([hipcc()] + _flags() + ["-c", "-o", obj, os.path.join(CSRC, src)],
+                             capture_output=True, text=True)
+        return src, obj, res
+
+    jobs = min(len(SOURCES), max(1, int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as pool:
+        results = list(pool.map(compile_one, SOURCES))
+    failed = False
+    for src, _, res in results:
+        if res.returncode != 0:
+            sys.stderr.write(f"--- {src}\n" + res.stdout + res.stderr)
+            failed = True
+        elif verbose:
+            sys.stderr.write(res.stderr)
+    if failed:
+        raise RuntimeError("hipcc failed")
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include"), "-o", tmp]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
-    res = subprocess.run(cmd, capture_output=True, text=True)
+    res = subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp]
+                         + [obj for _, obj, _ in results], capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed")
-    if verbose:
-        sys.stderr.write(res.stderr)
+        raise RuntimeError("hipcc link failed")
     os.replace(tmp, OUT)
     return OUT
 

@@ -35,15 +35,15 @@ __device__ inline void block_reduce2(double a, double b, double* sh_a, double* s
     *out_b = sh_b[0];
 }
 
-// r_j - r_i as the neighbour predicate forms it (the particle moved into the
-// neighbour's cell frame, see sph.hip), from the entry's 6-bit offset code.
+// r_j - r_i as the neighbour predicate forms it (offsets subtracted first,
+// the cell shift added after), from the entry's 6-bit offset code.
 __device__ inline float3 adj_d(const CaseDev& C, uint32_t code, const float4& oj, const float4& oi)
 {
 #pragma clang fp contract(off)
     const float sx = static_cast<float>(static_cast<int32_t>(code & 3u) - 1) * C.cs[0];
     const float sy = static_cast<float>(static_cast<int32_t>((code >> 2) & 3u) - 1) * C.cs[1];
     const float sz = static_cast<float>(static_cast<int32_t>((code >> 4) & 3u) - 1) * C.cs[2];
-    return make_float3(oj.x - (oi.x - sx), oj.y - (oi.y - sy), oj.z - (oi.z - sz));
+    return make_float3((oj.x - oi.x) + sx, (oj.y - oi.y) + sy, (oj.z - oi.z) + sz);
 }
 
 __device__ inline float adj_r2(const float3& d, int dim)

@@ -73,11 +73,16 @@ __device__ inline void interact_particle(const CaseDev& C, const ShiftTable& tab
             v[1] = gather4(q1, e);
             if constexpr (Law::kNA == 3) v[2] = gather4(q2, e);
         },
-        [&](uint32_t, const float4* v, uint32_t code) {
+        [&](uint32_t e, const float4* v, uint32_t code) {
             float3 d, sg = make_float3(1.0f, 1.0f, 1.0f);
-            if constexpr (kMirror) d = pair_d_img(tab.v[code], code, M, v[0].x, v[0].y, v[0].z, me.x, me.y, me.z, &sg);
-            else d = pair_d(tab.v[code], v[0].x, v[0].y, v[0].z, me.x, me.y, me.z);
-            const float3 F = Law::pair(C, own, v, d, pair_r2(d, dim), sg);
+            bool self = false;  // the particle's own mirror image (only images repeat the index)
+            if constexpr (kMirror) {
+                d = pair_d_img(tab.v[code], code, M, v[0].x, v[0].y, v[0].z, me.x, me.y, me.z, &sg);
+                self = (e & kIndexMask) == i;
+            } else {
+                d = pair_d(tab.v[code], v[0].x, v[0].y, v[0].z, me.x, me.y, me.z);
+            }
+            const float3 F = Law::pair(C, own, v, d, pair_r2(d, dim), sg, self);
             fx += F.x;
             fy += F.y;
             fz += F.z;

@@ -8,8 +8,9 @@
 //   Own            what the particle itself needs, loaded once,
 //   own(...)       loads it,
 //   pair(...)      the force of one neighbour on the particle, given
-//                  d = r_j - r_i (image-aware), r^2, the neighbour's records
-//                  and the image's velocity signs.
+//                  d = r_j - r_i (image-aware), r^2, the neighbour's records,
+//                  the image's velocity signs and whether the neighbour is
+//                  the particle's own mirror image.
 // k_interact<Law, ...> (interact.hip) walks the lists with the pipelined
 // walk of pairs.h, turns the summed force into a = F/m (+ the social force's
 // own relaxation term) + g, and integrates; a new law needs a struct, its
@@ -39,9 +40,13 @@ struct LawAttrsDev {
 //   f_n = k delta^(3/2) + c delta^(1/4) (v_i - v_j) . n,
 //   v_t = (v_j - v_i) - ((v_j - v_i) . n) n,
 //   F_i += -f_n n + c_f |f_n| v_t / |v_t|,
-// the friction only when |v_t| > 1e-5 |v_j - v_i| (its direction is
-// undefined at v_t = 0; against its own image on a symmetric face a
-// particle has v_t = 0 exactly, which FP32 leaves at a few ulps).
+// the friction only where v_t != 0 (its direction is undefined at v_t = 0,
+// where it is taken as 0).  Against its own image in a symmetric face a
+// particle has v_t = 0 exactly (d and v_j - v_i both lie along the face
+// normal), which FP32 would leave at a few ulps through the rounded normal:
+// that contact has no friction.  (The image in a corner, reflected along
+// two or three axes, is not normal to one face and is treated like any
+// other neighbour.)
 struct DemLaw {
     static constexpr uint32_t kNA = 3;
     struct Own {
@@ -53,7 +58,7 @@ struct DemLaw {
         return Own{r0.w, r1.w, r2.x, {r1.x, r1.y, r1.z}};
     }
     __device__ static float3 pair(const CaseDev& C, const Own& o, const float4* v, const float3& d, float r2,
-                                  const float3& sg)
+                                  const float3& sg, bool self)
     {
         const float r = __builtin_amdgcn_sqrtf(r2);
         const float delta = (o.R + v[0].w) - r;
@@ -74,8 +79,9 @@ struct DemLaw {
         const float fn = fmaf(k * delta, sd, -c * __builtin_amdgcn_sqrtf(sd) * dvn);
         const float tx = fmaf(-dvn, nx, dvx), ty = fmaf(-dvn, ny, dvy), tz = fmaf(-dvn, nz, dvz);
         const float t2 = fmaf(tz, tz, fmaf(ty, ty, tx * tx));
-        const float dv2 = fmaf(dvz, dvz, fmaf(dvy, dvy, dvx * dvx));
-        const float ft = t2 > 1e-10f * dv2 ? C.law[0] * fabsf(fn) / __builtin_amdgcn_sqrtf(t2) : 0.0f;
+        // the own image reflected along exactly one axis
+        const bool one_face = (sg.x < 0.0f ? 1 : 0) + (sg.y < 0.0f ? 1 : 0) + (sg.z < 0.0f ? 1 : 0) == 1;
+        const float ft = t2 > 0.0f && !(self && one_face) ? C.law[0] * fabsf(fn) / __builtin_amdgcn_sqrtf(t2) : 0.0f;
         return make_float3(fmaf(ft, tx, -fn * nx), fmaf(ft, ty, -fn * ny), fmaf(ft, tz, -fn * nz));
     }
 };
@@ -91,7 +97,7 @@ struct SocialLaw {
     };
     __device__ static Own own(const float4& r0, const float4& r1, const float4&) { return Own{r0.w, r1.x}; }
     __device__ static float3 pair(const CaseDev& C, const Own& o, const float4* v, const float3& d, float r2,
-                                  const float3&)
+                                  const float3&, bool)
     {
         // the list's padding pairs lie beyond 2h: only r < 2h acts
         if (!(r2 < C.R2) || !(r2 > 0.0f)) return make_float3(0.0f, 0.0f, 0.0f);

@@ -25,12 +25,13 @@ __device__ inline void fill_shift_table(const CaseDev& C, ShiftTable* tab)
     __syncthreads();
 }
 
-// r_j - r_i as the neighbour predicate forms it: the particle is moved into
-// the neighbour's cell frame, d_k = fl32(off_j,k - fl32(off_i,k - shift_k)).
+// r_j - r_i as the neighbour predicate forms it: the offsets are subtracted
+// first and the cell shift added after, d_k = fl32(fl32(off_j,k - off_i,k) +
+// shift_k), so the pair taken the other way round gives exactly -d.
 __device__ inline float3 pair_d(const float4& sh, float ojx, float ojy, float ojz, float oix, float oiy, float oiz)
 {
 #pragma clang fp contract(off)
-    return make_float3(ojx - (oix - sh.x), ojy - (oiy - sh.y), ojz - (oiz - sh.z));
+    return make_float3((ojx - oix) + sh.x, (ojy - oiy) + sh.y, (ojz - oiz) + sh.z);
 }
 
 // ---- symmetric faces ------------------------------------------------------------
@@ -52,11 +53,11 @@ __device__ inline ImageFrame image_frame(const CaseDev& C, uint32_t cell)
     return M;
 }
 
-// pair_d for an entry that may be an image: d_k = fl32(sg_k off_j,k - t_k),
-// t_k = fl32(off_i,k - shift_k), sg_k = -1 along image axes (negation is
-// exact, so this is the search predicate's arithmetic); sg receives the
-// signs for the neighbour's velocity.  Without image axes the values equal
-// pair_d's.
+// pair_d for an entry that may be an image: d_k = fl32(fl32(sg_k off_j,k -
+// off_i,k) + shift_k), with sg_k = -1 and shift_k = 0 or 2 cs along image
+// axes (negation is exact, so this is the search predicate's arithmetic);
+// sg receives the signs for the neighbour's velocity.  Without image axes
+// the values equal pair_d's.
 __device__ inline float3 pair_d_img(const float4& sh, uint32_t code, const ImageFrame& M, float ojx, float ojy,
                                     float ojz, float oix, float oiy, float oiz, float3* sg)
 {
@@ -65,11 +66,10 @@ __device__ inline float3 pair_d_img(const float4& sh, uint32_t code, const Image
     const bool iy = ((code >> 2) & 3u) == kMirrorCode;
     const bool iz = ((code >> 4) & 3u) == kMirrorCode;
     const float sx = ix ? -1.0f : 1.0f, sy = iy ? -1.0f : 1.0f, sz = iz ? -1.0f : 1.0f;
-    const float tx = oix - (ix ? M.shift[0] : sh.x);
-    const float ty = oiy - (iy ? M.shift[1] : sh.y);
-    const float tz = oiz - (iz ? M.shift[2] : sh.z);
     *sg = make_float3(sx, sy, sz);
-    return make_float3(__builtin_fmaf(sx, ojx, -tx), __builtin_fmaf(sy, ojy, -ty), __builtin_fmaf(sz, ojz, -tz));
+    return make_float3(__builtin_fmaf(sx, ojx, -oix) + (ix ? M.shift[0] : sh.x),
+                       __builtin_fmaf(sy, ojy, -oiy) + (iy ? M.shift[1] : sh.y),
+                       __builtin_fmaf(sz, ojz, -oiz) + (iz ? M.shift[2] : sh.z));
 }
 
 __device__ inline float pair_r2(const float3& d, int dim)
@@ -136,13 +136,15 @@ __device__ inline void load_entries(const uint32_t* __restrict__ nbr, uint32_t i
 // and a group is summed while the next group's gathers are outstanding.
 // The scheduling barriers keep the compiler from moving the sums across the
 // loads they are meant to overlap.  `gather(e, v)` fills the NA float4s of
-// the neighbour of list entry e; `body(k, v, code)` adds pair k with the
-// 6-bit cell-offset code of its entry.  Pairs k >= cnt (up to the end of the
-// last group) are padding pairs, whose terms are exactly zero.
+// the neighbour of list entry e; `body(e, v, code)` adds the pair of entry e
+// with the 6-bit cell-offset code of that entry.  Entries past the count (up
+// to the end of the last group) are padding pairs, whose terms are exactly
+// zero.  (A body that does not read e costs no register for it.)
 template <uint32_t G, uint32_t NA>
 struct PairStage {
     float4 v[G][NA];
     uint32_t code[G];
+    uint32_t entry[G];
 };
 
 template <uint32_t G, uint32_t NA, typename Gather>
@@ -152,6 +154,7 @@ __device__ inline void gather_stage(const uint32_t* e, Gather&& gather, PairStag
     for (uint32_t u = 0; u < G; ++u) {
         gather(e[u], S.v[u]);
         S.code[u] = e[u] >> NAUTICLE_NBR_INDEX_BITS;
+        S.entry[u] = e[u];
     }
 }
 
@@ -173,14 +176,14 @@ __device__ inline void walk_pairs(const uint32_t* __restrict__ nbr, uint32_t i, 
         gather_stage<G, NA>(ey, gather, B);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (uint32_t u = 0; u < G; ++u) body(k + u, A.v[u], A.code[u]);
+        for (uint32_t u = 0; u < G; ++u) body(A.entry[u], A.v[u], A.code[u]);
         __builtin_amdgcn_sched_barrier(0);
         if (k + G >= cnt) break;  // the second half would be padding only
         load_entries<G>(nbr, i, k + 3 * G, cnt, n_total, pad, ey);
         gather_stage<G, NA>(ex, gather, A);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (uint32_t u = 0; u < G; ++u) body(k + G + u, B.v[u], B.code[u]);
+        for (uint32_t u = 0; u < G; ++u) body(B.entry[u], B.v[u], B.code[u]);
         __builtin_amdgcn_sched_barrier(0);
     }
 }

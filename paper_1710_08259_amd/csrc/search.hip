@@ -341,9 +341,11 @@ hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipSt
 // One lane per sorted particle.  The 3^dim stencil is walked as 3^(dim-1)
 // rows of three cells along x; since keys run x fastest, a row's three cells
 // are one contiguous sorted range (two pieces where a periodic x axis wraps).
-// The predicate moves the particle into the candidate's cell frame,
-// t = off_i - delta cs: the y and z parts of t are fixed per row, and the x
-// part follows from the candidate's cell x index, packed with its offsets.
+// The predicate subtracts the offsets first and adds the cell shift after,
+// d = fl(fl(off_j - off_i) + delta cs), so the pair taken the other way round
+// gives exactly -d and the relation is symmetric.  The y and z shifts are
+// fixed per row; the x shift follows from the candidate's cell x index,
+// packed with its offsets.
 // Candidates come from the item's neighbourhood staged in LDS (global memory
 // for folded pieces), kUnroll at a time with the next kUnroll in flight; those
 // that pass set a bit in a 64-candidate mask, which is then emitted in
@@ -357,24 +359,23 @@ constexpr uint32_t kUnroll = 4;
 static_assert(2 * kUnroll <= kPosPad && 64 % (2 * kUnroll) == 0, "candidate groups must tile the 64-bit mask");
 
 // The same test for a piece of mirror images: along an axis with sign -1
-// the candidate's offset is negated, d = fl(-off_j - t) (negation is exact),
-// and a mirrored x piece (one boundary cell) takes cref = c_x - delta, delta
-// 0 at the lower face and 2 at the upper one.  With every sign +1 this is
-// shift_group's arithmetic.
+// the candidate's offset is negated, d = fl(fl(-off_j - off_i) + delta cs)
+// (negation is exact), and a mirrored x piece (one boundary cell) takes
+// cref = c_x - delta, delta 0 at the lower face and 2 at the upper one.
+// With every sign +1 this is shift_group's arithmetic.
 template <int DIM>
-__device__ inline uint32_t test_group_img(const float4* o, float cref, float mex, float csx, float ty, float tz,
-                                          float R2, float sx, float sy, float sz)
+__device__ inline uint32_t test_group_img(const float4* o, float cref, float mex, float csx, float mey, float shy,
+                                          float mez, float shz, float R2, float sx, float sy, float sz)
 {
 #pragma clang fp contract(off)
     uint32_t bits = 0;
 #pragma unroll
     for (uint32_t u = 0; u < kUnroll; ++u) {
-        const float tx = __builtin_fmaf(cref - o[u].w, csx, mex);
-        const float ddx = __builtin_fmaf(sx, o[u].x, -tx);
-        const float ddy = __builtin_fmaf(sy, o[u].y, -ty);
+        const float ddx = __builtin_fmaf(o[u].w - cref, csx, __builtin_fmaf(sx, o[u].x, -mex));
+        const float ddy = __builtin_fmaf(sy, o[u].y, -mey) + shy;
         float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
         if constexpr (DIM == 3) {
-            const float ddz = __builtin_fmaf(sz, o[u].z, -tz);
+            const float ddz = __builtin_fmaf(sz, o[u].z, -mez) + shz;
             r2 = __builtin_fmaf(ddz, ddz, r2);
         }
         bits |= r2 < R2 ? (1u << u) : 0u;
@@ -386,15 +387,16 @@ __device__ inline uint32_t test_group_img(const float4* o, float cref, float mex
 // read from `src` (a plain loop: such pieces are the few cells along a
 // symmetric face).
 template <int DIM>
-__device__ inline uint64_t scan_chunk_img(const float4* src, uint32_t m, float cref, float mex, float csx, float ty,
-                                          float tz, float R2, float sx, float sy, float sz)
+__device__ inline uint64_t scan_chunk_img(const float4* src, uint32_t m, float cref, float mex, float csx, float mey,
+                                          float shy, float mez, float shz, float R2, float sx, float sy, float sz)
 {
     uint64_t hits = 0;
     for (uint32_t b = 0; b < m; b += kUnroll) {
         float4 o[kUnroll];
 #pragma unroll
         for (uint32_t u = 0; u < kUnroll; ++u) o[u] = src[b + u];
-        hits |= static_cast<uint64_t>(test_group_img<DIM>(o, cref, mex, csx, ty, tz, R2, sx, sy, sz)) << b;
+        hits |= static_cast<uint64_t>(test_group_img<DIM>(o, cref, mex, csx, mey, shy, mez, shz, R2, sx, sy, sz))
+                << b;
     }
     return hits;
 }
@@ -407,20 +409,21 @@ __device__ inline uint64_t scan_chunk_img(const float4* src, uint32_t m, float c
 // zero.  One subtraction and one funnel shift per candidate, instead of a
 // compare, a select and the merging of group masks.  The candidate's cell x
 // index (o.w) against the piece's reference gives delta_x in {-1, 0, 1}, so
-// tx = fl(me.x - delta_x cs) is one fused multiply-add of an exact product.
+// d_x = fl(fl(off_j - off_i) + delta_x cs) is one fused multiply-add of an
+// exact product; the y and z shifts (shy, shz) are exact multiples of the
+// cell edge, fixed per row.
 template <int DIM>
-__device__ inline uint32_t shift_group(const float4* o, float cref, float mex, float csx, float ty, float tz, float R2,
-                                       uint32_t acc)
+__device__ inline uint32_t shift_group(const float4* o, float cref, float mex, float csx, float mey, float shy,
+                                       float mez, float shz, float R2, uint32_t acc)
 {
 #pragma clang fp contract(off)
 #pragma unroll
     for (uint32_t u = 0; u < kUnroll; ++u) {
-        const float tx = __builtin_fmaf(cref - o[u].w, csx, mex);
-        const float ddx = o[u].x - tx;
-        const float ddy = o[u].y - ty;
+        const float ddx = __builtin_fmaf(o[u].w - cref, csx, o[u].x - mex);
+        const float ddy = (o[u].y - mey) + shy;
         float r2 = __builtin_fmaf(ddy, ddy, ddx * ddx);
         if constexpr (DIM == 3) {
-            const float ddz = o[u].z - tz;
+            const float ddz = (o[u].z - mez) + shz;
             r2 = __builtin_fmaf(ddz, ddz, r2);
         }
         acc = __builtin_amdgcn_alignbit(acc, __builtin_bit_cast(uint32_t, r2 - R2), 31u);
@@ -434,8 +437,8 @@ __device__ inline uint32_t shift_group(const float4* o, float cref, float mex, f
 // the next A loads.  The loop tests b = 8 ceil(m/8) candidates; the shifted
 // mask is reversed and aligned at the end.
 template <int DIM>
-__device__ inline uint32_t scan32(const float4* src, uint32_t m, float cref, float mex, float csx, float ty, float tz,
-                                  float R2)
+__device__ inline uint32_t scan32(const float4* src, uint32_t m, float cref, float mex, float csx, float mey,
+                                  float shy, float mez, float shz, float R2)
 {
     uint32_t acc = 0;
     float4 oa[kUnroll], ob[kUnroll];
@@ -446,13 +449,13 @@ __device__ inline uint32_t scan32(const float4* src, uint32_t m, float cref, flo
 #pragma unroll
         for (uint32_t u = 0; u < kUnroll; ++u) ob[u] = src[b + kUnroll + u];
         __builtin_amdgcn_sched_barrier(0);
-        acc = shift_group<DIM>(oa, cref, mex, csx, ty, tz, R2, acc);
+        acc = shift_group<DIM>(oa, cref, mex, csx, mey, shy, mez, shz, R2, acc);
         // the next A group, or this one again past the end (stays readable)
         const uint32_t na = b + 2 * kUnroll < m ? b + 2 * kUnroll : b;
 #pragma unroll
         for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[na + u];
         __builtin_amdgcn_sched_barrier(0);
-        acc = shift_group<DIM>(ob, cref, mex, csx, ty, tz, R2, acc);
+        acc = shift_group<DIM>(ob, cref, mex, csx, mey, shy, mez, shz, R2, acc);
     }
     return __builtin_bitreverse32(acc) >> (32u - b);  // 8 <= b <= 32
 }
@@ -461,11 +464,11 @@ __device__ inline uint32_t scan32(const float4* src, uint32_t m, float cref, flo
 // (src[k] = candidate q0 + k; readable up to 2 kUnroll - 1 past m), as two
 // halves of 32.
 template <int DIM>
-__device__ inline uint64_t scan_chunk(const float4* src, uint32_t m, float cref, float mex, float csx, float ty,
-                                      float tz, float R2)
+__device__ inline uint64_t scan_chunk(const float4* src, uint32_t m, float cref, float mex, float csx, float mey,
+                                      float shy, float mez, float shz, float R2)
 {
-    const uint32_t lo = scan32<DIM>(src, m < 32u ? m : 32u, cref, mex, csx, ty, tz, R2);
-    const uint32_t hi = m > 32u ? scan32<DIM>(src + 32, m - 32u, cref, mex, csx, ty, tz, R2) : 0u;
+    const uint32_t lo = scan32<DIM>(src, m < 32u ? m : 32u, cref, mex, csx, mey, shy, mez, shz, R2);
+    const uint32_t hi = m > 32u ? scan32<DIM>(src + 32, m - 32u, cref, mex, csx, mey, shy, mez, shz, R2) : 0u;
     return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
 }
 
@@ -513,9 +516,9 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
                 mz = true;
             }
         }
-        // the particle's shift: delta cells, or 0 / 2 cells against a lower /
-        // upper face for an image plane
-        const float tz = me.z - static_cast<float>(mz ? (dz < 0 ? 0 : 2) : dz) * C.cs[2];
+        // the cell shift: delta cells, or 0 / 2 cells against a lower /
+        // upper face for an image plane (an exact multiple of the edge)
+        const float shz = static_cast<float>(mz ? (dz < 0 ? 0 : 2) : dz) * C.cs[2];
         for (int dy = -1; dy <= 1; ++dy) {
             int32_t cy = c[1] + dy;
             bool my = false;
@@ -528,7 +531,7 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
             }
             const uint32_t row = C.cell_base + static_cast<uint32_t>(nx) *
                                                    (static_cast<uint32_t>(cy) + static_cast<uint32_t>(C.nc[1]) * static_cast<uint32_t>(cz));
-            const float ty = me.y - static_cast<float>(my ? (dy < 0 ? 0 : 2) : dy) * C.cs[1];
+            const float shy = static_cast<float>(my ? (dy < 0 ? 0 : 2) : dy) * C.cs[1];
             // the row's x span [c-1, c+1] as up to two contiguous pieces of
             // cells; the second is the wrapped cell of a periodic x axis or
             // the image of the boundary cell of a symmetric one
@@ -581,12 +584,12 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
                     const float4* src = staged ? halo + (static_cast<int32_t>(q0) + hshift) : pos4 + q0;
                     uint64_t hits_all;
                     if (kMirror && image)
-                        hits_all = scan_chunk_img<DIM>(src, m, cref, me.x, csx, ty, tz, R2, mx ? -1.0f : 1.0f,
-                                                       my ? -1.0f : 1.0f, mz ? -1.0f : 1.0f);
+                        hits_all = scan_chunk_img<DIM>(src, m, cref, me.x, csx, me.y, shy, me.z, shz, R2,
+                                                       mx ? -1.0f : 1.0f, my ? -1.0f : 1.0f, mz ? -1.0f : 1.0f);
                     else
                         hits_all = staged ? scan_chunk<DIM>(halo + (static_cast<int32_t>(q0) + hshift), m, cref, me.x,
-                                                            csx, ty, tz, R2)
-                                          : scan_chunk<DIM>(pos4 + q0, m, cref, me.x, csx, ty, tz, R2);
+                                                            csx, me.y, shy, me.z, shz, R2)
+                                          : scan_chunk<DIM>(pos4 + q0, m, cref, me.x, csx, me.y, shy, me.z, shz, R2);
                     uint64_t hits = hits_all;
                     // drop candidates past the piece and the particle itself
                     // (its own image stays)

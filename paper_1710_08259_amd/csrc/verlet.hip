@@ -3,9 +3,9 @@
 //
 // The lists of a table with a skin reach 2h + skin.  Between two builds a
 // particle keeps the cell it had at the build and only its offset moves, so
-// the pair arithmetic d = off_j - (off_i - delta cs) (shift table, mirror
-// images) stays exact: it is linear in the offsets and its cell part is the
-// build-time one.  The paper reruns the search only when the layout has
+// the pair arithmetic d = (off_j - off_i) + delta cs (shift table, mirror
+// images) stays consistent: it is linear in the offsets and its cell part is
+// the build-time one.  The paper reruns the search only when the layout has
 // changed (Sec. 4); a skin lets the layout change a little without a new
 // search.  A particle that moved more than its case's lim (just under
 // skin / 2) from its build-time position, or left the box across a face of a

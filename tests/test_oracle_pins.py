@@ -203,6 +203,50 @@ def test_neighbour_sets_match_exact_distances(name, case):
     np.testing.assert_array_equal(cnt64, inside.sum(1))
 
 
+def _near_cutoff(dim, seed):
+    """Pairs placed at 2h (1 + U(-3e-7, 3e-7)) in random directions, so that
+    the FP32 predicate decides many pairs within a few ulps of the cut-off;
+    partners across cell faces and across the periodic faces included."""
+    base = WL.lattice_case(dim, (30, 28) if dim == 2 else (10, 9, 8), 0.01, 1.3 if dim == 2 else 1.2, 0.0, 0.0,
+                           seed=seed)
+    rng = np.random.default_rng(seed)
+    L = base.length()[:dim]
+    m = base.n // 2
+    a = rng.uniform(0, 1, (m, dim)) * L
+    u = rng.normal(size=(m, dim))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    b = a + u * (2 * base.h * (1 + rng.uniform(-3e-7, 3e-7, (m, 1))))
+    pts = np.mod(np.concatenate([a, b]), L)
+    return WL.scaled(base, pos=pts.astype(np.float32), vel=np.zeros((2 * m, dim), np.float32))
+
+
+@pytest.mark.parametrize("name,case", _layouts() + [(f"near_cutoff{d}", _near_cutoff(d, 50 + d)) for d in (2, 3)],
+                         ids=[n for n, _ in _layouts()] + ["near_cutoff2", "near_cutoff3"])
+def test_fp32_neighbour_relation_is_symmetric(name, case):
+    """i lists j exactly when j lists i, also for pairs within rounding of
+    2h: the FP32 displacement of the pair taken the other way round is
+    exactly the negated one (offsets subtracted first, cell shift added
+    after; rounding is symmetric about zero), as the exact relation
+    |r_ij| < 2h is symmetric."""
+    dom = domain_of(case)
+    cell, off = O.bin_f32(dom, case.pos)
+    cnt, lst = O.neighbours_f32(dom, case.h, cell, off, max_nbr=512)
+    assert cnt.max() <= 512
+    pairs = set()
+    for i in range(case.n):
+        for j in lst[i, : cnt[i]]:
+            pairs.add((i, int(j)))
+    assert pairs, name
+    asym = [(i, j) for (i, j) in pairs if (j, i) not in pairs]
+    assert not asym, (name, len(asym), asym[:5])
+    if name.startswith("near_cutoff"):
+        # the layout does put pairs on both sides of the cut-off
+        m = case.n // 2
+        partner = set(range(m))
+        linked = sum(1 for i in partner if (i, i + m) in pairs)
+        assert 0.2 * m < linked < 0.8 * m, linked
+
+
 # ---------------------------------------------------------------------------
 # density, pressure and accelerations on lattices
 # ---------------------------------------------------------------------------
