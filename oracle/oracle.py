@@ -647,9 +647,14 @@ def rollout_loss(dom: Domain, prm: Params, x0, v0, target, n_steps, fixed=None, 
     return float((d[mask] ** 2).sum() / (mask.sum() * dom.dim))
 
 
-def rollout_grad(dom: Domain, prm: Params, x0, v0, target, n_steps, checkpoint_every=20,
-                 fixed=None, nthreads=None):
-    """(L, dL/dv0, dL/dnu, dL/dc0) by a reverse sweep over one-step VJPs.
+def rollout_vjp(dom: Domain, prm: Params, x0, v0, n_steps, lam_x_T, lam_v_T, checkpoint_every=20,
+                fixed=None, nthreads=None):
+    """Reverse mode of ``n_steps`` of :func:`step` (the derivative the paper
+    does not have): given cotangents lam_x_T, lam_v_T of the final positions
+    and velocities (particle order of x0), returns (lam_x0, lam_v0, dL/dnu,
+    dL/dc0), the cotangents of the initial state and of the two constants.
+    The periodic shift of a leaving particle has derivative one, so the
+    final position's cotangent is taken as that of the unshifted position.
 
     Forward: store (x, v) every ``checkpoint_every`` steps.  Backward: for
     each segment, recompute its states from the checkpoint, then apply the
@@ -662,12 +667,8 @@ def rollout_grad(dom: Domain, prm: Params, x0, v0, target, n_steps, checkpoint_e
         if s % checkpoint_every == 0:
             ckpt.append((s, x.copy(), v.copy()))
         x, v, _, _, _ = step(dom, prm, x, v, fixed=fixed, n_steps=1, nthreads=nthreads)
-    delta = min_image(dom, x - np.asarray(target)[:, :d])
-    mask = np.ones(delta.shape[0], bool) if fixed is None else ~np.asarray(fixed, bool)
-    nf = int(mask.sum())
-    loss = float((delta[mask] ** 2).sum() / (nf * d))
-    lam_x = np.where(mask[:, None], 2.0 * delta / (nf * d), 0.0)
-    lam_v = np.zeros_like(lam_x)
+    lam_x = np.array(lam_x_T, np.float64)[:, :d].copy()
+    lam_v = np.array(lam_v_T, np.float64)[:, :d].copy()
     dnu = 0.0
     dc0 = 0.0
     for (s0, xc, vc) in reversed(ckpt):
@@ -682,6 +683,24 @@ def rollout_grad(dom: Domain, prm: Params, x0, v0, target, n_steps, checkpoint_e
                                           nthreads=nthreads)
             dnu += a
             dc0 += b
+    return lam_x, lam_v, dnu, dc0
+
+
+def rollout_grad(dom: Domain, prm: Params, x0, v0, target, n_steps, checkpoint_every=20,
+                 fixed=None, nthreads=None):
+    """(L, dL/dv0, dL/dnu, dL/dc0) of :func:`rollout_loss`: the loss's
+    derivative in the final positions, lam_x = 2 delta / (N d) over fluid
+    particles (delta the minimum-image displacement from the target), swept
+    back by :func:`rollout_vjp`."""
+    d = dom.dim
+    x, _, _, _, _ = step(dom, prm, x0, v0, fixed=fixed, n_steps=n_steps, nthreads=nthreads)
+    delta = min_image(dom, x - np.asarray(target)[:, :d])
+    mask = np.ones(delta.shape[0], bool) if fixed is None else ~np.asarray(fixed, bool)
+    nf = int(mask.sum())
+    loss = float((delta[mask] ** 2).sum() / (nf * d))
+    lam_x = np.where(mask[:, None], 2.0 * delta / (nf * d), 0.0)
+    _, lam_v, dnu, dc0 = rollout_vjp(dom, prm, x0, v0, n_steps, lam_x, np.zeros_like(lam_x),
+                                     checkpoint_every=checkpoint_every, fixed=fixed, nthreads=nthreads)
     return loss, lam_v, dnu, dc0
 
 

@@ -442,7 +442,9 @@ def test_periodic_shifting_keeps_particles_in_the_box():
 # adjoint: one-step VJP and rollout gradient vs central finite differences
 # ---------------------------------------------------------------------------
 
-def _small_case(walls=False):
+def _small_case(walls=False, dim=2):
+    if dim == 3 and not walls:
+        return WL.lattice_case(3, (6, 5, 5), 0.01, 1.2, 0.2, 0.3, seed=23, c0=10.0, nu=2e-3, dt=2e-4)
     if not walls:
         return WL.lattice_case(2, (9, 8), 0.01, 1.3, 0.2, 0.3, seed=17, c0=10.0, nu=2e-3, dt=2e-4)
     c = WL.dam_break_case(dx=0.08, h_over_dx=1.3, c0=10.0, nu=1e-3, fluid=(0.32, 0.24, 0.4),
@@ -450,9 +452,14 @@ def _small_case(walls=False):
     return WL.scaled(c, vel=(np.random.default_rng(3).normal(0, 0.2, c.vel.shape)).astype(np.float32))
 
 
-@pytest.mark.parametrize("walls", [False, True])
-def test_step_vjp_matches_central_differences(walls):
-    case = _small_case(walls)
+@pytest.mark.parametrize("walls,dim", [(False, 2), (False, 3), (True, 3)])
+def test_step_vjp_matches_central_differences(walls, dim):
+    """The one-step VJP against central differences of the forward step, on
+    random cotangents and random directions: 2-D periodic, 3-D periodic
+    (the z terms of every sum and of the F'/r Hessian) and the 3-D tank with
+    fixed walls."""
+    case = _small_case(walls, dim)
+    assert case.dim == dim
     dom, prm = domain_of(case), params_of(case)
     fixed = case.fixed_mask()
     x, v = x64(case), v64(case)
@@ -521,3 +528,50 @@ def test_rollout_gradient_matches_central_differences_and_vanishes_at_target():
     # at the target parameters the loss and every gradient vanish
     L0, g0, n0, c0_ = O.rollout_grad(dom, tgt, x0, v0, target, steps, checkpoint_every=5, nthreads=2)
     assert L0 == 0.0 and np.all(g0 == 0) and n0 == 0.0 and c0_ == 0.0
+
+
+def test_rollout_vjp_with_arbitrary_cotangents_matches_central_differences():
+    """The reverse sweep of a rollout from arbitrary cotangents of the final
+    positions and velocities (not those of one loss): <lam_x0, u_x> +
+    <lam_v0, u_v> and the constants' cotangents against central differences
+    of J = <w_x, x_T> + <w_v, v_T>, on a 3-D periodic box over 9 steps with
+    checkpoints every 4 (a partial last segment).  A mistake in the
+    checkpoint bookkeeping (a segment swept twice or skipped, a state off by
+    one step) changes every one of these."""
+    case = WL.lattice_case(3, (5, 5, 5), 0.01, 1.2, 0.15, 0.3, seed=29, c0=8.0, nu=2e-3, dt=2e-4)
+    dom, prm = domain_of(case), params_of(case)
+    x0, v0 = x64(case), v64(case)
+    steps = 9
+    rng = np.random.default_rng(31)
+    wx, wv = rng.normal(size=x0.shape), rng.normal(size=v0.shape)
+    lx0, lv0, dnu, dc0 = O.rollout_vjp(dom, prm, x0, v0, steps, wx, wv, checkpoint_every=4, nthreads=2)
+    xT, _, _, _, _ = O.step(dom, prm, x0, v0, n_steps=steps, nthreads=2)
+
+    def J(p, x, v):
+        xn, vn, _, _, _ = O.step(dom, p, x, v, n_steps=steps, nthreads=2)
+        # the final positions measured from the unperturbed run's, so a
+        # periodic shift taken in one run and not the other cancels
+        return (O.min_image(dom, xn - xT) * wx).sum() + (vn * wv).sum()
+
+    import copy
+
+    def with_(attr, val):
+        p = copy.copy(prm)
+        setattr(p, attr, val)
+        return p
+    ux, uv = rng.normal(size=x0.shape), rng.normal(size=v0.shape)
+    e = 1e-7
+    fd = (J(prm, x0 + e * ux, v0) - J(prm, x0 - e * ux, v0)) / (2 * e)
+    assert (lx0 * ux).sum() == pytest.approx(fd, rel=1e-5)
+    e = 1e-6
+    fd = (J(prm, x0, v0 + e * uv) - J(prm, x0, v0 - e * uv)) / (2 * e)
+    assert (lv0 * uv).sum() == pytest.approx(fd, rel=1e-5)
+    e = 1e-4 * prm.nu
+    fd = (J(with_("nu", prm.nu + e), x0, v0) - J(with_("nu", prm.nu - e), x0, v0)) / (2 * e)
+    assert dnu == pytest.approx(fd, rel=1e-5)
+    e = 1e-5 * prm.c0
+    fd = (J(with_("c0", prm.c0 + e), x0, v0) - J(with_("c0", prm.c0 - e), x0, v0)) / (2 * e)
+    assert dc0 == pytest.approx(fd, rel=1e-5)
+    # linear in the cotangents: zero in, zero out
+    z = O.rollout_vjp(dom, prm, x0, v0, steps, 0 * wx, 0 * wv, checkpoint_every=4, nthreads=2)
+    assert np.all(z[0] == 0) and np.all(z[1] == 0) and z[2] == 0.0 and z[3] == 0.0
