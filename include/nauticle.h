@@ -299,7 +299,27 @@ nauticle_status nauticle_unbin(const nauticle_case* cases, int32_t n_cases,
                                const nauticle_state* state, float* const pos[3], void* ws,
                                size_t ws_bytes, hipStream_t stream);
 
-/* Neighbour search [Sec. 3.2.1 cell grid; A8 ownership]: keys, stable
+/* nauticle_unbin with every particle's position written at its global
+ * input index (case offset + id) instead of its position in `state`: the
+ * positions in the order of nauticle_bin's input, whatever reordering the
+ * steps since have made.  pos[k] (device FP32, N_total long) is output
+ * only. */
+nauticle_status nauticle_unbin_by_id(const nauticle_case* cases, int32_t n_cases,
+                                     const nauticle_state* state, float* const pos[3], void* ws,
+                                     size_t ws_bytes, hipStream_t stream);
+
+/* The inverse bookkeeping: out[k][p] = g[k][offset + id[p]] for every
+ * particle p of `state` (only state->id is read).  Brings a per-particle
+ * vector given in input order (e.g. the cotangent of the positions
+ * nauticle_unbin_by_id returned) into the state's order, as
+ * nauticle_sph_adjoint takes it.  g[k], out[k]: device FP32, N_total long,
+ * k < dim; out must not alias g. */
+nauticle_status nauticle_gather_by_id(const nauticle_case* cases, int32_t n_cases,
+                                      const nauticle_state* state, const float* const g[3],
+                                      float* const out[3], void* ws, size_t ws_bytes,
+                                      hipStream_t stream);
+
+/* Neighbour search [Sec. 3.2.1 cell grid]: keys, stable
  * radix sort, cell start/end table, reorder of `in` into `sorted`
  * (sorted must not alias in), then every particle's neighbour list under
  * the FP32 predicate: with delta = j's cell minus i's cell (in {-1,0,1}^dim
@@ -372,8 +392,10 @@ nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases,
  *     touching pairs (delta = R_i + R_j - |r_j - r_i| > 0), n = (r_j - r_i)/|.|,
  *     f_n = k delta^(3/2) + c delta^(1/4) (v_i - v_j).n, k = (4/3) sqrt(R') E',
  *     c = sqrt(m' k)/8; F_i += -f_n n + c_f |f_n| v_t/|v_t|,
- *     v_t = (v_j - v_i) - ((v_j - v_i).n) n, the friction only when
- *     |v_t| > 1e-5 |v_j - v_i| (free slip against one's own image);
+ *     v_t = (v_j - v_i) - ((v_j - v_i).n) n, the friction only where
+ *     v_t != 0 (its direction is undefined at v_t = 0) and never against the
+ *     particle's own image in one symmetric face, where v_t = 0 exactly
+ *     (free slip) and FP32 would leave a few ulps;
  *   SOCIAL [eq. social_force_model, pair term of its listing]: for 0 < d < 2h,
  *     F_i -= [A exp((R_ij - d)/B) + k max(R_ij - d, 0) - c_ij] n, plus the
  *     particle's own term m (v0 e0 - v)/tau, e0 towards its goal;

@@ -483,8 +483,40 @@ nauticle_status nauticle_unbin(const nauticle_case* cases, int32_t n_cases, cons
     if (!pos) return fail(NAUTICLE_ERR_INVALID_ARG, "pos is null");
     for (int k = 0; k < P->dim_max; ++k)
         if (P->n_total && !pos[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "pos[%d] is null", k);
-    hipError_t e = launch_unbin(*P, ws, to_dev(state), pos, stream);
+    hipError_t e = launch_unbin(*P, ws, to_dev(state), pos, false, stream);
     return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_unbin");
+}
+
+nauticle_status nauticle_unbin_by_id(const nauticle_case* cases, int32_t n_cases, const nauticle_state* state,
+                                     float* const pos[3], void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_state(*P, state, false, "state")) != NAUTICLE_OK) return st;
+    if (!pos) return fail(NAUTICLE_ERR_INVALID_ARG, "pos is null");
+    for (int k = 0; k < P->dim_max; ++k)
+        if (P->n_total && !pos[k]) return fail(NAUTICLE_ERR_INVALID_ARG, "pos[%d] is null", k);
+    hipError_t e = launch_unbin(*P, ws, to_dev(state), pos, true, stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_unbin_by_id");
+}
+
+nauticle_status nauticle_gather_by_id(const nauticle_case* cases, int32_t n_cases, const nauticle_state* state,
+                                      const float* const g[3], float* const out[3], void* ws, size_t ws_bytes,
+                                      hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if (!state || (P->n_total && !state->id)) return fail(NAUTICLE_ERR_INVALID_ARG, "state or state->id is null");
+    if (!g || !out) return fail(NAUTICLE_ERR_INVALID_ARG, "g or out is null");
+    for (int k = 0; k < P->dim_max; ++k) {
+        if (P->n_total && (!g[k] || !out[k])) return fail(NAUTICLE_ERR_INVALID_ARG, "g[%d] or out[%d] is null", k, k);
+        for (int j = 0; j < P->dim_max; ++j)
+            if (P->n_total && out[k] == g[j]) return fail(NAUTICLE_ERR_INVALID_ARG, "out must not alias g");
+    }
+    hipError_t e = launch_gather_id(*P, ws, state->id, g, out, stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_gather_by_id");
 }
 
 nauticle_status nauticle_build_cells(const nauticle_case* cases, int32_t n_cases, const nauticle_state* in,
@@ -678,13 +710,15 @@ nauticle_status nauticle_sph_forces(const nauticle_case* cases, int32_t n_cases,
     return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_sph_forces");
 }
 
-nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauticle_state* state, int32_t n_steps,
-                              nauticle_cells* cells, nauticle_fields* fields, hipEvent_t* phase_events, void* ws,
-                              size_t ws_bytes, hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+// Host-side checks of nauticle_step's arguments against a plan.
+nauticle_status check_step_args(const Plan* P, const nauticle_state* state, int32_t n_steps,
+                                const nauticle_cells* cells, const nauticle_fields* fields)
 {
-    const Plan* P;
-    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
-    if (st != NAUTICLE_OK) return st;
+    nauticle_status st;
     if (n_steps < 0) return fail(NAUTICLE_ERR_INVALID_ARG, "n_steps < 0");
     if (is_law(*P)) return fail(NAUTICLE_ERR_INVALID_ARG, "pair-law tables step with nauticle_step_law");
     if (P->model == NAUTICLE_MODEL_CAHN_HILLIARD)
@@ -693,6 +727,14 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
     if ((st = check_state(*P, state, true, "state", cont)) != NAUTICLE_OK) return st;
     if ((st = check_cells(*P, cells, true)) != NAUTICLE_OK) return st;
     if ((st = check_fields(*P, fields, true)) != NAUTICLE_OK) return st;
+    return NAUTICLE_OK;
+}
+
+// The launch sequence of nauticle_step on a checked plan and workspace.
+nauticle_status run_steps(const Plan* P, nauticle_state* state, int32_t n_steps, nauticle_cells* cells,
+                          nauticle_fields* fields, hipEvent_t* phase_events, void* ws, hipStream_t stream)
+{
+    const bool cont = P->model == NAUTICLE_MODEL_CONTINUITY;
     const StateDev cur = to_dev_model(*P, state);
     const StateDev tmp = scratch_state(*P, ws);
     const FieldsDev f = to_dev(fields);
@@ -718,6 +760,21 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
         if (e != hipSuccess) return hip_fail(e, "nauticle_step");
     }
     return NAUTICLE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauticle_state* state, int32_t n_steps,
+                              nauticle_cells* cells, nauticle_fields* fields, hipEvent_t* phase_events, void* ws,
+                              size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_step_args(P, state, n_steps, cells, fields)) != NAUTICLE_OK) return st;
+    return run_steps(P, state, n_steps, cells, fields, phase_events, ws, stream);
 }
 
 nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,

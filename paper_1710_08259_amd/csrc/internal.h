@@ -342,7 +342,9 @@ hipError_t item_queue(const Plan& P, void* ws, int c, hipStream_t s, ItemQueue* 
 // ---- launchers (defined in the .hip files) -----------------------------------
 // search.hip
 hipError_t launch_bin(const Plan& P, void* ws, const float* const pos[3], StateDev st, hipStream_t s);
-hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3], hipStream_t s);
+hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3], bool by_id, hipStream_t s);
+hipError_t launch_gather_id(const Plan& P, void* ws, const uint32_t* id, const float* const g[3],
+                            float* const out[3], hipStream_t s);
 // mid (optional) is recorded between the sort/reorder and the neighbour lists
 hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sorted,
                               const nauticle_cells& cells, hipStream_t s, hipEvent_t mid = nullptr);

@@ -52,7 +52,7 @@ k_bin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_
 
 __global__ void __launch_bounds__(kMaxBlock)
 k_unbin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
-        float* px, float* py, float* pz)
+        float* px, float* py, float* pz, bool by_id)
 {
 #pragma clang fp contract(off)
     const uint32_t ix = xcd_item(n_items);
@@ -61,13 +61,43 @@ k_unbin(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint3
     if (threadIdx.x >= it.count) return;
     const CaseDev& C = cases[it.case_id];
     const uint32_t i = it.first + threadIdx.x;
+    uint32_t o = i;
+    if (by_id) {
+        uint32_t k = st.id[i];
+        if (k >= C.n) k = C.n - 1;  // corrupt id: keep the write inside the case
+        o = C.offset + k;
+    }
     int32_t c[3];
     cell_coords(C, st.cell[i], c);
     float* pos[3] = {px, py, pz};
     for (int k = 0; k < 3; ++k) {
         if (k >= C.dim) break;
         float corner = C.origin[k] + static_cast<float>(c[k]) * C.cs[k];
-        pos[k][i] = corner + st.off[k][i];
+        pos[k][o] = corner + st.off[k][i];
+    }
+}
+
+// out[k][p] = g[k][offset + id[p]]: a per-particle vector given in input
+// (id) order brought into the state's order.
+__global__ void __launch_bounds__(kMaxBlock)
+k_gather_id(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items,
+            const uint32_t* __restrict__ id, const float* g0, const float* g1, const float* g2, float* o0,
+            float* o1, float* o2)
+{
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;
+    const Item it = items[ix];
+    if (threadIdx.x >= it.count) return;
+    const CaseDev& C = cases[it.case_id];
+    const uint32_t p = it.first + threadIdx.x;
+    uint32_t k = id[p];
+    if (k >= C.n) k = C.n - 1;
+    const uint32_t q = C.offset + k;
+    const float* g[3] = {g0, g1, g2};
+    float* o[3] = {o0, o1, o2};
+    for (int a = 0; a < 3; ++a) {
+        if (a >= C.dim) break;
+        o[a][p] = g[a][q];
     }
 }
 
@@ -80,11 +110,20 @@ hipError_t launch_bin(const Plan& P, void* ws, const float* const pos[3], StateD
     return hipGetLastError();
 }
 
-hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3], hipStream_t s)
+hipError_t launch_unbin(const Plan& P, void* ws, StateDev st, float* const pos[3], bool by_id, hipStream_t s)
 {
     if (P.n_items == 0) return hipSuccess;
     k_unbin<<<xcd_grid(P.n_items), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
-                                                   P.n_items, st, pos[0], pos[1], pos[2]);
+                                                   P.n_items, st, pos[0], pos[1], pos[2], by_id);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_id(const Plan& P, void* ws, const uint32_t* id, const float* const g[3],
+                            float* const out[3], hipStream_t s)
+{
+    if (P.n_items == 0) return hipSuccess;
+    k_gather_id<<<xcd_grid(P.n_items), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items),
+                                                       P.n_items, id, g[0], g[1], g[2], out[0], out[1], out[2]);
     return hipGetLastError();
 }
 

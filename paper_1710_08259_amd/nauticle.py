@@ -41,7 +41,7 @@ NBR_INDEX_BITS = 26
 
 ENTRY_POINTS = (
     "nauticle_cells_total", "nauticle_workspace_bytes", "nauticle_prepare", "nauticle_bin",
-    "nauticle_unbin", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_continuity",
+    "nauticle_unbin", "nauticle_unbin_by_id", "nauticle_gather_by_id", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_continuity",
     "nauticle_sph_forces",
     "nauticle_step", "nauticle_step_verlet", "nauticle_interact", "nauticle_step_law", "nauticle_ch_steps", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
     "nauticle_last_error",
@@ -141,6 +141,10 @@ def lib():
     L.nauticle_bin.argtypes = [P(CCase), i32, P(ptr3), P(CState), vp, ctypes.c_size_t, vp]
     L.nauticle_unbin.restype = st
     L.nauticle_unbin.argtypes = [P(CCase), i32, P(CState), P(ptr3), vp, ctypes.c_size_t, vp]
+    L.nauticle_unbin_by_id.restype = st
+    L.nauticle_unbin_by_id.argtypes = [P(CCase), i32, P(CState), P(ptr3), vp, ctypes.c_size_t, vp]
+    L.nauticle_gather_by_id.restype = st
+    L.nauticle_gather_by_id.argtypes = [P(CCase), i32, P(CState), P(ptr3), P(ptr3), vp, ctypes.c_size_t, vp]
     L.nauticle_build_cells.restype = st
     L.nauticle_build_cells.argtypes = [P(CCase), i32, P(CState), P(CState), P(CCells), vp, ctypes.c_size_t, vp]
     L.nauticle_sph_density.restype = st
@@ -421,6 +425,20 @@ class Problem:
         _check(lib().nauticle_unbin(self.table, self.n_cases, ctypes.byref(st.c()), ctypes.byref(_ptr3(pos)),
                                     *self._ws()), "nauticle_unbin")
         return pos
+
+    def unbin_by_id(self, st: State) -> list:
+        """Absolute FP32 positions in input (id) order, one tensor per axis."""
+        pos = [torch.empty(max(self.n, 1), dtype=torch.float32, device=self.device) for _ in range(self.dim)]
+        _check(lib().nauticle_unbin_by_id(self.table, self.n_cases, ctypes.byref(st.c()),
+                                          ctypes.byref(_ptr3(pos)), *self._ws()), "nauticle_unbin_by_id")
+        return pos
+
+    def gather_by_id(self, st: State, g: Sequence[torch.Tensor]) -> list:
+        """out[k][p] = g[k][id of p]: input-order vectors into st's order."""
+        out = [torch.empty(max(self.n, 1), dtype=torch.float32, device=self.device) for _ in range(self.dim)]
+        _check(lib().nauticle_gather_by_id(self.table, self.n_cases, ctypes.byref(st.c()), ctypes.byref(_ptr3(g)),
+                                           ctypes.byref(_ptr3(out)), *self._ws()), "nauticle_gather_by_id")
+        return out
 
     def build_cells(self, st: State, sorted_: Optional[State] = None, cells: Optional[Cells] = None) -> State:
         out = self.sorted if sorted_ is None else sorted_

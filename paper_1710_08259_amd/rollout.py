@@ -75,8 +75,9 @@ class Rollout:
         loss, _ = prob.position_loss(st, target, grad=False)
         return float(loss.item())
 
-    def loss_and_grad(self, nu: float, c0: float, v0: torch.Tensor, target: N.State):
-        """(loss, dL/dv0 (n, dim) in id order, dL/dnu, dL/dc0)."""
+    def forward(self, nu: float, c0: float, v0: torch.Tensor):
+        """Runs the rollout keeping a checkpoint (a copy of the state) every
+        K steps; returns (final state, prepared problem, checkpoints)."""
         prob = self.problem(nu, c0)
         st = self.initial_state(prob, v0)
         ckpt = []
@@ -84,8 +85,16 @@ class Rollout:
             if s % self.K == 0:
                 ckpt.append((s, st.clone()))
             prob.step(st, 1)
-        loss, lam_x = prob.position_loss(st, target, grad=True)
-        lam_v = [torch.zeros_like(t) for t in lam_x]
+        return st, prob, ckpt
+
+    def vjp(self, prob: N.Problem, ckpt, lam_x, lam_v):
+        """Reverse sweep from cotangents (lam_x, lam_v: per-axis device FP32,
+        in the final state's order) of the final positions and velocities:
+        each segment is recomputed from its checkpoint, storing every step's
+        sorted state, lists and fields, then the one-step adjoints run in
+        reverse.  Returns (dL/dv0 (n, dim) in id order, dL/dnu, dL/dc0)."""
+        lam_x = [t.clone() for t in lam_x]
+        lam_v = [t.clone() for t in lam_v]
         dnu = torch.zeros(1, dtype=torch.float64, device=self.device)
         dc0 = torch.zeros(1, dtype=torch.float64, device=self.device)
         out_x = [torch.empty_like(t) for t in lam_x]
@@ -106,22 +115,51 @@ class Rollout:
                 lam_v, out_v = out_v, lam_v
         prob.check()
         gv0 = torch.stack(lam_v, dim=1)[: self.case.n]
-        return float(loss.item()), gv0, float(dnu.item()), float(dc0.item())
+        return gv0, float(dnu.item()), float(dc0.item())
+
+    def loss_and_grad(self, nu: float, c0: float, v0: torch.Tensor, target: N.State):
+        """(loss, dL/dv0 (n, dim) in id order, dL/dnu, dL/dc0) of the
+        position loss against ``target`` (nauticle_position_loss, which also
+        gives the loss's derivative in the final positions)."""
+        st, prob, ckpt = self.forward(nu, c0, v0)
+        loss, lam_x = prob.position_loss(st, target, grad=True)
+        lam_v = [torch.zeros_like(t) for t in lam_x]
+        gv0, dnu, dc0 = self.vjp(prob, ckpt, lam_x, lam_v)
+        return float(loss.item()), gv0, dnu, dc0
 
 
-class RolloutLoss(torch.autograd.Function):
-    """loss = RolloutLoss.apply(v0, nu, c0, rollout, target): differentiable in
-    v0 ((n, dim) float32, id order), nu and c0 (0-d float64 tensors)."""
+class NauticleRollout(torch.autograd.Function):
+    """r_T = NauticleRollout.apply(v0, nu, c0, rollout): the final absolute
+    FP32 positions ((n, dim), particle id order) of ``rollout``'s n_steps,
+    differentiable in v0 ((n, dim) float32, id order), nu and c0 (0-d
+    tensors).  The forward pass keeps only the checkpoints; the backward
+    pass seeds the positions' cotangent from grad_output (brought into the
+    final state's order by the library), recomputes each segment and runs
+    the hand-written adjoint.  Any loss built on r_T composes with it.  A
+    particle that left the box across a periodic face comes back shifted by
+    a box length; the shift has derivative one."""
 
     @staticmethod
-    def forward(ctx, v0, nu, c0, rollout: Rollout, target: N.State):
-        loss, gv0, gnu, gc0 = rollout.loss_and_grad(float(nu), float(c0), v0.detach(), target)
-        ctx.save_for_backward(gv0)
-        ctx.gnu, ctx.gc0 = gnu, gc0
-        return torch.tensor(loss, dtype=torch.float64, device=v0.device)
+    def forward(ctx, v0, nu, c0, rollout: Rollout):
+        st, prob, ckpt = rollout.forward(float(nu), float(c0), v0.detach())
+        pos = prob.unbin_by_id(st)
+        ctx.rollout, ctx.prob, ctx.ckpt, ctx.final = rollout, prob, ckpt, st
+        ctx.v0_dtype = v0.dtype
+        ctx.nu_like = (nu.dtype, nu.device)
+        ctx.c0_like = (c0.dtype, c0.device)
+        return torch.stack(pos, dim=1)[: rollout.case.n]
 
     @staticmethod
     def backward(ctx, g):
-        (gv0,) = ctx.saved_tensors
-        gs = g.to(torch.float64)
-        return ((gs * gv0.to(torch.float64)).to(gv0.dtype), gs * ctx.gnu, gs * ctx.gc0, None, None)
+        prob, n = ctx.prob, ctx.rollout.case.n
+        g = g.to(torch.float32)
+        gk = []
+        for k in range(prob.dim):
+            t = torch.zeros(max(prob.n, 1), dtype=torch.float32, device=prob.device)
+            t[:n] = g[:, k]
+            gk.append(t)
+        lam_x = prob.gather_by_id(ctx.final, gk)
+        lam_v = [torch.zeros_like(t) for t in lam_x]
+        gv0, dnu, dc0 = ctx.rollout.vjp(prob, ctx.ckpt, lam_x, lam_v)
+        return (gv0.to(ctx.v0_dtype), torch.tensor(dnu, dtype=ctx.nu_like[0], device=ctx.nu_like[1]),
+                torch.tensor(dc0, dtype=ctx.c0_like[0], device=ctx.c0_like[1]), None)
