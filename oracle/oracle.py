@@ -40,7 +40,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# NAUTICLE_ORACLE_LIB selects another build of the same source (the
+# sanitizer build of oracle/build.py)
+_LIB_PATH = os.environ.get("NAUTICLE_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 EMPTY = 0xFFFFFFFF
 

@@ -332,7 +332,7 @@ def _interior_cutoff_lattice(dim, hr, side):
 @pytest.mark.parametrize("dim,hr,side", [(2, 1.3, (24, 24)), (3, 1.2, (12, 12, 12))])
 def test_linear_pressure_field_gives_scaled_gradient(dim, hr, side):
     """Imposed p = P0 + G.x and uniform rho: a_i = -kappa G/rho on interior
-    particles, kappa the lattice gradient moment (P7 of the pins)."""
+    particles, kappa the lattice gradient moment."""
     case, x, interior = _interior_cutoff_lattice(dim, hr, side)
     dom, prm = domain_of(case), params_of(case)
     prm.g = (0.0, 0.0, 0.0)
