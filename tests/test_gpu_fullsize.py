@@ -13,6 +13,8 @@ any size.
 - 3-D dam break, 1,595,308 particles (571,308 fixed): the same one-step
   checks on a sample drawn from the fluid and the walls, and the 500th
   step's fields on the state the GPU reached after 499 steps.
+- Both, over 10 and 50 steps, every particle's position and velocity
+  against the oracle's rollout.
 - The 8.4M lattice recipe with cells for a skin of 0.1 2h, stepped 20 times
   with Verlet lists against 20 plain steps on the same table: positions and
   velocities of every particle within the rollout bar 5e-4 (the plain path
@@ -199,3 +201,36 @@ def test_dam_break_step_500_on_the_evolved_state_sampled():
           + f"; max |v| {np.abs(v).max():.3f} m/s", flush=True)
     for k, e in err.items():
         assert e < TOL_STEP, k
+
+
+@pytest.mark.parametrize("which,steps", [("lattice_8388608", 10), ("dam_break_1595308", 50)])
+def test_full_size_rollout_matches_the_oracle_for_every_particle(which, steps):
+    """Multi-step rollouts at full size in the bench's configuration, every
+    particle against the oracle's rollout from the same FP32 inputs: the
+    8.4M lattice over 10 steps, the dam break over 50 (the column starts to
+    fall; walls stay).  Positions against the largest displacement over the
+    rollout (a bar relative to the box length would hide every error),
+    velocities against max |v|; the rollout bar 5e-4."""
+    N = nauticle()
+    case = WL.periodic_3d_8m() if which.startswith("lattice") else WL.dam_break_3d()
+    prob = N.Problem([case])
+    st = prob.state_from_cases()
+    prob.step(st, steps)
+    torch.cuda.synchronize()
+    prob.check()
+    x_g, v_g = _positions_by_id(case, st)
+    del prob, st
+    torch.cuda.empty_cache()
+    print(f"{case.name}: {steps} GPU steps done; oracle rollout of {case.n} particles ...", flush=True)
+    dom, prm = domain_of(case), params_of(case)
+    x0 = x64(case)
+    x, v, _, _, _ = O.step(dom, prm, x0, v64(case), fixed=case.fixed_mask(), n_steps=steps)
+    moved = np.abs(O.min_image(dom, x - x0)).max()
+    err_x = np.abs(O.min_image(dom, x_g - x)).max() / moved
+    err_v = np.abs(v_g - v).max() / np.abs(v).max()
+    fixed = case.fixed_mask()
+    print(f"{case.name}, {steps} steps, all {case.n} particles: err x {err_x:.2e} of the largest "
+          f"displacement ({moved:.3e} m), v {err_v:.2e} of max |v| ({np.abs(v).max():.3e} m/s)", flush=True)
+    assert err_x < TOL_ROLLOUT and err_v < TOL_ROLLOUT
+    if fixed.any():
+        assert np.all(v_g[fixed] == 0.0) and np.abs(x_g[fixed] - x0[fixed]).max() < 1e-6

@@ -200,7 +200,11 @@ def test_density_pressure_acceleration_match_oracle(name):
     err_p = np.abs(g["p"] - p).max() / S["p"]
     fluid = ~case.fixed_mask()
     err_a = np.abs(g["a"][fluid] - a[fluid]).max() / S["a"]
-    print(f"{name}: err rho {err_rho:.2e} p {err_p:.2e} a {err_a:.2e}")
+    B = norms(case)  # the base scales, before raising them to the fields' own magnitudes
+    print(f"{name}: err rho {err_rho:.2e} p {err_p:.2e} a {err_a:.2e}; against the base scales "
+          f"rho {np.abs(g['rho'] - rho).max() / B['rho']:.2e} p {np.abs(g['p'] - p).max() / B['p']:.2e} "
+          f"a {np.abs(g['a'][fluid] - a[fluid]).max() / B['a']:.2e}; max rho/rho0 {rho.max() / case.rho0:.3f}, "
+          f"max |p|/(c0^2 rho0) {np.abs(p).max() / B['p']:.3f}, max |a|/(c0^2/h) {np.abs(a).max() / B['a']:.3f}")
     assert err_rho < TOL_STEP and err_p < TOL_STEP and err_a < TOL_STEP
     assert np.all(g["a"][~fluid] == 0.0)
 
