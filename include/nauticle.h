@@ -447,6 +447,26 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
                               int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
                               hipEvent_t* phase_events, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): nauticle_step
+ * with the default tuning and no caller workspace.  Its scratch is a fixed
+ * array of 64 MiB in the library's device code, one per device, held from
+ * the library's load until the process ends; cases needing more scratch
+ * than that (nauticle_workspace_bytes; about 140 bytes per particle, so
+ * roughly 470,000 particles) are rejected with NAUTICLE_ERR_WORKSPACE
+ * before anything is enqueued.  The call allocates nothing: it writes the
+ * case table into the scratch, enqueues the steps on `stream`, then waits
+ * for the stream and returns the most severe condition the kernels
+ * flagged (as nauticle_check would), so no separate check call is needed.
+ * state, cells and fields as in nauticle_step (caller-owned).  Every call
+ * on a device shares that device's scratch, which keeps the last call's
+ * contents: calls that overlap on one device (other host threads, other
+ * streams) race and must be serialised by the caller. */
+nauticle_status nauticle_step_fixed_scratch(const nauticle_case* cases, int32_t n_cases,
+                                            nauticle_state* state, int32_t n_steps,
+                                            nauticle_cells* cells, nauticle_fields* fields,
+                                            hipStream_t stream);
+
 /* n_steps steps of the SUMMATION or CONTINUITY model, as nauticle_step
  * computes them, or of the DEM contact law, as nauticle_step_law computes
  * them (attrs as there; NULL for the SPH models), with the neighbour lists

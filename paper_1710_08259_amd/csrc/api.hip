@@ -764,6 +764,56 @@ nauticle_status run_steps(const Plan* P, nauticle_state* state, int32_t n_steps,
 
 }  // namespace
 
+// Fixed device scratch of nauticle_step_fixed_scratch: a workspace that
+// lives in the code object, so that the entry point needs no allocation.
+// One copy per device (each at its own address), held until the process
+// ends.  Host code never passes `scratch` itself to a kernel or a copy:
+// its name on the host is a stand-in, not the device address; the address
+// comes from hipGetSymbolAddress, once per device.
+static constexpr size_t kFixedScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's scratch address (looked up on its first use).
+nauticle_status fixed_scratch(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(NAUTICLE_ERR_INVALID_ARG, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(NAUTICLE_ERR_HIP, "hipGetSymbolAddress(scratch) gave a null address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return NAUTICLE_OK;
+}
+
+// Reads and clears the error word of a workspace after the stream has drained.
+nauticle_status drain_and_read_error(const Plan& P, void* ws, hipStream_t stream, const char* where)
+{
+    uint32_t word = 0;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemcpy(&word, at<char>(ws, P.L.err), sizeof(word), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, where);
+    if (word & kErrNonFinite) return fail(NAUTICLE_ERR_NONFINITE, "a non-finite value was produced or given");
+    if (word & kErrOverflow) return fail(NAUTICLE_ERR_NEIGHBOUR_OVERFLOW, "a particle had more than max_nbr neighbours");
+    if (word & kErrOutOfDomain) return fail(NAUTICLE_ERR_OUT_OF_DOMAIN, "a position lies beyond 2^23 cells");
+    if (word & kErrAttribute) return fail(NAUTICLE_ERR_ATTRIBUTE, "a pair-law attribute is out of range");
+    return NAUTICLE_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauticle_state* state, int32_t n_steps,
@@ -775,6 +825,40 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
     if (st != NAUTICLE_OK) return st;
     if ((st = check_step_args(P, state, n_steps, cells, fields)) != NAUTICLE_OK) return st;
     return run_steps(P, state, n_steps, cells, fields, phase_events, ws, stream);
+}
+
+nauticle_status nauticle_step_fixed_scratch(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
+                                            int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
+                                            hipStream_t stream)
+{
+    Derived D;
+    nauticle_status st = derive(cases, n_cases, nullptr, &D);
+    if (st != NAUTICLE_OK) return st;
+    if (D.plan.L.total > kFixedScratchBytes)
+        return fail(NAUTICLE_ERR_WORKSPACE, "nauticle_step_fixed_scratch: these cases need %zu bytes of scratch, "
+                    "the fixed scratch holds %zu", D.plan.L.total, kFixedScratchBytes);
+    if ((st = check_step_args(&D.plan, state, n_steps, cells, fields)) != NAUTICLE_OK) return st;
+    void* ws = nullptr;
+    if ((st = fixed_scratch(&ws)) != NAUTICLE_OK) return st;
+    // the scratch keeps the last call's contents: the error word starts at
+    // zero, the case table and work lists are written anew (the persistent
+    // queue counters are zeroed by the launches themselves; this table runs
+    // grid launches)
+    hipError_t e = hipMemsetAsync(at<char>(ws, D.plan.L.err), 0, sizeof(uint32_t), stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(at<char>(ws, D.plan.L.cases), D.cases.data(), sizeof(CaseDev) * D.cases.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !D.items.empty())
+        e = hipMemcpyAsync(at<char>(ws, D.plan.L.items), D.items.data(), sizeof(Item) * D.items.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !D.queue.empty())
+        e = hipMemcpyAsync(at<char>(ws, D.plan.L.queue), D.queue.data(), sizeof(uint32_t) * D.queue.size(),
+                           hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "nauticle_step_fixed_scratch upload");
+    st = run_steps(&D.plan, state, n_steps, cells, fields, nullptr, ws, stream);
+    // the host copies of the table must outlive the uploads: drain before returning
+    const nauticle_status dev = drain_and_read_error(D.plan, ws, stream, "nauticle_step_fixed_scratch");
+    return st != NAUTICLE_OK ? st : dev;
 }
 
 nauticle_status nauticle_step_verlet(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,

@@ -43,7 +43,7 @@ ENTRY_POINTS = (
     "nauticle_cells_total", "nauticle_workspace_bytes", "nauticle_prepare", "nauticle_bin",
     "nauticle_unbin", "nauticle_unbin_by_id", "nauticle_gather_by_id", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_continuity",
     "nauticle_sph_forces",
-    "nauticle_step", "nauticle_step_verlet", "nauticle_interact", "nauticle_step_law", "nauticle_ch_steps", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
+    "nauticle_step", "nauticle_step_fixed_scratch", "nauticle_step_verlet", "nauticle_interact", "nauticle_step_law", "nauticle_ch_steps", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
     "nauticle_last_error",
 )
 
@@ -158,6 +158,8 @@ def lib():
     L.nauticle_step.restype = st
     L.nauticle_step.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(vp), vp,
                                 ctypes.c_size_t, vp]
+    L.nauticle_step_fixed_scratch.restype = st
+    L.nauticle_step_fixed_scratch.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), vp]
     L.nauticle_step_verlet.restype = st
     L.nauticle_step_verlet.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(CLawAttrs), P(i32),
                                        P(vp), vp, ctypes.c_size_t, vp]
@@ -534,6 +536,16 @@ class Problem:
         _check(lib().nauticle_step(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
                                    ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()), ev, *self._ws()),
                "nauticle_step")
+        return st
+
+    def step_fixed_scratch(self, st: State, n_steps: int = 1) -> State:
+        """n_steps steps in place through nauticle_step_fixed_scratch: the
+        library's fixed device scratch instead of this problem's workspace
+        (no allocation in the call; it waits for the steps and raises on
+        any condition the kernels flagged)."""
+        _check(lib().nauticle_step_fixed_scratch(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
+                                                 ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()),
+                                                 self.stream()), "nauticle_step_fixed_scratch")
         return st
 
     def step_verlet(self, st: State, n_steps: int = 1, attrs: Optional["LawAttrs"] = None, events=None) -> int:
