@@ -423,6 +423,34 @@ def step(dom: Domain, prm: Params, x, v, fixed=None, n_steps=1, nthreads=None):
     return x3[:, :d], v3[:, :d], rho, p, a[:, :d]
 
 
+def step_cfl(dom: Domain, prm: Params, x, v, cfl: float, n_steps: int, fixed=None, time: float = 0.0,
+             nthreads=None):
+    """n_steps of :func:`step`, each with its own time step from a CFL
+    condition on the sound speed and the flow speed: before every step
+    dt = cfl h / (c0 + max |v_i|) over the fluid particles (FP64); returns
+    (x, v, time + the sum of the dts, the last dt).  At rest this is the
+    fixed dt = cfl h / c0.
+
+    The paper keeps dt a variable that the scheduler may lower, and adapts it
+    from a maximum over the particles in Example 1b; for SPH this reading
+    takes the acoustic limit with the flow speed added."""
+    import copy
+
+    d = dom.dim
+    x = np.asarray(x, np.float64)[:, :d].copy()
+    v = np.asarray(v, np.float64)[:, :d].copy()
+    fluid = np.ones(x.shape[0], bool) if fixed is None else ~np.asarray(fixed, bool)
+    dt = 0.0
+    for _ in range(n_steps):
+        vmax = float(np.sqrt((v[fluid] ** 2).sum(axis=1)).max()) if fluid.any() else 0.0
+        dt = cfl * prm.h / (prm.c0 + vmax)
+        p = copy.copy(prm)
+        p.dt = dt
+        x, v, _, _, _ = step(dom, p, x, v, fixed=fixed, n_steps=1, nthreads=nthreads)
+        time += dt
+    return x, v, time, dt
+
+
 # --------------------------------------------------------------------------
 # Example 1a operator set
 # --------------------------------------------------------------------------

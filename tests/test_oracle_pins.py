@@ -575,3 +575,46 @@ def test_rollout_vjp_with_arbitrary_cotangents_matches_central_differences():
     # linear in the cotangents: zero in, zero out
     z = O.rollout_vjp(dom, prm, x0, v0, steps, 0 * wx, 0 * wv, checkpoint_every=4, nthreads=2)
     assert np.all(z[0] == 0) and np.all(z[1] == 0) and z[2] == 0.0 and z[3] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# CFL time step: dt = cfl h / (c0 + max |v|) before every step
+# ---------------------------------------------------------------------------
+
+def test_cfl_step_at_rest_is_the_fixed_acoustic_step():
+    """A lattice at rest stays at rest (it is an equilibrium, up to the
+    round-off of its force sums), so every step takes dt = cfl h / c0 and
+    the clock reads n cfl h / c0; the result is the fixed-step rollout at
+    that dt."""
+    case = WL.lattice_case(2, (20, 20), 0.01, 1.3, 0.0, 0.0, seed=0)
+    dom, prm = domain_of(case), params_of(case)
+    x0 = _exact_lattice(case, (20, 20))
+    cfl, n = 0.25, 12
+    x, v, t, dt = O.step_cfl(dom, prm, x0, np.zeros_like(x0), cfl, n, nthreads=2)
+    assert dt == pytest.approx(cfl * prm.h / prm.c0, rel=1e-12)
+    assert t == pytest.approx(n * cfl * prm.h / prm.c0, rel=1e-12)
+    import copy
+    p = copy.copy(prm)
+    p.dt = cfl * prm.h / prm.c0
+    xf, vf, _, _, _ = O.step(dom, p, x0, np.zeros_like(x0), n_steps=n, nthreads=2)
+    assert np.abs(x - xf).max() < 1e-15 and np.abs(v - vf).max() < 1e-15
+
+
+def test_cfl_step_of_a_falling_particle_keeps_v_equal_v0_plus_g_t():
+    """One particle under gravity: each step adds dt_n g to v, so whatever
+    the steps are, v = v0 + g t with t the clock; the steps shrink as the
+    particle speeds up, and the last one is cfl h / (c0 + |v|) of the speed
+    it started from (v - g dt)."""
+    dom = O.Domain(dim=3, n=(5, 5, 5), cs=(0.1, 0.1, 0.1), periodic=(True, True, True))
+    prm = O.Params(h=0.02, mass=0.3, rho0=1000.0, c0=2.0, nu=1e-3, dt=1e-3, g=(0.5, -1.0, -9.81))
+    x0 = np.array([[0.21, 0.22, 0.23]])
+    v0 = np.array([[0.3, 0.1, -0.2]])
+    cfl = 0.4
+    x, v, t, dt = O.step_cfl(dom, prm, x0, v0, cfl, 40, nthreads=1)
+    g = np.array(prm.g)
+    np.testing.assert_allclose(v[0], v0[0] + g * t, rtol=1e-12)
+    v_prev = v[0] - g * dt
+    assert dt == pytest.approx(cfl * prm.h / (prm.c0 + np.linalg.norm(v_prev)), rel=1e-12)
+    assert dt < cfl * prm.h / (prm.c0 + np.linalg.norm(v0[0]))
+    _, _, t1, dt1 = O.step_cfl(dom, prm, x0, v0, cfl, 1, nthreads=1)
+    assert dt1 == t1 == cfl * prm.h / (prm.c0 + np.linalg.norm(v0[0]))
