@@ -126,6 +126,10 @@ def parse():
     ap.add_argument("--ch-only", action="store_true", help="only the Example 1b Cahn-Hilliard sphere")
     ap.add_argument("--law-only", choices=("dem", "social"), default=None,
                     help="only one pair-law workload (DEM damper or social force room)")
+    ap.add_argument("--only", choices=("adjoint", "batched", "dam_break"), default=None,
+                    help="only one extra workload (for profiling runs)")
+    ap.add_argument("--batched-tuning", default=None,
+                    help="block/persistent/groups_per_cu for the batched workload instead of the autotuner's pick")
     ap.add_argument("--verlet-only", action="store_true",
                     help="only the main lattice with neighbour lists reused between builds")
     ap.add_argument("--skin-frac", type=float, default=0.1, help="Verlet skin in units of 2h")
@@ -314,17 +318,22 @@ def adjoint_extra(device):
             "fwd_plus_adjoint_vs_oracle": fa_sps * t_or}
 
 
-def batched_extra(device, steps=10):
-    """The 256-case batched workload, launch shape picked by the autotuner."""
+def batched_extra(device, steps=10, tuning=None):
+    """The 256-case batched workload, launch shape picked by the autotuner
+    (or the given one)."""
     from paper_1710_08259_amd import autotune
     from paper_1710_08259_amd import nauticle as N
     from paper_1710_08259_amd import workloads as WL
 
     cases = WL.batched_2d()
-    cands = (N.Tuning(), N.Tuning(block=128, persistent=1, groups_per_cu=4),
-             N.Tuning(block=256, persistent=1, groups_per_cu=4), N.Tuning(block=128))
-    cache = os.environ.get("NAUTICLE_TUNING_CACHE", os.path.join(tempfile.gettempdir(), "nauticle_tuning.json"))
-    best, timings = autotune.tune(cases, steps=2, candidates=cands, cache_path=cache, force=True)
+    if tuning is not None:
+        best, timings = tuning, {}
+    else:
+        cands = (N.Tuning(), N.Tuning(block=128), N.Tuning(block=128, persistent=1, groups_per_cu=0),
+                 N.Tuning(block=256, persistent=1, groups_per_cu=0))
+        cache = os.environ.get("NAUTICLE_TUNING_CACHE",
+                               os.path.join(tempfile.gettempdir(), "nauticle_tuning.json"))
+        best, timings = autotune.tune(cases, steps=2, candidates=cands, cache_path=cache, force=True)
     prob = N.Problem(cases, device=device, tuning=best)
     st = prob.state_from_cases()
     wall, phase, pairs = timed_steps(prob, st, steps, 2)
@@ -617,6 +626,15 @@ def main():
     if args.law_only:
         print(json.dumps({"extra": {args.law_only: law_extra(device, args.law_only, args.steps, args.warmup)}}),
               flush=True)
+        return
+    if args.only:
+        tn = None
+        if args.batched_tuning:
+            b, p, g = (int(v) for v in args.batched_tuning.split("/"))
+            tn = N.Tuning(block=b, persistent=p, groups_per_cu=g)
+        fn = {"adjoint": lambda: adjoint_extra(device), "batched": lambda: batched_extra(device, tuning=tn),
+              "dam_break": lambda: dam_break_extra(device)}[args.only]
+        print(json.dumps({"extra": {args.only: fn()}}), flush=True)
         return
     if args.ex1a_only:
         print(json.dumps({"extra": {"ex1a": ex1a_extra(device, args.ex1a_scale, args.steps, args.warmup)}}),

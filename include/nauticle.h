@@ -237,10 +237,15 @@ typedef struct {
  *                  64, 128, 256 (0 = 256);
  *   persistent:    0 = one workgroup per item; 1 = a persistent grid of
  *                  groups_per_cu workgroups per compute unit pulls items
- *                  from a queue ordered by decreasing estimated cost
- *                  (particles x expected neighbours), one atomic counter per
- *                  launch;
- *   groups_per_cu: persistent grid size per compute unit (0 = 4). */
+ *                  from 8 queues, one per XCD: queue x holds the items a
+ *                  grid launch gives XCD x (neighbouring tiles, which share
+ *                  that XCD's L2), ordered by decreasing estimated cost
+ *                  (particles x expected neighbours); a workgroup empties
+ *                  its own XCD's queue first, then takes from the others;
+ *                  one atomic counter per queue and launch;
+ *   groups_per_cu: persistent workgroups per compute unit, capped at what
+ *                  the kernel's registers and LDS let be resident at once
+ *                  (0 = that many). */
 typedef struct {
     int32_t block;
     int32_t persistent;
@@ -446,6 +451,23 @@ nauticle_status nauticle_ch_steps(const nauticle_case* cases, int32_t n_cases,
 nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
                               int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
                               hipEvent_t* phase_events, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* n_steps steps of the SUMMATION or CONTINUITY model as nauticle_step
+ * computes them, each with its own time step from a CFL condition on the
+ * sound speed and the flow speed (the paper adapts dt on the device for
+ * Example 1b [its listing's eq5]; the same device-side maximum serves
+ * here): before every step, per case,
+ *   dt = cfl * h / (c0 + max_i |v_i|)
+ * over the case's fluid particles at the step's start (|v_i| in FP32, the
+ * quotient in FP64, rounded to FP32 for the step), so a case at rest takes
+ * dt = cfl h / c0.  clock (device FP64, {time, dt} per case) is advanced on
+ * the device: time += dt, and dt holds the last step's.  The cases' own dt
+ * is ignored, and the workspace keeps it for later calls.  cfl must be
+ * finite and > 0. */
+nauticle_status nauticle_step_cfl(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
+                                  int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields,
+                                  double cfl, double* clock, void* ws, size_t ws_bytes,
+                                  hipStream_t stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, hosts that forbid hipMalloc): nauticle_step

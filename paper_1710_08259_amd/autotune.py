@@ -24,7 +24,7 @@ from . import nauticle as N
 
 CANDIDATES = tuple(N.Tuning(block=b, persistent=p, groups_per_cu=g)
                    for b in (64, 128, 256)
-                   for (p, g) in ((0, 4), (1, 2), (1, 4), (1, 8)))
+                   for (p, g) in ((0, 4), (1, 0), (1, 2), (1, 4)))
 
 
 def bucket(cases) -> str:

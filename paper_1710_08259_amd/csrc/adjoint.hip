@@ -249,19 +249,27 @@ k_adj_b(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
     });
 }
 
-// Adds each case's sum of item partials (in item order) to out_a / out_b.
-// With per_case_mean, out_a gets the sum divided by (n_fluid * dim).
-__global__ void k_reduce_cases(const CaseDev* __restrict__ cases, int n_cases, const double* __restrict__ partial,
-                               double* out_a, double* out_b, int accumulate, int per_case_mean)
+// Adds each case's sum of its item partials to out_a / out_b: one
+// workgroup per case, thread t summing the case's items t, t + blockDim,
+// ... in order, then a fixed tree across the threads (the same order on
+// every run, and for a case whether it is alone or in a batch).  With
+// per_case_mean, out_a gets the sum divided by (n_fluid * dim).
+__global__ void __launch_bounds__(kBlock)
+k_reduce_cases(const CaseDev* __restrict__ cases, const double* __restrict__ partial, double* out_a, double* out_b,
+               int accumulate, int per_case_mean)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n_cases) return;
+    __shared__ double sh_a[kBlock];
+    __shared__ double sh_b[kBlock];
+    const int b = blockIdx.x;
     const CaseDev& C = cases[b];
     double sa = 0.0, sb = 0.0;
-    for (uint32_t it = C.item_first; it < C.item_first + C.item_count; ++it) {
+    for (uint32_t k = threadIdx.x; k < C.item_count; k += blockDim.x) {
+        const uint32_t it = C.item_first + k;
         sa += partial[2 * it];
         sb += partial[2 * it + 1];
     }
+    block_reduce2(sa, sb, sh_a, sh_b, &sa, &sb);
+    if (threadIdx.x != 0) return;
     if (per_case_mean) {
         const double nf = static_cast<double>(C.n_fluid) * C.dim;
         sa = nf > 0.0 ? sa / nf : 0.0;
@@ -288,15 +296,14 @@ hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nautic
                                         lvn[2], pk.adj4);
     ItemQueue Qa, Qb;
     if ((e = item_queue(P, ws, 3, s, &Qa)) != hipSuccess) return e;
-    k_adj_a<<<grid_for(P), P.block, 0, s>>>(cases, items, Qa, sorted, pk.a4, pk.b4, pk.adj4, cells.nbr,
+    k_adj_a<<<grid_for(P, reinterpret_cast<const void*>(&k_adj_a)), P.block, 0, s>>>(cases, items, Qa, sorted, pk.a4, pk.b4, pk.adj4, cells.nbr,
                                             cells.nbr_count, mx, P.n_total, f, cells.perm, lxn[0], lxn[1], lxn[2],
                                             lvn[0], lvn[1], lvn[2], lv[0], lv[1], lv[2], pk.adj4b, partial);
     if ((e = item_queue(P, ws, 4, s, &Qb)) != hipSuccess) return e;
-    k_adj_b<<<grid_for(P), P.block, 0, s>>>(cases, items, Qb, sorted, pk.a4, pk.b4, pk.adj4b, cells.nbr,
+    k_adj_b<<<grid_for(P, reinterpret_cast<const void*>(&k_adj_b)), P.block, 0, s>>>(cases, items, Qb, sorted, pk.a4, pk.b4, pk.adj4b, cells.nbr,
                                             cells.nbr_count, mx, P.n_total, cells.perm, lxn[0], lxn[1], lxn[2],
                                             lx[0], lx[1], lx[2]);
-    const int nb = (P.n_cases + kBlock - 1) / kBlock;
-    k_reduce_cases<<<nb, kBlock, 0, s>>>(cases, P.n_cases, partial, dnu, dc0, 1, 0);
+    k_reduce_cases<<<P.n_cases, kBlock, 0, s>>>(cases, partial, dnu, dc0, 1, 0);
     return hipGetLastError();
 }
 
@@ -375,8 +382,82 @@ hipError_t launch_position_loss(const Plan& P, void* ws, StateDev a, StateDev b,
     k_inverse_id<<<grid, P.block, 0, s>>>(cases, items, P.n_items, b.id, inv);
     k_position_loss<<<grid, P.block, 0, s>>>(cases, items, P.n_items, a, b, inv, grad ? grad[0] : nullptr,
                                             grad ? grad[1] : nullptr, grad ? grad[2] : nullptr, partial);
-    const int nb = (P.n_cases + kBlock - 1) / kBlock;
-    k_reduce_cases<<<nb, kBlock, 0, s>>>(cases, P.n_cases, partial, loss, nullptr, 0, 1);
+    k_reduce_cases<<<P.n_cases, kBlock, 0, s>>>(cases, partial, loss, nullptr, 0, 1);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// CFL time step
+// ----------------------------------------------------------------------------
+
+// partial[2 * item] = the largest speed |v| among the item's fluid particles
+// (FP32 |v|, widened; 0 for an item without fluid).
+__global__ void __launch_bounds__(kMaxBlock)
+k_item_vmax(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
+            double* __restrict__ partial)
+{
+    __shared__ float sh[kMaxBlock];
+    const uint32_t ix = xcd_item(n_items);
+    if (ix >= n_items) return;  // uniform over the block
+    const Item it = items[ix];
+    const CaseDev& C = cases[it.case_id];
+    float v = 0.0f;
+    if (threadIdx.x < it.count) {
+        const uint32_t p = it.first + threadIdx.x;
+        if (st.id[p] < C.n_fluid) {
+            float s2 = 0.0f;
+            for (int k = 0; k < 3; ++k) {
+                if (k >= C.dim) break;
+                const float vk = st.vel[k][p];
+                s2 = fmaf(vk, vk, s2);
+            }
+            v = __builtin_sqrtf(s2);
+        }
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = static_cast<int>(blockDim.x) / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < static_cast<unsigned>(s)) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * ix] = static_cast<double>(sh[0]);
+        partial[2 * ix + 1] = 0.0;
+    }
+}
+
+// One workgroup per case: vmax = the largest item maximum (a maximum does
+// not depend on the order), dt = cfl h / (c0 + vmax) in FP64, rounded to FP32
+// into the device case table (the step's kernels read it there), and the
+// case's clock {time, dt} advanced by it.
+__global__ void __launch_bounds__(kBlock)
+k_cfl_cases(CaseDev* __restrict__ cases, const double* __restrict__ partial, double cfl, double* __restrict__ clock)
+{
+    __shared__ double sh[kBlock];
+    const int b = blockIdx.x;
+    CaseDev& C = cases[b];
+    double vmax = 0.0;
+    for (uint32_t k = threadIdx.x; k < C.item_count; k += blockDim.x) vmax = fmax(vmax, partial[2 * (C.item_first + k)]);
+    sh[threadIdx.x] = vmax;
+    __syncthreads();
+    for (int s = static_cast<int>(blockDim.x) / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < static_cast<unsigned>(s)) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const float dt = static_cast<float>(cfl * static_cast<double>(C.h) / (static_cast<double>(C.c0) + sh[0]));
+    C.dt = dt;
+    clock[2 * b] += static_cast<double>(dt);
+    clock[2 * b + 1] = static_cast<double>(dt);
+}
+
+hipError_t launch_cfl(const Plan& P, void* ws, StateDev st, double cfl, double* clock, hipStream_t s)
+{
+    if (P.n_items == 0) return hipSuccess;
+    CaseDev* cases = at<CaseDev>(ws, P.L.cases);
+    double* partial = at<double>(ws, P.L.partial);
+    k_item_vmax<<<xcd_grid(P.n_items), P.block, 0, s>>>(cases, at<Item>(ws, P.L.items), P.n_items, st, partial);
+    k_cfl_cases<<<P.n_cases, kBlock, 0, s>>>(cases, partial, cfl, clock);
     return hipGetLastError();
 }
 

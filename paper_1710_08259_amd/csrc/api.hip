@@ -73,10 +73,9 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     if (tuning) {
         tn = *tuning;
         if (tn.block == 0) tn.block = 256;
-        if (tn.groups_per_cu == 0) tn.groups_per_cu = 4;
         if ((tn.block != 64 && tn.block != 128 && tn.block != 256) || (tn.persistent != 0 && tn.persistent != 1) ||
-            tn.groups_per_cu < 1 || tn.groups_per_cu > 64)
-            return fail(NAUTICLE_ERR_INVALID_ARG, "tuning: block in {64,128,256}, persistent in {0,1}, groups_per_cu in [1,64]");
+            tn.groups_per_cu < 0 || tn.groups_per_cu > 64)
+            return fail(NAUTICLE_ERR_INVALID_ARG, "tuning: block in {64,128,256}, persistent in {0,1}, groups_per_cu in [0,64]");
     }
     const int64_t block = tn.block;
     if (!cases || n_cases < 1) return fail(NAUTICLE_ERR_INVALID_ARG, "cases is null or n_cases < 1");
@@ -247,15 +246,22 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             return fail(NAUTICLE_ERR_HIP, "could not query the number of compute units");
     }
-    P.persistent_grid = static_cast<uint32_t>(cus * tn.groups_per_cu);
-    // queue: items by decreasing estimated cost (particles x expected neighbours), ties in item order
+    P.cus = static_cast<uint32_t>(cus);
+    P.groups_per_cu = static_cast<uint32_t>(tn.groups_per_cu);
+    // queues: the item list cut into kXcds contiguous slices (the items a
+    // grid launch gives each XCD), each slice by decreasing estimated cost
+    // (particles x expected neighbours), ties in item order
     D->queue.resize(D->items.size());
     for (size_t k = 0; k < D->queue.size(); ++k) D->queue[k] = static_cast<uint32_t>(k);
-    std::stable_sort(D->queue.begin(), D->queue.end(), [&](uint32_t a, uint32_t b) {
-        const Item& A = D->items[a];
-        const Item& B = D->items[b];
-        return A.count * nbr_per_particle[A.case_id] > B.count * nbr_per_particle[B.case_id];
-    });
+    const size_t per_xcd = (D->queue.size() + kXcds - 1) / kXcds;
+    for (size_t first = 0; first < D->queue.size(); first += per_xcd) {
+        const size_t last = std::min(D->queue.size(), first + per_xcd);
+        std::stable_sort(D->queue.begin() + first, D->queue.begin() + last, [&](uint32_t a, uint32_t b) {
+            const Item& A = D->items[a];
+            const Item& B = D->items[b];
+            return A.count * nbr_per_particle[A.case_id] > B.count * nbr_per_particle[B.case_id];
+        });
+    }
     int bits = 1;
     while ((1ull << bits) < n_cells_total) ++bits;
     P.key_bits = bits;
@@ -276,7 +282,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     const size_t n_items_max = std::max<size_t>(static_cast<size_t>(worst_items), 1);
     L.items = take(sizeof(Item) * n_items_max);
     L.queue = take(sizeof(uint32_t) * n_items_max);
-    L.counters = take(sizeof(uint32_t) * kCounters);
+    L.counters = take(sizeof(uint32_t) * kCounters * kXcds * kCounterStride);
     for (int k = 0; k < 9; ++k) L.state[k] = take(4 * N);
     L.sort_keys = take(4 * N);
     L.sort_vals = take(4 * N);
@@ -825,6 +831,35 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
     if (st != NAUTICLE_OK) return st;
     if ((st = check_step_args(P, state, n_steps, cells, fields)) != NAUTICLE_OK) return st;
     return run_steps(P, state, n_steps, cells, fields, phase_events, ws, stream);
+}
+
+nauticle_status nauticle_step_cfl(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
+                                  int32_t n_steps, nauticle_cells* cells, nauticle_fields* fields, double cfl,
+                                  double* clock, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_step_args(P, state, n_steps, cells, fields)) != NAUTICLE_OK) return st;
+    if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(NAUTICLE_ERR_INVALID_ARG, "cfl must be finite and > 0");
+    if (!clock) return fail(NAUTICLE_ERR_INVALID_ARG, "clock is null");
+    // the host copy of the device case table: its fixed time steps are put
+    // back at the end, so that later calls on the workspace use them
+    const void* table = nullptr;
+    size_t table_bytes = 0;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        const Derived& D = g_plans.at(ws);
+        table = D.cases.data();
+        table_bytes = sizeof(CaseDev) * D.cases.size();
+    }
+    for (int32_t s = 0; s < n_steps; ++s) {
+        hipError_t e = launch_cfl(*P, ws, to_dev_model(*P, state), cfl, clock, stream);
+        if (e != hipSuccess) return hip_fail(e, "nauticle_step_cfl");
+        if ((st = run_steps(P, state, 1, cells, fields, nullptr, ws, stream)) != NAUTICLE_OK) return st;
+    }
+    hipError_t e = hipMemcpyAsync(at<char>(ws, P->L.cases), table, table_bytes, hipMemcpyHostToDevice, stream);
+    return e == hipSuccess ? NAUTICLE_OK : hip_fail(e, "nauticle_step_cfl restore");
 }
 
 nauticle_status nauticle_step_fixed_scratch(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,

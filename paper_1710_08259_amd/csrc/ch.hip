@@ -175,10 +175,10 @@ hipError_t launch_ch_steps(const Plan& P, void* ws, StateDev sorted, const nauti
     for (int32_t step = 0; step < n_steps && e == hipSuccess; ++step) {
         ItemQueue Q;
         if ((e = item_queue(P, ws, 6, s, &Q)) != hipSuccess) break;
-        kmu<<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.a4, pk.b4, cells.nbr, cells.nbr_count, mx,
+        kmu<<<grid_for(P, reinterpret_cast<const void*>(kmu)), P.block, 0, s>>>(cases, items, Q, sorted, pk.a4, pk.b4, cells.nbr, cells.nbr_count, mx,
                                             P.n_total, mu, err);
         if ((e = item_queue(P, ws, 7, s, &Q)) != hipSuccess) break;
-        kcd<<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.a4, pk.b4, cells.nbr, cells.nbr_count, mx,
+        kcd<<<grid_for(P, reinterpret_cast<const void*>(kcd)), P.block, 0, s>>>(cases, items, Q, sorted, pk.a4, pk.b4, cells.nbr, cells.nbr_count, mx,
                                             P.n_total, c, cdot, clock, item_max, err);
         k_ch_clock<<<P.n_cases, kBlock, 0, s>>>(cases, clock, item_max);
         e = hipGetLastError();

@@ -191,7 +191,8 @@ hipError_t launch_law(const Plan& P, void* ws, StateDev sorted, const nauticle_c
     static const Kern table[2][2] = {{k_interact<Law, false, false, G>, k_interact<Law, false, true, G>},
                                      {k_interact<Law, true, false, G>, k_interact<Law, true, true, G>}};
     const StateDev none{};
-    table[next ? 1 : 0][P.mirror ? 1 : 0]<<<grid_for(P), P.block, 0, s>>>(
+    const Kern kern = table[next ? 1 : 0][P.mirror ? 1 : 0];
+    kern<<<grid_for(P, reinterpret_cast<const void*>(kern)), P.block, 0, s>>>(
         cases, items, Q, sorted, at_, r0, r1, r2, cells.nbr, cells.nbr_count, static_cast<uint32_t>(cells.max_nbr),
         P.n_total, f, next ? *next : none, err);
     return hipGetLastError();

@@ -153,7 +153,8 @@ struct Plan {
     int key_bits;
     uint32_t block;          // threads per workgroup = particles per item
     uint32_t persistent;     // neighbour loops as persistent grids
-    uint32_t persistent_grid;
+    uint32_t cus;            // compute units of the device (persistent launches)
+    uint32_t groups_per_cu;  // persistent groups per compute unit (0: as many as fit)
     uint32_t halo_cap;       // LDS records staged per work item (neighbour loops)
     uint32_t mirror;         // some case has a symmetric axis: the image-aware kernels run
     int32_t model;           // NAUTICLE_MODEL_*, shared by all cases
@@ -172,16 +173,21 @@ inline Packed packed(const Plan& P, void* ws)
                   P.L.vr4 ? at<float4>(ws, P.L.vr4) : nullptr};
 }
 
-// How a neighbour-loop kernel finds its work items.
+// How a neighbour-loop kernel finds its work items.  A persistent launch
+// pulls them from kXcds queues: queue x holds the items an ordinary launch
+// gives XCD x (the x-th contiguous slice of the item list, so neighbouring
+// tiles share that XCD's L2), in decreasing estimated cost.
 struct ItemQueue {
     uint32_t n_items;
     uint32_t persistent;
-    const uint32_t* order;  // queue position -> item index
-    uint32_t* counter;      // next queue position (zeroed before the launch)
+    const uint32_t* order;  // slice x, position k -> item index, at order[x * ceil(n_items / kXcds) + k]
+    uint32_t* counter;      // kXcds counters kCounterStride words apart: the next position in each slice
+                            // (zeroed before the launch)
 };
 
 constexpr int kMaxBlock = 256;
-constexpr int kCounters = 8;  // queue counters in the workspace
+constexpr int kCounters = 8;  // launches of a sequence with counters of their own
+constexpr uint32_t kCounterStride = 32;  // words between two queue counters (one 128-byte line each)
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X, each
 // with its own L2.  Tiles are consecutive in space, so giving every XCD one
@@ -198,22 +204,45 @@ __device__ inline uint32_t xcd_item(uint32_t n_items)
 }
 
 // Runs body(item) for the items this workgroup owns: its one XCD-mapped
-// item (grid launch), or items pulled from the cost-ordered queue until the
-// queue is empty (persistent launch; every workgroup reaches the end).
-// Every thread of the block must call it; body may contain barriers.
+// item (grid launch), or items pulled from the queues (persistent launch):
+// first from its own XCD's queue, then, once that is empty, from the
+// others' in turn, until all are empty.  Thread 0 claims the next position
+// as soon as it has the current item, so the atomic's round trip overlaps
+// the item's work; each failed claim moves on to the next queue, so every
+// workgroup ends after at most kXcds of them.  Every thread of the block
+// must call it; body may contain barriers.
 template <typename Body>
 __device__ inline void for_each_item(const ItemQueue& Q, uint32_t* s_pos, Body&& body)
 {
+    const uint32_t per = (Q.n_items + kXcds - 1) / kXcds;
+    const uint32_t home = blockIdx.x % kXcds;
+    uint32_t tried = 0;  // thread 0: queues found empty
+    uint32_t claim = 0;  // thread 0: the claimed position in queue (home + tried) % kXcds
+    if (Q.persistent && threadIdx.x == 0) claim = atomicAdd(Q.counter + home * kCounterStride, 1u);
     // one loop for both launch modes, so the body is instantiated once
     for (uint32_t iter = 0;; ++iter) {
         uint32_t ix;
         if (Q.persistent) {
-            if (threadIdx.x == 0) *s_pos = atomicAdd(Q.counter, 1u);
+            if (threadIdx.x == 0) {
+                uint32_t found = Q.n_items;
+                while (tried < kXcds) {
+                    const uint32_t x = (home + tried) % kXcds;
+                    const uint32_t first = min(x * per, Q.n_items);
+                    const uint32_t len = min(per, Q.n_items - first);
+                    if (claim < len) {
+                        found = Q.order[first + claim];
+                        claim = atomicAdd(Q.counter + x * kCounterStride, 1u);  // the next one, ahead
+                        break;
+                    }
+                    if (++tried < kXcds)
+                        claim = atomicAdd(Q.counter + ((home + tried) % kXcds) * kCounterStride, 1u);
+                }
+                *s_pos = found;
+            }
             __syncthreads();
-            const uint32_t pos = *s_pos;
+            ix = *s_pos;
             __syncthreads();
-            if (pos >= Q.n_items) break;
-            ix = Q.order[pos];
+            if (ix >= Q.n_items) break;
         } else {
             ix = xcd_item(Q.n_items);
             if (iter > 0 || ix >= Q.n_items) break;
@@ -330,9 +359,16 @@ __device__ inline void halo_copy(const HaloRows& H, const float4* __restrict__ s
     __syncthreads();  // waits for the loads (vmcnt) before the barrier
 }
 
-inline uint32_t grid_for(const Plan& P)
+// Workgroups of a launch of `kernel` (P.block threads, `lds` bytes of
+// dynamic LDS): one per item, or for a persistent launch groups_per_cu per
+// compute unit, no more than can be resident at once (a group that could
+// only start after another had finished would find the queues empty; 0 =
+// as many as fit), in whole rounds of kXcds and no more than the items.
+uint32_t persistent_groups(const Plan& P, const void* kernel, size_t lds);
+
+inline uint32_t grid_for(const Plan& P, const void* kernel, size_t lds = 0)
 {
-    return P.persistent ? P.persistent_grid : xcd_grid(P.n_items);
+    return P.persistent ? persistent_groups(P, kernel, lds) : xcd_grid(P.n_items);
 }
 
 // Queue for the c-th neighbour-loop launch of a sequence (counter c, reset
@@ -378,6 +414,9 @@ hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nautic
                           FieldsDev f, const float* const lxn[3], const float* const lvn[3],
                           float* const lx[3], float* const lv[3], double* dnu, double* dc0,
                           hipStream_t s);
+// Sets every case's time step from the state's largest fluid speed (CFL),
+// writing it into the device case table and advancing the cases' clocks.
+hipError_t launch_cfl(const Plan& P, void* ws, StateDev st, double cfl, double* clock, hipStream_t s);
 hipError_t launch_position_loss(const Plan& P, void* ws, StateDev a, StateDev b, double* loss,
                                 float* const grad[3], hipStream_t s);
 // verlet.hip: steps between neighbour builds.  drift completes a step in

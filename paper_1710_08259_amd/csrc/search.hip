@@ -10,6 +10,11 @@
 // order.
 #include "sort.h"
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace nau {
 
 // ----------------------------------------------------------------------------
@@ -349,10 +354,36 @@ hipError_t item_queue(const Plan& P, void* ws, int c, hipStream_t s, ItemQueue* 
     Q->n_items = P.n_items;
     Q->persistent = P.persistent;
     Q->order = at<uint32_t>(ws, P.L.queue);
-    Q->counter = at<uint32_t>(ws, P.L.counters) + (c % kCounters);
+    Q->counter = at<uint32_t>(ws, P.L.counters) + (c % kCounters) * kXcds * kCounterStride;
     if (!P.persistent) return hipSuccess;
-    k_fill_u32<<<1, 64, 0, s>>>(Q->counter, 1, 0u);  // a kernel, not a memset: safe under graph capture
+    // a kernel, not a memset: safe under graph capture
+    k_fill_u32<<<1, kXcds * kCounterStride, 0, s>>>(Q->counter, kXcds * kCounterStride, 0u);
     return hipGetLastError();
+}
+
+uint32_t persistent_groups(const Plan& P, const void* kernel, size_t lds)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<const void*, uint32_t, size_t>, int> fit;  // resident groups per CU
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        const auto key = std::make_tuple(kernel, P.block, lds);
+        auto it = fit.find(key);
+        if (it != fit.end()) {
+            per_cu = it->second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, static_cast<int>(P.block), lds) !=
+                hipSuccess)
+                per_cu = 1;
+            fit.emplace(key, per_cu);
+        }
+    }
+    if (per_cu < 1) per_cu = 1;
+    const uint32_t g = P.groups_per_cu > 0 ? std::min<uint32_t>(P.groups_per_cu, per_cu) : per_cu;
+    uint32_t groups = P.cus * g / kXcds * kXcds;
+    groups = std::max<uint32_t>(groups, kXcds);
+    return std::min(groups, xcd_grid(P.n_items));
 }
 
 hipError_t launch_cell_first(const Plan& P, void* ws, const nauticle_cells& cells, hipStream_t s)
@@ -745,8 +776,8 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     const size_t lds = sizeof(float4) * (cap + kHaloPad);
     auto kern = P.dim_max == 3 ? (P.mirror ? k_nlist<3, true> : k_nlist<3, false>)
                                : (P.mirror ? k_nlist<2, true> : k_nlist<2, false>);
-    kern<<<grid_for(P), P.block, lds, s>>>(cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr,
-                                           cells.nbr_count, mx, n, cap, err);
+    kern<<<grid_for(P, reinterpret_cast<const void*>(kern), lds), P.block, lds, s>>>(
+        cases, items, Q, sorted, pk.pos4, pk.cell_first, cells.nbr, cells.nbr_count, mx, n, cap, err);
     return hipGetLastError();
 }
 

@@ -78,7 +78,7 @@ hipError_t launch_density(const Plan& P, void* ws, StateDev sorted, const nautic
     if (e != hipSuccess) return e;
     auto kern = P.dim_max == 3 ? (P.mirror ? k_density<true, kGroup3> : k_density<false, kGroup3>)
                                : (P.mirror ? k_density<true, kGroup2> : k_density<false, kGroup2>);
-    kern<<<grid_for(P), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), Q, sorted, pk.pos4,
+    kern<<<grid_for(P, reinterpret_cast<const void*>(kern)), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), Q, sorted, pk.pos4,
                                          cells.nbr, cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), P.n_total,
                                          f, pk.a4, pk.b4, at<uint32_t>(ws, P.L.err));
     return hipGetLastError();
@@ -204,7 +204,7 @@ hipError_t launch_continuity(const Plan& P, void* ws, StateDev sorted, const nau
     if (e != hipSuccess) return e;
     auto kern = P.dim_max == 3 ? (P.mirror ? k_continuity<true, kGroup3> : k_continuity<false, kGroup3>)
                                : (P.mirror ? k_continuity<true, kGroup2> : k_continuity<false, kGroup2>);
-    kern<<<grid_for(P), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), Q, sorted, pk.pos4,
+    kern<<<grid_for(P, reinterpret_cast<const void*>(kern)), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), Q, sorted, pk.pos4,
                                          pk.vr4, cells.nbr, cells.nbr_count, static_cast<uint32_t>(cells.max_nbr),
                                          P.n_total, f, pk.a4, pk.b4, at<uint32_t>(ws, P.L.err));
     return hipGetLastError();
@@ -398,7 +398,7 @@ hipError_t launch_forces(const Plan& P, void* ws, StateDev sorted, const nauticl
     const Kern kern = P.dim_max == 3 ? forces_kernel<kGroup3>(P, next != nullptr)
                                      : forces_kernel<kGroup2>(P, next != nullptr);
     const StateDev none{};
-    kern<<<grid_for(P), P.block, 0, s>>>(cases, items, Q, sorted, pk.a4, pk.b4, cells.nbr, cells.nbr_count, mx,
+    kern<<<grid_for(P, reinterpret_cast<const void*>(kern)), P.block, 0, s>>>(cases, items, Q, sorted, pk.a4, pk.b4, cells.nbr, cells.nbr_count, mx,
                                          P.n_total, f, next ? *next : none, err);
     return hipGetLastError();
 }

@@ -43,7 +43,7 @@ ENTRY_POINTS = (
     "nauticle_cells_total", "nauticle_workspace_bytes", "nauticle_prepare", "nauticle_bin",
     "nauticle_unbin", "nauticle_unbin_by_id", "nauticle_gather_by_id", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_continuity",
     "nauticle_sph_forces",
-    "nauticle_step", "nauticle_step_fixed_scratch", "nauticle_step_verlet", "nauticle_interact", "nauticle_step_law", "nauticle_ch_steps", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
+    "nauticle_step", "nauticle_step_cfl", "nauticle_step_fixed_scratch", "nauticle_step_verlet", "nauticle_interact", "nauticle_step_law", "nauticle_ch_steps", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
     "nauticle_last_error",
 )
 
@@ -158,6 +158,9 @@ def lib():
     L.nauticle_step.restype = st
     L.nauticle_step.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), P(vp), vp,
                                 ctypes.c_size_t, vp]
+    L.nauticle_step_cfl.restype = st
+    L.nauticle_step_cfl.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), ctypes.c_double, vp, vp,
+                                    ctypes.c_size_t, vp]
     L.nauticle_step_fixed_scratch.restype = st
     L.nauticle_step_fixed_scratch.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), vp]
     L.nauticle_step_verlet.restype = st
@@ -536,6 +539,15 @@ class Problem:
         _check(lib().nauticle_step(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
                                    ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()), ev, *self._ws()),
                "nauticle_step")
+        return st
+
+    def step_cfl(self, st: State, n_steps: int, cfl: float, clock: torch.Tensor) -> State:
+        """n_steps steps in place, each case's dt = cfl h / (c0 + max |v|)
+        before every step; clock: device float64 (n_cases, 2) = {time, dt},
+        advanced on the device."""
+        _check(lib().nauticle_step_cfl(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
+                                       ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()), float(cfl),
+                                       _p(clock), *self._ws()), "nauticle_step_cfl")
         return st
 
     def step_fixed_scratch(self, st: State, n_steps: int = 1) -> State:

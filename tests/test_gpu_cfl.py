@@ -1,0 +1,111 @@
+"""nauticle_step_cfl: every step's dt = cfl h / (c0 + max |v|) per case,
+computed on the device, against the oracle's CFL rollout (positions,
+velocities and the clock), per case in a batch, and without touching the
+fixed dt later calls on the workspace use."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1710_08259_amd import workloads as WL
+from tests.gpu_common import case_absolute_from_state, f32, nauticle, stack, u32
+from tests.oracle_helpers import domain_of, params_of, v64, x64
+
+pytestmark = pytest.mark.gpu
+
+TOL_ROLLOUT = 5e-4
+# dt = cfl h / (c0 + vmax) is a function of the state: its relative error is
+# that of the rollout's speeds carried through, |dvmax| / (c0 + vmax), plus a
+# few FP32 roundings (the FP32 speed, h and c0 of the device case table)
+TOL_DT_ROUNDING = 1e-6
+
+
+def _by_id(case, st, off):
+    n = case.n
+    sl = slice(off, off + n)
+    ids = u32(st.id)[sl]
+    x = np.empty((n, case.dim))
+    v = np.empty((n, case.dim))
+    x[ids] = case_absolute_from_state(case, u32(st.cell)[sl], np.stack([f32(t)[sl] for t in st.off], 1))
+    v[ids] = np.stack([f32(t)[sl] for t in st.vel], 1)
+    return x, v
+
+
+def _compare(case, x_g, v_g, t_g, dt_g, cfl, steps):
+    dom, prm = domain_of(case), params_of(case)
+    x, v, t, dt = O.step_cfl(dom, prm, x64(case), v64(case), cfl, steps, fixed=case.fixed_mask())
+    moved = np.abs(O.min_image(dom, x - x64(case))).max()
+    err_x = np.abs(O.min_image(dom, x_g - x)).max() / moved
+    err_v = np.abs(v_g - v).max() / np.abs(v).max()
+    err_t = abs(t_g - t) / t
+    err_dt = abs(dt_g - dt) / dt
+    vmax = float(np.sqrt((v ** 2).sum(axis=1)).max())
+    tol_dt = TOL_DT_ROUNDING + 2.0 * err_v * vmax / (case.c0 + vmax)
+    print(f"{case.name} ({case.n} particles), {steps} CFL steps: dt {dt_g:.4e} (oracle {dt:.4e}, {err_dt:.1e}), "
+          f"t {err_t:.1e} (bar {tol_dt:.1e}), x {err_x:.2e} of the largest displacement, v {err_v:.2e}")
+    assert err_t < tol_dt and err_dt < tol_dt
+    assert err_x < TOL_ROLLOUT and err_v < TOL_ROLLOUT
+    return dt
+
+
+def test_cfl_dam_break_matches_the_oracle():
+    """The dam-break shape (walls, gravity) from rest: the first steps take
+    cfl h / c0, then shrink as the column falls."""
+    N = nauticle()
+    case = WL.dam_break_case(dx=0.02)
+    cfl, steps = 0.25, 40
+    prob = N.Problem([case])
+    st = prob.state_from_cases()
+    clock = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+    prob.step_cfl(st, steps, cfl, clock)
+    torch.cuda.synchronize()
+    prob.check()
+    x_g, v_g = _by_id(case, st, 0)
+    t_g, dt_g = clock[0].tolist()
+    dt = _compare(case, x_g, v_g, t_g, dt_g, cfl, steps)
+    assert dt < cfl * case.h / case.c0  # the fall has sped the flow up
+
+
+def test_cfl_batched_cases_each_take_their_own_step():
+    """Cases of different c0, h and speeds in one table: each case's clock
+    and rollout against the oracle's for that case alone."""
+    N = nauticle()
+    cases = [WL.lattice_case(2, (20, 18), 0.01, 1.3, 0.05, 0.3, seed=81, c0=8.0, name="a"),
+             WL.lattice_case(2, (16, 16), 0.012, 1.3, 0.05, 0.05, seed=82, c0=15.0, name="b"),
+             WL.lattice_case(2, (24, 20), 0.008, 1.3, 0.05, 0.6, seed=83, c0=5.0, name="c")]
+    cfl, steps = 0.3, 25
+    prob = N.Problem(cases)
+    st = prob.state_from_cases()
+    clock = torch.zeros((len(cases), 2), dtype=torch.float64, device="cuda")
+    prob.step_cfl(st, steps, cfl, clock)
+    torch.cuda.synchronize()
+    prob.check()
+    offs = np.cumsum([0] + [c.n for c in cases])
+    dts = []
+    for b, c in enumerate(cases):
+        x_g, v_g = _by_id(c, st, offs[b])
+        t_g, dt_g = clock[b].tolist()
+        dts.append(_compare(c, x_g, v_g, t_g, dt_g, cfl, steps))
+    assert len(set(round(d, 12) for d in dts)) == len(cases)
+
+
+def test_cfl_steps_leave_the_workspace_time_step():
+    """After CFL steps, a plain step on the same workspace uses the case's
+    own dt again: bit for bit what a fresh workspace gives."""
+    N = nauticle()
+    case = WL.lattice_case(2, (20, 18), 0.01, 1.3, 0.05, 0.3, seed=84, c0=8.0)
+    prob = N.Problem([case])
+    st = prob.state_from_cases()
+    clock = torch.zeros((1, 2), dtype=torch.float64, device="cuda")
+    prob.step_cfl(st, 3, 0.5, clock)
+    torch.cuda.synchronize()
+    fresh = N.Problem([case])
+    st2 = st.clone()
+    prob.step(st, 2)
+    fresh.step(st2, 2)
+    torch.cuda.synchronize()
+    prob.check()
+    fresh.check()
+    n = case.n
+    np.testing.assert_array_equal(stack(st.off, n).view(np.uint32), stack(st2.off, n).view(np.uint32))
+    np.testing.assert_array_equal(stack(st.vel, n).view(np.uint32), stack(st2.vel, n).view(np.uint32))
