@@ -40,21 +40,22 @@ PEAK_HBM_GBS = 8000.0
 # summarised in profiles/neighbour_kernels_periodic_3d_8388608_traffic.md
 # (scaled by a plain 1 GiB copy); valid only for the search source the
 # counters were taken on, reported as null otherwise.
-NLIST_TRAFFIC_BYTES = 3.394e9
-NLIST_TRAFFIC_SOURCE_SHA256 = "53792ec679911904"
+NLIST_TRAFFIC_BYTES = 3.401e9
+NLIST_TRAFFIC_SOURCE_SHA256 = "b104c3a318614a35"
 
 
 # Issue-slot and vector-L1 figures from the counter runs summarised in
 # profiles/neighbour_kernels_periodic_3d_8388608_issue.md, guarded the same
 # way (by the sources of the kernels they were taken on).
-NLIST_VALU_ISSUE_FRAC = 0.946
-FORCE_L1_ACCESS_RATE = 1.08   # accesses per CU per clock; the vector L1 serves about one
+NLIST_VALU_ISSUE_FRAC = 0.988
+NLIST_VALU_INSTS = 1.339e9    # wave instructions per search launch (SQ_INSTS_VALU)
+FORCE_L1_ACCESS_RATE = 1.06   # accesses per CU per clock; the vector L1 serves about one
 # HBM bytes per density / force launch (FETCH_SIZE x2 + WRITE_SIZE, same
 # runs and guard as the L1 rate), and the force pass's VALU issue fraction.
-DENSITY_TRAFFIC_BYTES = 2.702e9 + 0.403e9
+DENSITY_TRAFFIC_BYTES = 2.706e9 + 0.403e9
 FORCE_TRAFFIC_BYTES = 3.019e9 + 0.369e9
-FORCE_VALU_ISSUE_FRAC = 0.474
-FORCE_SOURCES_SHA256 = "f8cafb7c444e8c70"
+FORCE_VALU_ISSUE_FRAC = 0.467
+FORCE_SOURCES_SHA256 = "cf39b082905f9d8b"
 
 
 def _digest(*rel):
@@ -73,6 +74,14 @@ def nlist_traffic():
 
 def nlist_issue_frac():
     return NLIST_VALU_ISSUE_FRAC if _digest("search.hip", "internal.h") == NLIST_TRAFFIC_SOURCE_SHA256 else None
+
+
+def nlist_lane_slots_per_candidate(candidates):
+    """VALU lane-slots (wave instructions x 64) the search spends per
+    candidate it tests, from the counter run; null for other sources."""
+    if _digest("search.hip", "internal.h") != NLIST_TRAFFIC_SOURCE_SHA256 or not candidates:
+        return None
+    return round(NLIST_VALU_INSTS * 64 / candidates, 2)
 
 
 def force_l1_rate():
@@ -668,6 +677,7 @@ def main():
                 "frac": round(search_tflops / PEAK_FP32_TFLOPS_UNPACKED, 4), "traffic": nlist_traffic(),
                 "peak_published_packed_fp32": PEAK_FP32_TFLOPS,
                 "valu_issue_frac": nlist_issue_frac(),
+                "lane_slots_per_candidate": nlist_lane_slots_per_candidate(cand),
                 "candidates_per_step": cand, "ms": round(phase_ms[1], 4)}
     line = {
         "metric": "particle-pair interactions/s (SPH force pass) + fwd+adjoint steps/s vs plain",

@@ -42,3 +42,15 @@ def test_search_traffic_constant_is_the_summarised_one():
     read, written, total = (float(x) for x in m.groups())
     assert abs(read + written - total) < 2e-3
     assert abs(total * 1e9 - bench.NLIST_TRAFFIC_BYTES) < 1e6
+
+
+def test_lane_slots_per_candidate_is_the_summarised_figure():
+    text = _read("neighbour_kernels_periodic_3d_8388608_issue.md")
+    m = re.search(r"([0-9.]+) lane-slots per candidate", text)
+    assert m, "lane-slot line missing"
+    assert f"{bench.NLIST_VALU_INSTS:.3e}" in text
+    live = bench._digest("search.hip", "internal.h") == bench.NLIST_TRAFFIC_SOURCE_SHA256
+    got = bench.nlist_lane_slots_per_candidate(3.135e9)
+    assert (got is None) == (not live)
+    if live:
+        assert abs(got - float(m.group(1))) < 0.1
