@@ -69,7 +69,8 @@ def test_rollout_gradient_matches_central_differences_3d_262k():
     # v0: along the gradient's own direction, scaled to |v0|.  Along a random
     # direction the loss moves by ~1e-6 of itself, the level of its FP32
     # rounding; element-wise v0 gradients are checked against the FP64
-    # oracle in the 2-D test.
+    # oracle in the 2-D test here and in the 3-D tests of test_gpu_adjoint_3d
+    # (one-step VJP, with and without walls, and a rollout gradient).
     u = gv0 / gv0.norm() * v0.norm()
     fd_v = (ro.loss(case.nu, case.c0, v0 + eps * u, target) - ro.loss(case.nu, case.c0, v0 - eps * u, target)) / (2 * eps)
     ad_v = float((gv0.double() * u.double()).sum())
