@@ -232,8 +232,10 @@ def cpu_single_thread(case):
 
 def cpu_baseline(args, case):
     """The oracle, as it stands, on the main workload itself (or a smaller box
-    of the same lattice recipe, --cpu-sample): one full FP64 step (density,
-    pressure, accelerations, integration) on the host's threads."""
+    of the same lattice recipe, --cpu-sample): full FP64 steps (density,
+    pressure, accelerations, integration) on the host's threads, each from
+    the last one's state, until 10 s have passed (at most 8 steps); each step
+    is credited with the first step's interaction count."""
     import numpy as np
 
     from oracle import oracle as O
@@ -250,12 +252,15 @@ def cpu_baseline(args, case):
     v = sample.vel.astype(np.float64)
     _, _, counts = O.density(dom, prm, x, counts=True, nthreads=threads)
     pairs = int(counts.sum())
-    t0 = time.perf_counter()
-    O.step(dom, prm, x, v, n_steps=1, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": pairs / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
-            "sample": f"one FP64 step of the {side[0]}x{side[1]}x{side[2]} lattice ({sample.n} particles, "
-                      f"{pairs} interactions{'' if sample is case else ', a smaller box of the same recipe'}), "
+    dt, steps = 0.0, 0
+    while dt < 10.0 and steps < 8:
+        t0 = time.perf_counter()
+        x, v, _, _, _ = O.step(dom, prm, x, v, n_steps=1, nthreads=threads)
+        dt += time.perf_counter() - t0
+        steps += 1
+    return {"value": pairs * steps / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the {side[0]}x{side[1]}x{side[2]} lattice ({sample.n} particles, "
+                      f"{pairs} interactions in the first{'' if sample is case else '; a smaller box of the same recipe'}), "
                       f"{dt:.2f} s"}
 
 
