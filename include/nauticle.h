@@ -469,8 +469,9 @@ nauticle_status nauticle_step_cfl(const nauticle_case* cases, int32_t n_cases, n
                                   double cfl, double* clock, void* ws, size_t ws_bytes,
                                   hipStream_t stream);
 
-/* For callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, hosts that forbid hipMalloc): nauticle_step
+/* For callers that cannot allocate device memory (tight serving loops,
+ * hosts that forbid hipMalloc, programs that must not allocate while other
+ * work on the device is being captured into a HIP graph): nauticle_step
  * with the default tuning and no caller workspace.  Its scratch is a fixed
  * array of 64 MiB in the library's device code, one per device, held from
  * the library's load until the process ends; cases needing more scratch
@@ -480,6 +481,8 @@ nauticle_status nauticle_step_cfl(const nauticle_case* cases, int32_t n_cases, n
  * case table into the scratch, enqueues the steps on `stream`, then waits
  * for the stream and returns the most severe condition the kernels
  * flagged (as nauticle_check would), so no separate check call is needed.
+ * Because it waits for the stream, the call itself cannot be recorded while
+ * `stream` is being captured.
  * state, cells and fields as in nauticle_step (caller-owned).  Every call
  * on a device shares that device's scratch, which keeps the last call's
  * contents: calls that overlap on one device (other host threads, other
