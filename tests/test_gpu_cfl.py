@@ -109,3 +109,26 @@ def test_cfl_steps_leave_the_workspace_time_step():
     n = case.n
     np.testing.assert_array_equal(stack(st.off, n).view(np.uint32), stack(st2.off, n).view(np.uint32))
     np.testing.assert_array_equal(stack(st.vel, n).view(np.uint32), stack(st2.vel, n).view(np.uint32))
+
+
+def test_cfl_step_rejects_bad_arguments_and_zero_steps_is_a_no_op():
+    """cfl <= 0, a non-finite cfl and a missing clock are refused on the host
+    with nothing enqueued (state and clock unchanged); zero steps change
+    nothing."""
+    N = nauticle()
+    case = WL.lattice_case(2, (12, 10), 0.01, 1.3, 0.05, 0.3, seed=85, c0=8.0)
+    prob = N.Problem([case])
+    st = prob.state_from_cases()
+    clock = torch.full((1, 2), 7.0, dtype=torch.float64, device="cuda")
+    before = st.clone()
+    for cfl, clk in ((0.0, clock), (-0.25, clock), (float("nan"), clock), (float("inf"), clock), (0.25, None)):
+        with pytest.raises(N.NauticleError) as info:
+            prob.step_cfl(st, 2, cfl, clk)
+        assert info.value.status == N.ERR_INVALID_ARG, (cfl, clk is None)
+    prob.step_cfl(st, 0, 0.25, clock)
+    torch.cuda.synchronize()
+    prob.check()
+    n = case.n
+    np.testing.assert_array_equal(stack(st.off, n).view(np.uint32), stack(before.off, n).view(np.uint32))
+    np.testing.assert_array_equal(stack(st.vel, n).view(np.uint32), stack(before.vel, n).view(np.uint32))
+    assert clock.cpu().tolist() == [[7.0, 7.0]]
