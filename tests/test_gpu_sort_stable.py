@@ -1,0 +1,95 @@
+"""The build's sort gives the stable sort of this build's keys, bit for
+bit, whatever the key and permutation arrays held before: checked against a
+stable argsort after a first build, after few and many particles change cell
+(a step's state, in the last build's order), when nothing changed, and with
+the key array left out of order or all equal."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1710_08259_amd import workloads as WL
+from tests.gpu_common import nauticle, u32
+
+pytestmark = pytest.mark.gpu
+
+
+def _keys(cases, cell):
+    """Each particle's key: its cell plus its case's first cell."""
+    keys = np.empty(len(cell), np.int64)
+    at, base = 0, 0
+    for c in cases:
+        keys[at:at + c.n] = base + cell[at:at + c.n].astype(np.int64)
+        at += c.n
+        base += c.n_cells
+    return keys
+
+
+def _build_and_check(N, prob, cases, st, what):
+    prob.build_cells(st)
+    torch.cuda.synchronize()
+    prob.check()
+    n = prob.n
+    keys = _keys(cases, u32(st.cell)[:n])
+    ref = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(u32(prob.cells.perm)[:n].astype(np.int64), ref, err_msg=what)
+    np.testing.assert_array_equal(u32(prob.cells.key)[:n].astype(np.int64), keys[ref], err_msg=what)
+
+
+def _moved(cases, st, frac, seed, far):
+    """A copy of st with a fraction of each case's particles put in another
+    cell of the same case: a neighbouring cell along x, or anywhere (far)."""
+    out = st.clone()
+    cell = out.cell
+    rng = np.random.default_rng(seed)
+    at = 0
+    for c in cases:
+        k = max(1, int(frac * c.n))
+        idx = at + rng.choice(c.n, size=k, replace=False)
+        cur = u32(cell)[idx].astype(np.int64)
+        if far:
+            new = rng.integers(0, c.n_cells, size=k)
+        else:
+            new = np.clip(cur + rng.choice([-1, 1], size=k), 0, c.n_cells - 1)
+        cell[torch.from_numpy(idx).cuda()] = torch.from_numpy(new.astype(np.int32)).cuda()
+        at += c.n
+    return out
+
+
+def _sparse_3d():
+    """Fewer particles than cells (uniform random points, cells of 2h
+    holding ~0.3 each): the sort orders each tile in LDS before storing."""
+    base = WL.lattice_case(3, (28, 28, 26), 0.01, 0.3, 0.0, 0.05, seed=93, name="sparse_3d")
+    rng = np.random.default_rng(93)
+    pts = rng.uniform(0, 1, (base.n, 3)) * base.length()[:3]
+    return [WL.scaled(base, pos=pts.astype(np.float32))]
+
+
+TABLES = {
+    "lattice_3d": lambda: [WL.lattice_case(3, (40, 37, 33), 0.01, 1.2, 0.05, 0.05, seed=91)],
+    "batched_2d": lambda: WL.batched_2d(n_cases=7, seed=92, max_side_exp=6.5),
+    "sparse_3d": _sparse_3d,
+}
+
+
+@pytest.mark.parametrize("name", list(TABLES))
+def test_sort_is_the_stable_sort_whatever_the_arrays_held(name):
+    N = nauticle()
+    cases = TABLES[name]()
+    # room for the crowding that particles moved to random cells can make
+    prob = N.Problem(cases, max_nbr=256)
+    st = prob.state_from_cases()
+    _build_and_check(N, prob, cases, st, "first build")
+    # the next builds start from the sorted state, as a step leaves it
+    base = prob.sorted.clone()
+    _build_and_check(N, prob, cases, base.clone(), "nothing changed")
+    for frac, far, seed in ((0.001, False, 1), (0.02, False, 2), (0.05, True, 3), (0.5, True, 4)):
+        prob.build_cells(base)  # the last keys: those of the sorted state
+        torch.cuda.synchronize()
+        _build_and_check(N, prob, cases, _moved(cases, base, frac, seed, far), f"{frac} moved, far={far}")
+    # last keys out of order, and all equal
+    n = prob.n
+    rng = np.random.default_rng(5)
+    prob.cells.key[:n] = torch.from_numpy(rng.integers(0, 1 << 20, n).astype(np.int32)).cuda()
+    _build_and_check(N, prob, cases, _moved(cases, base, 0.01, 6, False), "last keys out of order")
+    prob.cells.key[:n] = 0
+    _build_and_check(N, prob, cases, _moved(cases, base, 0.01, 7, False), "last keys all zero")
