@@ -135,7 +135,7 @@ def parse():
     ap.add_argument("--ch-only", action="store_true", help="only the Example 1b Cahn-Hilliard sphere")
     ap.add_argument("--law-only", choices=("dem", "social"), default=None,
                     help="only one pair-law workload (DEM damper or social force room)")
-    ap.add_argument("--only", choices=("adjoint", "batched", "dam_break"), default=None,
+    ap.add_argument("--only", choices=("adjoint", "batched", "dam_break", "paper_shape"), default=None,
                     help="only one extra workload (for profiling runs)")
     ap.add_argument("--batched-tuning", default=None,
                     help="block/persistent/groups_per_cu for the batched workload instead of the autotuner's pick")
@@ -367,6 +367,57 @@ def dam_break_extra(device, steps=10):
     wall, phase, pairs = timed_steps(prob, st, steps, 2)
     return {"workload": case.name, "particles": case.n, "fixed": case.n_fixed, "steps_per_s": steps / wall,
             "interactions_per_s": pairs / wall, "ms_per_step": wall * 1e3 / steps}
+
+
+def paper_shape_extra(device, passes=50):
+    """The shape of the paper's performance benchmark: density-summation
+    passes (nauticle_sph_density, lists built once) on 3-D periodic lattices
+    of 15^3 ... 100^3 sites with h = 1.05 dx, in particles per second per
+    pass, event-timed on the library's stream including each pass's launch
+    from Python.  Beside it, the FP64 oracle's density pass on the 15^3
+    lattice on one host thread.  Context only: the paper's own figure is a
+    CPU's, with an evaluation count it does not state."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as O
+    from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
+
+    out = {"h_over_dx": 1.05, "sizes": []}
+    for side in (15, 22, 47, 100):
+        case = WL.lattice_case(3, (side,) * 3, 0.01, 1.05, 0.0, 0.0, seed=side, name=f"paper_shape_{side}")
+        prob = N.Problem([case], device=device)
+        st = prob.state_from_cases()
+        prob.build_cells(st)
+        for _ in range(3):
+            prob.density()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(passes):
+            prob.density()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        prob.check()
+        ms = e0.elapsed_time(e1) / passes
+        nbr = float(prob.cells.nbr_count[: case.n].sum().item()) / case.n
+        out["sizes"].append({"particles": case.n, "ms_per_pass": round(ms, 5),
+                             "particles_per_s": case.n / (ms * 1e-3), "neighbours_per_particle": round(nbr, 2)})
+        del prob, st
+    case = WL.lattice_case(3, (15,) * 3, 0.01, 1.05, 0.0, 0.0, seed=15)
+    dom = O.Domain(dim=3, n=case.ncell, cs=case.cell_size, origin=case.origin)
+    prm = O.Params(h=case.h, mass=case.mass, rho0=case.rho0, c0=case.c0, gamma=case.gamma, nu=case.nu,
+                   dt=case.dt, g=case.g)
+    x = case.pos.astype(np.float64)
+    reps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < 1.0:
+        O.density(dom, prm, x, nthreads=1)
+        reps += 1
+    out["oracle_15^3_one_thread"] = {"particles_per_s": case.n * reps / (time.perf_counter() - t0),
+                                     "cores": 1, "kind": "oracle"}
+    return out
 
 
 def ex1a_extra(device, scale, steps=10, warmup=2):
@@ -647,7 +698,7 @@ def main():
             b, p, g = (int(v) for v in args.batched_tuning.split("/"))
             tn = N.Tuning(block=b, persistent=p, groups_per_cu=g)
         fn = {"adjoint": lambda: adjoint_extra(device), "batched": lambda: batched_extra(device, tuning=tn),
-              "dam_break": lambda: dam_break_extra(device)}[args.only]
+              "dam_break": lambda: dam_break_extra(device), "paper_shape": lambda: paper_shape_extra(device)}[args.only]
         print(json.dumps({"extra": {args.only: fn()}}), flush=True)
         return
     if args.ex1a_only:
@@ -725,6 +776,8 @@ def main():
         line["extra"]["social"] = law_extra(device, "social")
         torch.cuda.empty_cache()
         line["extra"]["ch"] = ch_extra(device)
+        torch.cuda.empty_cache()
+        line["extra"]["paper_shape"] = paper_shape_extra(device)
         torch.cuda.empty_cache()
         line["extra"]["verlet"] = verlet_extra(device, args.skin_frac, pairs_2h_per_step=pairs_per_step,
                                                plain_ms=wall * 1e3 / args.steps)
