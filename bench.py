@@ -135,7 +135,7 @@ def parse():
     ap.add_argument("--ch-only", action="store_true", help="only the Example 1b Cahn-Hilliard sphere")
     ap.add_argument("--law-only", choices=("dem", "social"), default=None,
                     help="only one pair-law workload (DEM damper or social force room)")
-    ap.add_argument("--only", choices=("adjoint", "batched", "dam_break", "paper_shape"), default=None,
+    ap.add_argument("--only", choices=("adjoint", "batched", "dam_break", "paper_shape", "small"), default=None,
                     help="only one extra workload (for profiling runs)")
     ap.add_argument("--batched-tuning", default=None,
                     help="block/persistent/groups_per_cu for the batched workload instead of the autotuner's pick")
@@ -367,6 +367,45 @@ def dam_break_extra(device, steps=10):
     wall, phase, pairs = timed_steps(prob, st, steps, 2)
     return {"workload": case.name, "particles": case.n, "fixed": case.n_fixed, "steps_per_s": steps / wall,
             "interactions_per_s": pairs / wall, "ms_per_step": wall * 1e3 / steps}
+
+
+def small_extra(device, steps=200, per_graph=20):
+    """The 4,096-particle 2-D periodic lattice, bound by launches rather than
+    by any kernel: ms per step with one nauticle_step call per step from
+    Python, and with per_graph steps captured once in a HIP graph and
+    replayed (the library's launches are all capturable)."""
+    import torch
+
+    from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
+
+    case = WL.periodic_2d_4096()
+    prob = N.Problem([case], device=device)
+    st = prob.state_from_cases()
+    for _ in range(5):
+        prob.step(st, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.step(st, 1)
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / steps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        prob.step(st, per_graph)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = max(steps // per_graph, 1)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph = (time.perf_counter() - t0) / (reps * per_graph)
+    prob.check()
+    pairs = float(prob.cells.nbr_count[: case.n].sum().item())
+    return {"workload": case.name, "particles": case.n, "eager_ms_per_step": round(eager * 1e3, 4),
+            "graph_ms_per_step": round(graph * 1e3, 4), "steps_per_graph": per_graph,
+            "graph_steps_per_s": 1.0 / graph, "graph_interactions_per_s": pairs / graph}
 
 
 def paper_shape_extra(device, passes=50):
@@ -698,7 +737,8 @@ def main():
             b, p, g = (int(v) for v in args.batched_tuning.split("/"))
             tn = N.Tuning(block=b, persistent=p, groups_per_cu=g)
         fn = {"adjoint": lambda: adjoint_extra(device), "batched": lambda: batched_extra(device, tuning=tn),
-              "dam_break": lambda: dam_break_extra(device), "paper_shape": lambda: paper_shape_extra(device)}[args.only]
+              "dam_break": lambda: dam_break_extra(device), "paper_shape": lambda: paper_shape_extra(device),
+              "small": lambda: small_extra(device)}[args.only]
         print(json.dumps({"extra": {args.only: fn()}}), flush=True)
         return
     if args.ex1a_only:
@@ -778,6 +818,8 @@ def main():
         line["extra"]["ch"] = ch_extra(device)
         torch.cuda.empty_cache()
         line["extra"]["paper_shape"] = paper_shape_extra(device)
+        torch.cuda.empty_cache()
+        line["extra"]["small"] = small_extra(device)
         torch.cuda.empty_cache()
         line["extra"]["verlet"] = verlet_extra(device, args.skin_frac, pairs_2h_per_step=pairs_per_step,
                                                plain_ms=wall * 1e3 / args.steps)
