@@ -266,16 +266,22 @@ def cpu_baseline(args, case):
 
 def adjoint_extra(device):
     """Forward and forward+adjoint steps/s of the 262,144-particle 3-D case
-    (one checkpoint segment of 20 steps: forward, then recompute with stored
-    step records and 20 adjoint steps), next to the FP64 oracle's forward +
-    adjoint step on the same case."""
+    over a segment of 20 steps, in the rollout's two modes:
+      - kept records (the default wherever every step's record fits in half
+        the free device memory; a 200-step rollout of this case takes ~31 GB
+        of the 288): the forward pass keeps each step's sorted state, lists
+        and fields, and the reverse sweep runs the adjoint passes only;
+      - checkpoints: plain forward steps, then each segment recomputed with
+        its records before the adjoint passes.
+    Next to them, the FP64 oracle's forward + adjoint step on the same
+    case."""
     import numpy as np
     import torch
 
     from oracle import oracle as O
     from paper_1710_08259_amd import nauticle as N
     from paper_1710_08259_amd import workloads as WL
-    from paper_1710_08259_amd.rollout import _StepRecord
+    from paper_1710_08259_amd.rollout import Rollout, record_bytes
 
     case = WL.periodic_3d_262k()
     prob = N.Problem([case], device=device)
@@ -284,35 +290,39 @@ def adjoint_extra(device):
     prob.step(st, 2)
     torch.cuda.synchronize()
     ck = st.clone()
-    t0 = time.perf_counter()
-    prob.step(st, K)
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
     lam = {"x": [torch.full((prob.n,), 1e-3, device=device) for _ in range(3)],
            "v": [torch.zeros(prob.n, device=device) for _ in range(3)],
            "ox": [torch.empty(prob.n, device=device) for _ in range(3)],
            "ov": [torch.empty(prob.n, device=device) for _ in range(3)]}
     dnu = torch.zeros(1, dtype=torch.float64, device=device)
     dc0 = torch.zeros(1, dtype=torch.float64, device=device)
-    records = [_StepRecord(prob.new_state(), prob.new_cells(), prob.new_fields()) for _ in range(K)]
 
-    def reverse_segment():
+    def timed(fn):
+        fn()  # warm (allocator, modules)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    def plain_forward():
         cur = ck.clone()
-        for rec in records:
-            prob.build_cells(cur, rec.sorted, rec.cells)
-            prob.density(rec.sorted, rec.cells, rec.fields)
-            prob.forces(rec.sorted, cur, rec.cells, rec.fields)
+        prob.step(cur, K)
+
+    def recorded_forward():
+        cur = ck.clone()
+        return Rollout._record_steps(prob, cur, K)
+
+    def sweep(records):
         for rec in reversed(records):
             prob.adjoint(rec.sorted, rec.cells, rec.fields, lam["x"], lam["v"], lam["ox"], lam["ov"], dnu, dc0)
             lam["x"], lam["ox"] = lam["ox"], lam["x"]
             lam["v"], lam["ov"] = lam["ov"], lam["v"]
 
-    reverse_segment()  # warm
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reverse_segment()
-    torch.cuda.synchronize()
-    t_rev = time.perf_counter() - t0
+    t_fwd, _ = timed(plain_forward)
+    t_fwd_rec, records = timed(recorded_forward)
+    t_adj, _ = timed(lambda: sweep(records))
+    t_rev, _ = timed(lambda: sweep(recorded_forward()))  # checkpoint mode: recompute, then sweep
     prob.check()
     # the oracle: one FP64 forward step and one step VJP on the same case
     dom = O.Domain(dim=3, n=case.ncell, cs=case.cell_size, origin=case.origin)
@@ -324,12 +334,17 @@ def adjoint_extra(device):
     O.step(dom, prm, x, v, n_steps=1, nthreads=threads)
     O.step_vjp(dom, prm, x, v, np.ones_like(x), np.zeros_like(v), nthreads=threads)
     t_or = time.perf_counter() - t0
-    fa_sps = K / (t_fwd + t_rev)
-    return {"workload": case.name, "particles": case.n, "checkpoint_every": K,
-            "forward_steps_per_s": K / t_fwd, "adjoint_steps_per_s": K / t_rev,
-            "adjoint_over_forward": t_rev / t_fwd, "fwd_plus_adjoint_steps_per_s": fa_sps,
+    fa_kept = K / (t_fwd_rec + t_adj)
+    fa_ckpt = K / (t_fwd + t_rev)
+    return {"workload": case.name, "particles": case.n, "segment_steps": K,
+            "record_bytes_per_step": record_bytes(prob),
+            "forward_steps_per_s": K / t_fwd, "recorded_forward_steps_per_s": K / t_fwd_rec,
+            "adjoint_steps_per_s": K / t_adj, "adjoint_over_forward": t_adj / t_fwd,
+            "fwd_plus_adjoint_steps_per_s": fa_kept,
+            "checkpointed": {"checkpoint_every": K, "adjoint_with_recompute_steps_per_s": K / t_rev,
+                             "adjoint_over_forward": t_rev / t_fwd, "fwd_plus_adjoint_steps_per_s": fa_ckpt},
             "oracle_fwd_plus_adjoint_steps_per_s": 1.0 / t_or, "oracle_cores": threads,
-            "fwd_plus_adjoint_vs_oracle": fa_sps * t_or}
+            "fwd_plus_adjoint_vs_oracle": fa_kept * t_or}
 
 
 def batched_extra(device, steps=10, tuning=None):

@@ -469,6 +469,17 @@ nauticle_status nauticle_step_cfl(const nauticle_case* cases, int32_t n_cases, n
                                   double cfl, double* clock, void* ws, size_t ws_bytes,
                                   hipStream_t stream);
 
+/* One full step as nauticle_step takes it, keeping what the step's adjoint
+ * (nauticle_sph_adjoint) needs: the sorted input state goes to `sorted`
+ * (caller-owned, the layout of `state`) instead of a workspace copy, the
+ * neighbour structure to `cells` and the fields to `fields`; `state` is
+ * advanced in place.  A differentiable rollout that keeps every step's
+ * record calls this once per step, so that its reverse sweep needs no
+ * recomputation.  Errors as nauticle_step. */
+nauticle_status nauticle_step_record(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
+                                     nauticle_state* sorted, nauticle_cells* cells, nauticle_fields* fields,
+                                     void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* For callers that cannot allocate device memory (tight serving loops,
  * hosts that forbid hipMalloc, programs that must not allocate while other
  * work on the device is being captured into a HIP graph): nauticle_step

@@ -738,11 +738,13 @@ nauticle_status check_step_args(const Plan* P, const nauticle_state* state, int3
 
 // The launch sequence of nauticle_step on a checked plan and workspace.
 nauticle_status run_steps(const Plan* P, nauticle_state* state, int32_t n_steps, nauticle_cells* cells,
-                          nauticle_fields* fields, hipEvent_t* phase_events, void* ws, hipStream_t stream)
+                          nauticle_fields* fields, hipEvent_t* phase_events, void* ws, hipStream_t stream,
+                          nauticle_state* sorted_out = nullptr)
 {
     const bool cont = P->model == NAUTICLE_MODEL_CONTINUITY;
     const StateDev cur = to_dev_model(*P, state);
-    const StateDev tmp = scratch_state(*P, ws);
+    // the sorted copy: the caller's, or the workspace's
+    const StateDev tmp = sorted_out ? to_dev_model(*P, sorted_out) : scratch_state(*P, ws);
     const FieldsDev f = to_dev(fields);
     // build_cells leaves packed positions for density, and density leaves
     // packed fields for forces, so the step needs no separate packing
@@ -831,6 +833,21 @@ nauticle_status nauticle_step(const nauticle_case* cases, int32_t n_cases, nauti
     if (st != NAUTICLE_OK) return st;
     if ((st = check_step_args(P, state, n_steps, cells, fields)) != NAUTICLE_OK) return st;
     return run_steps(P, state, n_steps, cells, fields, phase_events, ws, stream);
+}
+
+nauticle_status nauticle_step_record(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,
+                                     nauticle_state* sorted, nauticle_cells* cells, nauticle_fields* fields,
+                                     void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    const Plan* P;
+    nauticle_status st = plan_for(cases, n_cases, ws, ws_bytes, &P);
+    if (st != NAUTICLE_OK) return st;
+    if ((st = check_step_args(P, state, 1, cells, fields)) != NAUTICLE_OK) return st;
+    const bool cont = P->model == NAUTICLE_MODEL_CONTINUITY;
+    if ((st = check_state(*P, sorted, true, "sorted", cont)) != NAUTICLE_OK) return st;
+    if (P->n_total > 0 && (sorted->cell == state->cell || sorted->id == state->id))
+        return fail(NAUTICLE_ERR_INVALID_ARG, "sorted must not share arrays with state");
+    return run_steps(P, state, 1, cells, fields, nullptr, ws, stream, sorted);
 }
 
 nauticle_status nauticle_step_cfl(const nauticle_case* cases, int32_t n_cases, nauticle_state* state,

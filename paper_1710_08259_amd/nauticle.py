@@ -43,7 +43,7 @@ ENTRY_POINTS = (
     "nauticle_cells_total", "nauticle_workspace_bytes", "nauticle_prepare", "nauticle_bin",
     "nauticle_unbin", "nauticle_unbin_by_id", "nauticle_gather_by_id", "nauticle_build_cells", "nauticle_sph_density", "nauticle_sph_continuity",
     "nauticle_sph_forces",
-    "nauticle_step", "nauticle_step_cfl", "nauticle_step_fixed_scratch", "nauticle_step_verlet", "nauticle_interact", "nauticle_step_law", "nauticle_ch_steps", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
+    "nauticle_step", "nauticle_step_record", "nauticle_step_cfl", "nauticle_step_fixed_scratch", "nauticle_step_verlet", "nauticle_interact", "nauticle_step_law", "nauticle_ch_steps", "nauticle_sph_adjoint", "nauticle_position_loss", "nauticle_check",
     "nauticle_last_error",
 )
 
@@ -161,6 +161,9 @@ def lib():
     L.nauticle_step_cfl.restype = st
     L.nauticle_step_cfl.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), ctypes.c_double, vp, vp,
                                     ctypes.c_size_t, vp]
+    L.nauticle_step_record.restype = st
+    L.nauticle_step_record.argtypes = [P(CCase), i32, P(CState), P(CState), P(CCells), P(CFields), vp,
+                                       ctypes.c_size_t, vp]
     L.nauticle_step_fixed_scratch.restype = st
     L.nauticle_step_fixed_scratch.argtypes = [P(CCase), i32, P(CState), i32, P(CCells), P(CFields), vp]
     L.nauticle_step_verlet.restype = st
@@ -548,6 +551,15 @@ class Problem:
         _check(lib().nauticle_step_cfl(self.table, self.n_cases, ctypes.byref(st.c()), int(n_steps),
                                        ctypes.byref(self.cells.c()), ctypes.byref(self.fields.c()), float(cfl),
                                        _p(clock), *self._ws()), "nauticle_step_cfl")
+        return st
+
+    def step_record(self, st: State, sorted_: State, cells: Cells, fields: Fields) -> State:
+        """One step in place, as step() runs it, leaving the step's sorted
+        input state in `sorted_`, its neighbour structure in `cells` and its
+        fields in `fields` (what the step's adjoint needs)."""
+        _check(lib().nauticle_step_record(self.table, self.n_cases, ctypes.byref(st.c()), ctypes.byref(sorted_.c()),
+                                          ctypes.byref(cells.c()), ctypes.byref(fields.c()), *self._ws()),
+               "nauticle_step_record")
         return st
 
     def step_fixed_scratch(self, st: State, n_steps: int = 1) -> State:

@@ -93,3 +93,27 @@ def test_loss_and_gradient_vanish_at_the_target():
     L, gv0, gnu, gc0 = ro.loss_and_grad(case.nu * 1.5, case.c0 * 0.8, v0, target)
     assert L == 0.0 and gnu == 0.0 and gc0 == 0.0
     assert torch.count_nonzero(gv0).item() == 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_kept_records_and_checkpoints_give_the_same_gradients(dim):
+    """The forward pass's kept records and the checkpointed recomputation
+    feed the reverse sweep the same step records: loss and gradients agree
+    bit for bit."""
+    nauticle()
+    from paper_1710_08259_amd.rollout import Rollout
+
+    if dim == 2:
+        case = WL.lattice_case(2, (24, 22), 0.01, 1.3, 0.05, 0.2, seed=97)
+    else:
+        case = WL.lattice_case(3, (14, 13, 12), 0.01, 1.2, 0.05, 0.05, seed=98)
+    v0 = torch.from_numpy(case.vel).cuda()
+    out = {}
+    for keep in (True, False):
+        ro = Rollout(case, 23, checkpoint_every=5, keep_records=keep)
+        target = _target(ro, case)
+        L, gv0, gnu, gc0 = ro.loss_and_grad(case.nu * 1.2, case.c0 * 0.9, v0, target)
+        out[keep] = (L, gv0.cpu().numpy(), gnu, gc0)
+    a, b = out[True], out[False]
+    assert a[0] == b[0] and a[2] == b[2] and a[3] == b[3]
+    np.testing.assert_array_equal(a[1], b[1])

@@ -292,6 +292,43 @@ def test_step_equals_separate_passes_bitwise(name):
         np.testing.assert_array_equal(f32(a)[:n].view(np.uint32), f32(b)[:n].view(np.uint32))
 
 
+@pytest.mark.parametrize("name", ["periodic_3d_ragged", "dam_break_small"])
+def test_step_record_equals_step_and_keeps_the_step(name):
+    """nauticle_step_record advances the state as nauticle_step does, bit for
+    bit, and leaves the step's sorted input state, keys, permutation, lists
+    and fields where the caller asked (equal to those of the separate
+    entry points)."""
+    N = nauticle()
+    case = CASES[name]
+    mx = MAX_NBR.get(case.name)
+    whole = N.Problem([case], max_nbr=mx)
+    st = whole.state_from_cases()
+    whole.step(st, 1)
+    rec = N.Problem([case], max_nbr=mx)
+    st_r = rec.state_from_cases()
+    srt, cells, fields = rec.new_state(), rec.new_cells(), rec.new_fields()
+    rec.step_record(st_r, srt, cells, fields)
+    sep = N.Problem([case], max_nbr=mx)
+    sep.build_cells(sep.state_from_cases())
+    torch.cuda.synchronize()
+    whole.check()
+    rec.check()
+    sep.check()
+    n = case.n
+    np.testing.assert_array_equal(u32(st.cell)[:n], u32(st_r.cell)[:n])
+    for a, b in zip(st.off + st.vel, st_r.off + st_r.vel):
+        np.testing.assert_array_equal(f32(a)[:n].view(np.uint32), f32(b)[:n].view(np.uint32))
+    for a, b in [(whole.fields.rho, fields.rho), (whole.fields.p, fields.p)] + list(zip(whole.fields.acc, fields.acc)):
+        np.testing.assert_array_equal(f32(a)[:n].view(np.uint32), f32(b)[:n].view(np.uint32))
+    for field in ("key", "perm", "nbr_count"):
+        np.testing.assert_array_equal(u32(getattr(cells, field))[:n], u32(getattr(sep.cells, field))[:n])
+    np.testing.assert_array_equal(u32(srt.cell)[:n], u32(sep.sorted.cell)[:n])
+    for a, b in zip(srt.off + srt.vel, sep.sorted.off + sep.sorted.vel):
+        np.testing.assert_array_equal(f32(a)[:n].view(np.uint32), f32(b)[:n].view(np.uint32))
+    with pytest.raises(N.NauticleError):  # the sorted copy may not be the state itself
+        rec.step_record(st_r, st_r, cells, fields)
+
+
 def test_steps_are_deterministic():
     N = nauticle()
     case = CASES["periodic_3d_ragged"]
