@@ -224,10 +224,11 @@ class NauticleRollout(torch.autograd.Function):
     """r_T = NauticleRollout.apply(v0, nu, c0, rollout): the final absolute
     FP32 positions ((n, dim), particle id order) of ``rollout``'s n_steps,
     differentiable in v0 ((n, dim) float32, id order), nu and c0 (0-d
-    tensors).  The forward pass keeps only the checkpoints; the backward
-    pass seeds the positions' cotangent from grad_output (brought into the
-    final state's order by the library), recomputes each segment and runs
-    the hand-written adjoint.  Any loss built on r_T composes with it.  A
+    tensors).  The forward pass keeps every step's record, or only
+    checkpoints (``rollout.keep_records``); the backward pass seeds the
+    positions' cotangent from grad_output (brought into the final state's
+    order by the library), recomputes the segments if only checkpoints were
+    kept, and runs the hand-written adjoint.  Any loss built on r_T composes with it.  A
     particle that left the box across a periodic face comes back shifted by
     a box length; the shift has derivative one."""
 
