@@ -619,7 +619,7 @@ def law_tuning(case, max_nbr, device, force):
     if LAW_TUNING is not None:
         return LAW_TUNING, {}
 
-    cands = (N.Tuning(), N.Tuning(block=128), N.Tuning(block=64), N.Tuning(block=128, persistent=1, groups_per_cu=4))
+    cands = (N.Tuning(), N.Tuning(block=128), N.Tuning(block=64), N.Tuning(block=128, persistent=1, groups_per_cu=0))
     cache = os.environ.get("NAUTICLE_TUNING_CACHE", os.path.join(tempfile.gettempdir(), "nauticle_tuning.json"))
     best, timings = autotune.tune([case], steps=3, candidates=cands, cache_path=cache, device=device, force=force,
                                   max_nbr=max_nbr)
