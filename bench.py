@@ -385,8 +385,9 @@ def dam_break_extra(device, steps=10):
 
 
 def small_extra(device, steps=200, per_graph=20):
-    """The 4,096-particle 2-D periodic lattice, bound by launches rather than
-    by any kernel: ms per step with one nauticle_step call per step from
+    """The 4,096-particle 2-D periodic lattice, bound by the latency of its
+    kernels rather than by any one of them, in the launch shape the
+    autotuner picks: ms per step with one nauticle_step call per step from
     Python, and with per_graph steps captured once in a HIP graph and
     replayed (the library's launches are all capturable)."""
     import torch
@@ -394,8 +395,12 @@ def small_extra(device, steps=200, per_graph=20):
     from paper_1710_08259_amd import nauticle as N
     from paper_1710_08259_amd import workloads as WL
 
+    from paper_1710_08259_amd import autotune
+
     case = WL.periodic_2d_4096()
-    prob = N.Problem([case], device=device)
+    cache = os.environ.get("NAUTICLE_TUNING_CACHE", os.path.join(tempfile.gettempdir(), "nauticle_tuning.json"))
+    best, timings = autotune.tune([case], steps=5, cache_path=cache, device=device, force=True)
+    prob = N.Problem([case], device=device, tuning=best)
     st = prob.state_from_cases()
     for _ in range(5):
         prob.step(st, 1)
@@ -418,7 +423,10 @@ def small_extra(device, steps=200, per_graph=20):
     graph = (time.perf_counter() - t0) / (reps * per_graph)
     prob.check()
     pairs = float(prob.cells.nbr_count[: case.n].sum().item())
-    return {"workload": case.name, "particles": case.n, "eager_ms_per_step": round(eager * 1e3, 4),
+    return {"workload": case.name, "particles": case.n, "tuning": best.__dict__,
+            "tuning_ms_per_step": {f"{t.block}/{t.persistent}/{t.groups_per_cu}": round(v, 4)
+                                   for t, v in (timings or {}).items()},
+            "eager_ms_per_step": round(eager * 1e3, 4),
             "graph_ms_per_step": round(graph * 1e3, 4), "steps_per_graph": per_graph,
             "graph_steps_per_s": 1.0 / graph, "graph_interactions_per_s": pairs / graph}
 

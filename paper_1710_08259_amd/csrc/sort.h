@@ -14,7 +14,7 @@ constexpr uint32_t kSortBins = 256;   // digits of at most 8 bits
 // Number of digit passes for keys of `bits` bits (passes of at most 8 bits,
 // balanced).  The sorted pairs land in buffer (passes % 2) of the ping-pong
 // pair below.
-inline int radix_passes(int bits) { return (bits + 7) / 8; }
+__host__ __device__ inline int radix_passes(int bits) { return (bits + 7) / 8; }
 
 // Sorts the n pairs (keys[0][i], vals[0][i]) by the low `bits` bits of the
 // key, stably, ping-ponging between buffers 0 and 1; the result is in buffer

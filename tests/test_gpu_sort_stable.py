@@ -2,7 +2,8 @@
 bit, whatever the key and permutation arrays held before: checked against a
 stable argsort after a first build, after few and many particles change cell
 (a step's state, in the last build's order), when nothing changed, and with
-the key array left out of order or all equal."""
+the key array left out of order or all equal; for tables of one sort tile
+and larger."""
 import numpy as np
 import pytest
 import torch
@@ -64,10 +65,25 @@ def _sparse_3d():
     return [WL.scaled(base, pos=pts.astype(np.float32))]
 
 
+def _sparse_small_3d():
+    """Fewer particles than cells in a table of one sort tile."""
+    base = WL.lattice_case(3, (10, 10, 9), 0.01, 0.3, 0.0, 0.05, seed=94, name="sparse_small_3d")
+    rng = np.random.default_rng(94)
+    pts = rng.uniform(0, 1, (base.n, 3)) * base.length()[:3]
+    return [WL.scaled(base, pos=pts.astype(np.float32))]
+
+
+# Tables of at most one sort tile (4096 keys) are sorted by one workgroup,
+# larger ones pass by pass: both sides of that edge are here.
 TABLES = {
     "lattice_3d": lambda: [WL.lattice_case(3, (40, 37, 33), 0.01, 1.2, 0.05, 0.05, seed=91)],
     "batched_2d": lambda: WL.batched_2d(n_cases=7, seed=92, max_side_exp=6.5),
     "sparse_3d": _sparse_3d,
+    "tile_3d_2431": lambda: [WL.lattice_case(3, (11, 13, 17), 0.01, 1.2, 0.05, 0.05, seed=95)],
+    "tile_2d_4096": lambda: [WL.lattice_case(2, (64, 64), 0.01, 1.3, 0.05, 0.05, seed=96)],
+    "over_a_tile_2d_4097": lambda: [WL.lattice_case(2, (17, 241), 0.01, 1.3, 0.05, 0.05, seed=97)],
+    "tile_batched_2d": lambda: WL.batched_2d(n_cases=3, seed=98, max_side_exp=5.0),
+    "tile_sparse_3d": _sparse_small_3d,
 }
 
 
