@@ -224,118 +224,35 @@ k_rs_scatter(const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ 
     }
 }
 
-// A table of at most one tile: one workgroup runs every digit pass in LDS.
-// Keys ping-pong between two LDS arrays with each one's place in the input
-// (16 bits: a tile holds at most 4096), ranked per pass as in k_rs_scatter
-// (ballots within a wave, counts across the waves of an iteration, a
-// running place per digit); the values are gathered once at the end.  The
-// output buffers may be the input ones.
-// Separate launches of the three pass kernels would each cost a launch and
-// leave all but one CU idle.
-constexpr int kTileThreads = 1024;
-constexpr int kTileWaves = kTileThreads / kWave;
-constexpr int kTileIters = static_cast<int>(kSortTile) / kTileThreads;
-static_assert(kTileIters * kTileThreads == static_cast<int>(kSortTile), "a tile is a whole number of rows");
-
+// A table of at most one tile: one workgroup sorts it in LDS (tile_sort in
+// sort.h) and gathers the values once at the end.  The output buffers may be
+// the input ones.  Separate launches of the three pass kernels would each
+// cost a launch and leave all but one CU idle.
 __global__ void __launch_bounds__(kTileThreads)
 k_rs_tile(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t n, int bits, uint32_t* keys_out,
           uint32_t* vals_out)
 {
-    __shared__ uint32_t s_key[2][kSortTile];
-    __shared__ uint16_t s_idx[2][kSortTile];
-    __shared__ uint16_t wave_cnt[kTileWaves][kSortBins];
-    __shared__ uint32_t next[kSortBins];
-    __shared__ uint32_t tmp[kSortBins / kWave];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = __lane_id();
-    const uint32_t wave = tid / kWave;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    for (uint32_t i = tid; i < n; i += kTileThreads) {
-        s_key[0][i] = keys_in[i];
-        s_idx[0][i] = static_cast<uint16_t>(i);
+    __shared__ TileSort sm;
+    for (uint32_t i = threadIdx.x; i < n; i += kTileThreads) {
+        sm.key[0][i] = keys_in[i];
+        sm.idx[0][i] = static_cast<uint16_t>(i);
     }
-    const int passes = radix_passes(bits);
-    const int per = (bits + passes - 1) / passes;
-    int src = 0;
-    for (int pass = 0; pass < passes; ++pass) {
-        const int shift = pass * per;
-        const int b = (bits - shift) < per ? (bits - shift) : per;
-        const uint32_t mask = (1u << b) - 1u;
-        for (uint32_t d = tid; d < kSortBins; d += kTileThreads) next[d] = 0;
-        for (uint32_t x = tid; x < kTileWaves * kSortBins; x += kTileThreads) (&wave_cnt[0][0])[x] = 0;
-        __syncthreads();
-        for (uint32_t i = tid; i < n; i += kTileThreads) atomicAdd(&next[(s_key[src][i] >> shift) & mask], 1u);
-        __syncthreads();
-        // digit counts -> where each digit's keys start (exclusive scan)
-        uint32_t c = 0, inc = 0;
-        if (tid < kSortBins) {
-            c = next[tid];
-            inc = c;
-#pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                const uint32_t o = __shfl_up(inc, d, kWave);
-                if (lane >= static_cast<uint32_t>(d)) inc += o;
-            }
-            if (lane == kWave - 1) tmp[wave] = inc;
-        }
-        __syncthreads();
-        if (tid < kSortBins) {
-            uint32_t before = 0;
-            for (uint32_t w = 0; w < wave; ++w) before += tmp[w];
-            next[tid] = before + inc - c;
-        }
-        __syncthreads();
-        for (int k = 0; k < kTileIters; ++k) {
-            const uint32_t i = k * kTileThreads + tid;
-            const bool valid = i < n;
-            const uint32_t key = valid ? s_key[src][i] : 0u;
-            const uint16_t idx = valid ? s_idx[src][i] : uint16_t{0};
-            const uint32_t d = (key >> shift) & mask;
-            uint64_t peers = __ballot(valid);
-            for (int bb = 0; bb < b; ++bb) {
-                const bool bit = (d >> bb) & 1u;
-                const uint64_t m = __ballot(bit);
-                peers &= bit ? m : ~m;
-            }
-            const uint32_t rank = __popcll(peers & lt_mask);
-            if (valid && rank == 0) wave_cnt[wave][d] = static_cast<uint16_t>(__popcll(peers));
-            __syncthreads();
-            if (valid) {
-                uint32_t at = next[d] + rank;
-                for (uint32_t w = 0; w < wave; ++w) at += wave_cnt[w][d];
-                if (at < kSortTile) {  // always, for a consistent count; keeps the stores inside
-                    s_key[1 - src][at] = key;
-                    s_idx[1 - src][at] = idx;
-                }
-            }
-            __syncthreads();
-            for (uint32_t dd = tid; dd < kSortBins; dd += kTileThreads) {
-                uint32_t add = 0;
-                for (int w = 0; w < kTileWaves; ++w) {
-                    add += wave_cnt[w][dd];
-                    wave_cnt[w][dd] = 0;
-                }
-                next[dd] += add;
-            }
-            __syncthreads();
-        }
-        src = 1 - src;
-    }
+    const int src = tile_sort(sm, n, bits);
     // the output may be the input (an even number of passes): every value
     // is read before any is stored
     uint32_t v[kTileIters];
 #pragma unroll
     for (int k = 0; k < kTileIters; ++k) {
-        const uint32_t i = k * kTileThreads + tid;
-        const uint32_t from = i < n ? s_idx[src][i] : 0u;
+        const uint32_t i = k * kTileThreads + threadIdx.x;
+        const uint32_t from = i < n ? sm.idx[src][i] : 0u;
         v[k] = i < n ? vals_in[from < n ? from : 0u] : 0u;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kTileIters; ++k) {
-        const uint32_t i = k * kTileThreads + tid;
+        const uint32_t i = k * kTileThreads + threadIdx.x;
         if (i < n) {
-            keys_out[i] = s_key[src][i];
+            keys_out[i] = sm.key[src][i];
             vals_out[i] = v[k];
         }
     }

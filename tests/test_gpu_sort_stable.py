@@ -34,6 +34,22 @@ def _build_and_check(N, prob, cases, st, what):
     ref = np.argsort(keys, kind="stable")
     np.testing.assert_array_equal(u32(prob.cells.perm)[:n].astype(np.int64), ref, err_msg=what)
     np.testing.assert_array_equal(u32(prob.cells.key)[:n].astype(np.int64), keys[ref], err_msg=what)
+    # the cell table: each cell's sorted range, empty cells marked
+    nc = sum(c.n_cells for c in cases)
+    cells = np.arange(nc)
+    lo = np.searchsorted(keys[ref], cells, side="left")
+    hi = np.searchsorted(keys[ref], cells, side="right")
+    empty = np.uint32(0xFFFFFFFF)
+    np.testing.assert_array_equal(u32(prob.cells.cell_start)[:nc], np.where(hi > lo, lo, empty).astype(np.uint32),
+                                  err_msg=what)
+    np.testing.assert_array_equal(u32(prob.cells.cell_end)[:nc], np.where(hi > lo, hi, empty).astype(np.uint32),
+                                  err_msg=what)
+    # the reordered state
+    np.testing.assert_array_equal(u32(prob.sorted.cell)[:n], u32(st.cell)[:n][ref], err_msg=what)
+    np.testing.assert_array_equal(u32(prob.sorted.id)[:n], u32(st.id)[:n][ref], err_msg=what)
+    for k in range(cases[0].dim):
+        np.testing.assert_array_equal(u32(prob.sorted.off[k])[:n], u32(st.off[k])[:n][ref], err_msg=what)
+        np.testing.assert_array_equal(u32(prob.sorted.vel[k])[:n], u32(st.vel[k])[:n][ref], err_msg=what)
 
 
 def _moved(cases, st, frac, seed, far):
@@ -73,8 +89,19 @@ def _sparse_small_3d():
     return [WL.scaled(base, pos=pts.astype(np.float32))]
 
 
-# Tables of at most one sort tile (4096 keys) are sorted by one workgroup,
-# larger ones pass by pass: both sides of that edge are here.
+def _sparse_many_cells_3d():
+    """A table of one sort tile with more cells than the one-workgroup build
+    takes: the general path, with the one-tile sort."""
+    base = WL.lattice_case(3, (10, 10, 9), 0.01, 0.1, 0.0, 0.05, seed=99, name="sparse_many_cells_3d")
+    rng = np.random.default_rng(99)
+    pts = rng.uniform(0, 1, (base.n, 3)) * base.length()[:3]
+    return [WL.scaled(base, pos=pts.astype(np.float32))]
+
+
+# Tables of at most one sort tile (4096 keys) and 8192 cells are built by one
+# workgroup; larger ones take the general path, whose sort runs one tile in
+# one workgroup and more tiles pass by pass: all sides of those edges are
+# here.
 TABLES = {
     "lattice_3d": lambda: [WL.lattice_case(3, (40, 37, 33), 0.01, 1.2, 0.05, 0.05, seed=91)],
     "batched_2d": lambda: WL.batched_2d(n_cases=7, seed=92, max_side_exp=6.5),
@@ -84,6 +111,7 @@ TABLES = {
     "over_a_tile_2d_4097": lambda: [WL.lattice_case(2, (17, 241), 0.01, 1.3, 0.05, 0.05, seed=97)],
     "tile_batched_2d": lambda: WL.batched_2d(n_cases=3, seed=98, max_side_exp=5.0),
     "tile_sparse_3d": _sparse_small_3d,
+    "tile_many_cells_3d": _sparse_many_cells_3d,
 }
 
 
