@@ -58,12 +58,16 @@ constexpr uint32_t kAdjGroup = 4;
 
 }  // namespace
 
-// A_i = dt (lam_v'_i + dt lam_x'_i) for fluid particles, 0 for fixed ones.
+// A_i = dt (lam_v'_i + dt lam_x'_i) for fluid particles, 0 for fixed ones,
+// stored with the particle's offsets (from a4) as pass A gathers them: the
+// offsets and A_x in one 16-byte record, A_y and A_z in an 8-byte one.  Pass
+// A reads neither s_j nor a fourth word of A, so a neighbour takes 10
+// registers in its pipeline instead of 12.
 __global__ void __launch_bounds__(kMaxBlock)
 k_adj_prep(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, StateDev st,
            const float* __restrict__ lxn0, const float* __restrict__ lxn1, const float* __restrict__ lxn2,
            const float* __restrict__ lvn0, const float* __restrict__ lvn1, const float* __restrict__ lvn2,
-           float4* __restrict__ adj4)
+           const float4* __restrict__ a4, float4* __restrict__ adj4, float2* __restrict__ adj2)
 {
     const uint32_t ix = xcd_item(n_items);
     if (ix >= n_items) return;
@@ -79,13 +83,15 @@ k_adj_prep(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ui
         if (k >= C.dim) break;
         A[k] = fixed ? 0.0f : C.dt * fmaf(C.dt, lx[k][i], lv[k][i]);
     }
-    adj4[i] = make_float4(A[0], A[1], A[2], 0.0f);
+    const float4 o = a4[i];
+    adj4[i] = make_float4(o.x, o.y, o.z, A[0]);
+    adj2[i] = make_float2(A[1], A[2]);
 }
 
 // Pass A.
 __global__ void __launch_bounds__(kMaxBlock)
 k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
-        const float4* __restrict__ a4, const float4* __restrict__ b4, const float4* __restrict__ adj4,
+        const float4* __restrict__ b4, const float4* __restrict__ adj4, const float2* __restrict__ adj2,
         const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count, uint32_t max_nbr,
         uint32_t n_total, FieldsDev f, const uint32_t* __restrict__ perm, const float* __restrict__ lxn0,
         const float* __restrict__ lxn1, const float* __restrict__ lxn2, const float* __restrict__ lvn0,
@@ -104,25 +110,29 @@ k_adj_a(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
             const uint32_t i = it.first + threadIdx.x;
             const int dim = C.dim;
             const bool fixed = st.id[i] >= C.n_fluid;
-            const float4 ai = a4[i], bi = b4[i], Ai = adj4[i];
+            const float4 oi = adj4[i], bi = b4[i];
+            const float2 Ayz = adj2[i];
+            const float4 ai = make_float4(oi.x, oi.y, oi.z, 0.0f);
+            const float4 Ai = make_float4(oi.w, Ayz.x, Ayz.y, 0.0f);
             const float m = C.m, mnu = C.m * C.nu;
             uint32_t cnt = nbr_count[i];
             if (cnt > max_nbr) cnt = max_nbr;
             float sbar = 0.0f, kbar = 0.0f, nubar = 0.0f;
             float vvx = 0.0f, vvy = 0.0f, vvz = 0.0f;
-            const __amdgpu_buffer_rsrc_t ra = float4_rsrc(a4, n_total), rb = float4_rsrc(b4, n_total),
-                                         rA = float4_rsrc(adj4, n_total);
+            const __amdgpu_buffer_rsrc_t ro = float4_rsrc(adj4, n_total), rb = float4_rsrc(b4, n_total);
+            const __amdgpu_buffer_rsrc_t r2 = float2_rsrc(adj2, n_total);
             walk_pairs<kAdjGroup, 3>(
                 nbr, i, cnt, n_total, dim,
                 [&](uint32_t e, float4* v) {
-                    v[0] = gather4(ra, e);
+                    v[0] = gather4(ro, e);  // offsets, A_x
                     v[1] = gather4(rb, e);
-                    v[2] = gather4(rA, e);
+                    const float2 yz = gather2(r2, e);
+                    v[2] = make_float4(yz.x, yz.y, 0.0f, 0.0f);
                 },
                 [&](uint32_t, const float4* v, uint32_t code) {
-                    const float4& aj = v[0];
+                    const float4 aj = make_float4(v[0].x, v[0].y, v[0].z, 0.0f);
                     const float4& bj = v[1];
-                    const float4& Aj = v[2];
+                    const float4 Aj = make_float4(v[0].w, v[2].x, v[2].y, 0.0f);
                     const float3 d = adj_d(C, code, aj, ai);
                     const float q = pair_sqrt(adj_r2(d, dim)) * C.inv_h;
                     const float t = fmaxf(1.0f - 0.5f * q, 0.0f);
@@ -293,10 +303,10 @@ hipError_t launch_adjoint(const Plan& P, void* ws, StateDev sorted, const nautic
     hipError_t e = launch_pack_fields(P, ws, sorted, f, s);
     if (e != hipSuccess) return e;
     k_adj_prep<<<grid, P.block, 0, s>>>(cases, items, P.n_items, sorted, lxn[0], lxn[1], lxn[2], lvn[0], lvn[1],
-                                        lvn[2], pk.adj4);
+                                        lvn[2], pk.a4, pk.adj4, pk.adj2);
     ItemQueue Qa, Qb;
     if ((e = item_queue(P, ws, 3, s, &Qa)) != hipSuccess) return e;
-    k_adj_a<<<grid_for(P, reinterpret_cast<const void*>(&k_adj_a)), P.block, 0, s>>>(cases, items, Qa, sorted, pk.a4, pk.b4, pk.adj4, cells.nbr,
+    k_adj_a<<<grid_for(P, reinterpret_cast<const void*>(&k_adj_a)), P.block, 0, s>>>(cases, items, Qa, sorted, pk.b4, pk.adj4, pk.adj2, cells.nbr,
                                             cells.nbr_count, mx, P.n_total, f, cells.perm, lxn[0], lxn[1], lxn[2],
                                             lvn[0], lvn[1], lvn[2], lv[0], lv[1], lv[2], pk.adj4b, partial);
     if ((e = item_queue(P, ws, 4, s, &Qb)) != hipSuccess) return e;

@@ -293,6 +293,7 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     L.a4 = take(16 * N);
     L.b4 = take(16 * N);
     L.adj4 = take(16 * N);
+    L.adj2 = take(8 * N);
     L.adj4b = take(16 * N);
     L.vr4 = model0 == NAUTICLE_MODEL_CONTINUITY ? take(16 * N) : 0;
     L.chmax = take(sizeof(float) * n_items_max);

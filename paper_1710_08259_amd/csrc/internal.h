@@ -119,7 +119,8 @@ struct Layout {
     size_t pos4;         // float4 per sorted particle: offsets, bits of the cell's x index
     size_t a4;           // float4: offsets, s = p / rho^2
     size_t b4;           // float4: velocity (0 for fixed particles), 1 / rho
-    size_t adj4;         // float4: adjoint A = dt (lam_v' + dt lam_x'), 0
+    size_t adj4;         // float4: offsets, A_x of the adjoint A = dt (lam_v' + dt lam_x')
+    size_t adj2;         // float2: A_y, A_z
     size_t adj4b;        // float4: A, rhobar (after adjoint pass A)
     size_t vr4;          // float4: velocity (0 for fixed), 1 / rho of the step's start (continuity model)
     size_t chmax;        // per-item max |cdot| (Cahn-Hilliard)
@@ -139,6 +140,7 @@ struct Packed {
     float4* adj4b;
     uint32_t* cell_first;
     float4* vr4;
+    float2* adj2;
 };
 
 // Everything derived from a case table.
@@ -170,7 +172,7 @@ inline Packed packed(const Plan& P, void* ws)
 {
     return Packed{at<float4>(ws, P.L.pos4),  at<float4>(ws, P.L.a4),    at<float4>(ws, P.L.b4),
                   at<float4>(ws, P.L.adj4),  at<float4>(ws, P.L.adj4b), at<uint32_t>(ws, P.L.cell_first),
-                  P.L.vr4 ? at<float4>(ws, P.L.vr4) : nullptr};
+                  P.L.vr4 ? at<float4>(ws, P.L.vr4) : nullptr, at<float2>(ws, P.L.adj2)};
 }
 
 // How a neighbour-loop kernel finds its work items.  A persistent launch

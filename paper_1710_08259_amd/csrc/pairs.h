@@ -100,6 +100,17 @@ __device__ inline float4 gather4(__amdgpu_buffer_rsrc_t r, uint32_t e)
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (e & kIndexMask) << 4, 0, 0));
 }
 
+// The same for 8-byte records (the descriptor from float2_rsrc).
+__device__ inline __amdgpu_buffer_rsrc_t float2_rsrc(const float2* p, uint32_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(p), 0, static_cast<int32_t>(n * 8u), 0x00020000);
+}
+
+__device__ inline float2 gather2(__amdgpu_buffer_rsrc_t r, uint32_t e)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (e & kIndexMask) << 3, 0, 0));
+}
+
 // Entries k .. k + G - 1 of particle i's list (k a multiple of G, G a
 // multiple of the four-entry chunk): one 16-byte load per chunk, and the 64
 // lanes of a wave read 64 adjacent chunks.  Chunks at or past the particle's
