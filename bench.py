@@ -40,22 +40,22 @@ PEAK_HBM_GBS = 8000.0
 # summarised in profiles/neighbour_kernels_periodic_3d_8388608_traffic.md
 # (scaled by a plain 1 GiB copy); valid only for the search source the
 # counters were taken on, reported as null otherwise.
-NLIST_TRAFFIC_BYTES = 3.401e9
-NLIST_TRAFFIC_SOURCE_SHA256 = "45ae8b5d034d1c37"
+NLIST_TRAFFIC_BYTES = 3.402e9
+NLIST_TRAFFIC_SOURCE_SHA256 = "3b75b7c21e8db112"
 
 
 # Issue-slot and vector-L1 figures from the counter runs summarised in
 # profiles/neighbour_kernels_periodic_3d_8388608_issue.md, guarded the same
 # way (by the sources of the kernels they were taken on).
-NLIST_VALU_ISSUE_FRAC = 0.984
+NLIST_VALU_ISSUE_FRAC = 0.990
 NLIST_VALU_INSTS = 1.339e9    # wave instructions per search launch (SQ_INSTS_VALU)
-FORCE_L1_ACCESS_RATE = 1.05   # accesses per CU per clock; the vector L1 serves about one
+FORCE_L1_ACCESS_RATE = 1.06   # accesses per CU per clock; the vector L1 serves about one
 # HBM bytes per density / force launch (FETCH_SIZE x2 + WRITE_SIZE, same
 # runs and guard as the L1 rate), and the force pass's VALU issue fraction.
 DENSITY_TRAFFIC_BYTES = 2.706e9 + 0.403e9
 FORCE_TRAFFIC_BYTES = 3.019e9 + 0.369e9
 FORCE_VALU_ISSUE_FRAC = 0.467
-FORCE_SOURCES_SHA256 = "cf39b082905f9d8b"
+FORCE_SOURCES_SHA256 = "fc084a524de1e5fd"
 
 
 def _digest(*rel):
