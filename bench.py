@@ -41,15 +41,15 @@ PEAK_HBM_GBS = 8000.0
 # (scaled by a plain 1 GiB copy); valid only for the search source the
 # counters were taken on, reported as null otherwise.
 NLIST_TRAFFIC_BYTES = 3.402e9
-NLIST_TRAFFIC_SOURCE_SHA256 = "3b75b7c21e8db112"
+NLIST_TRAFFIC_SOURCE_SHA256 = "289e068b0f381b81"
 
 
 # Issue-slot and vector-L1 figures from the counter runs summarised in
 # profiles/neighbour_kernels_periodic_3d_8388608_issue.md, guarded the same
 # way (by the sources of the kernels they were taken on).
-NLIST_VALU_ISSUE_FRAC = 0.990
+NLIST_VALU_ISSUE_FRAC = 0.987
 NLIST_VALU_INSTS = 1.339e9    # wave instructions per search launch (SQ_INSTS_VALU)
-FORCE_L1_ACCESS_RATE = 1.06   # accesses per CU per clock; the vector L1 serves about one
+FORCE_L1_ACCESS_RATE = 1.04   # accesses per CU per clock; the vector L1 serves about one
 # HBM bytes per density / force launch (FETCH_SIZE x2 + WRITE_SIZE, same
 # runs and guard as the L1 rate), and the force pass's VALU issue fraction.
 DENSITY_TRAFFIC_BYTES = 2.706e9 + 0.403e9

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "search.hip", "sort.hip", "sph.hip", "adjoint.hip", "interact.hip", "ch.hip", "verlet.hip"]
+SOURCES = ["api.hip", "search.hip", "sort.hip", "tile.hip", "sph.hip", "adjoint.hip", "interact.hip", "ch.hip", "verlet.hip"]
 OUT = os.path.join(HERE, "libnauticle.so")
 ARCH = os.environ.get("NAUTICLE_ARCH", "gfx950")
 

@@ -725,153 +725,6 @@ k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQ
 }
 
 // ----------------------------------------------------------------------------
-// a table of at most one sort tile, built by one workgroup
-// ----------------------------------------------------------------------------
-// Keys, their stable sort in LDS, the cell table and the reorder in one
-// kernel.  Such tables are bound by latency: the general path's dependent
-// launches (two fills, keys, sort, ranges, cell_first, reorder) each cost
-// more than their work here.  The cell table comes from binary searches of
-// the sorted keys in LDS, per cell: first[c] is the first position whose key
-// is >= c, and a cell is occupied where first[c + 1] > first[c].  Each thread
-// takes a run of consecutive cells, so the tables stay small (kTileCells).
-constexpr uint32_t kTileCells = 8192;
-
-__device__ inline uint32_t lower_bound_u32(const uint32_t* k, uint32_t lo, uint32_t hi, uint32_t c)
-{
-    while (lo < hi) {
-        const uint32_t mid = lo + (hi - lo) / 2;
-        if (k[mid] < c) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// Each phase issues all its global loads before it uses any: a thread's
-// kTileIters particles are loaded together, and each particle's case comes
-// from LDS (s_case, filled from the items first), so every phase costs one
-// trip to memory.
-__global__ void __launch_bounds__(kTileThreads)
-k_build_tile(const CaseDev* __restrict__ cases, const Item* __restrict__ items, uint32_t n_items, uint32_t n,
-             uint32_t n_cells, int bits, int dim_max, StateDev in, StateDev out, uint32_t* __restrict__ cell_key,
-             uint32_t* __restrict__ perm, uint32_t* __restrict__ start, uint32_t* __restrict__ end,
-             uint32_t* __restrict__ first, float4* __restrict__ pos4)
-{
-    __shared__ TileSort sm;
-    __shared__ uint32_t s_case[kSortTile];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = __lane_id();
-    const uint32_t wave = tid / kWave;
-    // each particle's case: a wave per item, four items' loads at a time
-    constexpr uint32_t kItemsAtOnce = 4;
-    for (uint32_t base = 0; base < n_items; base += kTileWaves * kItemsAtOnce) {
-        Item it[kItemsAtOnce];
-#pragma unroll
-        for (uint32_t j = 0; j < kItemsAtOnce; ++j) {
-            const uint32_t ix = base + j * kTileWaves + wave;
-            it[j] = items[ix < n_items ? ix : n_items - 1];
-            if (ix >= n_items) it[j].count = 0;
-        }
-#pragma unroll
-        for (uint32_t j = 0; j < kItemsAtOnce; ++j)
-            for (uint32_t l = lane; l < it[j].count; l += kWave) s_case[min(it[j].first + l, kSortTile - 1)] = it[j].case_id;
-    }
-    __syncthreads();
-    {
-        // loads at a valid position for every lane (n >= 1), used where live
-        uint32_t cell[kTileIters], cid[kTileIters];
-#pragma unroll
-        for (int k = 0; k < kTileIters; ++k) {
-            const uint32_t i = k * kTileThreads + tid;
-            const uint32_t at = i < n ? i : 0u;
-            cell[k] = in.cell[at];
-            cid[k] = s_case[at];
-        }
-#pragma unroll
-        for (int k = 0; k < kTileIters; ++k) {
-            const uint32_t i = k * kTileThreads + tid;
-            const CaseDev& C = cases[cid[k]];
-            // a corrupt cell index: keep the key inside the case
-            const uint32_t c = cell[k] < C.n_cells ? cell[k] : C.n_cells - 1;
-            if (i < n) {
-                sm.key[0][i] = C.cell_base + c;
-                sm.idx[0][i] = static_cast<uint16_t>(i);
-            }
-        }
-    }
-    const int src = tile_sort(sm, n, bits);
-    const uint32_t* key = sm.key[src];
-    const uint16_t* idx = sm.idx[src];
-    for (uint32_t i = tid; i < n; i += kTileThreads) {
-        cell_key[i] = key[i];
-        perm[i] = idx[i];
-    }
-    const uint32_t per = (n_cells + 1 + kTileThreads - 1) / kTileThreads;
-    const uint32_t c_begin = tid * per;
-    const uint32_t c_end = min(c_begin + per, n_cells + 1);
-    if (c_begin < c_end) {
-        uint32_t f = lower_bound_u32(key, 0, n, c_begin);
-        for (uint32_t c = c_begin; c < c_end; ++c) {
-            first[c] = f;
-            if (c == n_cells) break;
-            const uint32_t fn = lower_bound_u32(key, f, n, c + 1);
-            const bool occupied = fn > f;
-            start[c] = occupied ? f : NAUTICLE_EMPTY;
-            end[c] = occupied ? fn : NAUTICLE_EMPTY;
-            f = fn;
-        }
-    }
-    // the reorder (as k_reorder): sorting keeps every particle inside its
-    // case's range, so sorted position p has the case of input position p.
-    // The state holds dim_max components for every particle.
-    // every load at a valid position (n >= 1) before any store
-    uint32_t q[kTileIters], cid[kTileIters], cell[kTileIters], id[kTileIters], ncx[kTileIters];
-    int dim[kTileIters];
-    float rho[kTileIters], o[kTileIters][3], v[kTileIters][3];
-#pragma unroll
-    for (int k = 0; k < kTileIters; ++k) {
-        const uint32_t p = k * kTileThreads + tid;
-        const uint32_t at = p < n ? p : 0u;
-        q[k] = idx[at];
-        cid[k] = s_case[at];
-    }
-#pragma unroll
-    for (int k = 0; k < kTileIters; ++k) {
-        const CaseDev& C = cases[cid[k]];
-        ncx[k] = static_cast<uint32_t>(C.nc[0]);
-        dim[k] = C.dim;
-        cell[k] = in.cell[q[k]];
-        id[k] = in.id[q[k]];
-        rho[k] = 0.0f;
-        if (in.rho) rho[k] = in.rho[q[k]];
-        for (int a = 0; a < 3; ++a) {
-            o[k][a] = 0.0f;
-            v[k][a] = 0.0f;
-            if (a < dim_max) {
-                o[k][a] = in.off[a][q[k]];
-                v[k][a] = in.vel[a][q[k]];
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < kTileIters; ++k) {
-        const uint32_t p = k * kTileThreads + tid;
-        if (p >= n) continue;
-        out.cell[p] = cell[k];
-        out.id[p] = id[k];
-        if (in.rho) out.rho[p] = rho[k];
-        for (int a = 0; a < 3; ++a) {
-            if (a >= dim[k]) {
-                o[k][a] = 0.0f;
-                continue;
-            }
-            out.off[a][p] = o[k][a];
-            out.vel[a][p] = v[k][a];
-        }
-        pos4[p] = make_float4(o[k][0], o[k][1], o[k][2], static_cast<float>(cell[k] % ncx[k]));
-    }
-}
-
-// ----------------------------------------------------------------------------
 // build_cells
 // ----------------------------------------------------------------------------
 
@@ -926,10 +779,9 @@ hipError_t launch_build_cells(const Plan& P, void* ws, StateDev in, StateDev sor
     const Item* items = at<Item>(ws, P.L.items);
     uint32_t* err = at<uint32_t>(ws, P.L.err);
     const Packed pk = packed(P, ws);
-    if (n > 0 && n <= kSortTile && nc <= kTileCells) {
-        k_build_tile<<<1, kTileThreads, 0, s>>>(cases, items, P.n_items, n, nc, P.key_bits, P.dim_max, in, sorted,
-                                                cells.key, cells.perm, cells.cell_start, cells.cell_end,
-                                                pk.cell_first, pk.pos4);
+    if (one_tile_build(n, nc)) {
+        const hipError_t e = launch_build_tile(P, ws, in, sorted, cells, s);
+        if (e != hipSuccess) return e;
     } else {
         const hipError_t e = build_table(P, ws, in, sorted, cells, s);
         if (e != hipSuccess || n == 0) return e;

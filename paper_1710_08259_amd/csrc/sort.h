@@ -137,6 +137,17 @@ __device__ inline int tile_sort(TileSort& sm, uint32_t n, int bits)
     return src;
 }
 
+// ---- the whole cell table of a table of one tile ------------------------------------
+// Tables of at most kSortTile particles and kTileCells cells are built by one
+// workgroup (tile.hip): keys, tile_sort, the cell start/end table,
+// cell_first and the reorder in one kernel.
+constexpr uint32_t kTileCells = 8192;
+
+inline bool one_tile_build(uint32_t n, uint32_t n_cells) { return n > 0 && n <= kSortTile && n_cells <= kTileCells; }
+
+hipError_t launch_build_tile(const Plan& P, void* ws, StateDev in, StateDev sorted, const nauticle_cells& cells,
+                             hipStream_t s);
+
 hipError_t launch_radix_sort(uint32_t* const keys[2], uint32_t* const vals[2], uint32_t n, int bits,
                              bool ordered, uint32_t* hist, uint32_t* totals, hipStream_t s);
 

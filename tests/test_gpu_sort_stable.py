@@ -112,6 +112,7 @@ TABLES = {
     "tile_batched_2d": lambda: WL.batched_2d(n_cases=3, seed=98, max_side_exp=5.0),
     "tile_sparse_3d": _sparse_small_3d,
     "tile_many_cells_3d": _sparse_many_cells_3d,
+    "tile_64_cases_2d": lambda: [WL.lattice_case(2, (8, 8), 0.01, 1.3, 0.05, 0.05, seed=200 + b) for b in range(64)],
 }
 
 
