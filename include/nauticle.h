@@ -486,8 +486,8 @@ nauticle_status nauticle_step_record(const nauticle_case* cases, int32_t n_cases
  * with the default tuning and no caller workspace.  Its scratch is a fixed
  * array of 64 MiB in the library's device code, one per device, held from
  * the library's load until the process ends; cases needing more scratch
- * than that (nauticle_workspace_bytes; about 140 bytes per particle, so
- * roughly 470,000 particles) are rejected with NAUTICLE_ERR_WORKSPACE
+ * than that (nauticle_workspace_bytes; about 150 bytes per particle for a
+ * 3-D table, so roughly 450,000 particles) are rejected with NAUTICLE_ERR_WORKSPACE
  * before anything is enqueued.  The call allocates nothing: it writes the
  * case table into the scratch, enqueues the steps on `stream`, then waits
  * for the stream and returns the most severe condition the kernels
