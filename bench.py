@@ -135,8 +135,8 @@ def parse():
     ap.add_argument("--ch-only", action="store_true", help="only the Example 1b Cahn-Hilliard sphere")
     ap.add_argument("--law-only", choices=("dem", "social"), default=None,
                     help="only one pair-law workload (DEM damper or social force room)")
-    ap.add_argument("--only", choices=("adjoint", "batched", "dam_break", "paper_shape", "small"), default=None,
-                    help="only one extra workload (for profiling runs)")
+    ap.add_argument("--only", choices=("adjoint", "batched", "dam_break", "paper_shape", "small", "largest"),
+                    default=None, help="only one extra workload (for profiling runs)")
     ap.add_argument("--batched-tuning", default=None,
                     help="block/persistent/groups_per_cu for the batched workload instead of the autotuner's pick")
     ap.add_argument("--verlet-only", action="store_true",
@@ -429,6 +429,32 @@ def small_extra(device, steps=200, per_graph=20):
             "eager_ms_per_step": round(eager * 1e3, 4),
             "graph_ms_per_step": round(graph * 1e3, 4), "steps_per_graph": per_graph,
             "graph_steps_per_s": 1.0 / graph, "graph_interactions_per_s": pairs / graph}
+
+
+def largest_extra(device, steps=5, warmup=2):
+    """The largest lattice of the headline recipe under the 26-bit index
+    limit of a list entry: 512 x 512 x 255 sites (66,846,720 particles),
+    whole steps as the headline line times them, with the device memory
+    the table holds."""
+    import torch
+
+    from paper_1710_08259_amd import nauticle as N
+    from paper_1710_08259_amd import workloads as WL
+
+    case = WL.lattice_case(3, (512, 512, 255), 0.01, 1.2, 0.05, 0.05, seed=3, c0=10.0, nu=1e-3, dt=1e-4,
+                           name="periodic_3d_66846720")
+    torch.cuda.reset_peak_memory_stats()
+    prob = N.Problem([case], device=device)
+    st = prob.state_from_cases()
+    wall, phase, pairs = timed_steps(prob, st, steps, warmup)
+    prob.check()
+    out = {"workload": case.name, "particles": case.n, "cells": list(case.ncell),
+           "ms_per_step": round(wall * 1e3 / steps, 3), "interactions_per_s": pairs / wall,
+           "phases": {"sort_reorder_ms": round(phase[0], 4), "neighbour_lists_ms": round(phase[1], 4),
+                      "density_ms": round(phase[2], 4), "forces_integrate_ms": round(phase[3], 4)},
+           "device_gib": round(torch.cuda.max_memory_allocated() / 2**30, 1)}
+    del prob, st
+    return out
 
 
 def paper_shape_extra(device, passes=50):
@@ -779,7 +805,7 @@ def main():
             tn = N.Tuning(block=b, persistent=p, groups_per_cu=g)
         fn = {"adjoint": lambda: adjoint_extra(device), "batched": lambda: batched_extra(device, tuning=tn),
               "dam_break": lambda: dam_break_extra(device), "paper_shape": lambda: paper_shape_extra(device),
-              "small": lambda: small_extra(device)}[args.only]
+              "small": lambda: small_extra(device), "largest": lambda: largest_extra(device)}[args.only]
         print(json.dumps({"extra": {args.only: fn()}}), flush=True)
         return
     if args.ex1a_only:
@@ -861,6 +887,8 @@ def main():
         line["extra"]["paper_shape"] = paper_shape_extra(device)
         torch.cuda.empty_cache()
         line["extra"]["small"] = small_extra(device)
+        torch.cuda.empty_cache()
+        line["extra"]["largest"] = largest_extra(device)
         torch.cuda.empty_cache()
         line["extra"]["verlet"] = verlet_extra(device, args.skin_frac, pairs_2h_per_step=pairs_per_step,
                                                plain_ms=wall * 1e3 / args.steps)

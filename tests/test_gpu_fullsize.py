@@ -10,6 +10,8 @@ any size.
   positions and velocities within 1e-5, for 2048 sampled particles
   (velocities against max |v'| or dt times the acceleration scale, the
   larger: from rest v' is dt a).
+- The same recipe at 66,846,720 particles, the largest lattice under the
+  26-bit index limit of a list entry: the same one-step checks.
 - 3-D dam break, 1,595,308 particles (571,308 fixed): the same one-step
   checks on a sample drawn from the fluid and the walls, and the 500th
   step's fields on the state the GPU reached after 499 steps.
@@ -110,6 +112,18 @@ def _one_step_sampled(N, case, n_nbr_sample, n_field_sample, seed):
 def test_periodic_lattice_8388608_one_step_sampled():
     N = nauticle()
     _one_step_sampled(N, WL.periodic_3d_8m(), 4096, 2048, seed=101)
+
+
+def test_largest_table_66846720_one_step_sampled():
+    """The largest lattice of the recipe under the 26-bit index limit of a
+    list entry (512 x 512 x 255 sites, 99.6 % of 2^26 particles; ~49 GiB of
+    device memory): the same checks, where list offsets pass 2^32 bytes."""
+    N = nauticle()
+    case = WL.lattice_case(3, (512, 512, 255), 0.01, 1.2, 0.05, 0.05, seed=3, c0=10.0, nu=1e-3, dt=1e-4,
+                           name="periodic_3d_66846720")
+    assert case.n < (1 << 26)
+    _one_step_sampled(N, case, 2048, 1024, seed=103)
+    torch.cuda.empty_cache()
 
 
 def test_dam_break_1595308_one_step_sampled():
