@@ -130,8 +130,8 @@ k_build_tile(const CaseDev* __restrict__ cases, const Item* __restrict__ items, 
     }
     // the reorder (as k_reorder): sorting keeps every particle inside its
     // case's range, so sorted position p has the case of input position p.
-    // The state holds dim_max components for every particle.
-    // every load at a valid position (n >= 1) before any store
+    // The state holds dim_max components for every particle; every load is
+    // issued at a valid position (n >= 1) before any store.
     uint32_t q[kTileIters], cid[kTileIters], cell[kTileIters], id[kTileIters], ncx[kTileIters];
     int dim[kTileIters];
     float rho[kTileIters], o[kTileIters][3], v[kTileIters][3];
