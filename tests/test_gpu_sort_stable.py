@@ -98,6 +98,15 @@ def _sparse_many_cells_3d():
     return [WL.scaled(base, pos=pts.astype(np.float32))]
 
 
+def _sparse_8192_cells_2d():
+    """2,048 random points in 128 x 64 = 8,192 cells: the most cells the
+    one-workgroup build takes (nine cells per thread)."""
+    base = WL.lattice_case(2, (64, 32), 0.01, 0.2499, 0.0, 0.05, seed=104, name="sparse_8192_cells_2d")
+    rng = np.random.default_rng(104)
+    pts = rng.uniform(0, 1, (base.n, 2)) * base.length()[:2]
+    return [WL.scaled(base, pos=pts.astype(np.float32))]
+
+
 # Tables of at most one sort tile (4096 keys) and 8192 cells are built by one
 # workgroup; larger ones take the general path, whose sort runs one tile in
 # one workgroup and more tiles pass by pass: all sides of those edges are
@@ -112,6 +121,7 @@ TABLES = {
     "tile_batched_2d": lambda: WL.batched_2d(n_cases=3, seed=98, max_side_exp=5.0),
     "tile_sparse_3d": _sparse_small_3d,
     "tile_many_cells_3d": _sparse_many_cells_3d,
+    "tile_8192_cells_2d": _sparse_8192_cells_2d,
     "tile_64_cases_2d": lambda: [WL.lattice_case(2, (8, 8), 0.01, 1.3, 0.05, 0.05, seed=200 + b) for b in range(64)],
 }
 
