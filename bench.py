@@ -47,15 +47,15 @@ NLIST_TRAFFIC_SOURCE_SHA256 = "289e068b0f381b81"
 # Issue-slot and vector-L1 figures from the counter runs summarised in
 # profiles/neighbour_kernels_periodic_3d_8388608_issue.md, guarded the same
 # way (by the sources of the kernels they were taken on).
-NLIST_VALU_ISSUE_FRAC = 0.987
+NLIST_VALU_ISSUE_FRAC = 0.985
 NLIST_VALU_INSTS = 1.339e9    # wave instructions per search launch (SQ_INSTS_VALU)
-FORCE_L1_ACCESS_RATE = 1.04   # accesses per CU per clock; the vector L1 serves about one
+FORCE_L1_ACCESS_RATE = 1.06   # accesses per CU per clock; the vector L1 serves about one
 # HBM bytes per density / force launch (FETCH_SIZE x2 + WRITE_SIZE, same
 # runs and guard as the L1 rate), and the force pass's VALU issue fraction.
-DENSITY_TRAFFIC_BYTES = 2.706e9 + 0.403e9
+DENSITY_TRAFFIC_BYTES = 2.681e9 + 0.403e9
 FORCE_TRAFFIC_BYTES = 3.019e9 + 0.369e9
-FORCE_VALU_ISSUE_FRAC = 0.467
-FORCE_SOURCES_SHA256 = "fc084a524de1e5fd"
+FORCE_VALU_ISSUE_FRAC = 0.471
+FORCE_SOURCES_SHA256 = "e0dedb8d5c9aa505"
 
 
 def _digest(*rel):

@@ -18,9 +18,12 @@ namespace nau {
 // Pairs per pipeline stage of the pair passes: 8 in 3-D (~57 neighbours per
 // particle); 4 in 2-D, where lists are short (~12-25 entries) and the
 // smaller stages leave registers for more resident waves to hide the
-// walk's latency.  The order of every sum does not depend on it.
+// walk's latency.  The 3-D density sum, one record per neighbour, takes 12:
+// three waves per SIMD with 24 gathers in flight each beat four with 16.
+// The order of every sum does not depend on it.
 constexpr uint32_t kGroup3 = 8;
 constexpr uint32_t kGroup2 = 4;
+constexpr uint32_t kDensityGroup3 = 12;
 
 // ----------------------------------------------------------------------------
 // density + equation of state (arithmetic in pairs.h)
@@ -76,7 +79,7 @@ hipError_t launch_density(const Plan& P, void* ws, StateDev sorted, const nautic
     ItemQueue Q;
     hipError_t e = item_queue(P, ws, 1, s, &Q);
     if (e != hipSuccess) return e;
-    auto kern = P.dim_max == 3 ? (P.mirror ? k_density<true, kGroup3> : k_density<false, kGroup3>)
+    auto kern = P.dim_max == 3 ? (P.mirror ? k_density<true, kDensityGroup3> : k_density<false, kDensityGroup3>)
                                : (P.mirror ? k_density<true, kGroup2> : k_density<false, kGroup2>);
     kern<<<grid_for(P, reinterpret_cast<const void*>(kern)), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), Q, sorted, pk.pos4,
                                          cells.nbr, cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), P.n_total,
