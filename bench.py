@@ -40,22 +40,25 @@ PEAK_HBM_GBS = 8000.0
 # summarised in profiles/neighbour_kernels_periodic_3d_8388608_traffic.md
 # (scaled by a plain 1 GiB copy); valid only for the search source the
 # counters were taken on, reported as null otherwise.
-NLIST_TRAFFIC_BYTES = 3.402e9
-NLIST_TRAFFIC_SOURCE_SHA256 = "289e068b0f381b81"
+NLIST_TRAFFIC_BYTES = 3.571e9
+NLIST_TRAFFIC_SOURCE_SHA256 = "14b1231db5479d18"
 
 
-# Issue-slot and vector-L1 figures from the counter runs summarised in
+# VALU and vector-L1 figures from the counter runs summarised in
 # profiles/neighbour_kernels_periodic_3d_8388608_issue.md, guarded the same
-# way (by the sources of the kernels they were taken on).
-NLIST_VALU_ISSUE_FRAC = 0.985
-NLIST_VALU_INSTS = 1.339e9    # wave instructions per search launch (SQ_INSTS_VALU)
-FORCE_L1_ACCESS_RATE = 1.06   # accesses per CU per clock; the vector L1 serves about one
+# way (by the sources of the kernels they were taken on).  VALU rates are
+# wave instructions per SIMD per 4 cycles (SQ_INSTS_VALU over 1024 SIMDs x
+# cycles / 4); gfx950 exceeds 1.0 on this measure, so it is a rate, not a
+# fraction of a ceiling.
+NLIST_VALU_PER_SIMD_4CYC = 1.147
+NLIST_VALU_INSTS = 1.335e9    # wave instructions per search launch (SQ_INSTS_VALU)
+FORCE_L1_ACCESS_RATE = 1.10   # accesses per CU per clock
 # HBM bytes per density / force launch (FETCH_SIZE x2 + WRITE_SIZE, same
-# runs and guard as the L1 rate), and the force pass's VALU issue fraction.
-DENSITY_TRAFFIC_BYTES = 2.681e9 + 0.403e9
-FORCE_TRAFFIC_BYTES = 3.019e9 + 0.369e9
-FORCE_VALU_ISSUE_FRAC = 0.471
-FORCE_SOURCES_SHA256 = "e0dedb8d5c9aa505"
+# runs and guard as the L1 rate), and the force pass's VALU rate.
+DENSITY_TRAFFIC_BYTES = 2.683e9 + 0.403e9
+FORCE_TRAFFIC_BYTES = 3.025e9 + 0.369e9
+FORCE_VALU_PER_SIMD_4CYC = 0.487
+FORCE_SOURCES_SHA256 = "ba689c7634be8a33"
 
 
 def _digest(*rel):
@@ -72,8 +75,8 @@ def nlist_traffic():
     return NLIST_TRAFFIC_BYTES if _digest("search.hip", "internal.h") == NLIST_TRAFFIC_SOURCE_SHA256 else None
 
 
-def nlist_issue_frac():
-    return NLIST_VALU_ISSUE_FRAC if _digest("search.hip", "internal.h") == NLIST_TRAFFIC_SOURCE_SHA256 else None
+def nlist_valu_rate():
+    return NLIST_VALU_PER_SIMD_4CYC if _digest("search.hip", "internal.h") == NLIST_TRAFFIC_SOURCE_SHA256 else None
 
 
 def nlist_lane_slots_per_candidate(candidates):
@@ -116,7 +119,7 @@ def hbm_fractions(n, phase_ms):
                     "algorithmic": rate(DENSITY_ALGO_BYTES * n, phase_ms[2])},
         "force_pass": {"measured": rate(_force_guard(FORCE_TRAFFIC_BYTES), phase_ms[3]),
                        "algorithmic": rate(FORCE_ALGO_BYTES * n, phase_ms[3]),
-                       "valu_issue_frac": _force_guard(FORCE_VALU_ISSUE_FRAC)},
+                       "valu_per_simd_4_cycles": _force_guard(FORCE_VALU_PER_SIMD_4CYC)},
         "sort_cells_reorder": {"algorithmic": rate(SORT_REORDER_ALGO_BYTES * n, phase_ms[0])},
     }
 
@@ -839,7 +842,7 @@ def main():
                 "achieved": round(search_tflops, 3), "peak": PEAK_FP32_TFLOPS_UNPACKED, "unit": "TFLOP/s",
                 "frac": round(search_tflops / PEAK_FP32_TFLOPS_UNPACKED, 4), "traffic": nlist_traffic(),
                 "peak_published_packed_fp32": PEAK_FP32_TFLOPS,
-                "valu_issue_frac": nlist_issue_frac(),
+                "valu_per_simd_4_cycles": nlist_valu_rate(),
                 "lane_slots_per_candidate": nlist_lane_slots_per_candidate(cand),
                 "candidates_per_step": cand, "ms": round(phase_ms[1], 4)}
     line = {

@@ -231,6 +231,8 @@ nauticle_status derive(const nauticle_case* cases, int32_t n_cases, const nautic
     }
     P.dim_max = dim0;
     P.model = model0;
+    // D->cases keeps its buffer when the plan is moved into the table of plans
+    P.host_cases = D->cases.data();
     P.mirror = any_mirror ? 1u : 0u;
     P.n_total = static_cast<uint32_t>(n_total);
     P.n_cells_total = static_cast<uint32_t>(n_cells_total);

@@ -274,7 +274,7 @@ inline uint32_t halo_records(uint32_t planned, uint32_t na, uint32_t bytes)
     const uint32_t fit = bytes / (16u * na) - kHaloPad;
     return planned < fit ? planned : fit;
 }
-constexpr uint32_t kHaloBytes = 48u * 1024u;  // 3 items of 256 per CU
+constexpr uint32_t kHaloBytes = 38u * 1024u;  // 4 items of 256 per CU
 
 struct HaloRows {
     uint32_t lo[kHaloRows];    // staged sorted range [lo, hi) of row r

@@ -18,12 +18,23 @@ namespace nau {
 // Pairs per pipeline stage of the pair passes: 8 in 3-D (~57 neighbours per
 // particle); 4 in 2-D, where lists are short (~12-25 entries) and the
 // smaller stages leave registers for more resident waves to hide the
-// walk's latency.  The 3-D density sum, one record per neighbour, takes 12:
-// three waves per SIMD with 24 gathers in flight each beat four with 16.
-// The order of every sum does not depend on it.
+// walk's latency.  The 3-D density sum, one record per neighbour, takes 12
+// where lists are long (three waves per SIMD with 24 gathers in flight each
+// beat four with 16); where they are short, padding to whole stages of 12
+// costs more than that gains.  The order of every sum does not depend on it.
 constexpr uint32_t kGroup3 = 8;
 constexpr uint32_t kGroup2 = 4;
-constexpr uint32_t kDensityGroup3 = 12;
+constexpr uint32_t kDensityGroup3Long = 12;
+constexpr double kLongList = 48.0;  // expected neighbours per particle
+
+// Expected neighbours per particle at a case's mean number density: the
+// particles per cell times the ball of radius 2h over the cell (3-D).
+inline double expected_neighbours_3d(const CaseDev& C)
+{
+    const double r = std::sqrt(static_cast<double>(C.R2));
+    const double cell = static_cast<double>(C.cs[0]) * C.cs[1] * C.cs[2];
+    return static_cast<double>(C.n) / C.n_cells * (4.0 / 3.0 * M_PI * r * r * r) / cell;
+}
 
 // ----------------------------------------------------------------------------
 // density + equation of state (arithmetic in pairs.h)
@@ -79,7 +90,12 @@ hipError_t launch_density(const Plan& P, void* ws, StateDev sorted, const nautic
     ItemQueue Q;
     hipError_t e = item_queue(P, ws, 1, s, &Q);
     if (e != hipSuccess) return e;
-    auto kern = P.dim_max == 3 ? (P.mirror ? k_density<true, kDensityGroup3> : k_density<false, kDensityGroup3>)
+    bool long_lists = false;
+    for (int b = 0; b < P.n_cases && P.dim_max == 3; ++b)
+        long_lists |= expected_neighbours_3d(P.host_cases[b]) >= kLongList;
+    auto k3 = long_lists ? (P.mirror ? k_density<true, kDensityGroup3Long> : k_density<false, kDensityGroup3Long>)
+                         : (P.mirror ? k_density<true, kGroup3> : k_density<false, kGroup3>);
+    auto kern = P.dim_max == 3 ? k3
                                : (P.mirror ? k_density<true, kGroup2> : k_density<false, kGroup2>);
     kern<<<grid_for(P, reinterpret_cast<const void*>(kern)), P.block, 0, s>>>(at<CaseDev>(ws, P.L.cases), at<Item>(ws, P.L.items), Q, sorted, pk.pos4,
                                          cells.nbr, cells.nbr_count, static_cast<uint32_t>(cells.max_nbr), P.n_total,

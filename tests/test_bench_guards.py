@@ -23,7 +23,7 @@ def test_counter_figures_are_null_unless_taken_on_the_current_sources():
     live = bench._digest("search.hip", "internal.h") == bench.NLIST_TRAFFIC_SOURCE_SHA256
     assert (bench.nlist_traffic() == bench.NLIST_TRAFFIC_BYTES) == live
     assert (bench.nlist_traffic() is None) == (not live)
-    assert (bench.nlist_issue_frac() is None) == (not live)
+    assert (bench.nlist_valu_rate() is None) == (not live)
     live_f = bench._digest("sph.hip", "pairs.h", "internal.h") == bench.FORCE_SOURCES_SHA256
     assert (bench.force_l1_rate() is None) == (not live_f)
 
