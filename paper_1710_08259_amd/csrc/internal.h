@@ -274,7 +274,11 @@ inline uint32_t halo_records(uint32_t planned, uint32_t na, uint32_t bytes)
     const uint32_t fit = bytes / (16u * na) - kHaloPad;
     return planned < fit ? planned : fit;
 }
-constexpr uint32_t kHaloBytes = 38u * 1024u;  // 4 items of 256 per CU
+// The search's halo budget: five items of 256 particles per CU.  An item of
+// the dense lattice needs ~41 KB for all nine rows; the rows that do not fit
+// are read from global memory, which costs less than the occupancy a larger
+// halo would take (48 KB: three items per CU, 38 KB: four, 31 KB: five).
+constexpr uint32_t kHaloBytes = 31u * 1024u;
 
 struct HaloRows {
     uint32_t lo[kHaloRows];    // staged sorted range [lo, hi) of row r

@@ -703,8 +703,12 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
     if (cnt > max_nbr) set_error(err, kErrOverflow);
 }
 
+// The search is bound by the latency of each wave's dependent LDS reads and
+// emission steps, so it runs as many items per CU as fit: the LDS halo
+// (kHaloBytes) admits five of 256 particles, and five waves per SIMD hold
+// the kernel to 96 VGPRs (one small spill, outside the loops).
 template <int DIM, bool kMirror>
-__global__ void __launch_bounds__(kMaxBlock)
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5)))
 k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
         const float4* __restrict__ pos4, const uint32_t* __restrict__ cell_first, uint32_t* __restrict__ nbr,
         uint32_t* __restrict__ nbr_count, uint32_t max_nbr, uint32_t n_total, uint32_t halo_cap, uint32_t* err)
