@@ -146,8 +146,12 @@ __device__ inline void interact_particle(const CaseDev& C, const ShiftTable& tab
     }
 }
 
+// Contact lists are short (a few pairs per particle), so a wave's time is the
+// latency of its gathers and more resident waves hide it: four per SIMD hold
+// the DEM instances to 128 VGPRs (the stepped one with symmetric faces needs
+// 129 otherwise), with no spill.
 template <class Law, bool kIntegrate, bool kMirror, uint32_t G>
-__global__ void __launch_bounds__(kMaxBlock)
+__global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(4)))
 k_interact(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st, LawAttrsDev at_,
            const float4* __restrict__ r0, const float4* __restrict__ r1, const float4* __restrict__ r2,
            const uint32_t* __restrict__ nbr, const uint32_t* __restrict__ nbr_count, uint32_t max_nbr,
