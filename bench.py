@@ -40,8 +40,8 @@ PEAK_HBM_GBS = 8000.0
 # summarised in profiles/neighbour_kernels_periodic_3d_8388608_traffic.md
 # (scaled by a plain 1 GiB copy); valid only for the search source the
 # counters were taken on, reported as null otherwise.
-NLIST_TRAFFIC_BYTES = 3.773e9
-NLIST_TRAFFIC_SOURCE_SHA256 = "283bed7cd431c158"
+NLIST_TRAFFIC_BYTES = 3.711e9
+NLIST_TRAFFIC_SOURCE_SHA256 = "f3f0d4aae76e8902"
 
 
 # VALU and vector-L1 figures from the counter runs summarised in
@@ -50,14 +50,14 @@ NLIST_TRAFFIC_SOURCE_SHA256 = "283bed7cd431c158"
 # wave instructions per SIMD per 4 cycles (SQ_INSTS_VALU over 1024 SIMDs x
 # cycles / 4); gfx950 exceeds 1.0 on this measure, so it is a rate, not a
 # fraction of a ceiling.
-NLIST_VALU_PER_SIMD_4CYC = 1.183
-NLIST_VALU_INSTS = 1.330e9    # wave instructions per search launch (SQ_INSTS_VALU)
-FORCE_L1_ACCESS_RATE = 1.09   # accesses per CU per clock
+NLIST_VALU_PER_SIMD_4CYC = 1.184
+NLIST_VALU_INSTS = 1.274e9    # wave instructions per search launch (SQ_INSTS_VALU)
+FORCE_L1_ACCESS_RATE = 1.12   # accesses per CU per clock
 # HBM bytes per density / force launch (FETCH_SIZE x2 + WRITE_SIZE, same
 # runs and guard as the L1 rate), and the force pass's VALU rate.
-DENSITY_TRAFFIC_BYTES = 2.680e9 + 0.403e9
-FORCE_TRAFFIC_BYTES = 3.018e9 + 0.369e9
-FORCE_VALU_PER_SIMD_4CYC = 0.494
+DENSITY_TRAFFIC_BYTES = 2.684e9 + 0.403e9
+FORCE_TRAFFIC_BYTES = 3.026e9 + 0.369e9
+FORCE_VALU_PER_SIMD_4CYC = 0.495
 FORCE_SOURCES_SHA256 = "258c56d86fb8744c"
 
 

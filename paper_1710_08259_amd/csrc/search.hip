@@ -421,12 +421,13 @@ hipError_t launch_pack_positions(const Plan& P, void* ws, StateDev sorted, hipSt
 // that pass set a bit in a 64-candidate mask, which is then emitted in
 // ascending order into a four-entry register buffer that is stored as one
 // 16-byte chunk when full.  Lanes of one home cell read the same candidate at
-// the same time.  Reads may run up to 2 kUnroll - 1 candidates past a piece
+// the same time.  Reads may run up to 3 kUnroll - 1 candidates past a piece
 // (LDS and the packed positions are padded for it); such candidates are
 // masked off.
 
 constexpr uint32_t kUnroll = 4;
-static_assert(2 * kUnroll <= kPosPad && 64 % (2 * kUnroll) == 0, "candidate groups must tile the 64-bit mask");
+static_assert(64 % (2 * kUnroll) == 0, "candidate groups must tile the 64-bit mask");
+static_assert(3 * kUnroll <= kPosPad && 3 * kUnroll <= kHaloPad, "read-ahead past a piece must stay in the padding");
 
 // The same test for a piece of mirror images: along an axis with sign -1
 // the candidate's offset is negated, d = fl(fl(-off_j - off_i) + delta cs)
@@ -502,10 +503,11 @@ __device__ inline uint32_t shift_group(const float4* o, float cref, float mex, f
 }
 
 // Hit mask (bit k = candidate k) of the candidates src[0 .. m-1], 1 <= m <=
-// 32 (readable up to 2 kUnroll - 1 past m).  Two groups per iteration in
+// 32 (readable up to 3 kUnroll - 1 past m - 1).  Two groups per iteration in
 // ping-pong registers: group A is tested while group B loads, then B while
-// the next A loads.  The loop tests b = 8 ceil(m/8) candidates; the shifted
-// mask is reversed and aligned at the end.
+// the next A loads (on the last pass a group past the end, read and not
+// used, so the address needs no select).  The loop tests b = 8 ceil(m/8)
+// candidates; the shifted mask is reversed and aligned at the end.
 template <int DIM>
 __device__ inline uint32_t scan32(const float4* src, uint32_t m, float cref, float mex, float csx, float mey,
                                   float shy, float mez, float shz, float R2)
@@ -520,10 +522,8 @@ __device__ inline uint32_t scan32(const float4* src, uint32_t m, float cref, flo
         for (uint32_t u = 0; u < kUnroll; ++u) ob[u] = src[b + kUnroll + u];
         __builtin_amdgcn_sched_barrier(0);
         acc = shift_group<DIM>(oa, cref, mex, csx, mey, shy, mez, shz, R2, acc);
-        // the next A group, or this one again past the end (stays readable)
-        const uint32_t na = b + 2 * kUnroll < m ? b + 2 * kUnroll : b;
 #pragma unroll
-        for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[na + u];
+        for (uint32_t u = 0; u < kUnroll; ++u) oa[u] = src[b + 2 * kUnroll + u];
         __builtin_amdgcn_sched_barrier(0);
         acc = shift_group<DIM>(ob, cref, mex, csx, mey, shy, mez, shz, R2, acc);
     }
@@ -531,8 +531,8 @@ __device__ inline uint32_t scan32(const float4* src, uint32_t m, float cref, flo
 }
 
 // Hit mask of the candidates q0 .. q0 + m - 1 (m <= 64) read from `src`
-// (src[k] = candidate q0 + k; readable up to 2 kUnroll - 1 past m), as two
-// halves of 32.
+// (src[k] = candidate q0 + k; readable up to 3 kUnroll - 1 past m - 1), as
+// two halves of 32.
 template <int DIM>
 __device__ inline uint64_t scan_chunk(const float4* src, uint32_t m, float cref, float mex, float csx, float mey,
                                       float shy, float mez, float shz, float R2)
@@ -540,6 +540,35 @@ __device__ inline uint64_t scan_chunk(const float4* src, uint32_t m, float cref,
     const uint32_t lo = scan32<DIM>(src, m < 32u ? m : 32u, cref, mex, csx, mey, shy, mez, shz, R2);
     const uint32_t hi = m > 32u ? scan32<DIM>(src + 32, m - 32u, cref, mex, csx, mey, shy, mez, shz, R2) : 0u;
     return static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32);
+}
+
+// Appends the entries of the hits (ascending) to a lane's list: each enters
+// a four-entry register buffer (newest in w), stored as one 16-byte chunk
+// when full.  The entry of candidate q0 + b is e0 + b plus one x step of the
+// offset code per cell boundary (r1, r2, relative to q0) at or before b; the
+// three bases are formed once.  kCheck: stop storing past max_nbr entries
+// (the count still grows).
+template <bool kCheck>
+__device__ inline void emit_hits(uint64_t hits, uint32_t e0, int32_t r1, int32_t r2, uint4& buf, uint32_t& cnt,
+                                 uint4*& dst, uint32_t n_total, uint32_t max_nbr)
+{
+    constexpr uint32_t kStep = 1u << NAUTICLE_NBR_INDEX_BITS;
+    const uint32_t e1 = e0 + kStep, e2 = e0 + 2u * kStep;
+    while (hits) {
+        const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(hits));
+        hits &= hits - 1;
+        const int32_t sb = static_cast<int32_t>(b);
+        const uint32_t base = sb >= r2 ? e2 : (sb >= r1 ? e1 : e0);
+        buf.x = buf.y;
+        buf.y = buf.z;
+        buf.z = buf.w;
+        buf.w = base + b;
+        ++cnt;
+        if ((cnt & 3u) == 0u && (!kCheck || cnt <= max_nbr)) {
+            *dst = buf;
+            dst += n_total;
+        }
+    }
 }
 
 // kMirror: the case may have symmetric faces.  A stencil cell beyond such a
@@ -670,22 +699,14 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
                     // boundary at or before it
                     const uint32_t e0 =
                         q0 + (code_yz | (static_cast<uint32_t>(dx0 + 1) << NAUTICLE_NBR_INDEX_BITS));
-                    const uint32_t r1 = b1 - q0, r2 = b2 - q0;  // boundaries relative to q0 (wrap if before)
-                    while (hits) {
-                        const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(hits));
-                        hits &= hits - 1;
-                        const uint32_t step = (static_cast<int32_t>(b) >= static_cast<int32_t>(r1) ? 1u : 0u) +
-                                              (static_cast<int32_t>(b) >= static_cast<int32_t>(r2) ? 1u : 0u);
-                        buf.x = buf.y;
-                        buf.y = buf.z;
-                        buf.z = buf.w;
-                        buf.w = e0 + b + (step << NAUTICLE_NBR_INDEX_BITS);
-                        ++cnt;
-                        if ((cnt & 3u) == 0u && cnt <= max_nbr) {
-                            *dst = buf;
-                            dst += n_total;
-                        }
-                    }
+                    // boundaries relative to q0 (negative if before it)
+                    const int32_t r1 = static_cast<int32_t>(b1 - q0), r2 = static_cast<int32_t>(b2 - q0);
+                    // a list with room for every hit of the chunk stores them
+                    // without the capacity test
+                    if (cnt + static_cast<uint32_t>(__popcll(hits)) <= max_nbr)
+                        emit_hits<false>(hits, e0, r1, r2, buf, cnt, dst, n_total, max_nbr);
+                    else
+                        emit_hits<true>(hits, e0, r1, r2, buf, cnt, dst, n_total, max_nbr);
                 }
             }
         }
@@ -706,7 +727,8 @@ __device__ inline void nlist_particle(const CaseDev& C, const Item& it, StateDev
 // The search is bound by the latency of each wave's dependent LDS reads and
 // emission steps, so it runs as many items per CU as fit: the LDS halo
 // (kHaloBytes) admits five of 256 particles, and five waves per SIMD hold
-// the kernel to 96 VGPRs (one small spill, outside the loops).
+// the kernel to 96 VGPRs (no spill without symmetric faces; 8 registers
+// spilled with them).
 template <int DIM, bool kMirror>
 __global__ void __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(5)))
 k_nlist(const CaseDev* __restrict__ cases, const Item* __restrict__ items, ItemQueue Q, StateDev st,
